@@ -1,0 +1,372 @@
+// graphgen.cpp -- seeded synthetic graph generators (input data only).
+//
+// This module produces the symmetric CSR inputs that both the GPU library
+// and the CPU oracle consume.  It contains no part of the label-propagation
+// method.  Every random draw comes from the counter-based generator
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011), keyed by the seed and addressed by a counter
+// that names the draw, so the output does not depend on the thread count.
+//
+// Generators:
+//   * planted partition (stochastic block model, Condon & Karp 2001): each
+//     unordered pair inside a block is an edge with probability p_in, each
+//     pair across blocks with probability p_out; pairs are enumerated with
+//     geometric skipping (Batagelj & Brandes 2005), so the cost is linear in
+//     the number of edges;
+//   * R-MAT (Chakrabarti, Zhan, Faloutsos 2004): 2^scale vertices,
+//     edge_factor * 2^scale samples, quadrant probabilities a/b/c/d chosen
+//     per bit level, no noise and no vertex permutation;
+//   * symmetric integer edge weights from a hash of the unordered pair.
+//
+// All generators drop self-loops and duplicate edges, add both directions
+// and sort every row by target id.
+#include <omp.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace {
+
+// ---- Philox4x32-10 (Salmon et al. 2011) ------------------------------------
+struct P4 { uint32_t v[4]; };
+
+inline void mulhilo(uint32_t a, uint32_t b, uint32_t* hi, uint32_t* lo) {
+  const uint64_t p = (uint64_t)a * (uint64_t)b;
+  *hi = (uint32_t)(p >> 32);
+  *lo = (uint32_t)p;
+}
+
+inline P4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                 uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0, lo0, hi1, lo1;
+    mulhilo(M0, c0, &hi0, &lo0);
+    mulhilo(M1, c2, &hi1, &lo1);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += W0; k1 += W1;
+  }
+  return P4{{c0, c1, c2, c3}};
+}
+
+// Uniform double in [0, 1) from two 32-bit words (53 random bits).
+inline double u01(uint32_t hi, uint32_t lo) {
+  return ((double)(hi >> 5) * 67108864.0 + (double)(lo >> 6)) *
+         (1.0 / 9007199254740992.0);
+}
+
+// Geometric skip for Bernoulli(p) pair enumeration: number of failures
+// before the next success.
+inline int64_t geo_skip(double u, double log1mp) {
+  if (log1mp == 0.0) return INT64_MAX / 4;   // p == 0: no success ever
+  if (std::isinf(log1mp)) return 0;          // p == 1: every pair
+  const double s = std::floor(std::log1p(-u) / log1mp);
+  return s > 4.0e18 ? (int64_t)4e18 : (int64_t)s;
+}
+
+struct Pair { int32_t u, v; };
+
+// Emit the pairs of one SBM region (block a with itself when a == b, else
+// block a x block b).  Draw k of the region uses counter (region, k, g, tag).
+void sbm_region(int64_t a0, int64_t sa, int64_t b0, int64_t sb, bool same,
+                double p, uint32_t region, uint32_t graph, uint32_t k0,
+                uint32_t k1, std::vector<Pair>* out) {
+  if (p <= 0.0) return;
+  const double log1mp = p >= 1.0 ? -INFINITY : std::log1p(-p);
+  const int64_t total = same ? sa * (sa - 1) / 2 : sa * sb;
+  if (total <= 0) return;
+  int64_t idx = -1;
+  uint64_t k = 0;
+  // For the triangle walk: current row r covers indices [row_lo, row_lo + sa-1-r).
+  int64_t r = 0, row_lo = 0;
+  for (;;) {
+    const P4 x = philox(region, (uint32_t)k, (uint32_t)(k >> 32), graph, k0, k1);
+    ++k;
+    idx += geo_skip(u01(x.v[0], x.v[1]), log1mp) + 1;
+    if (idx >= total) break;
+    if (same) {
+      while (idx >= row_lo + (sa - 1 - r)) { row_lo += sa - 1 - r; ++r; }
+      const int64_t c = r + 1 + (idx - row_lo);
+      out->push_back(Pair{(int32_t)(a0 + r), (int32_t)(a0 + c)});
+    } else {
+      const int64_t r2 = idx / sb, c2 = idx % sb;
+      out->push_back(Pair{(int32_t)(a0 + r2), (int32_t)(b0 + c2)});
+    }
+  }
+}
+
+// Build a symmetric CSR (rows sorted, no duplicates, no self-loops) from an
+// undirected pair list into caller-visible malloc'd arrays.
+struct Csr {
+  int64_t n = 0, m = 0;
+  int64_t* off = nullptr;
+  int32_t* tgt = nullptr;
+};
+
+bool csr_from_pairs(int64_t n, const std::vector<Pair>& pairs, Csr* g) {
+  std::vector<int64_t> deg(n + 1, 0);
+  for (const Pair& p : pairs) {
+    if (p.u == p.v) continue;
+    ++deg[p.u]; ++deg[p.v];
+  }
+  g->n = n;
+  g->off = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  if (!g->off) return false;
+  g->off[0] = 0;
+  for (int64_t i = 0; i < n; ++i) g->off[i + 1] = g->off[i] + deg[i];
+  const int64_t m0 = g->off[n];
+  int32_t* t0 = (int32_t*)malloc(sizeof(int32_t) * (m0 > 0 ? m0 : 1));
+  if (!t0) return false;
+  std::vector<int64_t> cur(g->off, g->off + n);
+  for (const Pair& p : pairs) {
+    if (p.u == p.v) continue;
+    t0[cur[p.u]++] = p.v;
+    t0[cur[p.v]++] = p.u;
+  }
+  // sort + unique each row, then compact
+  std::vector<int64_t> nd(n, 0);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t* b = t0 + g->off[i];
+    int32_t* e = t0 + g->off[i + 1];
+    std::sort(b, e);
+    nd[i] = std::unique(b, e) - b;
+  }
+  int64_t* noff = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  if (!noff) { free(t0); return false; }
+  noff[0] = 0;
+  for (int64_t i = 0; i < n; ++i) noff[i + 1] = noff[i] + nd[i];
+  g->m = noff[n];
+  g->tgt = (int32_t*)malloc(sizeof(int32_t) * (g->m > 0 ? g->m : 1));
+  if (!g->tgt) { free(t0); free(noff); return false; }
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; ++i)
+    memcpy(g->tgt + noff[i], t0 + g->off[i], sizeof(int32_t) * nd[i]);
+  free(t0);
+  free(g->off);
+  g->off = noff;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Raw Philox4x32-10 block (exported for known-answer tests).
+void gg_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                      uint32_t out[4]) {
+  const P4 x = philox(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+  memcpy(out, x.v, sizeof(x.v));
+}
+
+// Handle to a generated CSR held in malloc'd memory until gg_free.
+typedef struct gg_graph {
+  int64_t n;
+  int64_t m;
+  int64_t* off;
+  int32_t* tgt;
+} gg_graph;
+
+void gg_free(gg_graph* g) {
+  if (!g) return;
+  free(g->off);
+  free(g->tgt);
+  g->off = nullptr;
+  g->tgt = nullptr;
+}
+
+// Planted partition on n vertices split into consecutive blocks of the given
+// sizes (sum must be n).  Pairs inside block b are edges with probability
+// p_in[b]; pairs across blocks with probability p_out.  graph_id separates
+// the random streams of graphs generated with one seed.
+int gg_sbm(int64_t n, int32_t nblocks, const int64_t* block_sizes,
+           const double* p_in, double p_out, uint64_t seed, uint32_t graph_id,
+           gg_graph* out) {
+  memset(out, 0, sizeof(*out));
+  if (n < 0 || nblocks < 0 || n > INT32_MAX) return -1;
+  std::vector<int64_t> start(nblocks + 1, 0);
+  for (int32_t b = 0; b < nblocks; ++b) start[b + 1] = start[b] + block_sizes[b];
+  if (start[nblocks] != n) return -1;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x53424D31u;
+  // region id: intra b -> b; inter (a<b) -> nblocks + a*nblocks + b
+  const int64_t nreg = (int64_t)nblocks + (int64_t)nblocks * nblocks;
+  std::vector<std::vector<Pair>> parts(nblocks);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t a = 0; a < nblocks; ++a) {
+    std::vector<Pair>& v = parts[a];
+    sbm_region(start[a], block_sizes[a], start[a], block_sizes[a], true,
+               p_in[a], (uint32_t)a, graph_id, k0, k1, &v);
+    for (int32_t b = a + 1; b < nblocks; ++b) {
+      const uint32_t reg = (uint32_t)(nblocks + (int64_t)a * nblocks + b);
+      sbm_region(start[a], block_sizes[a], start[b], block_sizes[b], false,
+                 p_out, reg, graph_id, k0, k1, &v);
+    }
+  }
+  (void)nreg;
+  std::vector<Pair> all;
+  size_t tot = 0;
+  for (auto& v : parts) tot += v.size();
+  all.reserve(tot);
+  for (auto& v : parts) all.insert(all.end(), v.begin(), v.end());
+  Csr g;
+  if (!csr_from_pairs(n, all, &g)) return -2;
+  out->n = g.n; out->m = g.m; out->off = g.off; out->tgt = g.tgt;
+  return 0;
+}
+
+// R-MAT: n = 2^scale, edge_factor * n samples.  At each of the scale bit
+// levels (most significant first) the quadrant is chosen with probabilities
+// a, b, c, 1-a-b-c from a 16-bit uniform draw; the quadrant (row bit, column
+// bit) is (0,0), (0,1), (1,0), (1,1) respectively.  Sample s uses Philox
+// counters (s, level group, tag).  Self-loops and duplicates are dropped and
+// both directions added.
+int gg_rmat(int32_t scale, int64_t edge_factor, double a, double b, double c,
+            uint64_t seed, gg_graph* out) {
+  memset(out, 0, sizeof(*out));
+  if (scale < 1 || scale > 30 || edge_factor < 0) return -1;
+  const int64_t n = (int64_t)1 << scale;
+  const int64_t S = edge_factor * n;
+  const uint32_t ta = (uint32_t)std::lround(a * 65536.0);
+  const uint32_t tb = (uint32_t)std::lround((a + b) * 65536.0);
+  const uint32_t tc = (uint32_t)std::lround((a + b + c) * 65536.0);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x524D4154u;
+  auto sample = [&](int64_t s, int32_t* pu, int32_t* pv) {
+    uint32_t u = 0, v = 0;
+    uint32_t words[8];
+    int have = 0, used = 0;
+    for (int lev = 0; lev < scale; ++lev) {
+      if (used == have) {
+        const P4 x = philox((uint32_t)s, (uint32_t)(s >> 32), (uint32_t)(lev >> 3),
+                            0x45444745u, k0, k1);
+        for (int q = 0; q < 4; ++q) { words[2 * q] = x.v[q] & 0xFFFFu; words[2 * q + 1] = x.v[q] >> 16; }
+        have = 8; used = 0;
+      }
+      const uint32_t r = words[used++];
+      const uint32_t bit = 1u << (scale - 1 - lev);
+      if (r < ta) {
+      } else if (r < tb) {
+        v |= bit;
+      } else if (r < tc) {
+        u |= bit;
+      } else {
+        u |= bit; v |= bit;
+      }
+    }
+    *pu = (int32_t)u; *pv = (int32_t)v;
+  };
+  // pass 1: degrees
+  std::atomic<int64_t>* deg = new (std::nothrow) std::atomic<int64_t>[n + 1];
+  if (!deg) return -2;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i <= n; ++i) deg[i].store(0, std::memory_order_relaxed);
+#pragma omp parallel for schedule(static, 65536)
+  for (int64_t s = 0; s < S; ++s) {
+    int32_t u, v;
+    sample(s, &u, &v);
+    if (u == v) continue;
+    deg[u].fetch_add(1, std::memory_order_relaxed);
+    deg[v].fetch_add(1, std::memory_order_relaxed);
+  }
+  int64_t* off0 = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  if (!off0) { delete[] deg; return -2; }
+  off0[0] = 0;
+  for (int64_t i = 0; i < n; ++i) off0[i + 1] = off0[i] + deg[i].load(std::memory_order_relaxed);
+  const int64_t m0 = off0[n];
+  int32_t* t0 = (int32_t*)malloc(sizeof(int32_t) * (m0 > 0 ? m0 : 1));
+  if (!t0) { delete[] deg; free(off0); return -2; }
+  // pass 2: scatter (deg reused as cursors)
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) deg[i].store(off0[i], std::memory_order_relaxed);
+#pragma omp parallel for schedule(static, 65536)
+  for (int64_t s = 0; s < S; ++s) {
+    int32_t u, v;
+    sample(s, &u, &v);
+    if (u == v) continue;
+    t0[deg[u].fetch_add(1, std::memory_order_relaxed)] = v;
+    t0[deg[v].fetch_add(1, std::memory_order_relaxed)] = u;
+  }
+  delete[] deg;
+  // pass 3: sort + unique per row
+  int64_t* nd = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  if (!nd) { free(off0); free(t0); return -2; }
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t* bb = t0 + off0[i];
+    int32_t* ee = t0 + off0[i + 1];
+    std::sort(bb, ee);
+    nd[i] = std::unique(bb, ee) - bb;
+  }
+  // pass 4: compact
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  if (!off) { free(off0); free(t0); free(nd); return -2; }
+  off[0] = 0;
+  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + nd[i];
+  free(nd);
+  const int64_t m = off[n];
+  int32_t* tgt = (int32_t*)malloc(sizeof(int32_t) * (m > 0 ? m : 1));
+  if (!tgt) { free(off0); free(t0); free(off); return -2; }
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n; ++i)
+    memcpy(tgt + off[i], t0 + off0[i], sizeof(int32_t) * (off[i + 1] - off[i]));
+  free(t0);
+  free(off0);
+  out->n = n; out->m = m; out->off = off; out->tgt = tgt;
+  return 0;
+}
+
+// Symmetric integer weights: w(u,v) = 1 + (h(min(u,v), max(u,v)) mod wmax)
+// where h is the first Philox word of counter (min, max) under the seed.
+void gg_pair_weights(int64_t n, const int64_t* off, const int32_t* tgt,
+                     uint64_t seed, int32_t wmax, float* w) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x57454947u;
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = off[i]; e < off[i + 1]; ++e) {
+      const uint32_t x = (uint32_t)std::min<int64_t>(i, tgt[e]);
+      const uint32_t y = (uint32_t)std::max<int64_t>(i, tgt[e]);
+      const P4 r = philox(x, y, 0u, 0x57u, k0, k1);
+      w[e] = (float)(1 + (int32_t)(r.v[0] % (uint32_t)wmax));
+    }
+  }
+}
+
+// Parallel fill of a float array (unit weights for large graphs).
+void gg_fill_f32(int64_t m, float value, float* w) {
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m; ++e) w[e] = value;
+}
+
+// Copy a generated CSR into caller buffers (offsets as int64 or int32).
+int gg_copy_out(const gg_graph* g, int64_t* off64, int32_t* off32,
+                int32_t* tgt) {
+  if (off64) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i <= g->n; ++i) off64[i] = g->off[i];
+  }
+  if (off32) {
+    if (g->m > INT32_MAX) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i <= g->n; ++i) off32[i] = (int32_t)g->off[i];
+  }
+  if (tgt) {
+    const int64_t chunk = 1 << 22;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < g->m; s += chunk) {
+      const int64_t len = std::min<int64_t>(chunk, g->m - s);
+      memcpy(tgt + s, g->tgt + s, sizeof(int32_t) * len);
+    }
+  }
+  return 0;
+}
+
+int gg_max_threads(void) { return omp_get_max_threads(); }
+
+}  // extern "C"
