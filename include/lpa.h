@@ -1,0 +1,217 @@
+/*
+ * lpa.h -- C ABI of the MI355X (gfx950) label-propagation library.
+ *
+ * The library runs the per-vertex label sweep of nu-LPA (S. Sahu, "nu-LPA:
+ * Fast GPU-based Label Propagation Algorithm (LPA) for Community
+ * Detection", arXiv 2411.11468) on one AMD Instinct GPU with hand-written HIP
+ * kernels.  The method:
+ *   - every vertex starts in its own community and unprocessed (Algorithm 1);
+ *   - in each iteration every unprocessed vertex is marked processed, sums the
+ *     weights of its neighbours per neighbour label in a per-vertex hashtable
+ *     with hybrid quadratic-double probing (Algorithm 2, Sec. 4.2), and takes
+ *     the label of largest sum (Eq. 3); ties go to the smallest label;
+ *   - Pick-Less (Sec. 4.1): in iterations l with l mod pl_period == 0 a vertex
+ *     may only move to a strictly smaller label;
+ *   - a vertex that changes label marks all its neighbours unprocessed
+ *     (vertex pruning, Sec. 4 item 4);
+ *   - the run stops after an iteration that is not Pick-Less and in which the
+ *     fraction of changed vertices is below the tolerance, or at the
+ *     iteration cap (Algorithm 1; defaults 0.05 and 20, Sec. 4).
+ *
+ * Conventions for every call:
+ *   - Return value is an lpa_status; LPA_OK (0) on success.  Nothing aborts
+ *     and no C++ exception crosses this boundary.  On error a description is
+ *     kept per thread and returned by lpa_last_error().
+ *   - Pointers named "device" must be HIP device (or managed) memory of the
+ *     current device; pointers named "host" ordinary host memory.  Where a
+ *     call accepts either, the kind is detected with hipPointerGetAttributes.
+ *   - One lpa_graph handle must not be used from two threads at once.
+ *   - All GPU work is enqueued on the stream given to lpa_create (NULL = the
+ *     null stream); every call returns after that work has completed.
+ */
+#ifndef LPA_H_
+#define LPA_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lpa_status {
+  LPA_OK = 0,
+  LPA_ERR_INVALID = 1,     /* bad argument or malformed graph */
+  LPA_ERR_OOM = 2,         /* device or host allocation failed */
+  LPA_ERR_HIP = 3,         /* a HIP runtime call failed */
+  LPA_ERR_STATE = 4,       /* call not valid for this handle */
+  LPA_ERR_UNSUPPORTED = 5  /* feature not available in this build */
+} lpa_status;
+
+typedef enum lpa_index_t { LPA_INDEX_I32 = 0, LPA_INDEX_I64 = 1 } lpa_index_t;
+
+typedef enum lpa_mode {
+  /* Synchronous (Jacobi) sweep: every vertex of an iteration reads the labels
+   * as they stood when the iteration began.  Deterministic; with integer
+   * weights and every weighted degree below 2^24 its labels and statistics
+   * equal the sequential reference exactly. */
+  LPA_MODE_DETERMINISTIC = 0,
+  /* Asynchronous sweep of the paper (Sec. 4 item 1): one label array updated
+   * in place while the sweep runs.  Results depend on scheduling. */
+  LPA_MODE_ASYNC = 1
+} lpa_mode;
+
+/*
+ * Symmetric CSR input (Sec. 3: undirected graph, w_ij = w_ji; every
+ * undirected edge is stored in both directions).
+ *   num_vertices  N, 0 <= N <= 2^31 - 1
+ *   num_edges     M = offsets[N] (directed CSR entries)
+ *   offset_type   LPA_INDEX_I32 (requires M <= 2^31 - 1) or LPA_INDEX_I64
+ *   offsets       N+1 entries, offsets[0] = 0, non-decreasing, offsets[N] = M
+ *   targets       M entries in [0, N); a target equal to its row is a
+ *                 self-loop, skipped by the label scan
+ *   weights       M finite fp32 values >= 0 (no -0.0), or NULL for all 1.0f
+ *   on_device     0: host arrays, copied into library-owned device memory;
+ *                 1: device arrays, borrowed: the caller keeps them alive and
+ *                 unchanged until lpa_destroy
+ *   validate      1: check the conditions above (on the GPU) and fail with
+ *                 LPA_ERR_INVALID; 0: trust the caller
+ */
+typedef struct lpa_csr {
+  int64_t num_vertices;
+  int64_t num_edges;
+  int32_t offset_type;
+  int32_t on_device;
+  const void* offsets;
+  const int32_t* targets;
+  const float* weights;
+  int32_t validate;
+  int32_t reserved;
+} lpa_csr;
+
+typedef struct lpa_graph_s* lpa_graph;
+
+/*
+ * Degree thresholds that split vertices into kernel classes (all inclusive
+ * upper bounds; a vertex of degree D goes to the first class whose bound is
+ * >= D; degree 0 is never processed):
+ *   small4   rows processed by 4-lane groups in registers     (default 4)
+ *   small16  rows processed by 16-lane groups in registers    (default 16)
+ *   wave     one wavefront per vertex, LDS hashtable          (default 1023)
+ *   block    one workgroup per vertex, LDS hashtable up to 16383 slots
+ *                                                             (default 16383)
+ *   larger degrees: several workgroups per vertex, each with an LDS table for
+ *   its slice of the row, merged in a global-memory hashtable.
+ * hub_chunk: edges per workgroup slice for the largest rows (default 8192).
+ * max_retries: hybrid probes before the linear continuation (default 32).
+ */
+typedef struct lpa_tuning {
+  int32_t small4;
+  int32_t small16;
+  int32_t wave;
+  int32_t block;
+  int32_t hub_chunk;
+  int32_t max_retries;
+  int32_t reserved[2];
+} lpa_tuning;
+
+/*
+ * Per-run options (Algorithm 1 and Sec. 4).
+ *   mode            lpa_mode
+ *   tolerance       stop when not Pick-Less and changed < tolerance * N,
+ *                   compared in double precision (default 0.05)
+ *   max_iterations  iteration cap (default 20)
+ *   pl_period       Pick-Less in iterations l with l % pl_period == 0,
+ *                   counting from 0; 0 disables Pick-Less (default 4)
+ *   prune           1: only flagged vertices are processed (default 1)
+ *   initial_labels  NULL: label = vertex id; else N labels in [0, N), host or
+ *                   device memory
+ */
+typedef struct lpa_options {
+  int32_t mode;
+  int32_t max_iterations;
+  double tolerance;
+  int32_t pl_period;
+  int32_t prune;
+  const int32_t* initial_labels;
+} lpa_options;
+
+/* Statistics of one iteration. */
+typedef struct lpa_iter_stats {
+  int32_t iteration;      /* 0-based */
+  int32_t pick_less;      /* 1 if Pick-Less applied */
+  int64_t changed;        /* vertices whose label changed */
+  int64_t processed;      /* vertices processed (flagged at the start) */
+  int64_t edges_scanned;  /* CSR entries read by the label scan */
+  float ms;               /* GPU time of the iteration */
+  int32_t reserved;
+} lpa_iter_stats;
+
+/* Fill *opt with the defaults above. */
+void lpa_options_default(lpa_options* opt);
+
+/* Fill *t with the default thresholds above. */
+void lpa_tuning_default(lpa_tuning* t);
+
+/*
+ * Upload (or borrow) a graph and build its degree classes on the GPU.
+ * stream: a hipStream_t or NULL.  tuning: NULL for the defaults.
+ * On success *out holds a new handle; on error *out is NULL.
+ * Errors: LPA_ERR_INVALID (bad sizes, malformed CSR when validate = 1),
+ * LPA_ERR_OOM, LPA_ERR_HIP.
+ */
+lpa_status lpa_create(const lpa_csr* g, void* stream, const lpa_tuning* tuning,
+                      lpa_graph* out);
+
+/*
+ * Run label propagation to termination.
+ *   labels      caller-owned output, N int32, host or device memory
+ *   stats       caller-owned host array of stats_cap records (may be NULL
+ *               when stats_cap = 0); record l describes iteration l
+ *   iters_done  host int32: number of iterations performed (may be NULL)
+ * Errors: LPA_ERR_INVALID (bad options, stats_cap < 0, bad initial labels),
+ * LPA_ERR_HIP.
+ */
+lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
+                   lpa_iter_stats* stats, int32_t stats_cap,
+                   int32_t* iters_done);
+
+/*
+ * Modularity of a labelling, Eq. 1, in fp64:
+ *   Q = sum_c [ sigma_c / 2m - (Sigma_c / 2m)^2 ]
+ * with 2m the total CSR weight, Sigma_c the summed weighted degree of the
+ * vertices of c and sigma_c the CSR weight between vertices of c.
+ *   labels  N int32 in [0, N), host or device memory
+ *   q       host double; 0 when the graph has no weight
+ * Errors: LPA_ERR_INVALID (label out of range), LPA_ERR_HIP.
+ */
+lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q);
+
+/*
+ * Number of vertices in each degree class, in the order: degree 0, small4,
+ * small16, wave, block (all LDS sizes), hub.  counts must hold 6 entries.
+ */
+lpa_status lpa_graph_classes(lpa_graph g, int64_t* counts);
+
+/*
+ * Copy the per-vertex flags left by the last lpa_run into flags (N bytes, host
+ * or device memory): 1 = the vertex was marked unprocessed by a neighbour's
+ * change and would be processed in a further iteration, 0 = not flagged.
+ * Used to check an asynchronous run: every vertex that is not flagged holds a
+ * label of maximum weight (Eq. 3), unless Pick-Less refused its move.
+ */
+lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags);
+
+/* Release the handle and all library-owned memory.  NULL is allowed. */
+void lpa_destroy(lpa_graph g);
+
+/* Static description of a status code. */
+const char* lpa_status_string(lpa_status s);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* lpa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPA_H_ */

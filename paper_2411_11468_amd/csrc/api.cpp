@@ -1,0 +1,490 @@
+// api.cpp -- host runtime of the label-propagation library and its C ABI
+// (declared in include/lpa.h).  Owns device memory, builds the degree classes
+// at create time and drives the iterations of Algorithm 1 (lpa): per
+// iteration it enqueues the hub plan, the frontier, the class sweeps and (in
+// deterministic mode) the label apply, reads back the iteration counters and
+// applies the stop rule.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lpa.h"
+#include "lpa_internal.h"
+
+using namespace lpa;
+
+namespace {
+
+thread_local std::string g_err;
+
+lpa_status fail(lpa_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define LPA_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(LPA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct lpa_graph_s {
+  hipStream_t stream = nullptr;
+  int64_t n = 0, m = 0;
+  bool off64 = false;
+  const void* off = nullptr;
+  const int32_t* tgt = nullptr;
+  const float* w = nullptr;
+  lpa_tuning tun{};
+  uint8_t* cls = nullptr;
+  int32_t* C = nullptr;
+  uint8_t* F = nullptr;
+  int32_t* lists[kNumClasses] = {};
+  int64_t cls_count[kNumClasses] = {};
+  int grid[kNumClasses] = {};
+  int frontier_grid = 1, apply_grid = 1, hub_acc_grid = 1, hub_fin_grid = 1;
+  int32_t* pend_v = nullptr;
+  int32_t* pend_c = nullptr;
+  DevStats* st = nullptr;
+  DevStats* st_host = nullptr;
+  int32_t H = 0;
+  int32_t* hub_vid = nullptr;
+  int64_t* hub_tab = nullptr;
+  unsigned long long* hub_best = nullptr;
+  int32_t* hub_old = nullptr;
+  uint32_t* gkeys = nullptr;
+  float* gvals = nullptr;
+  uint32_t* items = nullptr;
+  int32_t* rec = nullptr;
+  int32_t* nrec = nullptr;
+  int64_t max_items = 0;
+  double* mod_sig = nullptr;
+  double* mod_acc = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<void*> dev_allocs;
+
+  template <typename T>
+  lpa_status dalloc(T** p, int64_t count) {
+    void* q = nullptr;
+    const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(LPA_ERR_OOM, "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " +
+                                   hipGetErrorString(e));
+    }
+    dev_allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return LPA_OK;
+  }
+
+  HubArgs hub_args(int pl, int async_mode) const {
+    HubArgs a;
+    a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F;
+    a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
+    a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
+    a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.rec = rec; a.nrec = nrec;
+    a.H = H; a.chunk = tun.hub_chunk; a.pl = pl; a.async_mode = async_mode;
+    a.max_retries = tun.max_retries;
+    return a;
+  }
+
+  ~lpa_graph_s() {
+    for (void* p : dev_allocs) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+extern "C" {
+
+void lpa_options_default(lpa_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->mode = LPA_MODE_ASYNC;
+  opt->max_iterations = 20;
+  opt->tolerance = 0.05;
+  opt->pl_period = 4;
+  opt->prune = 1;
+  opt->initial_labels = nullptr;
+}
+
+void lpa_tuning_default(lpa_tuning* t) {
+  if (!t) return;
+  std::memset(t, 0, sizeof(*t));
+  t->small4 = 4;
+  t->small16 = 16;
+  t->wave = 1023;
+  t->block = 16383;
+  t->hub_chunk = 8192;
+  t->max_retries = 32;
+}
+
+const char* lpa_status_string(lpa_status s) {
+  switch (s) {
+    case LPA_OK: return "ok";
+    case LPA_ERR_INVALID: return "invalid argument";
+    case LPA_ERR_OOM: return "out of memory";
+    case LPA_ERR_HIP: return "HIP runtime error";
+    case LPA_ERR_STATE: return "invalid state";
+    case LPA_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* lpa_last_error(void) { return g_err.c_str(); }
+
+static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* tuning,
+                              lpa_graph_s* G) {
+  G->stream = (hipStream_t)stream;
+  G->n = g->num_vertices;
+  G->m = g->num_edges;
+  G->off64 = g->offset_type == LPA_INDEX_I64;
+  if (tuning) G->tun = *tuning; else lpa_tuning_default(&G->tun);
+  const lpa_tuning& t = G->tun;
+  if (!(0 <= t.small4 && t.small4 <= 4 && t.small4 <= t.small16 && t.small16 <= 16 &&
+        t.small16 <= t.wave && t.wave <= 1023 && t.wave <= t.block && t.block <= 16383 &&
+        t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0))
+    return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
+  hipStream_t s = G->stream;
+  const int64_t n = G->n, m = G->m;
+
+  // graph arrays: borrow device pointers or copy host arrays in
+  const size_t osz = G->off64 ? sizeof(int64_t) : sizeof(int32_t);
+  if (g->on_device) {
+    if ((n >= 0 && !is_device_ptr(g->offsets)) || (m > 0 && !is_device_ptr(g->targets)) ||
+        (g->weights && !is_device_ptr(g->weights)))
+      return fail(LPA_ERR_INVALID, "on_device = 1 but an array is not device memory");
+    G->off = g->offsets;
+    G->tgt = g->targets;
+    G->w = g->weights;
+  } else {
+    void* doff = nullptr;
+    int32_t* dtgt = nullptr;
+    float* dw = nullptr;
+    if (G->off64) {
+      int64_t* p; if (lpa_status e = G->dalloc(&p, n + 1)) return e; doff = p;
+    } else {
+      int32_t* p; if (lpa_status e = G->dalloc(&p, n + 1)) return e; doff = p;
+    }
+    if (lpa_status e = G->dalloc(&dtgt, m)) return e;
+    LPA_HIP(hipMemcpyAsync(doff, g->offsets, osz * (size_t)(n + 1), hipMemcpyHostToDevice, s));
+    if (m > 0)
+      LPA_HIP(hipMemcpyAsync(dtgt, g->targets, sizeof(int32_t) * (size_t)m,
+                             hipMemcpyHostToDevice, s));
+    if (g->weights) {
+      if (lpa_status e = G->dalloc(&dw, m)) return e;
+      if (m > 0)
+        LPA_HIP(hipMemcpyAsync(dw, g->weights, sizeof(float) * (size_t)m,
+                               hipMemcpyHostToDevice, s));
+    }
+    G->off = doff;
+    G->tgt = dtgt;
+    G->w = dw;
+  }
+
+  // counters
+  if (lpa_status e = G->dalloc(&G->st, 1)) return e;
+  {
+    void* h = nullptr;
+    LPA_HIP(hipHostMalloc(&h, sizeof(DevStats), hipHostMallocDefault));
+    G->st_host = static_cast<DevStats*>(h);
+  }
+  LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(G->st), 0u,
+                          sizeof(DevStats) / sizeof(uint32_t), s));
+  if (g->validate) {
+    LPA_HIP(launch_validate(G->off64, G->off, G->tgt, G->w, n, m, G->st, s));
+    LPA_HIP(hipMemcpyAsync(G->st_host, G->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    LPA_HIP(hipStreamSynchronize(s));
+    const unsigned err = G->st_host->error;
+    if (err) {
+      std::string why;
+      if (err & 1u) why += " offsets are not 0..M non-decreasing;";
+      if (err & 2u) why += " a target is outside [0, N);";
+      if (err & 8u) why += " a weight is negative, -0, infinite or NaN;";
+      return fail(LPA_ERR_INVALID, "malformed CSR:" + why);
+    }
+  }
+
+  // labels, flags, deterministic-mode queue
+  if (lpa_status e = G->dalloc(&G->C, n)) return e;
+  if (lpa_status e = G->dalloc(&G->F, n)) return e;
+  if (lpa_status e = G->dalloc(&G->pend_v, n)) return e;
+  if (lpa_status e = G->dalloc(&G->pend_c, n)) return e;
+  if (lpa_status e = G->dalloc(&G->cls, n)) return e;
+
+  // degree classes
+  int32_t bounds[kNumClasses] = {0};
+  bounds[1] = t.small4;
+  bounds[2] = t.small16;
+  bounds[3] = std::min(127, t.wave);
+  bounds[4] = t.wave;
+  bounds[5] = std::min(2047, t.block);
+  bounds[6] = std::min(4095, t.block);
+  bounds[7] = std::min(8191, t.block);
+  bounds[8] = t.block;
+  bounds[9] = INT32_MAX;
+  unsigned long long* counts = nullptr;
+  unsigned int* hub_count = nullptr;
+  int32_t* hub_tmp = nullptr;
+  const int64_t hub_cap = m / ((int64_t)t.block + 1) + 1;
+  if (lpa_status e = G->dalloc(&counts, kNumClasses + 2)) return e;
+  hub_count = reinterpret_cast<unsigned int*>(counts + kNumClasses);
+  if (lpa_status e = G->dalloc(&hub_tmp, hub_cap)) return e;
+  LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(counts), 0u, 2 * (kNumClasses + 2), s));
+  if (n > 0)
+    LPA_HIP(launch_classify(G->off64, G->off, n, bounds, G->cls, counts, hub_tmp, hub_count, s));
+  unsigned long long hcounts[kNumClasses + 2];
+  LPA_HIP(hipMemcpyAsync(hcounts, counts, sizeof(hcounts), hipMemcpyDeviceToHost, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < kNumClasses; ++c) G->cls_count[c] = (int64_t)hcounts[c];
+  G->H = (int32_t)(uint32_t)hcounts[kNumClasses];
+  for (int c = 1; c < kNumClasses; ++c) {
+    if (c == kClassHub) continue;
+    if (lpa_status e = G->dalloc(&G->lists[c], G->cls_count[c])) return e;
+    const int64_t per = sweep_items_per_block(c);
+    const int64_t need = (G->cls_count[c] + per - 1) / per;
+    G->grid[c] = (int)std::max<int64_t>(1, std::min<int64_t>(need, sweep_max_resident(c)));
+  }
+  G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 256 * 8));
+  G->apply_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256 * 8));
+
+  // hubs: sorted ids, global table offsets (p1 = nextPow2(D) - 1 slots each),
+  // slice scratch
+  if (G->H > 0) {
+    std::vector<int32_t> hv(G->H);
+    std::vector<int64_t> hd(G->H);
+    LPA_HIP(hipMemcpyAsync(hv.data(), hub_tmp, sizeof(int32_t) * G->H, hipMemcpyDeviceToHost, s));
+    LPA_HIP(hipStreamSynchronize(s));
+    std::sort(hv.begin(), hv.end());
+    if (lpa_status e = G->dalloc(&G->hub_vid, G->H)) return e;
+    LPA_HIP(hipMemcpyAsync(G->hub_vid, hv.data(), sizeof(int32_t) * G->H, hipMemcpyHostToDevice, s));
+    int64_t* ddeg = nullptr;
+    if (lpa_status e = G->dalloc(&ddeg, G->H)) return e;
+    LPA_HIP(launch_gather_degrees(G->off64, G->off, G->hub_vid, G->H, ddeg, s));
+    LPA_HIP(hipMemcpyAsync(hd.data(), ddeg, sizeof(int64_t) * G->H, hipMemcpyDeviceToHost, s));
+    LPA_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> tab(G->H);
+    int64_t slots = 0, items = 0;
+    for (int32_t h = 0; h < G->H; ++h) {
+      if (hd[h] > (int64_t)INT32_MAX / 2)
+        return fail(LPA_ERR_INVALID, "a vertex degree exceeds 2^30");
+      int64_t p = 1;
+      while (p <= hd[h]) p <<= 1;
+      tab[h] = slots;
+      slots += p - 1;
+      items += (hd[h] + t.hub_chunk - 1) / t.hub_chunk;
+    }
+    G->max_items = items;
+    if (lpa_status e = G->dalloc(&G->hub_tab, G->H)) return e;
+    LPA_HIP(hipMemcpyAsync(G->hub_tab, tab.data(), sizeof(int64_t) * G->H, hipMemcpyHostToDevice, s));
+    if (lpa_status e = G->dalloc(&G->hub_best, G->H)) return e;
+    if (lpa_status e = G->dalloc(&G->hub_old, G->H)) return e;
+    if (lpa_status e = G->dalloc(&G->gkeys, slots)) return e;
+    if (lpa_status e = G->dalloc(&G->gvals, slots)) return e;
+    LPA_HIP(launch_fill_u32(G->gkeys, kEmpty, slots, s));
+    LPA_HIP(launch_fill_f32(G->gvals, 0.0f, slots, s));
+    if (lpa_status e = G->dalloc(&G->items, 2 * items)) return e;
+    if (lpa_status e = G->dalloc(&G->rec, items * (int64_t)t.hub_chunk)) return e;
+    if (lpa_status e = G->dalloc(&G->nrec, items)) return e;
+    G->hub_acc_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, hub_max_resident()));
+    G->hub_fin_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, 256 * 8));
+    LPA_HIP(hipStreamSynchronize(s));
+  }
+  LPA_HIP(hipEventCreate(&G->ev0));
+  LPA_HIP(hipEventCreate(&G->ev1));
+  LPA_HIP(hipStreamSynchronize(s));
+  return LPA_OK;
+}
+
+lpa_status lpa_create(const lpa_csr* g, void* stream, const lpa_tuning* tuning,
+                      lpa_graph* out) {
+  if (!out) return fail(LPA_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
+  if (g->num_vertices < 0 || g->num_vertices > (int64_t)INT32_MAX)
+    return fail(LPA_ERR_INVALID, "num_vertices must lie in [0, 2^31 - 1]");
+  if (g->num_edges < 0) return fail(LPA_ERR_INVALID, "num_edges < 0");
+  if (g->offset_type != LPA_INDEX_I32 && g->offset_type != LPA_INDEX_I64)
+    return fail(LPA_ERR_INVALID, "offset_type must be LPA_INDEX_I32 or LPA_INDEX_I64");
+  if (g->offset_type == LPA_INDEX_I32 && g->num_edges > (int64_t)INT32_MAX)
+    return fail(LPA_ERR_INVALID, "int32 offsets cannot address more than 2^31 - 1 edges");
+  if (!g->offsets || (g->num_edges > 0 && !g->targets))
+    return fail(LPA_ERR_INVALID, "offsets or targets is NULL");
+  lpa_graph_s* G = new (std::nothrow) lpa_graph_s();
+  if (!G) return fail(LPA_ERR_OOM, "host allocation failed");
+  const lpa_status st = create_impl(g, stream, tuning, G);
+  if (st != LPA_OK) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    delete G;
+    return st;
+  }
+  *out = G;
+  g_err.clear();
+  return LPA_OK;
+}
+
+void lpa_destroy(lpa_graph g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  delete g;
+}
+
+lpa_status lpa_graph_classes(lpa_graph g, int64_t* counts) {
+  if (!g || !counts) return fail(LPA_ERR_INVALID, "NULL argument");
+  counts[0] = g->cls_count[0];
+  counts[1] = g->cls_count[1];
+  counts[2] = g->cls_count[2];
+  counts[3] = g->cls_count[3] + g->cls_count[4];
+  counts[4] = g->cls_count[5] + g->cls_count[6] + g->cls_count[7] + g->cls_count[8];
+  counts[5] = g->cls_count[kClassHub];
+  return LPA_OK;
+}
+
+// Copy n int32 labels from host or device memory into dst (device).
+static lpa_status stage_labels(lpa_graph g, const int32_t* src, int32_t* dst) {
+  const hipMemcpyKind kind = is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  LPA_HIP(hipMemcpyAsync(dst, src, sizeof(int32_t) * (size_t)g->n, kind, g->stream));
+  return LPA_OK;
+}
+
+lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
+                   lpa_iter_stats* stats, int32_t stats_cap, int32_t* iters_done) {
+  if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
+  lpa_options o;
+  if (opt) o = *opt; else lpa_options_default(&o);
+  if (o.mode != LPA_MODE_DETERMINISTIC && o.mode != LPA_MODE_ASYNC)
+    return fail(LPA_ERR_INVALID, "mode must be LPA_MODE_DETERMINISTIC or LPA_MODE_ASYNC");
+  if (o.max_iterations < 0) return fail(LPA_ERR_INVALID, "max_iterations < 0");
+  if (o.pl_period < 0) return fail(LPA_ERR_INVALID, "pl_period < 0");
+  if (stats_cap < 0 || (stats_cap > 0 && !stats))
+    return fail(LPA_ERR_INVALID, "stats_cap < 0 or stats is NULL");
+  if (g->n > 0 && !labels) return fail(LPA_ERR_INVALID, "labels is NULL");
+  if (iters_done) *iters_done = 0;
+  const int64_t n = g->n;
+  if (n == 0) return LPA_OK;
+  hipStream_t s = g->stream;
+  const int async_mode = o.mode == LPA_MODE_ASYNC;
+
+  LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(g->st), 0u,
+                          sizeof(DevStats) / sizeof(uint32_t), s));
+  const int32_t* init = nullptr;
+  if (o.initial_labels) {
+    if (lpa_status e = stage_labels(g, o.initial_labels, g->pend_v)) return e;
+    init = g->pend_v;
+  }
+  LPA_HIP(launch_init(n, init, g->C, g->F, g->st, s));
+  if (init) {
+    LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    LPA_HIP(hipStreamSynchronize(s));
+    if (g->st_host->error & 4u)
+      return fail(LPA_ERR_INVALID, "initial_labels must lie in [0, N)");
+  }
+  int32_t done = 0;
+  for (int32_t l = 0; l < o.max_iterations; ++l) {
+    const int pl = (o.pl_period > 0) && (l % o.pl_period == 0);
+    LPA_HIP(hipEventRecord(g->ev0, s));
+    // without pruning every vertex is processed in every iteration
+    if (!o.prune && l > 0) LPA_HIP(launch_fill_u8(g->F, 1, n, s));
+    const HubArgs ha = g->hub_args(pl, async_mode);
+    LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
+    LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->st, g->frontier_grid, s));
+    if (g->H > 0) LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
+    SweepArgs a;
+    a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.F = g->F;
+    a.pend_v = g->pend_v; a.pend_c = g->pend_c; a.st = g->st;
+    a.pl = pl; a.async_mode = async_mode; a.max_retries = g->tun.max_retries;
+    for (int c = kClassHub - 1; c >= 1; --c) {
+      if (g->cls_count[c] == 0) continue;
+      a.cls = c;
+      a.active = g->lists[c];
+      LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], s));
+    }
+    if (g->H > 0) LPA_HIP(launch_hub_fin(g->off64, ha, g->hub_fin_grid, s));
+    if (!async_mode) LPA_HIP(launch_apply(g->st, g->pend_v, g->pend_c, g->C, g->apply_grid, s));
+    LPA_HIP(hipEventRecord(g->ev1, s));
+    LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+    LPA_HIP(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    LPA_HIP(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+    const DevStats& h = *g->st_host;
+    if (l < stats_cap) {
+      lpa_iter_stats& r = stats[l];
+      std::memset(&r, 0, sizeof(r));
+      r.iteration = l;
+      r.pick_less = pl;
+      r.changed = (int64_t)h.changed;
+      r.processed = (int64_t)h.processed;
+      r.edges_scanned = (int64_t)h.edges;
+      r.ms = ms;
+    }
+    done = l + 1;
+    if (!pl && (double)h.changed < o.tolerance * (double)n) break;
+  }
+  if (iters_done) *iters_done = done;
+  const hipMemcpyKind kind = is_device_ptr(labels) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  LPA_HIP(hipMemcpyAsync(labels, g->C, sizeof(int32_t) * (size_t)n, kind, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  return LPA_OK;
+}
+
+lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags) {
+  if (!g || (g->n > 0 && !flags)) return fail(LPA_ERR_INVALID, "NULL argument");
+  if (g->n == 0) return LPA_OK;
+  const hipMemcpyKind kind = is_device_ptr(flags) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  LPA_HIP(hipMemcpyAsync(flags, g->F, (size_t)g->n, kind, g->stream));
+  LPA_HIP(hipStreamSynchronize(g->stream));
+  return LPA_OK;
+}
+
+lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q) {
+  if (!g || !q) return fail(LPA_ERR_INVALID, "NULL argument");
+  *q = 0.0;
+  if (g->n == 0) return LPA_OK;
+  if (!labels) return fail(LPA_ERR_INVALID, "labels is NULL");
+  hipStream_t s = g->stream;
+  if (!g->mod_sig) {
+    if (lpa_status e = g->dalloc(&g->mod_sig, g->n)) return e;
+    if (lpa_status e = g->dalloc(&g->mod_acc, 4)) return e;
+  }
+  const int32_t* lab = labels;
+  if (!is_device_ptr(labels)) {
+    if (lpa_status e = stage_labels(g, labels, g->pend_v)) return e;
+    lab = g->pend_v;
+  }
+  LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(g->st), 0u,
+                          sizeof(DevStats) / sizeof(uint32_t), s));
+  LPA_HIP(launch_check_labels(g->n, lab, g->st, s));
+  LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  if (g->st_host->error & 4u) return fail(LPA_ERR_INVALID, "labels must lie in [0, N)");
+  LPA_HIP(launch_modularity(g->off64, g->off, g->tgt, g->w, g->n, g->m, lab, g->mod_sig,
+                            g->mod_acc, s));
+  double acc[4];
+  LPA_HIP(hipMemcpyAsync(acc, g->mod_acc, sizeof(acc), hipMemcpyDeviceToHost, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  const double two_m = acc[1];
+  *q = two_m > 0.0 ? acc[0] / two_m - acc[2] / (two_m * two_m) : 0.0;
+  return LPA_OK;
+}
+
+}  // extern "C"

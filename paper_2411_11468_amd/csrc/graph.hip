@@ -1,0 +1,398 @@
+// graph.hip -- set-up and per-iteration bookkeeping kernels around the sweep:
+// validation, degree classes, initial labels and flags (Algorithm 1: every
+// vertex in its own community and unprocessed), the frontier of flagged
+// vertices ("for all unprocessed i ... mark i processed"), the hub slice plan,
+// the deterministic-mode label apply, and fp64 modularity (Eq. 1).
+#include "lpa_device.h"
+
+namespace lpa {
+
+namespace {
+
+constexpr int kBT = 256;
+
+__device__ __forceinline__ void set_error(DevStats* st, unsigned int bit) {
+  atomicOr(&st->error, bit);
+}
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int grid_for(int64_t n, int per_block, int cap) {
+  const int64_t g = (n + per_block - 1) / per_block;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+// ---- init ---------------------------------------------------------------------
+__global__ void k_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
+                       DevStats* st) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = init ? init[i] : (int32_t)i;
+    if (c < 0 || (int64_t)c >= n) set_error(st, 4u);
+    C[i] = c;
+    F[i] = 1;
+  }
+}
+
+hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
+                       DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, n, init, C, F, st);
+  return hipGetLastError();
+}
+
+// ---- validation (error bits: 1 offsets, 2 targets, 8 weights) ----------------
+template <typename OffT>
+__global__ void k_validate(const OffT* off, const int32_t* tgt, const float* w,
+                           int64_t n, int64_t m, DevStats* st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t0 == 0 && ((int64_t)off[0] != 0 || (int64_t)off[n] != m)) set_error(st, 1u);
+  for (int64_t i = t0; i < n; i += stride)
+    if (off[i] > off[i + 1]) set_error(st, 1u);
+  for (int64_t e = t0; e < m; e += stride) {
+    const int32_t j = tgt[e];
+    if (j < 0 || (int64_t)j >= n) set_error(st, 2u);
+    if (w) {
+      const uint32_t b = __float_as_uint(w[e]);
+      // reject negative (sign bit set, including -0.0), infinities and NaN
+      if ((b >> 31) || ((b >> 23) & 0xFFu) == 0xFFu) set_error(st, 8u);
+    }
+  }
+}
+
+hipError_t launch_validate(bool off64, const void* off, const int32_t* tgt,
+                           const float* w, int64_t n, int64_t m, DevStats* st,
+                           hipStream_t s) {
+  const int g = grid_for(m > n ? m : n, kBT, 8192);
+  if (off64)
+    hipLaunchKernelGGL(k_validate<int64_t>, dim3(g), dim3(kBT), 0, s,
+                       (const int64_t*)off, tgt, w, n, m, st);
+  else
+    hipLaunchKernelGGL(k_validate<int32_t>, dim3(g), dim3(kBT), 0, s,
+                       (const int32_t*)off, tgt, w, n, m, st);
+  return hipGetLastError();
+}
+
+__global__ void k_check_labels(int64_t n, const int32_t* lab, DevStats* st) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (lab[i] < 0 || (int64_t)lab[i] >= n) set_error(st, 4u);
+}
+
+hipError_t launch_check_labels(int64_t n, const int32_t* lab, DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_labels, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, n, lab, st);
+  return hipGetLastError();
+}
+
+// ---- degree classes -------------------------------------------------------------
+struct Bounds { int32_t hi[kNumClasses]; };
+
+template <typename OffT>
+__global__ void k_classify(const OffT* off, int64_t n, Bounds b, uint8_t* cls,
+                           unsigned long long* counts, int32_t* hub_out,
+                           unsigned int* hub_count) {
+  __shared__ unsigned int cnt[kNumClasses];
+  if (threadIdx.x < kNumClasses) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+    int c = kClassHub;
+    if (d == 0) {
+      c = 0;
+    } else {
+      for (int q = 1; q < kClassHub; ++q)
+        if (d <= b.hi[q]) { c = q; break; }
+    }
+    cls[v] = (uint8_t)c;
+    atomicAdd(&cnt[c], 1u);
+    if (c == kClassHub) hub_out[atomicAdd(hub_count, 1u)] = (int32_t)v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumClasses && cnt[threadIdx.x])
+    atomicAdd(&counts[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+}
+
+hipError_t launch_classify(bool off64, const void* off, int64_t n, const int32_t* bounds,
+                           uint8_t* cls, unsigned long long* counts, int32_t* hub_out,
+                           unsigned int* hub_count, hipStream_t s) {
+  Bounds b;
+  for (int q = 0; q < kNumClasses; ++q) b.hi[q] = bounds[q];
+  const int g = grid_for(n, kBT, 8192);
+  if (off64)
+    hipLaunchKernelGGL(k_classify<int64_t>, dim3(g), dim3(kBT), 0, s, (const int64_t*)off,
+                       n, b, cls, counts, hub_out, hub_count);
+  else
+    hipLaunchKernelGGL(k_classify<int32_t>, dim3(g), dim3(kBT), 0, s, (const int32_t*)off,
+                       n, b, cls, counts, hub_out, hub_count);
+  return hipGetLastError();
+}
+
+template <typename OffT>
+__global__ void k_gather_degrees(const OffT* off, const int32_t* vids, int32_t h, int64_t* deg) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < h; i += gridDim.x * blockDim.x)
+    deg[i] = (int64_t)off[vids[i] + 1] - (int64_t)off[vids[i]];
+}
+
+hipError_t launch_gather_degrees(bool off64, const void* off, const int32_t* vids, int32_t h,
+                                 int64_t* deg, hipStream_t s) {
+  const int g = grid_for(h, kBT, 4096);
+  if (off64)
+    hipLaunchKernelGGL(k_gather_degrees<int64_t>, dim3(g), dim3(kBT), 0, s, (const int64_t*)off, vids, h, deg);
+  else
+    hipLaunchKernelGGL(k_gather_degrees<int32_t>, dim3(g), dim3(kBT), 0, s, (const int32_t*)off, vids, h, deg);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0, s, p, v, count);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0, s, p, v, count);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0, s, p, v, count);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+// ---- hub plan: reset the iteration counters, take the flagged hubs, queue
+// their slices.  One workgroup of 1024 threads. ----------------------------------
+template <typename OffT>
+__global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_t* F) {
+  __shared__ uint32_t scan[1024];
+  __shared__ uint32_t running;
+  __shared__ uint32_t nproc;
+  const int tid = threadIdx.x;
+  DevStats* st = a.st;
+  if (tid == 0) {
+    st->processed = 0; st->changed = 0; st->edges = 0; st->pending = 0;
+    running = 0; nproc = 0;
+  }
+  if (tid < kNumClasses) st->active[tid] = 0;
+  __syncthreads();
+  const OffT* off = reinterpret_cast<const OffT*>(a.off);
+  for (int32_t tile = 0; tile < a.H; tile += 1024) {
+    const int32_t h = tile + tid;
+    uint32_t nch = 0;
+    if (h < a.H) {
+      const int32_t v = a.hub_vid[h];
+      a.hub_best[h] = 0ull;
+      if (F[v]) {
+        F[v] = 0;
+        a.hub_old[h] = C[v];
+        const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+        nch = (uint32_t)((d + a.chunk - 1) / a.chunk);
+        atomicAdd(&nproc, 1u);
+      }
+    }
+    // inclusive Hillis-Steele scan of nch over the workgroup
+    scan[tid] = nch;
+    __syncthreads();
+    for (int ofs = 1; ofs < 1024; ofs <<= 1) {
+      const uint32_t add = tid >= ofs ? scan[tid - ofs] : 0u;
+      __syncthreads();
+      scan[tid] += add;
+      __syncthreads();
+    }
+    const uint32_t first = running + scan[tid] - nch;
+    for (uint32_t c = 0; c < nch; ++c) {
+      a.items[2 * (uint64_t)(first + c)] = (uint32_t)h;
+      a.items[2 * (uint64_t)(first + c) + 1] = c;
+    }
+    __syncthreads();
+    if (tid == 0) running += scan[1023];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    st->hub_items = running;
+    st->processed = nproc;
+  }
+}
+
+hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
+                           hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL(k_hub_plan<int64_t>, dim3(1), dim3(1024), 0, s, a, C, F);
+  else
+    hipLaunchKernelGGL(k_hub_plan<int32_t>, dim3(1), dim3(1024), 0, s, a, C, F);
+  return hipGetLastError();
+}
+
+// ---- frontier: append flagged vertices to their class list, clear flags ------
+struct ListPtrs { int32_t* p[kNumClasses]; };
+
+__global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
+                                                  ListPtrs lists, DevStats* st) {
+  __shared__ uint32_t cnt[kNumClasses];
+  __shared__ uint32_t base[kNumClasses];
+  const int tid = threadIdx.x;
+  uint32_t proc = 0;
+  for (int64_t chunk = (int64_t)blockIdx.x * kBT * 4; chunk < n;
+       chunk += (int64_t)gridDim.x * kBT * 4) {
+    if (tid < kNumClasses) cnt[tid] = 0;
+    __syncthreads();
+    int32_t cq[4];
+    uint32_t pos[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t v = chunk + (int64_t)tid * 4 + q;
+      cq[q] = -1;
+      if (v < n && F[v]) {
+        F[v] = 0;
+        ++proc;
+        const int c = cls[v];
+        if (c != 0 && c != kClassHub) {
+          cq[q] = c;
+          pos[q] = atomicAdd(&cnt[c], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < kNumClasses) base[tid] = cnt[tid] ? atomicAdd(&st->active[tid], cnt[tid]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (cq[q] >= 0) lists.p[cq[q]][base[cq[q]] + pos[q]] = (int32_t)(chunk + (int64_t)tid * 4 + q);
+    __syncthreads();
+  }
+  // one atomic per wave for the processed count
+  uint32_t x = proc;
+  for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
+  if ((tid & 63) == 0 && x) atomicAdd(&st->processed, (unsigned long long)x);
+}
+
+hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
+                           int32_t* const* lists, DevStats* st, int grid, hipStream_t s) {
+  ListPtrs lp;
+  for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
+  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kBT), 0, s, n, F, cls, lp, st);
+  return hipGetLastError();
+}
+
+// ---- deterministic mode: apply the queued label writes ------------------------
+__global__ void k_apply(const DevStats* st, const int32_t* pv, const int32_t* pc,
+                        int32_t* C) {
+  const unsigned long long cnt = st->pending;
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+       i < cnt; i += (unsigned long long)gridDim.x * blockDim.x)
+    C[pv[i]] = pc[i];
+}
+
+hipError_t launch_apply(const DevStats* st, const int32_t* pv, const int32_t* pc,
+                        int32_t* C, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply, dim3(grid), dim3(kBT), 0, s, st, pv, pc, C);
+  return hipGetLastError();
+}
+
+// ---- modularity, Eq. 1 ------------------------------------------------------
+// Each thread owns a contiguous run of CSR entries, finds the row of its first
+// entry by binary search, and walks rows: K_i is added into Sigma[C_i] when the
+// row ends, entries with C_i = C_j add to sigma.
+namespace {
+constexpr int kModEpt = 16;
+
+__device__ __forceinline__ double block_sum_f64(double x, double* sh) {
+  for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = x;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+  __syncthreads();
+  return t;
+}
+}  // namespace
+
+template <typename OffT>
+__global__ __launch_bounds__(kBT) void k_mod_edges(const OffT* off, const int32_t* tgt,
+                                                   const float* w, int64_t n, int64_t m,
+                                                   const int32_t* C, double* sig,
+                                                   double* acc) {
+  __shared__ double sh[kBT / 64];
+  double sigma = 0.0, two_m = 0.0;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kModEpt < m;
+       t += nthreads) {
+    const int64_t e0 = t * kModEpt;
+    const int64_t e1 = (e0 + kModEpt < m) ? e0 + kModEpt : m;
+    // row containing e0: largest i with off[i] <= e0 and off[i+1] > e0
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)off[mid] <= e0) lo = mid; else hi = mid - 1;
+    }
+    int64_t i = lo;
+    while ((int64_t)off[i + 1] <= e0) ++i;  // skip empty rows sharing the offset
+    int64_t row_end = (int64_t)off[i + 1];
+    int32_t ci = C[i];
+    double ki = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+      while (e >= row_end) {
+        if (ki != 0.0) atomicAdd(&sig[ci], ki);
+        ki = 0.0;
+        ++i;
+        row_end = (int64_t)off[i + 1];
+        ci = C[i];
+      }
+      const double we = w ? (double)w[e] : 1.0;
+      ki += we;
+      two_m += we;
+      if (C[tgt[e]] == ci) sigma += we;
+    }
+    if (ki != 0.0) atomicAdd(&sig[ci], ki);
+  }
+  const double s1 = block_sum_f64(sigma, sh);
+  const double s2 = block_sum_f64(two_m, sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(&acc[0], s1);
+    atomicAdd(&acc[1], s2);
+  }
+}
+
+__global__ __launch_bounds__(kBT) void k_mod_sq(const double* sig, int64_t n, double* acc) {
+  __shared__ double sh[kBT / 64];
+  double s = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    s += sig[c] * sig[c];
+  const double t = block_sum_f64(s, sh);
+  if (threadIdx.x == 0) atomicAdd(&acc[2], t);
+}
+
+hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt, const float* w,
+                             int64_t n, int64_t m, const int32_t* C, double* sig,
+                             double* acc, hipStream_t s) {
+  hipError_t e = launch_fill_f64(sig, 0.0, n, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_f64(acc, 0.0, 4, s);
+  if (e != hipSuccess) return e;
+  if (m > 0) {
+    const int g = grid_for((m + kModEpt - 1) / kModEpt, kBT, 16384);
+    if (off64)
+      hipLaunchKernelGGL(k_mod_edges<int64_t>, dim3(g), dim3(kBT), 0, s, (const int64_t*)off,
+                         tgt, w, n, m, C, sig, acc);
+    else
+      hipLaunchKernelGGL(k_mod_edges<int32_t>, dim3(g), dim3(kBT), 0, s, (const int32_t*)off,
+                         tgt, w, n, m, C, sig, acc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, sig, n, acc);
+  return hipGetLastError();
+}
+
+}  // namespace lpa

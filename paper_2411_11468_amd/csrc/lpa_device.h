@@ -1,0 +1,181 @@
+// lpa_device.h -- device helpers for the label sweep on gfx950 (wave64).
+//
+//  * packed arg-max keys: (fp32 weight bits << 32) | ~label.  Weights are
+//    >= 0, so their bit patterns order like the values; the complemented
+//    label makes the smaller label win a tie (the reading of the "strict"
+//    rule of Sec. 4 item 5 used throughout).  An empty key packs to 0, below
+//    every real entry.
+//  * DPP cross-lane reductions and rotations (no LDS traffic).
+//  * the per-vertex hashtable of Sec. 4.2 / Algorithm 2: capacity
+//    p1 = nextPow2(D) - 1 where nextPow2 is the smallest power of two strictly
+//    above D (so D <= p1), secondary modulus p2 = 2 p1 + 1 (co-prime with p1),
+//    first slot k mod p1, probe step starting at 1 and updated as
+//    step <- 2 step + (k mod p2) (hybrid quadratic-double probing).  After
+//    max_retries probes the walk continues linearly, which visits every slot,
+//    so an insert always lands and no weight is ever dropped.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lpa_internal.h"
+
+namespace lpa {
+
+__device__ __forceinline__ unsigned long long pack_key(float w, uint32_t label) {
+  return ((unsigned long long)__float_as_uint(w) << 32) | (unsigned long long)(~label);
+}
+__device__ __forceinline__ uint32_t unpack_label(unsigned long long k) {
+  return ~(uint32_t)k;
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a,
+                                                     unsigned long long b) {
+  return a > b ? a : b;
+}
+
+// Table capacity for a row of d entries: smallest 2^m > d, minus one.
+__device__ __forceinline__ uint32_t table_p1(uint32_t d) {
+  return (d == 0) ? 0u : ((1u << (32 - __clz(d))) - 1u);
+}
+
+// ---- DPP -------------------------------------------------------------------
+// dpp_ctrl encodings (GCN/CDNA): quad_perm 0x00-0xFF, row_shr:n 0x110+n,
+// row_ror:n 0x120+n, row_bcast:15 0x142, row_bcast:31 0x143.
+template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF, bool BOUND_ZERO = true>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, BANK_MASK,
+                                               BOUND_ZERO);
+}
+template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF, bool BOUND_ZERO = true>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long x) {
+  const uint32_t lo = dpp32<CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO>((uint32_t)x);
+  const uint32_t hi = dpp32<CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO>((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float x) {
+  return __uint_as_float(dpp32<CTRL>(__float_as_uint(x)));
+}
+
+// Max over all 64 lanes; every lane must be active.  Result is uniform.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+  x = umax64(x, dpp64<0x111>(x));             // row_shr:1
+  x = umax64(x, dpp64<0x112>(x));             // row_shr:2
+  x = umax64(x, dpp64<0x114>(x));             // row_shr:4
+  x = umax64(x, dpp64<0x118>(x));             // row_shr:8  -> lane 15 of a row
+  x = umax64(x, dpp64<0x142, 0xA>(x));        // row_bcast:15 into rows 1, 3
+  x = umax64(x, dpp64<0x143, 0xC>(x));        // row_bcast:31 into rows 2, 3
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum over all 64 lanes of a small integer (uniform result).
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += dpp32<0x111>(x);
+  x += dpp32<0x112>(x);
+  x += dpp32<0x114>(x);
+  x += dpp32<0x118>(x);
+  x += dpp32<0x142, 0xA>(x);
+  x += dpp32<0x143, 0xC>(x);
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Max within each 16-lane row, result in every lane of the row.
+__device__ __forceinline__ unsigned long long row16_max_u64(unsigned long long x) {
+  x = umax64(x, dpp64<0x128>(x));  // row_ror:8
+  x = umax64(x, dpp64<0x124>(x));  // row_ror:4
+  x = umax64(x, dpp64<0x122>(x));  // row_ror:2
+  x = umax64(x, dpp64<0x121>(x));  // row_ror:1
+  return x;
+}
+// Max within each quad, result in every lane of the quad.
+__device__ __forceinline__ unsigned long long quad_max_u64(unsigned long long x) {
+  x = umax64(x, dpp64<0xB1>(x));  // quad_perm [1,0,3,2]
+  x = umax64(x, dpp64<0x4E>(x));  // quad_perm [2,3,0,1]
+  return x;
+}
+
+// ---- hashtable probing -------------------------------------------------------
+// Next probe slot.  t counts probes already made.  s, step < p1; r = (k mod p2)
+// mod p1.
+__device__ __forceinline__ void probe_next(uint32_t& s, uint32_t& step, uint32_t r,
+                                           uint32_t p1, int t, int max_retries) {
+  if (t < max_retries) {
+    s += step;
+    if (s >= p1) s -= p1;
+    step = 2u * step + r;
+    if (step >= p1) step -= p1;
+    if (step >= p1) step -= p1;
+  } else {
+    s = (s + 1u == p1) ? 0u : s + 1u;
+  }
+}
+
+// Accumulate (k, v) into an LDS table of p1 slots shared by the lanes of one
+// wave or workgroup: atomic compare-and-swap claims an empty key slot, atomic
+// add accumulates the weight (Algorithm 2, shared branch).
+__device__ __forceinline__ void lds_accumulate(uint32_t* keys, float* vals, uint32_t p1,
+                                               uint32_t k, float v, int max_retries) {
+  const uint32_t p2 = 2u * p1 + 1u;
+  uint32_t s = k % p1;
+  uint32_t step = 1u % p1;
+  const uint32_t r = (k % p2) % p1;
+  for (int t = 0;; ++t) {
+    uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == kEmpty) {
+      uint32_t expected = kEmpty;
+      __hip_atomic_compare_exchange_strong(&keys[s], &expected, k, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      cur = (expected == kEmpty) ? k : expected;
+    }
+    if (cur == k) {
+      __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+    probe_next(s, step, r, p1, t, max_retries);
+  }
+}
+
+// Accumulate (k, v) into a global-memory table; returns the slot and the
+// value the slot holds after this add (values only grow, so the largest value
+// ever returned for a key is its final sum).
+__device__ __forceinline__ uint32_t global_accumulate(uint32_t* keys, float* vals,
+                                                      uint32_t p1, uint32_t k, float v,
+                                                      int max_retries, float* after) {
+  const uint32_t p2 = 2u * p1 + 1u;
+  uint32_t s = k % p1;
+  uint32_t step = 1u % p1;
+  const uint32_t r = (k % p2) % p1;
+  for (int t = 0;; ++t) {
+    uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kEmpty) {
+      uint32_t expected = kEmpty;
+      __hip_atomic_compare_exchange_strong(&keys[s], &expected, k, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      cur = (expected == kEmpty) ? k : expected;
+    }
+    if (cur == k) {
+      const float old = __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+      *after = old + v;
+      return s;
+    }
+    probe_next(s, step, r, p1, t, max_retries);
+  }
+}
+
+template <typename OffT>
+__device__ __forceinline__ void row_of(const void* off, int32_t v, int64_t* o, int64_t* d) {
+  const OffT* p = reinterpret_cast<const OffT*>(off);
+  const int64_t a = (int64_t)p[v];
+  const int64_t b = (int64_t)p[v + 1];
+  *o = a;
+  *d = b - a;
+}
+
+__device__ __forceinline__ float edge_weight(const float* w, int64_t e) {
+  return w ? w[e] : 1.0f;
+}
+
+}  // namespace lpa

@@ -1,0 +1,115 @@
+// lpa_internal.h -- declarations shared by the host runtime and the kernel
+// translation units of the label-propagation library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpa {
+
+// Vertex classes by degree (bounds come from lpa_tuning):
+//   0 degree 0 (never processed: no neighbour to adopt a label from)
+//   1 4-lane register groups          2 16-lane register groups
+//   3 wave, LDS table <= 127 slots    4 wave, LDS table <= 1023 slots
+//   5..8 workgroup, LDS table <= 2047 / 4095 / 8191 / 16383 slots
+//   9 hub: several workgroups per vertex + global-memory table
+constexpr int kNumClasses = 10;
+constexpr int kClassHub = 9;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hashtable key
+
+// Per-iteration device counters.  Reset at the start of every iteration by
+// the hub-plan kernel, read back by the host after the iteration.
+struct DevStats {
+  unsigned long long processed;
+  unsigned long long changed;
+  unsigned long long edges;
+  unsigned long long pending;       // deterministic mode: queued label writes
+  unsigned int active[kNumClasses]; // vertices appended per class this iteration
+  unsigned int hub_items;           // hub slices queued this iteration
+  unsigned int error;               // sticky error bits (validation, labels)
+};
+
+// Everything a sweep kernel needs, passed by value.
+struct SweepArgs {
+  const void* off;        // int32_t* or int64_t* (kernel template picks)
+  const int32_t* tgt;
+  const float* w;         // NULL: unit weights
+  int32_t* C;             // labels (read; written in place in async mode)
+  uint8_t* F;             // flags for the next iteration (set on change)
+  const int32_t* active;  // active vertex list of this class
+  int32_t* pend_v;        // deterministic mode: queued (vertex, label)
+  int32_t* pend_c;
+  DevStats* st;
+  int cls;                // class index (selects st->active[cls])
+  int pl;                 // Pick-Less on in this iteration
+  int async_mode;         // 1: write labels in place, 0: queue them
+  int max_retries;        // hybrid probes before the linear continuation
+};
+
+struct HubArgs {
+  const void* off;
+  const int32_t* tgt;
+  const float* w;
+  int32_t* C;
+  uint8_t* F;
+  int32_t* pend_v;
+  int32_t* pend_c;
+  DevStats* st;
+  const int32_t* hub_vid;          // H hub vertex ids
+  const int64_t* hub_tab;          // H offsets into the global table
+  unsigned long long* hub_best;    // H packed (weight, ~label) maxima
+  int32_t* hub_old;                // H labels at iteration start
+  uint32_t* gkeys;                 // global table keys
+  float* gvals;                    // global table values
+  uint32_t* items;                 // queued slices: (hub index, slice index) word pairs
+  int32_t* rec;                    // per slice: recorded global slots
+  int32_t* nrec;                   // per slice: number of recorded slots
+  int32_t H;
+  int32_t chunk;                   // edges per slice
+  int pl;
+  int async_mode;
+  int max_retries;
+};
+
+// ---- launch wrappers (defined in the .hip files) ----------------------------
+hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
+                       DevStats* st, hipStream_t s);
+hipError_t launch_validate(bool off64, const void* off, const int32_t* tgt,
+                           const float* w, int64_t n, int64_t m, DevStats* st,
+                           hipStream_t s);
+hipError_t launch_check_labels(int64_t n, const int32_t* lab, DevStats* st,
+                               hipStream_t s);
+hipError_t launch_classify(bool off64, const void* off, int64_t n,
+                           const int32_t* bounds, uint8_t* cls,
+                           unsigned long long* counts, int32_t* hub_out,
+                           unsigned int* hub_count, hipStream_t s);
+hipError_t launch_gather_degrees(bool off64, const void* off, const int32_t* vids,
+                                 int32_t h, int64_t* deg, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
+hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
+                           hipStream_t s);
+hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
+                           int32_t* const* lists_dev, DevStats* st, int grid,
+                           hipStream_t s);
+hipError_t launch_apply(const DevStats* st, const int32_t* pv, const int32_t* pc,
+                        int32_t* C, int grid, hipStream_t s);
+hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid,
+                        hipStream_t s);
+hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_hub_fin(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt,
+                             const float* w, int64_t n, int64_t m,
+                             const int32_t* C, double* sig, double* acc,
+                             hipStream_t s);
+
+// Threads per workgroup of each sweep class and resident-workgroup estimate.
+int sweep_block_threads(int cls);
+int sweep_items_per_block(int cls);
+int sweep_max_resident(int cls);
+int hub_block_threads();
+int hub_max_resident();
+
+}  // namespace lpa

@@ -1,0 +1,493 @@
+// sweep.hip -- the per-vertex label sweep (one iteration of lpaMove,
+// Algorithm 1) for gfx950, split by degree class.
+//
+// Every kernel processes the active vertices of its class (built by the
+// frontier kernel) and, per vertex i:
+//   1. sums the weight towards each neighbour label, skipping self-loops
+//      (Eq. 3; Algorithm 1 neighbour scan, Algorithm 2 accumulation),
+//   2. takes the label of maximum sum, smallest label on ties,
+//   3. moves if the label differs and, under Pick-Less, is strictly smaller
+//      (Sec. 4.1),
+//   4. on a move, flags every CSR neighbour for the next iteration (Sec. 4
+//      item 4) and counts the change.
+// In asynchronous mode the new label is stored in place before the flags
+// (release fence between them); in deterministic mode it is queued and
+// applied after the sweep, so every vertex reads the iteration-start labels.
+//
+// Classes:
+//   k_sweep_small<G>  G lanes per vertex (G = 4 or 16), one edge per lane,
+//                     per-label sums by DPP rotations inside the group; no
+//                     hashtable is needed for rows this short.
+//   k_sweep_wave      one wave per vertex, LDS hashtable per wave.
+//   k_sweep_block     one workgroup per vertex, LDS hashtable per workgroup.
+//   k_hub_acc/fin     rows longer than the largest LDS table: each slice of
+//                     the row is reduced in an LDS table, then merged into a
+//                     global-memory table with atomics; the merge also
+//                     maintains the packed maximum, since sums only grow.
+#include "lpa_device.h"
+
+namespace lpa {
+
+namespace {
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+  x += dpp64<0x111>(x);
+  x += dpp64<0x112>(x);
+  x += dpp64<0x114>(x);
+  x += dpp64<0x118>(x);
+  x += dpp64<0x142, 0xA>(x);
+  x += dpp64<0x143, 0xC>(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Lane rank among the lanes of the wave whose bit is set in mask.
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Wave-aggregated append of (v, c) to the deterministic-mode queue for the
+// lanes with pred set.  All lanes of the wave must call it.
+__device__ __forceinline__ void queue_moves(bool pred, int32_t v, uint32_t c,
+                                            const SweepArgs& a) {
+  const unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return;
+  unsigned long long base = 0;
+  const int leader = __ffsll((long long)mask) - 1;
+  if ((int)(threadIdx.x & 63) == leader)
+    base = atomicAdd(&a.st->pending, (unsigned long long)__popcll(mask));
+  base = ((unsigned long long)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+  if (pred) {
+    const unsigned long long pos = base + lane_rank(mask);
+    a.pend_v[pos] = v;
+    a.pend_c[pos] = (int32_t)c;
+  }
+}
+
+__device__ __forceinline__ void flush_stats(unsigned long long edges, uint32_t changed,
+                                            DevStats* st) {
+  const unsigned long long e = wave_sum_u64(edges);
+  const uint32_t c = wave_sum_u32(changed);
+  if ((threadIdx.x & 63) == 0) {
+    if (e) atomicAdd(&st->edges, e);
+    if (c) atomicAdd(&st->changed, (unsigned long long)c);
+  }
+}
+
+__device__ __forceinline__ bool decide(unsigned long long best, int32_t cur, int pl,
+                                       uint32_t* cstar) {
+  if (best == 0ull) return false;  // no neighbour other than itself
+  const uint32_t c = unpack_label(best);
+  *cstar = c;
+  return (int32_t)c != cur && (!pl || (int32_t)c < cur);
+}
+
+template <int R>
+__device__ __forceinline__ void rot16_accum(uint32_t lab, float wt, float& sum) {
+  const uint32_t ol = dpp32<0x120 + R, 0xF, 0xF, false>(lab);
+  const float ow = __uint_as_float(dpp32<0x120 + R, 0xF, 0xF, false>(__float_as_uint(wt)));
+  if (ol == lab) sum += ow;
+}
+template <int Q>
+__device__ __forceinline__ void rot4_accum(uint32_t lab, float wt, float& sum) {
+  const uint32_t ol = dpp32<Q, 0xF, 0xF, false>(lab);
+  const float ow = __uint_as_float(dpp32<Q, 0xF, 0xF, false>(__float_as_uint(wt)));
+  if (ol == lab) sum += ow;
+}
+
+}  // namespace
+
+// ---- small rows: G lanes per vertex, registers only -------------------------
+template <typename OffT, int G>
+__global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int k = lane & (G - 1);
+  const uint32_t count = a.st->active[a.cls];
+  constexpr uint32_t kVpw = 64 / G;
+  const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  unsigned long long my_edges = 0;
+  uint32_t my_changed = 0;
+  for (uint64_t base = (uint64_t)wave_id * kVpw; base < count;
+       base += (uint64_t)nwaves * kVpw) {
+    const uint64_t idx = base + (uint32_t)lane / G;
+    const bool valid = idx < count;
+    int32_t v = valid ? a.active[idx] : 0;
+    int64_t o = 0, d = 0;
+    if (valid) row_of<OffT>(a.off, v, &o, &d);
+    const bool has = valid && k < d;
+    const int32_t j = has ? a.tgt[o + k] : -1;
+    const float wt = has ? edge_weight(a.w, o + k) : 0.0f;
+    const uint32_t lab = (has && j != v) ? (uint32_t)a.C[j] : kEmpty;
+    // Per-label sum seen from this lane: its own weight plus every other lane
+    // of the group holding the same label.
+    float sum = wt;
+    if constexpr (G == 16) {
+      rot16_accum<1>(lab, wt, sum);  rot16_accum<2>(lab, wt, sum);
+      rot16_accum<3>(lab, wt, sum);  rot16_accum<4>(lab, wt, sum);
+      rot16_accum<5>(lab, wt, sum);  rot16_accum<6>(lab, wt, sum);
+      rot16_accum<7>(lab, wt, sum);  rot16_accum<8>(lab, wt, sum);
+      rot16_accum<9>(lab, wt, sum);  rot16_accum<10>(lab, wt, sum);
+      rot16_accum<11>(lab, wt, sum); rot16_accum<12>(lab, wt, sum);
+      rot16_accum<13>(lab, wt, sum); rot16_accum<14>(lab, wt, sum);
+      rot16_accum<15>(lab, wt, sum);
+    } else {
+      rot4_accum<0x39>(lab, wt, sum);  // quad_perm [1,2,3,0]
+      rot4_accum<0x4E>(lab, wt, sum);  // quad_perm [2,3,0,1]
+      rot4_accum<0x93>(lab, wt, sum);  // quad_perm [3,0,1,2]
+    }
+    const unsigned long long packed = (lab != kEmpty) ? pack_key(sum, lab) : 0ull;
+    const unsigned long long best =
+        (G == 16) ? row16_max_u64(packed) : quad_max_u64(packed);
+    uint32_t cstar = 0;
+    const int32_t cur = valid ? a.C[v] : 0;
+    const bool moved = valid && decide(best, cur, a.pl, &cstar);
+    const bool leader = valid && k == 0;
+    if (a.async_mode) {
+      if (moved && leader) a.C[v] = (int32_t)cstar;
+      if (__any(moved)) __threadfence();
+    } else {
+      queue_moves(moved && leader, v, cstar, a);
+    }
+    if (moved && has) a.F[j] = 1;
+    if (leader) {
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+    }
+  }
+  flush_stats(my_edges, my_changed, a.st);
+}
+
+// ---- one wave per vertex, LDS table per wave -------------------------------
+template <typename OffT, int SLOTS, int WAVES, int U>
+__global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
+  __shared__ uint32_t keys_all[WAVES][SLOTS];
+  __shared__ float vals_all[WAVES][SLOTS];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  uint32_t* keys = keys_all[wv];
+  float* vals = vals_all[wv];
+  for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const uint32_t count = a.st->active[a.cls];
+  unsigned long long my_edges = 0;
+  uint32_t my_changed = 0;
+  for (uint32_t item = blockIdx.x * WAVES + wv; item < count; item += gridDim.x * WAVES) {
+    const int32_t v = a.active[item];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    const int32_t cur = a.C[v];
+    const uint32_t p1 = table_p1((uint32_t)d);
+    for (int64_t base = 0; base < d; base += 64 * U) {
+      int32_t j[U];
+      float wt[U];
+      uint32_t lab[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * 64 + lane;
+        const bool has = e < d;
+        j[u] = has ? a.tgt[o + e] : v;
+        wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) lab[u] = (j[u] != v) ? (uint32_t)a.C[j[u]] : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned long long best = 0;
+    for (uint32_t s = lane; s < p1; s += 64) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(vals[s], kk));
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
+      }
+    }
+    best = wave_max_u64(best);
+    uint32_t cstar = 0;
+    const bool moved = decide(best, cur, a.pl, &cstar);
+    if (moved) {
+      if (a.async_mode) {
+        if (lane == 0) a.C[v] = (int32_t)cstar;
+        __threadfence();
+      }
+      for (int64_t e = lane; e < d; e += 64) a.F[a.tgt[o + e]] = 1;
+    }
+    if (!a.async_mode) queue_moves(moved && lane == 0, v, cstar, a);
+    if (lane == 0) {
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  flush_stats(my_edges, my_changed, a.st);
+}
+
+// ---- one workgroup per vertex, LDS table per workgroup ---------------------
+template <typename OffT, int SLOTS, int BT, int U>
+__global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
+  __shared__ uint32_t keys[SLOTS];
+  __shared__ float vals[SLOTS];
+  __shared__ unsigned long long red[BT / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  __syncthreads();
+  const uint32_t count = a.st->active[a.cls];
+  unsigned long long my_edges = 0;
+  uint32_t my_changed = 0;
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    const int32_t v = a.active[item];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    // Own label, read before the barriers below: in asynchronous mode thread 0
+    // overwrites it, and every thread must reach the same move decision.
+    const int32_t cur = a.C[v];
+    const uint32_t p1 = table_p1((uint32_t)d);
+    for (int64_t base = 0; base < d; base += (int64_t)BT * U) {
+      int32_t j[U];
+      float wt[U];
+      uint32_t lab[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * BT + tid;
+        const bool has = e < d;
+        j[u] = has ? a.tgt[o + e] : v;
+        wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) lab[u] = (j[u] != v) ? (uint32_t)a.C[j[u]] : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+    }
+    __syncthreads();
+    unsigned long long best = 0;
+    for (uint32_t s = tid; s < p1; s += BT) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(vals[s], kk));
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) red[tid >> 6] = best;
+    __syncthreads();
+    best = red[0];
+#pragma unroll
+    for (int q = 1; q < BT / 64; ++q) best = umax64(best, red[q]);
+    uint32_t cstar = 0;
+    const bool moved = decide(best, cur, a.pl, &cstar);
+    if (moved) {
+      if (tid == 0) {
+        if (a.async_mode) {
+          a.C[v] = (int32_t)cstar;
+        } else {
+          const unsigned long long pos = atomicAdd(&a.st->pending, 1ull);
+          a.pend_v[pos] = v;
+          a.pend_c[pos] = (int32_t)cstar;
+        }
+      }
+      if (a.async_mode) __threadfence();
+      __syncthreads();
+      for (int64_t e = tid; e < d; e += BT) a.F[a.tgt[o + e]] = 1;
+    }
+    if (tid == 0) {
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+    }
+    __syncthreads();
+  }
+  flush_stats(my_edges, my_changed, a.st);
+}
+
+// ---- hubs: slices reduced in LDS, merged in a global table -----------------
+template <typename OffT, int SLOTS, int BT>
+__global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
+  __shared__ uint32_t keys[SLOTS];
+  __shared__ float vals[SLOTS];
+  __shared__ unsigned long long red[BT / 64];
+  __shared__ uint32_t nrec;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  if (tid == 0) nrec = 0;
+  __syncthreads();
+  const uint32_t nitems = a.st->hub_items;
+  unsigned long long my_edges = 0;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
+    const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    const int32_t v = a.hub_vid[h];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    const int64_t e0 = (int64_t)c * a.chunk;
+    const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
+    const uint32_t p1c = table_p1((uint32_t)n);
+    for (int64_t e = tid; e < n; e += BT) {
+      const int32_t j = a.tgt[o + e0 + e];
+      if (j != v)
+        lds_accumulate(keys, vals, p1c, (uint32_t)a.C[j], edge_weight(a.w, o + e0 + e),
+                       a.max_retries);
+    }
+    __syncthreads();
+    const uint32_t p1g = table_p1((uint32_t)d);
+    uint32_t* gk = a.gkeys + a.hub_tab[h];
+    float* gv = a.gvals + a.hub_tab[h];
+    int32_t* rec = a.rec + (int64_t)it * a.chunk;
+    unsigned long long best = 0;
+    for (uint32_t s = tid; s < p1c; s += BT) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        float after;
+        const uint32_t gs = global_accumulate(gk, gv, p1g, kk, vals[s], a.max_retries, &after);
+        best = umax64(best, pack_key(after, kk));
+        const uint32_t r = atomicAdd(&nrec, 1u);
+        rec[r] = (int32_t)gs;
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) red[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long b = red[0];
+      for (int q = 1; q < BT / 64; ++q) b = umax64(b, red[q]);
+      if (b) atomicMax(&a.hub_best[h], b);
+      a.nrec[it] = (int32_t)nrec;
+      nrec = 0;
+      my_edges += (unsigned long long)n;
+    }
+    __syncthreads();
+  }
+  const unsigned long long e = wave_sum_u64(my_edges);
+  if (tid == 0 && e) atomicAdd(&a.st->edges, e);
+}
+
+template <typename OffT, int BT>
+__global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
+  const int tid = threadIdx.x;
+  const uint32_t nitems = a.st->hub_items;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
+    const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    const int32_t v = a.hub_vid[h];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    const int64_t e0 = (int64_t)c * a.chunk;
+    const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
+    uint32_t cstar = 0;
+    const bool moved = decide(a.hub_best[h], a.hub_old[h], a.pl, &cstar);
+    if (moved) {
+      if (c == 0 && tid == 0) {
+        if (a.async_mode) {
+          a.C[v] = (int32_t)cstar;
+        } else {
+          const unsigned long long pos = atomicAdd(&a.st->pending, 1ull);
+          a.pend_v[pos] = v;
+          a.pend_c[pos] = (int32_t)cstar;
+        }
+        atomicAdd(&a.st->changed, 1ull);
+      }
+      for (int64_t e = tid; e < n; e += BT) a.F[a.tgt[o + e0 + e]] = 1;
+    }
+    uint32_t* gk = a.gkeys + a.hub_tab[h];
+    float* gv = a.gvals + a.hub_tab[h];
+    const int32_t* rec = a.rec + (int64_t)it * a.chunk;
+    const int32_t nr = a.nrec[it];
+    for (int32_t r = tid; r < nr; r += BT) {
+      const int32_t s = rec[r];
+      gk[s] = kEmpty;
+      gv[s] = 0.0f;
+    }
+  }
+}
+
+// ---- launch wrappers ----------------------------------------------------------
+namespace {
+constexpr int kWaveWaves = 4;
+constexpr int kBlockBig = 1024;   // threads for the 16383-slot table
+constexpr int kBlockMid = 512;
+constexpr int kHubThreads = 1024;
+constexpr int kHubSlots = 16383;  // slice of up to 8192 edges
+}  // namespace
+
+int sweep_block_threads(int cls) {
+  switch (cls) {
+    case 1: case 2: case 3: case 4: return 256;
+    case 5: case 6: return 256;
+    case 7: return kBlockMid;
+    case 8: return kBlockBig;
+    default: return 256;
+  }
+}
+int sweep_items_per_block(int cls) {
+  switch (cls) {
+    case 1: return 256 / 4;
+    case 2: return 256 / 16;
+    case 3: case 4: return kWaveWaves;
+    default: return 1;
+  }
+}
+// Workgroups resident on the whole GPU (256 CUs) for each class; LDS bound
+// for the table kernels (160 KB per CU).
+int sweep_max_resident(int cls) {
+  switch (cls) {
+    case 1: case 2: return 256 * 8;   // 32 waves per CU
+    case 3: return 256 * 8;           // 4 KB LDS per workgroup
+    case 4: return 256 * 4;           // 32 KB
+    case 5: return 256 * 8;           // 16 KB
+    case 6: return 256 * 4;           // 32 KB
+    case 7: return 256 * 2;           // 64 KB
+    case 8: return 256 * 1;           // 128 KB
+    default: return 256;
+  }
+}
+int hub_block_threads() { return kHubThreads; }
+int hub_max_resident() { return 256; }
+
+template <typename OffT>
+static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
+  switch (cls) {
+    case 1: hipLaunchKernelGGL((k_sweep_small<OffT, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_sweep_wave<OffT, 127, kWaveWaves, 1>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sweep_wave<OffT, 1023, kWaveWaves, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4>), dim3(grid), dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4>), dim3(grid), dim3(kBlockMid), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep_block<OffT, 16383, kBlockBig, 4>), dim3(grid), dim3(kBlockBig), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, hipStream_t s) {
+  return off64 ? sweep_t<int64_t>(cls, a, grid, s) : sweep_t<int32_t>(cls, a, grid, s);
+}
+
+hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+  if (a.chunk > (kHubSlots + 1) / 2) return hipErrorInvalidValue;
+  if (off64)
+    hipLaunchKernelGGL((k_hub_acc<int64_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hub_acc<int32_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hub_fin(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL((k_hub_fin<int64_t, 256>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hub_fin<int32_t, 256>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lpa

@@ -1,0 +1,287 @@
+"""ctypes binding of the C ABI in include/lpa.h (liblpa.so, HIP for gfx950).
+
+Argument marshalling only: every step of the label sweep runs in the HIP
+kernels of liblpa.so.  There is no CPU fallback; if the library is missing
+the import of a function raises.  torch supplies device memory and the
+stream (``torch.cuda.current_stream().cuda_stream``); numpy arrays are
+accepted as host memory.
+
+Names follow the C ABI: lpa_create, lpa_run, lpa_modularity, lpa_destroy,
+lpa_graph_classes, plus the ``LpaGraph`` convenience wrapper.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpa.so")
+
+LPA_OK = 0
+MODE_DETERMINISTIC = 0
+MODE_ASYNC = 1
+INDEX_I32 = 0
+INDEX_I64 = 1
+CLASS_NAMES = ("degree0", "small4", "small16", "wave", "block", "hub")
+
+
+class LpaError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"lpa status {status}: {detail}")
+        self.status = status
+
+
+class lpa_csr(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_int64), ("num_edges", ctypes.c_int64),
+                ("offset_type", ctypes.c_int32), ("on_device", ctypes.c_int32),
+                ("offsets", ctypes.c_void_p), ("targets", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("validate", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class lpa_tuning(ctypes.Structure):
+    _fields_ = [("small4", ctypes.c_int32), ("small16", ctypes.c_int32),
+                ("wave", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("hub_chunk", ctypes.c_int32), ("max_retries", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class lpa_options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
+                ("tolerance", ctypes.c_double), ("pl_period", ctypes.c_int32),
+                ("prune", ctypes.c_int32), ("initial_labels", ctypes.c_void_p)]
+
+
+class lpa_iter_stats(ctypes.Structure):
+    _fields_ = [("iteration", ctypes.c_int32), ("pick_less", ctypes.c_int32),
+                ("changed", ctypes.c_int64), ("processed", ctypes.c_int64),
+                ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
+EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run",
+            "lpa_modularity", "lpa_graph_classes", "lpa_get_flags", "lpa_destroy",
+            "lpa_status_string", "lpa_last_error")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblpa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2411_11468_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.lpa_options_default.argtypes = [ctypes.POINTER(lpa_options)]
+    lib.lpa_options_default.restype = None
+    lib.lpa_tuning_default.argtypes = [ctypes.POINTER(lpa_tuning)]
+    lib.lpa_tuning_default.restype = None
+    lib.lpa_create.argtypes = [ctypes.POINTER(lpa_csr), vp, ctypes.POINTER(lpa_tuning),
+                               ctypes.POINTER(vp)]
+    lib.lpa_create.restype = ctypes.c_int
+    lib.lpa_run.argtypes = [vp, ctypes.POINTER(lpa_options), vp,
+                            ctypes.POINTER(lpa_iter_stats), ctypes.c_int32,
+                            ctypes.POINTER(ctypes.c_int32)]
+    lib.lpa_run.restype = ctypes.c_int
+    lib.lpa_modularity.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.lpa_modularity.restype = ctypes.c_int
+    lib.lpa_graph_classes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.lpa_graph_classes.restype = ctypes.c_int
+    lib.lpa_get_flags.argtypes = [vp, vp]
+    lib.lpa_get_flags.restype = ctypes.c_int
+    lib.lpa_destroy.argtypes = [vp]
+    lib.lpa_destroy.restype = None
+    lib.lpa_status_string.argtypes = [ctypes.c_int]
+    lib.lpa_status_string.restype = ctypes.c_char_p
+    lib.lpa_last_error.argtypes = []
+    lib.lpa_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != LPA_OK:
+        lib = load_library()
+        raise LpaError(status, f"{lib.lpa_status_string(status).decode()}: "
+                               f"{lib.lpa_last_error().decode()}")
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _addr(x):
+    """Data address of a torch tensor or numpy array (None stays None)."""
+    if x is None:
+        return None
+    if _is_torch(x):
+        return ctypes.c_void_p(x.data_ptr())
+    return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _current_stream(device_arrays: bool):
+    if not device_arrays:
+        return None
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_tuning() -> lpa_tuning:
+    t = lpa_tuning()
+    load_library().lpa_tuning_default(ctypes.byref(t))
+    return t
+
+
+def default_options() -> lpa_options:
+    o = lpa_options()
+    load_library().lpa_options_default(ctypes.byref(o))
+    return o
+
+
+# ---- thin wrappers with the C names ---------------------------------------------
+
+def lpa_create(offsets, targets, weights=None, *, validate: bool = True,
+               tuning: lpa_tuning | None = None, stream=None):
+    """Create a graph handle.  torch CUDA tensors are borrowed (keep them alive);
+    numpy arrays are copied to the device.  Returns an opaque handle."""
+    lib = load_library()
+    on_dev = _is_torch(offsets) and offsets.is_cuda
+    if on_dev:
+        import torch
+        assert offsets.dtype in (torch.int32, torch.int64) and targets.dtype == torch.int32
+        assert weights is None or weights.dtype == torch.float32
+        for t in (offsets, targets, weights):
+            assert t is None or t.is_contiguous()
+        off_t = INDEX_I64 if offsets.dtype == torch.int64 else INDEX_I32
+    else:
+        offsets = np.ascontiguousarray(offsets)
+        targets = np.ascontiguousarray(targets, dtype=np.int32)
+        if weights is not None:
+            weights = np.ascontiguousarray(weights, dtype=np.float32)
+        assert offsets.dtype in (np.int32, np.int64)
+        off_t = INDEX_I64 if offsets.dtype == np.int64 else INDEX_I32
+    g = lpa_csr()
+    g.num_vertices = int(offsets.shape[0]) - 1
+    g.num_edges = int(targets.shape[0])
+    g.offset_type = off_t
+    g.on_device = int(on_dev)
+    g.offsets = _addr(offsets)
+    g.targets = _addr(targets)
+    g.weights = _addr(weights)
+    g.validate = int(validate)
+    h = ctypes.c_void_p()
+    s = stream if stream is not None else _current_stream(on_dev)
+    _check(lib.lpa_create(ctypes.byref(g), s, ctypes.byref(tuning) if tuning else None,
+                          ctypes.byref(h)))
+    return h
+
+
+def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
+            max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
+            initial_labels=None):
+    """Run to termination; labels is a preallocated int32 torch tensor or numpy
+    array of N entries.  Returns (iterations, list of stats dicts)."""
+    lib = load_library()
+    o = default_options()
+    o.mode = int(mode)
+    o.tolerance = float(tolerance)
+    o.max_iterations = int(max_iterations)
+    o.pl_period = int(pl_period)
+    o.prune = int(bool(prune))
+    o.initial_labels = _addr(initial_labels)
+    cap = max(int(max_iterations), 1)
+    st = (lpa_iter_stats * cap)()
+    it = ctypes.c_int32(0)
+    _check(lib.lpa_run(handle, ctypes.byref(o), _addr(labels), st, cap, ctypes.byref(it)))
+    stats = [dict(iteration=s.iteration, pick_less=s.pick_less, changed=s.changed,
+                  processed=s.processed, edges_scanned=s.edges_scanned, ms=s.ms)
+             for s in st[:it.value]]
+    return int(it.value), stats
+
+
+def lpa_modularity(handle, labels) -> float:
+    q = ctypes.c_double(0.0)
+    _check(load_library().lpa_modularity(handle, _addr(labels), ctypes.byref(q)))
+    return float(q.value)
+
+
+def lpa_graph_classes(handle) -> dict:
+    c = (ctypes.c_int64 * 6)()
+    _check(load_library().lpa_graph_classes(handle, c))
+    return dict(zip(CLASS_NAMES, list(c)))
+
+
+def lpa_get_flags(handle, out) -> None:
+    _check(load_library().lpa_get_flags(handle, _addr(out)))
+
+
+def lpa_destroy(handle) -> None:
+    if handle:
+        load_library().lpa_destroy(handle)
+
+
+# ---- convenience wrapper -----------------------------------------------------------
+
+@dataclass
+class RunResult:
+    labels: object          # torch.int32 tensor (device) or numpy array (host)
+    iterations: int
+    stats: list
+
+    @property
+    def gpu_ms(self) -> float:
+        return float(sum(s["ms"] for s in self.stats))
+
+
+class LpaGraph:
+    """Owns an lpa_graph handle (and keeps borrowed device arrays alive)."""
+
+    def __init__(self, offsets, targets, weights=None, *, validate: bool = True,
+                 tuning: lpa_tuning | None = None):
+        self._keep = (offsets, targets, weights)
+        self.on_device = _is_torch(offsets) and offsets.is_cuda
+        self.num_vertices = int(offsets.shape[0]) - 1
+        self.num_edges = int(targets.shape[0])
+        self.handle = lpa_create(offsets, targets, weights, validate=validate, tuning=tuning)
+
+    def run(self, mode: str | int = "async", out=None, **kw) -> RunResult:
+        m = {"async": MODE_ASYNC, "det": MODE_DETERMINISTIC,
+             "deterministic": MODE_DETERMINISTIC}.get(mode, mode)
+        if out is None:
+            if self.on_device:
+                import torch
+                out = torch.empty(self.num_vertices, dtype=torch.int32,
+                                  device=self._keep[0].device)
+            else:
+                out = np.empty(self.num_vertices, dtype=np.int32)
+        iters, stats = lpa_run(self.handle, out, mode=m, **kw)
+        return RunResult(out, iters, stats)
+
+    def modularity(self, labels) -> float:
+        return lpa_modularity(self.handle, labels)
+
+    def classes(self) -> dict:
+        return lpa_graph_classes(self.handle)
+
+    def flags(self) -> np.ndarray:
+        out = np.empty(self.num_vertices, dtype=np.uint8)
+        lpa_get_flags(self.handle, out)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lpa_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

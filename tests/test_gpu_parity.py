@@ -1,0 +1,253 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Deterministic mode must equal the oracle exactly (labels, iteration count and
+every per-iteration counter) on integer-valued weights.  Asynchronous mode is
+judged by invariants: with Pick-Less off, every vertex that is not flagged at
+exit holds a label of maximum weight; with Pick-Less on, modularity within
+0.01 of the oracle's.  Modularity itself must match the fp64 oracle to 1e-9
+relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2411_11468_amd import lpa  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _graph_on_gpu(g, tuning=None, on_device=True, weights=True):
+    w = g.weights if weights else None
+    if on_device:
+        return lpa.LpaGraph(_dev(g.offsets), _dev(g.targets),
+                            None if w is None else _dev(w), tuning=tuning)
+    return lpa.LpaGraph(g.offsets, g.targets, w, tuning=tuning)
+
+
+def _tuning(**kw):
+    t = lpa.default_tuning()
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+SMALL_TUNING = dict(small4=2, small16=8, wave=40, block=100, hub_chunk=64)
+
+
+def assert_det_parity(g, tuning=None, on_device=True, weights=True, initial=None, **kw):
+    ref = oracle.lpa_sync(g.offsets, g.targets, g.weights if weights else None,
+                          initial_labels=initial, **kw)
+    G = _graph_on_gpu(g, tuning, on_device, weights)
+    init = None if initial is None else (_dev(initial) if on_device else initial)
+    res = G.run("det", initial_labels=init, **kw)
+    labels = res.labels.cpu().numpy() if on_device else res.labels
+    assert res.iterations == ref.iterations
+    for s_gpu, s_ref in zip(res.stats, ref.stats):
+        for key in ("iteration", "pick_less", "changed", "processed", "edges_scanned"):
+            assert s_gpu[key] == s_ref[key], (key, s_gpu, s_ref)
+    mism = np.nonzero(labels != ref.labels)[0]
+    assert mism.size == 0, f"{mism.size} labels differ, first at {mism[:5]}"
+    G.close()
+    return ref
+
+
+def _golden_cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["lpa_cases"]
+
+
+def _golden_graph(spec):
+    k = spec["kind"]
+    if k == "disjoint_cliques":
+        return graphgen.disjoint_cliques(spec["r"], spec["s"])
+    if k == "complete_bipartite":
+        return graphgen.complete_bipartite(spec["n"])
+    return graphgen.from_edges(spec["n"], [tuple(e) for e in spec["edges"]])
+
+
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_det_hand_derived_cases(case):
+    g = _golden_graph(case["graph"])
+    G = _graph_on_gpu(g)
+    res = G.run("det", pl_period=case["pl_period"], tolerance=case.get("tolerance", 0.05))
+    assert res.iterations == case["iterations"]
+    assert res.labels.cpu().tolist() == case["labels"]
+    for key in ("changed", "processed", "edges_scanned"):
+        if key in case:
+            assert [s[key] for s in res.stats] == case[key]
+
+
+def test_det_planted_partition_10k():
+    ref = assert_det_parity(graphgen.planted_partition_10k(1))
+    assert ref.iterations >= 3
+
+
+@pytest.mark.parametrize("n,p,wmax", [(3000, 0.01, 8), (2000, 0.2, 8), (600, 0.9, 3),
+                                      (5000, 0.002, 1)])
+def test_det_random_graphs(n, p, wmax):
+    assert_det_parity(graphgen.random_graph(n, p, seed=n + int(p * 1000), wmax=wmax))
+
+
+def test_det_every_class_small_thresholds():
+    # thresholds shrunk so that a small graph exercises the 4- and 16-lane
+    # groups, both wave tables, the workgroup tables and the multi-slice path
+    t = _tuning(**SMALL_TUNING)
+    g = graphgen.random_graph(1500, 0.25, seed=5, wmax=8)
+    G = _graph_on_gpu(g, t)
+    cls = G.classes()
+    assert cls["hub"] > 0
+    G.close()
+    assert_det_parity(g, tuning=t)
+    r = graphgen.rmat_graph(12, 7, "int8")
+    assert_det_parity(r, tuning=t)
+
+
+def test_det_rmat_default_tuning():
+    g = graphgen.rmat_graph(15, 15, "int8")
+    G = _graph_on_gpu(g)
+    cls = G.classes()
+    G.close()
+    assert cls["small4"] > 0 and cls["wave"] > 0 and cls["block"] > 0
+    assert_det_parity(g)
+
+
+def test_det_int64_offsets_and_host_arrays():
+    g = graphgen.rmat_graph(13, 3, "int8")
+    g64 = graphgen.Graph(g.offsets.astype(np.int64), g.targets, g.weights)
+    assert_det_parity(g64, tuning=_tuning(**SMALL_TUNING))
+    assert_det_parity(g64, on_device=False)
+    assert_det_parity(g, on_device=False, tuning=_tuning(**SMALL_TUNING))
+
+
+def test_det_unit_weights_null_pointer():
+    g = graphgen.planted_partition_10k(2)
+    assert_det_parity(g, weights=False)
+
+
+def test_det_options():
+    g = graphgen.rmat_graph(12, 9, "int8")
+    t = _tuning(**SMALL_TUNING)
+    assert_det_parity(g, tuning=t, pl_period=0)
+    assert_det_parity(g, tuning=t, pl_period=0, prune=False)
+    assert_det_parity(g, tuning=t, pl_period=3, prune=False, max_iterations=7)
+    assert_det_parity(g, tuning=t, tolerance=0.0, max_iterations=13)
+    rng = np.random.default_rng(3)
+    init = rng.integers(0, g.num_vertices, size=g.num_vertices).astype(np.int32)
+    assert_det_parity(g, tuning=t, initial=init)
+    assert_det_parity(g, tuning=t, initial=init, on_device=False)
+
+
+def test_edge_cases():
+    # empty graph
+    G = lpa.LpaGraph(_dev(np.zeros(1, np.int32)), _dev(np.zeros(0, np.int32)))
+    res = G.run("det")
+    assert res.iterations == 0
+    assert G.modularity(res.labels) == 0.0
+    # vertices without edges, and self-loops only
+    for g in (graphgen.from_edges(5, []), graphgen.from_edges(4, [(1, 1), (2, 2)])):
+        assert_det_parity(g)
+        assert_det_parity(g, pl_period=0)
+
+
+def test_modularity_matches_oracle():
+    rng = np.random.default_rng(9)
+    for g in (graphgen.planted_partition_10k(1), graphgen.rmat_graph(14, 4, "int8"),
+              graphgen.ring_of_cliques(30, 5)):
+        G = _graph_on_gpu(g)
+        res = G.run("det")
+        labs = [res.labels.cpu().numpy(), np.arange(g.num_vertices, dtype=np.int32),
+                np.zeros(g.num_vertices, dtype=np.int32),
+                rng.integers(0, 50, size=g.num_vertices).astype(np.int32)]
+        for lab in labs:
+            want = oracle.modularity(g.offsets, g.targets, g.weights, lab)
+            got_dev = G.modularity(_dev(lab))
+            got_host = G.modularity(lab)
+            assert got_dev == pytest.approx(want, rel=1e-9, abs=1e-12)
+            assert got_host == pytest.approx(want, rel=1e-9, abs=1e-12)
+        G.close()
+    g = graphgen.ring_of_cliques(30, 5)
+    G = _graph_on_gpu(g)
+    lab = (np.arange(150) // 5).astype(np.int32)
+    assert G.modularity(lab) == pytest.approx(20 / 22 - 1 / 30, abs=1e-12)
+
+
+def _async_invariant(g, tuning=None, seed_runs=2):
+    G = _graph_on_gpu(g, tuning)
+    for _ in range(seed_runs):
+        res = G.run("async", pl_period=0)
+        lab = res.labels.cpu().numpy()
+        flags = G.flags().astype(bool)
+        ok = oracle.local_optimal(g.offsets, g.targets, g.weights, lab)
+        bad = np.nonzero(~ok & ~flags)[0]
+        assert bad.size == 0, f"{bad.size} unflagged vertices hold a non-maximal label"
+        for s in res.stats:
+            assert 0 <= s["changed"] <= s["processed"] <= g.num_vertices
+    G.close()
+
+
+def test_async_local_optimality_invariant():
+    _async_invariant(graphgen.planted_partition_10k(1))
+    _async_invariant(graphgen.rmat_graph(14, 5, "int8"))
+    _async_invariant(graphgen.rmat_graph(12, 6, "int8"), _tuning(**SMALL_TUNING))
+
+
+def test_async_modularity_band():
+    for g, t in ((graphgen.planted_partition_10k(1), None),
+                 (graphgen.rmat_graph(15, 8, "int8"), None),
+                 (graphgen.rmat_graph(13, 2, "int8"), _tuning(**SMALL_TUNING))):
+        ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+        q_ref = oracle.modularity(g.offsets, g.targets, g.weights, ref.labels)
+        G = _graph_on_gpu(g, t)
+        res = G.run("async")
+        q = oracle.modularity(g.offsets, g.targets, g.weights, res.labels.cpu().numpy())
+        assert abs(q - q_ref) <= 0.01, (q, q_ref)
+        assert G.modularity(res.labels) == pytest.approx(q, rel=1e-9, abs=1e-12)
+        G.close()
+
+
+def test_invalid_inputs_rejected():
+    g = graphgen.from_edges(4, [(0, 1), (1, 2)])
+    bad_t = g.targets.copy()
+    bad_t[0] = 7
+    with pytest.raises(lpa.LpaError):
+        lpa.LpaGraph(_dev(g.offsets), _dev(bad_t), _dev(g.weights))
+    bad_w = g.weights.copy()
+    bad_w[1] = -1.0
+    with pytest.raises(lpa.LpaError):
+        lpa.LpaGraph(_dev(g.offsets), _dev(g.targets), _dev(bad_w))
+    bad_w[1] = -0.0
+    with pytest.raises(lpa.LpaError):
+        lpa.LpaGraph(_dev(g.offsets), _dev(g.targets), _dev(bad_w))
+    bad_o = g.offsets.copy()
+    bad_o[2] = 0
+    with pytest.raises(lpa.LpaError):
+        lpa.LpaGraph(_dev(bad_o), _dev(g.targets), _dev(g.weights))
+    G = _graph_on_gpu(g)
+    with pytest.raises(lpa.LpaError):
+        G.run("det", initial_labels=_dev(np.array([0, 1, 2, 9], np.int32)))
+    with pytest.raises(lpa.LpaError):
+        G.modularity(np.array([0, -1, 2, 3], np.int32))
+    with pytest.raises(lpa.LpaError):
+        G.run(mode=7)
+    res = G.run("det")  # still usable after rejected calls
+    assert res.labels.cpu().tolist() == [0, 0, 0, 3]
+    G.close()
+
+
+def test_det_rmat_scale22_full_size():
+    # full-size R-MAT scale 22 with integer weights 1..8 (exact fp32 sums)
+    g = graphgen.rmat_graph(22, 22, "int8")
+    assert int(g.weights.max()) * int(g.degrees().max()) < 2 ** 24
+    assert_det_parity(g)
