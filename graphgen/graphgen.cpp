@@ -228,6 +228,13 @@ int gg_sbm(int64_t n, int32_t nblocks, const int64_t* block_sizes,
 // bit) is (0,0), (0,1), (1,0), (1,1) respectively.  Sample s uses Philox
 // counters (s, level group, tag).  Self-loops and duplicates are dropped and
 // both directions added.
+//
+// CSR construction without shared atomics: vertices are split into 2^k
+// consecutive bins; pass 1 counts, per thread, the directed entries each bin
+// receives; pass 2 regenerates the samples and streams (row, target) pairs
+// into per-thread slots of each bin; each bin is then counting-sorted by row
+// in cache, rows are sorted and de-duplicated, and the bins are copied into
+// the final arrays.
 int gg_rmat(int32_t scale, int64_t edge_factor, double a, double b, double c,
             uint64_t seed, gg_graph* out) {
   memset(out, 0, sizeof(*out));
@@ -238,86 +245,123 @@ int gg_rmat(int32_t scale, int64_t edge_factor, double a, double b, double c,
   const uint32_t tb = (uint32_t)std::lround((a + b) * 65536.0);
   const uint32_t tc = (uint32_t)std::lround((a + b + c) * 65536.0);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x524D4154u;
-  auto sample = [&](int64_t s, int32_t* pu, int32_t* pv) {
+  auto sample = [&](int64_t s, uint32_t* pu, uint32_t* pv) {
     uint32_t u = 0, v = 0;
-    uint32_t words[8];
-    int have = 0, used = 0;
-    for (int lev = 0; lev < scale; ++lev) {
-      if (used == have) {
-        const P4 x = philox((uint32_t)s, (uint32_t)(s >> 32), (uint32_t)(lev >> 3),
-                            0x45444745u, k0, k1);
-        for (int q = 0; q < 4; ++q) { words[2 * q] = x.v[q] & 0xFFFFu; words[2 * q + 1] = x.v[q] >> 16; }
-        have = 8; used = 0;
-      }
-      const uint32_t r = words[used++];
-      const uint32_t bit = 1u << (scale - 1 - lev);
-      if (r < ta) {
-      } else if (r < tb) {
-        v |= bit;
-      } else if (r < tc) {
-        u |= bit;
-      } else {
-        u |= bit; v |= bit;
+    for (int g = 0; g * 8 < scale; ++g) {
+      const P4 x = philox((uint32_t)s, (uint32_t)(s >> 32), (uint32_t)g, 0x45444745u, k0, k1);
+      for (int q = 0; q < 8 && g * 8 + q < scale; ++q) {
+        const uint32_t r = (q & 1) ? (x.v[q >> 1] >> 16) : (x.v[q >> 1] & 0xFFFFu);
+        // quadrant a: no bit; b: column bit; c: row bit; d: both
+        const int sh = scale - 1 - (g * 8 + q);
+        const uint32_t ub = (uint32_t)(r >= tb);
+        const uint32_t vb = (uint32_t)(r >= ta) ^ (uint32_t)(r >= tb) ^ (uint32_t)(r >= tc);
+        u |= ub << sh;
+        v |= vb << sh;
       }
     }
-    *pu = (int32_t)u; *pv = (int32_t)v;
+    *pu = u; *pv = v;
   };
-  // pass 1: degrees
-  std::atomic<int64_t>* deg = new (std::nothrow) std::atomic<int64_t>[n + 1];
-  if (!deg) return -2;
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i <= n; ++i) deg[i].store(0, std::memory_order_relaxed);
-#pragma omp parallel for schedule(static, 65536)
-  for (int64_t s = 0; s < S; ++s) {
-    int32_t u, v;
-    sample(s, &u, &v);
-    if (u == v) continue;
-    deg[u].fetch_add(1, std::memory_order_relaxed);
-    deg[v].fetch_add(1, std::memory_order_relaxed);
+  const int bin_bits = std::min(scale, 12);
+  const int nb = 1 << bin_bits;
+  const int shift = scale - bin_bits;
+  const int T = omp_get_max_threads();
+  // contiguous sample range per thread, so pass 2 sees the same samples
+  std::vector<int64_t> lo(T + 1);
+  for (int t = 0; t <= T; ++t) lo[t] = S * t / T;
+  std::vector<int64_t> cnt((size_t)T * nb, 0);
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    int64_t* my = &cnt[(size_t)t * nb];
+    for (int64_t s = lo[t]; s < lo[t + 1]; ++s) {
+      uint32_t u, v;
+      sample(s, &u, &v);
+      if (u == v) continue;
+      ++my[u >> shift];
+      ++my[v >> shift];
+    }
   }
-  int64_t* off0 = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
-  if (!off0) { delete[] deg; return -2; }
-  off0[0] = 0;
-  for (int64_t i = 0; i < n; ++i) off0[i + 1] = off0[i] + deg[i].load(std::memory_order_relaxed);
-  const int64_t m0 = off0[n];
-  int32_t* t0 = (int32_t*)malloc(sizeof(int32_t) * (m0 > 0 ? m0 : 1));
-  if (!t0) { delete[] deg; free(off0); return -2; }
-  // pass 2: scatter (deg reused as cursors)
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i) deg[i].store(off0[i], std::memory_order_relaxed);
-#pragma omp parallel for schedule(static, 65536)
-  for (int64_t s = 0; s < S; ++s) {
-    int32_t u, v;
-    sample(s, &u, &v);
-    if (u == v) continue;
-    t0[deg[u].fetch_add(1, std::memory_order_relaxed)] = v;
-    t0[deg[v].fetch_add(1, std::memory_order_relaxed)] = u;
+  // bin b, thread t writes at pos[t][b]
+  std::vector<int64_t> bin_lo(nb + 1, 0), pos((size_t)T * nb);
+  for (int bb = 0; bb < nb; ++bb) {
+    int64_t acc = bin_lo[bb];
+    for (int t = 0; t < T; ++t) { pos[(size_t)t * nb + bb] = acc; acc += cnt[(size_t)t * nb + bb]; }
+    bin_lo[bb + 1] = acc;
   }
-  delete[] deg;
-  // pass 3: sort + unique per row
-  int64_t* nd = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
-  if (!nd) { free(off0); free(t0); return -2; }
-#pragma omp parallel for schedule(dynamic, 4096)
-  for (int64_t i = 0; i < n; ++i) {
-    int32_t* bb = t0 + off0[i];
-    int32_t* ee = t0 + off0[i + 1];
-    std::sort(bb, ee);
-    nd[i] = std::unique(bb, ee) - bb;
+  const int64_t m0 = bin_lo[nb];
+  uint64_t* pairs = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m0 > 0 ? m0 : 1));
+  if (!pairs) return -2;
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    int64_t* my = &pos[(size_t)t * nb];
+    for (int64_t s = lo[t]; s < lo[t + 1]; ++s) {
+      uint32_t u, v;
+      sample(s, &u, &v);
+      if (u == v) continue;
+      pairs[my[u >> shift]++] = ((uint64_t)u << 32) | v;
+      pairs[my[v >> shift]++] = ((uint64_t)v << 32) | u;
+    }
   }
-  // pass 4: compact
-  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
-  if (!off) { free(off0); free(t0); free(nd); return -2; }
+  // per bin: counting sort by row, sort + unique rows, targets written back
+  // as int32 at the start of the bin's region; deduplicated degrees kept
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!off) { free(pairs); return -2; }
+  const int64_t vpb = (int64_t)1 << shift;  // vertices per bin
+  std::vector<int> order(nb);
+  for (int bb = 0; bb < nb; ++bb) order[bb] = bb;
+  std::sort(order.begin(), order.end(), [&](int x, int y) {
+    return bin_lo[x + 1] - bin_lo[x] > bin_lo[y + 1] - bin_lo[y];
+  });
+  bool ok = true;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(T)
+  for (int oi = 0; oi < nb; ++oi) {
+    const int bb = order[oi];
+    const int64_t e0 = bin_lo[bb], ne = bin_lo[bb + 1] - e0;
+    const int64_t v0 = (int64_t)bb << shift;
+    std::vector<int64_t> rs(vpb + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) ++rs[(pairs[e0 + e] >> 32) - v0 + 1];
+    for (int64_t i = 0; i < vpb; ++i) rs[i + 1] += rs[i];
+    int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+    if (!tmp) { ok = false; continue; }
+    {
+      std::vector<int64_t> cur(rs.begin(), rs.end() - 1);
+      for (int64_t e = 0; e < ne; ++e) {
+        const uint64_t p = pairs[e0 + e];
+        tmp[cur[(p >> 32) - v0]++] = (int32_t)(uint32_t)p;
+      }
+    }
+    int32_t* dst = reinterpret_cast<int32_t*>(pairs + e0);
+    int64_t w = 0;
+    for (int64_t i = 0; i < vpb; ++i) {
+      int32_t* rb = tmp + rs[i];
+      int32_t* re = tmp + rs[i + 1];
+      std::sort(rb, re);
+      int32_t* ue = std::unique(rb, re);
+      const int64_t k = ue - rb;
+      memcpy(dst + w, rb, sizeof(int32_t) * (size_t)k);
+      w += k;
+      off[v0 + i + 1] = k;  // degree for now
+    }
+    free(tmp);
+  }
+  if (!ok) { free(pairs); free(off); return -2; }
   off[0] = 0;
-  for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + nd[i];
-  free(nd);
+  std::vector<int64_t> bin_out(nb + 1, 0);
+  for (int bb = 0; bb < nb; ++bb) {
+    int64_t acc = 0;
+    for (int64_t i = 0; i < vpb; ++i) acc += off[((int64_t)bb << shift) + i + 1];
+    bin_out[bb + 1] = bin_out[bb] + acc;
+  }
+  for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
   const int64_t m = off[n];
-  int32_t* tgt = (int32_t*)malloc(sizeof(int32_t) * (m > 0 ? m : 1));
-  if (!tgt) { free(off0); free(t0); free(off); return -2; }
-#pragma omp parallel for schedule(dynamic, 4096)
-  for (int64_t i = 0; i < n; ++i)
-    memcpy(tgt + off[i], t0 + off0[i], sizeof(int32_t) * (off[i + 1] - off[i]));
-  free(t0);
-  free(off0);
+  int32_t* tgt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  if (!tgt) { free(pairs); free(off); return -2; }
+#pragma omp parallel for schedule(dynamic, 1) num_threads(T)
+  for (int bb = 0; bb < nb; ++bb)
+    memcpy(tgt + bin_out[bb], reinterpret_cast<int32_t*>(pairs + bin_lo[bb]),
+           sizeof(int32_t) * (size_t)(bin_out[bb + 1] - bin_out[bb]));
+  free(pairs);
   out->n = n; out->m = m; out->off = off; out->tgt = tgt;
   return 0;
 }

@@ -94,13 +94,17 @@ typedef struct lpa_graph_s* lpa_graph;
  * Degree thresholds that split vertices into kernel classes (all inclusive
  * upper bounds; a vertex of degree D goes to the first class whose bound is
  * >= D; degree 0 is never processed):
- *   small4   rows processed by 4-lane groups in registers     (default 4)
- *   small16  rows processed by 16-lane groups in registers    (default 16)
- *   wave     one wavefront per vertex, LDS hashtable          (default 1023)
+ *   small4   rows processed by 4-lane groups in registers     (default 4,
+ *                                                              at most 4)
+ *   small16  rows processed by 16-lane groups in registers    (default 16,
+ *                                                              at most 16)
+ *   wave     one wavefront per vertex, LDS hashtable          (default 512,
+ *                                                              at most 512)
  *   block    one workgroup per vertex, LDS hashtable up to 16383 slots
- *                                                             (default 16383)
+ *                                                 (default 8192, at most 8192)
  *   larger degrees: several workgroups per vertex, each with an LDS table for
  *   its slice of the row, merged in a global-memory hashtable.
+ * Every hashtable holding D keys has 2^m - 1 >= 2D - 1 slots (load <= 1/2).
  * hub_chunk: edges per workgroup slice for the largest rows (default 8192).
  * max_retries: hybrid probes before the linear continuation (default 32).
  */
@@ -125,7 +129,27 @@ typedef struct lpa_tuning {
  *   prune           1: only flagged vertices are processed (default 1)
  *   initial_labels  NULL: label = vertex id; else N labels in [0, N), host or
  *                   device memory
+ *   profile         1: bracket every kernel launch with HIP events and add its
+ *                   duration and algorithmic bytes to the per-kernel profile
+ *                   read by lpa_profile (default 0)
+ *   flag_mode       how the neighbours of the vertices changed in an
+ *                   iteration are flagged after its sweep (the flags are
+ *                   identical on a symmetric graph):
+ *                   LPA_FLAGS_PUSH  each changed vertex writes its neighbours'
+ *                                   flags;
+ *                   LPA_FLAGS_PULL  every vertex reads its neighbours' change
+ *                                   marks up to the first changed one;
+ *                   LPA_FLAGS_AUTO  pull when the changed vertices' rows hold
+ *                                   at least half of the CSR entries, push
+ *                                   otherwise, decided on the GPU per
+ *                                   iteration (default)
  */
+typedef enum lpa_flag_mode {
+  LPA_FLAGS_AUTO = 0,
+  LPA_FLAGS_PUSH = 1,
+  LPA_FLAGS_PULL = 2
+} lpa_flag_mode;
+
 typedef struct lpa_options {
   int32_t mode;
   int32_t max_iterations;
@@ -133,6 +157,8 @@ typedef struct lpa_options {
   int32_t pl_period;
   int32_t prune;
   const int32_t* initial_labels;
+  int32_t profile;
+  int32_t flag_mode;
 } lpa_options;
 
 /* Statistics of one iteration. */
@@ -145,6 +171,26 @@ typedef struct lpa_iter_stats {
   float ms;               /* GPU time of the iteration */
   int32_t reserved;
 } lpa_iter_stats;
+
+/*
+ * Accumulated per-kernel profile of the runs made with profile = 1.
+ * name: kernel ("sweep_block16383", "hub_acc", "frontier", ...);
+ * launches, total_ms: launches and summed GPU durations (HIP events on the
+ * handle's stream); bytes: algorithmic bytes moved -- per scanned CSR entry
+ * the target (4 B), the weight (4 B, none for unit weights) and the gathered
+ * neighbour label (4 B); per processed vertex its active-list id (4 B), two
+ * row offsets and its own label (4 B); per change the new label (4 B, 8 B for
+ * a queued pair in deterministic mode) and one flag byte per neighbour;
+ * edges, vertices: CSR entries scanned and vertices processed.
+ */
+typedef struct lpa_kernel_profile {
+  char name[24];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+  int64_t edges;
+  int64_t vertices;
+} lpa_kernel_profile;
 
 /* Fill *opt with the defaults above. */
 void lpa_options_default(lpa_options* opt);
@@ -200,6 +246,16 @@ lpa_status lpa_graph_classes(lpa_graph g, int64_t* counts);
  * label of maximum weight (Eq. 3), unless Pick-Less refused its move.
  */
 lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags);
+
+/*
+ * Copy up to cap kernel records (kernels launched at least once since the
+ * last reset) into out; *count receives the number of such kernels.
+ */
+lpa_status lpa_profile(lpa_graph g, lpa_kernel_profile* out, int32_t cap,
+                       int32_t* count);
+
+/* Clear the accumulated per-kernel profile. */
+lpa_status lpa_profile_reset(lpa_graph g);
 
 /* Release the handle and all library-owned memory.  NULL is allowed. */
 void lpa_destroy(lpa_graph g);

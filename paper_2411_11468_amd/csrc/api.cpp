@@ -18,6 +18,16 @@ using namespace lpa;
 
 namespace {
 
+// kernel ids of the optional profile
+constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubAcc = 2, kKidSweep0 = 2,
+              kKidHubFin = 11, kKidApply = 12, kKidPull = 13, kKidPullHubs = 14,
+              kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kNumKids = 18;
+const char* const kKidNames[kNumKids] = {
+    "hub_plan", "frontier", "hub_acc", "sweep_small4", "sweep_small16", "sweep_wave127",
+    "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
+    "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
+    "push_hubs", "flag_decide"};
+
 thread_local std::string g_err;
 
 lpa_status fail(lpa_status s, const std::string& msg) {
@@ -59,9 +69,12 @@ struct lpa_graph_s {
   int32_t* lists[kNumClasses] = {};
   int64_t cls_count[kNumClasses] = {};
   int grid[kNumClasses] = {};
-  int frontier_grid = 1, apply_grid = 1, hub_acc_grid = 1, hub_fin_grid = 1;
+  int frontier_grid = 1, apply_grid = 1, hub_acc_grid = 1, hub_fin_grid = 1, pull_grid = 1,
+      push_grid = 1;
   int32_t* pend_v = nullptr;
   int32_t* pend_c = nullptr;
+  int32_t* Cn = nullptr;
+  uint8_t* chg = nullptr;
   DevStats* st = nullptr;
   DevStats* st_host = nullptr;
   int32_t H = 0;
@@ -74,11 +87,88 @@ struct lpa_graph_s {
   uint32_t* items = nullptr;
   int32_t* rec = nullptr;
   int32_t* nrec = nullptr;
+  int32_t* hub_nrec = nullptr;
   int64_t max_items = 0;
   double* mod_sig = nullptr;
   double* mod_acc = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<void*> dev_allocs;
+  // optional per-kernel profile: events bracketing each launch, and the
+  // accumulated launches, time and algorithmic bytes per kernel
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kid;
+  lpa_kernel_profile prof[kNumKids] = {};
+
+  lpa_status ensure_events(int count) {
+    while ((int)ev_pool.size() < count) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return fail(LPA_ERR_HIP, "hipEventCreate failed");
+      ev_pool.push_back(e);
+      ev_kid.push_back(-1);
+    }
+    return LPA_OK;
+  }
+
+  // Algorithmic bytes of one launch: what the method must read and write,
+  // independent of caching (per scanned CSR entry: target 4 B, weight 4 B
+  // unless unit weights, gathered neighbour label 4 B; per processed vertex:
+  // its active-list id 4 B, its two row offsets, its own label 4 B, and in
+  // deterministic mode its next label 4 B; per change: the new label 4 B in
+  // asynchronous mode (a queued hub pair 8 B in deterministic mode) and one
+  // flag byte per neighbour).
+  void account(int kid, float ms, const DevStats& h, bool async_mode, bool pull) {
+    if (kid < 0 || kid >= kNumKids) return;
+    lpa_kernel_profile& p = prof[kid];
+    const double eb = 8.0 + (w ? 4.0 : 0.0);
+    const double ob = off64 ? 16.0 : 8.0;
+    const double chb = async_mode ? 4.0 : 8.0;
+    double bytes = 0.0;
+    int64_t edges = 0, verts = 0;
+    if (kid >= kKidSweep0 + 1 && kid <= kKidSweep0 + 8) {
+      const int c = kid - kKidSweep0;
+      edges = (int64_t)h.edges[c];
+      verts = (int64_t)h.active[c];
+      bytes = eb * edges + (4.0 + ob + 4.0) * verts + (double)h.changed[c] +
+              (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
+    } else if (kid == kKidHubAcc) {
+      edges = (int64_t)h.edges[kClassHub];
+      bytes = eb * edges;
+    } else if (kid == kKidHubFin) {
+      bytes = chb * h.changed[kClassHub] + (double)h.changed[kClassHub];
+    } else if (kid == kKidFrontier) {
+      verts = (int64_t)h.processed;
+      // flag, class and change byte per vertex; flag clear + list id per
+      // taken vertex
+      bytes = 3.0 * n + 5.0 * (double)h.processed;
+    } else if (kid == kKidPull || kid == kKidPullHubs) {
+      // row offsets and class per vertex, target + change byte per entry
+      // read, flag byte per vertex; the two kernels share one counter, so
+      // the whole figure is booked on the first
+      if (kid == kKidPull && pull) {
+        edges = (int64_t)h.pull_scanned;
+        bytes = (double)n * ((off64 ? 8.0 : 4.0) + 2.0) + 5.0 * (double)h.pull_scanned;
+      }
+    } else if (kid == kKidPush || kid == kKidPushHubs) {
+      // per changed row: its offsets and, per entry, target read + flag byte
+      if (kid == kKidPush && !pull) {
+        unsigned long long fw = 0, ch = 0, listed = 0;
+        for (int c = 0; c < kNumClasses; ++c) { fw += h.flagw[c]; ch += h.changed[c]; }
+        for (int c = 1; c < kClassHub; ++c) listed += h.active[c];
+        edges = (int64_t)fw;
+        bytes = 5.0 * (double)listed + (off64 ? 16.0 : 8.0) * (double)ch + 5.0 * (double)fw;
+      }
+    } else if (kid == kKidApply) {
+      unsigned long long listed = 0;
+      for (int c = 1; c < kClassHub; ++c) listed += h.active[c];
+      verts = (int64_t)(h.pending + listed);
+      bytes = 12.0 * (double)h.pending + 12.0 * (double)listed;
+    }
+    p.launches += 1;
+    p.total_ms += ms;
+    p.bytes += bytes;
+    p.edges += edges;
+    p.vertices += verts;
+  }
 
   template <typename T>
   lpa_status dalloc(T** p, int64_t count) {
@@ -98,16 +188,18 @@ struct lpa_graph_s {
 
   HubArgs hub_args(int pl, int async_mode) const {
     HubArgs a;
-    a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F;
+    a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F; a.chg = chg;
     a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
     a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
     a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.rec = rec; a.nrec = nrec;
+    a.hub_nrec = hub_nrec;
     a.H = H; a.chunk = tun.hub_chunk; a.pl = pl; a.async_mode = async_mode;
     a.max_retries = tun.max_retries;
     return a;
   }
 
   ~lpa_graph_s() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : dev_allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -126,6 +218,8 @@ void lpa_options_default(lpa_options* opt) {
   opt->pl_period = 4;
   opt->prune = 1;
   opt->initial_labels = nullptr;
+  opt->profile = 0;
+  opt->flag_mode = LPA_FLAGS_AUTO;
 }
 
 void lpa_tuning_default(lpa_tuning* t) {
@@ -133,8 +227,8 @@ void lpa_tuning_default(lpa_tuning* t) {
   std::memset(t, 0, sizeof(*t));
   t->small4 = 4;
   t->small16 = 16;
-  t->wave = 1023;
-  t->block = 16383;
+  t->wave = 512;
+  t->block = 8192;
   t->hub_chunk = 8192;
   t->max_retries = 32;
 }
@@ -162,7 +256,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   if (tuning) G->tun = *tuning; else lpa_tuning_default(&G->tun);
   const lpa_tuning& t = G->tun;
   if (!(0 <= t.small4 && t.small4 <= 4 && t.small4 <= t.small16 && t.small16 <= 16 &&
-        t.small16 <= t.wave && t.wave <= 1023 && t.wave <= t.block && t.block <= 16383 &&
+        t.small16 <= t.wave && t.wave <= 512 && t.wave <= t.block && t.block <= 8192 &&
         t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   hipStream_t s = G->stream;
@@ -230,18 +324,21 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   if (lpa_status e = G->dalloc(&G->F, n)) return e;
   if (lpa_status e = G->dalloc(&G->pend_v, n)) return e;
   if (lpa_status e = G->dalloc(&G->pend_c, n)) return e;
+  if (lpa_status e = G->dalloc(&G->Cn, n)) return e;
+  if (lpa_status e = G->dalloc(&G->chg, n)) return e;
   if (lpa_status e = G->dalloc(&G->cls, n)) return e;
 
   // degree classes
   int32_t bounds[kNumClasses] = {0};
+  // a table of 2^s - 1 slots holds rows of up to 2^(s-1) entries at load <= 1/2
   bounds[1] = t.small4;
   bounds[2] = t.small16;
-  bounds[3] = std::min(127, t.wave);
-  bounds[4] = t.wave;
-  bounds[5] = std::min(2047, t.block);
-  bounds[6] = std::min(4095, t.block);
-  bounds[7] = std::min(8191, t.block);
-  bounds[8] = t.block;
+  bounds[3] = std::min(64, t.wave);     // 127 slots
+  bounds[4] = t.wave;                   // 1023 slots
+  bounds[5] = std::min(1024, t.block);  // 2047 slots
+  bounds[6] = std::min(2048, t.block);  // 4095 slots
+  bounds[7] = std::min(4096, t.block);  // 8191 slots
+  bounds[8] = t.block;                  // 16383 slots
   bounds[9] = INT32_MAX;
   unsigned long long* counts = nullptr;
   unsigned int* hub_count = nullptr;
@@ -267,6 +364,8 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   }
   G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 256 * 8));
   G->apply_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256 * 8));
+  G->pull_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 31) / 32, 256 * 8));
+  G->push_grid = 256 * 8;
 
   // hubs: sorted ids, global table offsets (p1 = nextPow2(D) - 1 slots each),
   // slice scratch
@@ -289,7 +388,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
       if (hd[h] > (int64_t)INT32_MAX / 2)
         return fail(LPA_ERR_INVALID, "a vertex degree exceeds 2^30");
       int64_t p = 1;
-      while (p <= hd[h]) p <<= 1;
+      while (p < 2 * hd[h]) p <<= 1;  // capacity: smallest 2^m >= 2D, minus one
       tab[h] = slots;
       slots += p - 1;
       items += (hd[h] + t.hub_chunk - 1) / t.hub_chunk;
@@ -299,6 +398,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     LPA_HIP(hipMemcpyAsync(G->hub_tab, tab.data(), sizeof(int64_t) * G->H, hipMemcpyHostToDevice, s));
     if (lpa_status e = G->dalloc(&G->hub_best, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->hub_old, G->H)) return e;
+    if (lpa_status e = G->dalloc(&G->hub_nrec, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->gkeys, slots)) return e;
     if (lpa_status e = G->dalloc(&G->gvals, slots)) return e;
     LPA_HIP(launch_fill_u32(G->gkeys, kEmpty, slots, s));
@@ -376,6 +476,8 @@ lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
     return fail(LPA_ERR_INVALID, "mode must be LPA_MODE_DETERMINISTIC or LPA_MODE_ASYNC");
   if (o.max_iterations < 0) return fail(LPA_ERR_INVALID, "max_iterations < 0");
   if (o.pl_period < 0) return fail(LPA_ERR_INVALID, "pl_period < 0");
+  if (o.flag_mode < LPA_FLAGS_AUTO || o.flag_mode > LPA_FLAGS_PULL)
+    return fail(LPA_ERR_INVALID, "flag_mode must be LPA_FLAGS_AUTO, _PUSH or _PULL");
   if (stats_cap < 0 || (stats_cap > 0 && !stats))
     return fail(LPA_ERR_INVALID, "stats_cap < 0 or stats is NULL");
   if (g->n > 0 && !labels) return fail(LPA_ERR_INVALID, "labels is NULL");
@@ -400,50 +502,129 @@ lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
       return fail(LPA_ERR_INVALID, "initial_labels must lie in [0, N)");
   }
   int32_t done = 0;
+  const bool prof = o.profile != 0;
   for (int32_t l = 0; l < o.max_iterations; ++l) {
     const int pl = (o.pl_period > 0) && (l % o.pl_period == 0);
+
+    int nev = 0;
+    // launch bracketing for the optional per-kernel profile
+    auto mark = [&](int kid) -> lpa_status {
+      if (!prof) return LPA_OK;
+      if (lpa_status e = g->ensure_events(nev + 1)) return e;
+      g->ev_kid[nev] = kid;
+      LPA_HIP(hipEventRecord(g->ev_pool[nev], s));
+      ++nev;
+      return LPA_OK;
+    };
     LPA_HIP(hipEventRecord(g->ev0, s));
     // without pruning every vertex is processed in every iteration
     if (!o.prune && l > 0) LPA_HIP(launch_fill_u8(g->F, 1, n, s));
     const HubArgs ha = g->hub_args(pl, async_mode);
+    if (lpa_status e = mark(kKidPlan)) return e;
     LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
-    LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->st, g->frontier_grid, s));
-    if (g->H > 0) LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
+    if (lpa_status e = mark(kKidFrontier)) return e;
+    LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
+    if (g->H > 0) {
+      if (lpa_status e = mark(kKidHubAcc)) return e;
+      LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
+    }
     SweepArgs a;
-    a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.F = g->F;
-    a.pend_v = g->pend_v; a.pend_c = g->pend_c; a.st = g->st;
-    a.pl = pl; a.async_mode = async_mode; a.max_retries = g->tun.max_retries;
+    a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;
+    a.chg = g->chg; a.st = g->st;
+    a.pl = pl; a.async_mode = async_mode;
+    a.max_retries = g->tun.max_retries;
     for (int c = kClassHub - 1; c >= 1; --c) {
       if (g->cls_count[c] == 0) continue;
       a.cls = c;
       a.active = g->lists[c];
+      if (lpa_status e = mark(kKidSweep0 + c)) return e;
       LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], s));
     }
-    if (g->H > 0) LPA_HIP(launch_hub_fin(g->off64, ha, g->hub_fin_grid, s));
-    if (!async_mode) LPA_HIP(launch_apply(g->st, g->pend_v, g->pend_c, g->C, g->apply_grid, s));
+    if (g->H > 0) {
+      if (lpa_status e = mark(kKidHubFin)) return e;
+      LPA_HIP(launch_hub_fin(g->off64, ha, g->hub_fin_grid, s));
+    }
+    if (!async_mode) {
+      if (lpa_status e = mark(kKidApply)) return e;
+      LPA_HIP(launch_apply(g->st, g->lists, g->Cn, g->pend_v, g->pend_c, g->C, g->apply_grid,
+                           s));
+    }
+    // flag the neighbours of the changed vertices: the decide kernel picks
+    // push or pull from this iteration's counters, the other kernels return
+    if (lpa_status e = mark(kKidDecide)) return e;
+    LPA_HIP(launch_flag_decide(g->st, g->m, o.flag_mode, s));
+    if (lpa_status e = mark(kKidPush)) return e;
+    LPA_HIP(launch_push_lists(g->off64, g->off, g->tgt, g->lists, g->chg, g->F, g->st,
+                              g->push_grid, s));
+    if (g->H > 0) {
+      if (lpa_status e = mark(kKidPushHubs)) return e;
+      LPA_HIP(launch_push_hubs(g->off64, ha, g->hub_fin_grid, s));
+    }
+    if (lpa_status e = mark(kKidPull)) return e;
+    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, n, g->cls, g->chg, g->F, g->st,
+                              g->pull_grid, s));
+    if (g->H > 0) {
+      if (lpa_status e = mark(kKidPullHubs)) return e;
+      LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg, g->F,
+                               g->st, s));
+    }
+    if (lpa_status e = mark(-1)) return e;
     LPA_HIP(hipEventRecord(g->ev1, s));
     LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
     LPA_HIP(hipStreamSynchronize(s));
     float ms = 0.0f;
     LPA_HIP(hipEventElapsedTime(&ms, g->ev0, g->ev1));
     const DevStats& h = *g->st_host;
+    unsigned long long changed = 0, edges = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+      changed += h.changed[c];
+      edges += h.edges[c];
+    }
+    if (prof) {
+      for (int q = 0; q + 1 < nev; ++q) {
+        float kms = 0.0f;
+        LPA_HIP(hipEventElapsedTime(&kms, g->ev_pool[q], g->ev_pool[q + 1]));
+        g->account(g->ev_kid[q], kms, h, async_mode != 0, h.pull_mode != 0);
+      }
+    }
     if (l < stats_cap) {
       lpa_iter_stats& r = stats[l];
       std::memset(&r, 0, sizeof(r));
       r.iteration = l;
       r.pick_less = pl;
-      r.changed = (int64_t)h.changed;
+      r.changed = (int64_t)changed;
       r.processed = (int64_t)h.processed;
-      r.edges_scanned = (int64_t)h.edges;
+      r.edges_scanned = (int64_t)edges;
       r.ms = ms;
     }
     done = l + 1;
-    if (!pl && (double)h.changed < o.tolerance * (double)n) break;
+    if (!pl && (double)changed < o.tolerance * (double)n) break;
   }
   if (iters_done) *iters_done = done;
   const hipMemcpyKind kind = is_device_ptr(labels) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   LPA_HIP(hipMemcpyAsync(labels, g->C, sizeof(int32_t) * (size_t)n, kind, s));
   LPA_HIP(hipStreamSynchronize(s));
+  return LPA_OK;
+}
+
+lpa_status lpa_profile(lpa_graph g, lpa_kernel_profile* out, int32_t cap, int32_t* count) {
+  if (!g || (cap > 0 && !out) || cap < 0) return fail(LPA_ERR_INVALID, "bad argument");
+  int32_t k = 0;
+  for (int q = 0; q < kNumKids; ++q) {
+    if (g->prof[q].launches == 0) continue;
+    if (k < cap) {
+      out[k] = g->prof[q];
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", kKidNames[q]);
+    }
+    ++k;
+  }
+  if (count) *count = k;
+  return LPA_OK;
+}
+
+lpa_status lpa_profile_reset(lpa_graph g) {
+  if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
+  for (int q = 0; q < kNumKids; ++q) g->prof[q] = lpa_kernel_profile{};
   return LPA_OK;
 }
 

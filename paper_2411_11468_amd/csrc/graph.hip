@@ -178,10 +178,16 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
   const int tid = threadIdx.x;
   DevStats* st = a.st;
   if (tid == 0) {
-    st->processed = 0; st->changed = 0; st->edges = 0; st->pending = 0;
+    st->processed = 0; st->pending = 0;
     running = 0; nproc = 0;
   }
-  if (tid < kNumClasses) st->active[tid] = 0;
+  if (tid == 0) { st->pull_scanned = 0; st->pull_mode = 0; }
+  if (tid < kNumClasses) {
+    st->active[tid] = 0;
+    st->edges[tid] = 0;
+    st->changed[tid] = 0;
+    st->flagw[tid] = 0;
+  }
   __syncthreads();
   const OffT* off = reinterpret_cast<const OffT*>(a.off);
   for (int32_t tile = 0; tile < a.H; tile += 1024) {
@@ -190,6 +196,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     if (h < a.H) {
       const int32_t v = a.hub_vid[h];
       a.hub_best[h] = 0ull;
+      a.hub_nrec[h] = 0;
       if (F[v]) {
         F[v] = 0;
         a.hub_old[h] = C[v];
@@ -235,7 +242,8 @@ hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
 struct ListPtrs { int32_t* p[kNumClasses]; };
 
 __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
-                                                  ListPtrs lists, DevStats* st) {
+                                                  ListPtrs lists, uint8_t* chg_clear,
+                                                  DevStats* st) {
   __shared__ uint32_t cnt[kNumClasses];
   __shared__ uint32_t base[kNumClasses];
   const int tid = threadIdx.x;
@@ -250,6 +258,7 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
     for (int q = 0; q < 4; ++q) {
       const int64_t v = chunk + (int64_t)tid * 4 + q;
       cq[q] = -1;
+      if (v < n) chg_clear[v] = 0;
       if (v < n && F[v]) {
         F[v] = 0;
         ++proc;
@@ -275,34 +284,253 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
 }
 
 hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
-                           int32_t* const* lists, DevStats* st, int grid, hipStream_t s) {
+                           int32_t* const* lists, uint8_t* chg_clear, DevStats* st, int grid,
+                           hipStream_t s) {
   ListPtrs lp;
   for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
-  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kBT), 0, s, n, F, cls, lp, st);
+  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kBT), 0, s, n, F, cls, lp, chg_clear, st);
   return hipGetLastError();
 }
 
-// ---- deterministic mode: apply the queued label writes ------------------------
-__global__ void k_apply(const DevStats* st, const int32_t* pv, const int32_t* pc,
-                        int32_t* C) {
-  const unsigned long long cnt = st->pending;
-  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
-       i < cnt; i += (unsigned long long)gridDim.x * blockDim.x)
-    C[pv[i]] = pc[i];
+// ---- neighbour flags ------------------------------------------------------------
+// The sweep records each changed vertex in chg.  Every CSR neighbour of a
+// changed vertex is then flagged for the next iteration (Sec. 4 item 4), in
+// one of two equivalent ways on a symmetric CSR:
+//   push: each changed vertex writes the flag byte of each neighbour;
+//   pull: each vertex reads the change bytes of its neighbours and stops at
+//         the first changed one.
+// Push costs one scattered byte store per entry of a changed row; pull costs
+// a read per entry up to the first changed neighbour.  k_flag_decide picks
+// pull when the changed rows hold at least half of the CSR entries (then most
+// vertices find a changed neighbour within a few entries), push otherwise;
+// the kernels of the other way return at once.
+__global__ void k_flag_decide(DevStats* st, int64_t m, int force) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long fw = 0;
+  for (int c = 0; c < kNumClasses; ++c) fw += st->flagw[c];
+  st->pull_mode = force == 2 ? 1u : force == 1 ? 0u : (2ull * fw >= (unsigned long long)m ? 1u : 0u);
 }
 
-hipError_t launch_apply(const DevStats* st, const int32_t* pv, const int32_t* pc,
-                        int32_t* C, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply, dim3(grid), dim3(kBT), 0, s, st, pv, pc, C);
+hipError_t launch_flag_decide(DevStats* st, int64_t m, int force, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_decide, dim3(1), dim3(64), 0, s, st, m, force);
+  return hipGetLastError();
+}
+
+// push: classes 1..4 with 8 lanes per vertex, classes 5..8 with a workgroup
+// per vertex (hub rows: k_push_hubs, one workgroup per slice)
+template <typename OffT>
+__global__ __launch_bounds__(kBT) void k_push_lists(const OffT* off, const int32_t* tgt,
+                                                    ListPtrs lists, const uint8_t* chg,
+                                                    uint8_t* F, DevStats* st) {
+  if (st->pull_mode) return;
+  const int lane = threadIdx.x & 63;
+  const int k = lane & 7;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int c = 1; c <= 4; ++c) {
+    const int64_t cnt = st->active[c];
+    const int32_t* list = lists.p[c];
+    for (int64_t base = wave * 8; base < cnt; base += nwaves * 8) {
+      const int64_t idx = base + (lane >> 3);
+      if (idx >= cnt) continue;
+      const int32_t v = list[idx];
+      if (!chg[v]) continue;
+      const int64_t o = (int64_t)off[v], d = (int64_t)off[v + 1] - o;
+      for (int64_t e = k; e < d; e += 8) F[tgt[o + e]] = 1;
+    }
+  }
+  for (int c = 5; c < kClassHub; ++c) {
+    const int64_t cnt = st->active[c];
+    const int32_t* list = lists.p[c];
+    for (int64_t item = blockIdx.x; item < cnt; item += gridDim.x) {
+      const int32_t v = list[item];
+      if (!chg[v]) continue;
+      const int64_t o = (int64_t)off[v], d = (int64_t)off[v + 1] - o;
+      for (int64_t e = threadIdx.x; e < d; e += blockDim.x) F[tgt[o + e]] = 1;
+    }
+  }
+}
+
+hipError_t launch_push_lists(bool off64, const void* off, const int32_t* tgt,
+                             int32_t* const* lists, const uint8_t* chg, uint8_t* F,
+                             DevStats* st, int grid, hipStream_t s) {
+  ListPtrs lp;
+  for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
+  if (off64)
+    hipLaunchKernelGGL(k_push_lists<int64_t>, dim3(grid), dim3(kBT), 0, s,
+                       (const int64_t*)off, tgt, lp, chg, F, st);
+  else
+    hipLaunchKernelGGL(k_push_lists<int32_t>, dim3(grid), dim3(kBT), 0, s,
+                       (const int32_t*)off, tgt, lp, chg, F, st);
+  return hipGetLastError();
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kBT) void k_push_hubs(HubArgs a) {
+  if (a.st->pull_mode) return;
+  const uint32_t nitems = a.st->hub_items;
+  const OffT* off = reinterpret_cast<const OffT*>(a.off);
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
+    const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    const int32_t v = a.hub_vid[h];
+    if (!a.chg[v]) continue;
+    const int64_t o = (int64_t)off[v], d = (int64_t)off[v + 1] - o;
+    const int64_t e0 = (int64_t)c * a.chunk;
+    const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) a.F[a.tgt[o + e0 + e]] = 1;
+  }
+}
+
+hipError_t launch_push_hubs(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL(k_push_hubs<int64_t>, dim3(grid), dim3(kBT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_push_hubs<int32_t>, dim3(grid), dim3(kBT), 0, s, a);
+  return hipGetLastError();
+}
+
+// pull: non-hub rows with 8 lanes per vertex, 8 entries per step; hub rows
+// with one workgroup per hub.
+namespace {
+__device__ __forceinline__ uint32_t or8(uint32_t x) {
+  x |= dpp32<0xB1, 0xF, 0xF, false>(x);   // quad_perm [1,0,3,2]
+  x |= dpp32<0x4E, 0xF, 0xF, false>(x);   // quad_perm [2,3,0,1]
+  x |= dpp32<0x141, 0xF, 0xF, false>(x);  // row_half_mirror
+  return x;
+}
+}  // namespace
+
+template <typename OffT>
+__global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32_t* tgt,
+                                                    int64_t n, const uint8_t* cls,
+                                                    const uint8_t* chg, uint8_t* F,
+                                                    DevStats* st) {
+  if (!st->pull_mode) return;
+  const int lane = threadIdx.x & 63;
+  const int k = lane & 7;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  unsigned long long scanned = 0;
+  for (int64_t base = wave * 8; base < n; base += nwaves * 8) {
+    const int64_t v = base + (lane >> 3);
+    const bool valid = v < n && cls[v] != kClassHub;
+    int64_t o = 0, d = 0;
+    if (valid) {
+      o = (int64_t)off[v];
+      d = (int64_t)off[v + 1] - o;
+    }
+    bool done = d == 0;   // the same for the 8 lanes of a vertex
+    bool found = false;
+    for (int64_t t = 0; __any(!done); t += 8) {
+      uint32_t hit = 0;
+      const int64_t e = t + k;
+      if (!done && e < d) {
+        hit = chg[tgt[o + e]];
+        ++scanned;
+      }
+      hit = or8(hit);
+      if (!done) {
+        if (hit) { found = true; done = true; }
+        else if (t + 8 >= d) done = true;
+      }
+    }
+    if (found && k == 0) F[v] = 1;
+  }
+  for (int ofs = 32; ofs > 0; ofs >>= 1) scanned += __shfl_xor(scanned, ofs);
+  if (lane == 0 && scanned) atomicAdd(&st->pull_scanned, scanned);
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_t* tgt,
+                                                   const int32_t* hub_vid, int32_t H,
+                                                   const uint8_t* chg, uint8_t* F,
+                                                   DevStats* st) {
+  __shared__ int any;
+  if (!st->pull_mode) return;
+  unsigned long long scanned = 0;
+  for (int32_t h = blockIdx.x; h < H; h += gridDim.x) {
+    const int32_t v = hub_vid[h];
+    const int64_t o = (int64_t)off[v];
+    const int64_t d = (int64_t)off[v + 1] - o;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int64_t t = 0; t < d; t += kBT) {
+      const int64_t e = t + threadIdx.x;
+      if (e < d) {
+        ++scanned;
+        if (chg[tgt[o + e]]) any = 1;
+      }
+      if (__syncthreads_or(any)) break;
+    }
+    if (threadIdx.x == 0 && any) F[v] = 1;
+    __syncthreads();
+  }
+  for (int ofs = 32; ofs > 0; ofs >>= 1) scanned += __shfl_xor(scanned, ofs);
+  if ((threadIdx.x & 63) == 0 && scanned) atomicAdd(&st->pull_scanned, scanned);
+}
+
+hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
+                             const uint8_t* cls, const uint8_t* chg, uint8_t* F,
+                             DevStats* st, int grid, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL(k_pull_flags<int64_t>, dim3(grid), dim3(kBT), 0, s,
+                       (const int64_t*)off, tgt, n, cls, chg, F, st);
+  else
+    hipLaunchKernelGGL(k_pull_flags<int32_t>, dim3(grid), dim3(kBT), 0, s,
+                       (const int32_t*)off, tgt, n, cls, chg, F, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pull_hubs(bool off64, const void* off, const int32_t* tgt,
+                            const int32_t* hub_vid, int32_t H, const uint8_t* chg,
+                            uint8_t* F, DevStats* st, hipStream_t s) {
+  const int g = H < 2048 ? H : 2048;
+  if (off64)
+    hipLaunchKernelGGL(k_pull_hubs<int64_t>, dim3(g), dim3(kBT), 0, s,
+                       (const int64_t*)off, tgt, hub_vid, H, chg, F, st);
+  else
+    hipLaunchKernelGGL(k_pull_hubs<int32_t>, dim3(g), dim3(kBT), 0, s,
+                       (const int32_t*)off, tgt, hub_vid, H, chg, F, st);
+  return hipGetLastError();
+}
+
+// ---- deterministic mode: publish the labels of this iteration -------------
+// Every vertex processed by a class kernel wrote its next label to Cn; hubs
+// queued their moves.  Copy both into C.
+__global__ void k_apply(const DevStats* st, ListPtrs lists, const int32_t* Cn,
+                        const int32_t* pv, const int32_t* pc, int32_t* C) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  const unsigned long long t0 = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+  const unsigned long long nq = st->pending;
+  for (unsigned long long i = t0; i < nq; i += stride) C[pv[i]] = pc[i];
+  for (int c = 1; c < kClassHub; ++c) {
+    const unsigned long long cnt = st->active[c];
+    const int32_t* list = lists.p[c];
+    for (unsigned long long i = t0; i < cnt; i += stride) {
+      const int32_t v = list[i];
+      C[v] = Cn[v];
+    }
+  }
+}
+
+hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t* Cn,
+                        const int32_t* pv, const int32_t* pc, int32_t* C, int grid,
+                        hipStream_t s) {
+  ListPtrs lp;
+  for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
+  hipLaunchKernelGGL(k_apply, dim3(grid), dim3(kBT), 0, s, st, lp, Cn, pv, pc, C);
   return hipGetLastError();
 }
 
 // ---- modularity, Eq. 1 ------------------------------------------------------
 // Each thread owns a contiguous run of CSR entries, finds the row of its first
-// entry by binary search, and walks rows: K_i is added into Sigma[C_i] when the
-// row ends, entries with C_i = C_j add to sigma.
+// entry by binary search, and walks rows: K_i is gathered into a running sum
+// that is added into Sigma[C_i] when the label changes (and, across a wave,
+// once per label shared with the wave's first lane); entries with C_i = C_j
+// add to sigma.
 namespace {
-constexpr int kModEpt = 16;
+constexpr int kModEpt = 64;
 
 __device__ __forceinline__ double block_sum_f64(double x, double* sh) {
   for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
@@ -324,36 +552,51 @@ __global__ __launch_bounds__(kBT) void k_mod_edges(const OffT* off, const int32_
                                                    double* acc) {
   __shared__ double sh[kBT / 64];
   double sigma = 0.0, two_m = 0.0;
-  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t * kModEpt < m;
-       t += nthreads) {
-    const int64_t e0 = t * kModEpt;
-    const int64_t e1 = (e0 + kModEpt < m) ? e0 + kModEpt : m;
-    // row containing e0: largest i with off[i] <= e0 and off[i+1] > e0
-    int64_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if ((int64_t)off[mid] <= e0) lo = mid; else hi = mid - 1;
-    }
-    int64_t i = lo;
-    while ((int64_t)off[i + 1] <= e0) ++i;  // skip empty rows sharing the offset
-    int64_t row_end = (int64_t)off[i + 1];
-    int32_t ci = C[i];
-    double ki = 0.0;
-    for (int64_t e = e0; e < e1; ++e) {
-      while (e >= row_end) {
-        if (ki != 0.0) atomicAdd(&sig[ci], ki);
-        ki = 0.0;
-        ++i;
-        row_end = (int64_t)off[i + 1];
-        ci = C[i];
+  const int64_t nchunks = (m + kModEpt - 1) / kModEpt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // wave-uniform trip count: every lane takes part in the wave combine below
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nchunks;
+       base += stride) {
+    const int64_t t = base + (threadIdx.x & 63);
+    int32_t run_c = -1;   // label of the pending Sigma contribution
+    double run_k = 0.0;
+    if (t < nchunks) {
+      const int64_t e0 = t * kModEpt;
+      const int64_t e1 = (e0 + kModEpt < m) ? e0 + kModEpt : m;
+      // row containing e0: largest i with off[i] <= e0
+      int64_t lo = 0, hi = n - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((int64_t)off[mid] <= e0) lo = mid; else hi = mid - 1;
       }
-      const double we = w ? (double)w[e] : 1.0;
-      ki += we;
-      two_m += we;
-      if (C[tgt[e]] == ci) sigma += we;
+      int64_t i = lo;
+      int64_t row_end = (int64_t)off[i + 1];
+      int32_t ci = C[i];
+      run_c = ci;
+      for (int64_t e = e0; e < e1; ++e) {
+        while (e >= row_end) {
+          ++i;
+          row_end = (int64_t)off[i + 1];
+          ci = C[i];
+          if (ci != run_c) {
+            if (run_k != 0.0) atomicAdd(&sig[run_c], run_k);
+            run_c = ci;
+            run_k = 0.0;
+          }
+        }
+        const double we = w ? (double)w[e] : 1.0;
+        run_k += we;
+        two_m += we;
+        if (C[tgt[e]] == ci) sigma += we;
+      }
     }
-    if (ki != 0.0) atomicAdd(&sig[ci], ki);
+    // lanes holding the same label as the first lane add it with one atomic
+    const int32_t lead = __builtin_amdgcn_readfirstlane(run_c);
+    const bool same = run_c == lead;
+    double part = same ? run_k : 0.0;
+    for (int ofs = 32; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs);
+    if ((threadIdx.x & 63) == 0 && lead >= 0 && part != 0.0) atomicAdd(&sig[lead], part);
+    if (!same && run_c >= 0 && run_k != 0.0) atomicAdd(&sig[run_c], run_k);
   }
   const double s1 = block_sum_f64(sigma, sh);
   const double s2 = block_sum_f64(two_m, sh);

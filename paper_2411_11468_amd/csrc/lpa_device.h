@@ -6,13 +6,17 @@
 //    rule of Sec. 4 item 5 used throughout).  An empty key packs to 0, below
 //    every real entry.
 //  * DPP cross-lane reductions and rotations (no LDS traffic).
-//  * the per-vertex hashtable of Sec. 4.2 / Algorithm 2: capacity
-//    p1 = nextPow2(D) - 1 where nextPow2 is the smallest power of two strictly
-//    above D (so D <= p1), secondary modulus p2 = 2 p1 + 1 (co-prime with p1),
-//    first slot k mod p1, probe step starting at 1 and updated as
+//  * the per-vertex hashtable of Sec. 4.2 / Algorithm 2 with a Mersenne
+//    capacity p1 = 2^m - 1 and secondary modulus p2 = 2 p1 + 1 (co-prime with
+//    p1), first slot k mod p1, probe step starting at 1 and updated as
 //    step <- 2 step + (k mod p2) (hybrid quadratic-double probing).  After
 //    max_retries probes the walk continues linearly, which visits every slot,
-//    so an insert always lands and no weight is ever dropped.
+//    so an insert always lands and no weight is ever dropped.  The capacity
+//    for a row of D entries is the smallest 2^m >= 2D, minus one: the paper
+//    reserves 2D slots per vertex but sizes the table nextPow2(D) - 1, which
+//    runs near full load when every neighbour label is distinct (always the
+//    case in the first iteration); using the reserved 2D keeps the load at or
+//    below one half.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,9 +37,10 @@ __device__ __forceinline__ unsigned long long umax64(unsigned long long a,
   return a > b ? a : b;
 }
 
-// Table capacity for a row of d entries: smallest 2^m > d, minus one.
+// Table capacity for a row of d >= 1 entries: smallest 2^m >= 2d, minus one
+// (so 2d - 1 <= p1 <= 4d - 3: load at most one half).  d <= 2^30.
 __device__ __forceinline__ uint32_t table_p1(uint32_t d) {
-  return (d == 0) ? 0u : ((1u << (32 - __clz(d))) - 1u);
+  return (d <= 1u) ? 1u : ((1u << (32 - __clz(2u * d - 1u))) - 1u);
 }
 
 // ---- DPP -------------------------------------------------------------------

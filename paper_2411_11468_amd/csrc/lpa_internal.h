@@ -20,13 +20,16 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hashtable key
 // Per-iteration device counters.  Reset at the start of every iteration by
 // the hub-plan kernel, read back by the host after the iteration.
 struct DevStats {
-  unsigned long long processed;
-  unsigned long long changed;
-  unsigned long long edges;
-  unsigned long long pending;       // deterministic mode: queued label writes
-  unsigned int active[kNumClasses]; // vertices appended per class this iteration
-  unsigned int hub_items;           // hub slices queued this iteration
-  unsigned int error;               // sticky error bits (validation, labels)
+  unsigned long long processed;                 // vertices taken this iteration
+  unsigned long long pending;                   // deterministic mode: queued hub label writes
+  unsigned long long edges[kNumClasses];        // CSR entries scanned, per class
+  unsigned long long changed[kNumClasses];      // label changes, per class
+  unsigned long long flagw[kNumClasses];        // sum of degrees of changed vertices
+  unsigned long long pull_scanned;              // entries read by the pull-flag kernels
+  unsigned int pull_mode;                       // 1: flags of this iteration pulled
+  unsigned int active[kNumClasses];             // vertices appended per class
+  unsigned int hub_items;                       // hub slices queued this iteration
+  unsigned int error;                           // sticky error bits (validation, labels)
 };
 
 // Everything a sweep kernel needs, passed by value.
@@ -35,10 +38,11 @@ struct SweepArgs {
   const int32_t* tgt;
   const float* w;         // NULL: unit weights
   int32_t* C;             // labels (read; written in place in async mode)
+  int32_t* Cn;            // deterministic mode: label after this iteration,
+                          // written for every processed vertex
   uint8_t* F;             // flags for the next iteration (set on change)
+  uint8_t* chg;           // changed-in-this-iteration byte per vertex
   const int32_t* active;  // active vertex list of this class
-  int32_t* pend_v;        // deterministic mode: queued (vertex, label)
-  int32_t* pend_c;
   DevStats* st;
   int cls;                // class index (selects st->active[cls])
   int pl;                 // Pick-Less on in this iteration
@@ -52,7 +56,8 @@ struct HubArgs {
   const float* w;
   int32_t* C;
   uint8_t* F;
-  int32_t* pend_v;
+  uint8_t* chg;
+  int32_t* pend_v;                 // deterministic mode: queued (hub, label)
   int32_t* pend_c;
   DevStats* st;
   const int32_t* hub_vid;          // H hub vertex ids
@@ -64,6 +69,7 @@ struct HubArgs {
   uint32_t* items;                 // queued slices: (hub index, slice index) word pairs
   int32_t* rec;                    // per slice: recorded global slots
   int32_t* nrec;                   // per slice: number of recorded slots
+  int32_t* hub_nrec;               // per hub: slots recorded by all its slices
   int32_t H;
   int32_t chunk;                   // edges per slice
   int pl;
@@ -92,10 +98,22 @@ hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
 hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
                            hipStream_t s);
 hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
-                           int32_t* const* lists_dev, DevStats* st, int grid,
-                           hipStream_t s);
-hipError_t launch_apply(const DevStats* st, const int32_t* pv, const int32_t* pc,
-                        int32_t* C, int grid, hipStream_t s);
+                           int32_t* const* lists_dev, uint8_t* chg_clear, DevStats* st,
+                           int grid, hipStream_t s);
+hipError_t launch_flag_decide(DevStats* st, int64_t m, int force, hipStream_t s);
+hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
+                             const uint8_t* cls, const uint8_t* chg, uint8_t* F,
+                             DevStats* st, int grid, hipStream_t s);
+hipError_t launch_push_lists(bool off64, const void* off, const int32_t* tgt,
+                             int32_t* const* lists, const uint8_t* chg, uint8_t* F,
+                             DevStats* st, int grid, hipStream_t s);
+hipError_t launch_push_hubs(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_pull_hubs(bool off64, const void* off, const int32_t* tgt,
+                            const int32_t* hub_vid, int32_t H, const uint8_t* chg,
+                            uint8_t* F, DevStats* st, hipStream_t s);
+hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t* Cn,
+                        const int32_t* pv, const int32_t* pc, int32_t* C, int grid,
+                        hipStream_t s);
 hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid,
                         hipStream_t s);
 hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s);

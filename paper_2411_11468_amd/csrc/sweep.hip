@@ -8,11 +8,16 @@
 //   2. takes the label of maximum sum, smallest label on ties,
 //   3. moves if the label differs and, under Pick-Less, is strictly smaller
 //      (Sec. 4.1),
-//   4. on a move, flags every CSR neighbour for the next iteration (Sec. 4
-//      item 4) and counts the change.
-// In asynchronous mode the new label is stored in place before the flags
-// (release fence between them); in deterministic mode it is queued and
-// applied after the sweep, so every vertex reads the iteration-start labels.
+//   4. on a move, records the change (one byte per vertex) and counts it;
+//      the neighbours of changed vertices are flagged for the next iteration
+//      (Sec. 4 item 4) after the sweep, by the flag kernels of graph.hip.
+// In asynchronous mode the new label is stored in place; in deterministic
+// mode it is queued and applied after the sweep, so every vertex reads the
+// iteration-start labels.  Flags are cleared only by the frontier kernel
+// before the sweep and set only after it, so a neighbour that read an old
+// label is always flagged for the next iteration and no fence is needed
+// between a label store and anything else.  (An agent-scope fence would
+// also write back the XCD's L2 on every move.)
 //
 // Classes:
 //   k_sweep_small<G>  G lanes per vertex (G = 4 or 16), one edge per lane,
@@ -48,32 +53,16 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Wave-aggregated append of (v, c) to the deterministic-mode queue for the
-// lanes with pred set.  All lanes of the wave must call it.
-__device__ __forceinline__ void queue_moves(bool pred, int32_t v, uint32_t c,
-                                            const SweepArgs& a) {
-  const unsigned long long mask = __ballot(pred);
-  if (mask == 0ull) return;
-  unsigned long long base = 0;
-  const int leader = __ffsll((long long)mask) - 1;
-  if ((int)(threadIdx.x & 63) == leader)
-    base = atomicAdd(&a.st->pending, (unsigned long long)__popcll(mask));
-  base = ((unsigned long long)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader) << 32) |
-         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
-  if (pred) {
-    const unsigned long long pos = base + lane_rank(mask);
-    a.pend_v[pos] = v;
-    a.pend_c[pos] = (int32_t)c;
-  }
-}
-
 __device__ __forceinline__ void flush_stats(unsigned long long edges, uint32_t changed,
-                                            DevStats* st) {
+                                            unsigned long long flagw, DevStats* st,
+                                            int cls) {
   const unsigned long long e = wave_sum_u64(edges);
   const uint32_t c = wave_sum_u32(changed);
+  const unsigned long long f = wave_sum_u64(flagw);
   if ((threadIdx.x & 63) == 0) {
-    if (e) atomicAdd(&st->edges, e);
-    if (c) atomicAdd(&st->changed, (unsigned long long)c);
+    if (e) atomicAdd(&st->edges[cls], e);
+    if (c) atomicAdd(&st->changed[cls], (unsigned long long)c);
+    if (f) atomicAdd(&st->flagw[cls], f);
   }
 }
 
@@ -109,7 +98,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   constexpr uint32_t kVpw = 64 / G;
   const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-  unsigned long long my_edges = 0;
+  unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0;
   for (uint64_t base = (uint64_t)wave_id * kVpw; base < count;
        base += (uint64_t)nwaves * kVpw) {
@@ -146,19 +135,21 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     const int32_t cur = valid ? a.C[v] : 0;
     const bool moved = valid && decide(best, cur, a.pl, &cstar);
     const bool leader = valid && k == 0;
-    if (a.async_mode) {
-      if (moved && leader) a.C[v] = (int32_t)cstar;
-      if (__any(moved)) __threadfence();
-    } else {
-      queue_moves(moved && leader, v, cstar, a);
+    if (leader) {
+      if (a.async_mode) {
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : cur;
+      }
     }
-    if (moved && has) a.F[j] = 1;
+    if (moved && leader) a.chg[v] = 1;
     if (leader) {
       my_edges += (unsigned long long)d;
       my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
     }
   }
-  flush_stats(my_edges, my_changed, a.st);
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
 }
 
 // ---- one wave per vertex, LDS table per wave -------------------------------
@@ -173,7 +164,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const uint32_t count = a.st->active[a.cls];
-  unsigned long long my_edges = 0;
+  unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0;
   for (uint32_t item = blockIdx.x * WAVES + wv; item < count; item += gridDim.x * WAVES) {
     const int32_t v = a.active[item];
@@ -211,21 +202,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     best = wave_max_u64(best);
     uint32_t cstar = 0;
     const bool moved = decide(best, cur, a.pl, &cstar);
-    if (moved) {
+    if (lane == 0) {
       if (a.async_mode) {
-        if (lane == 0) a.C[v] = (int32_t)cstar;
-        __threadfence();
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : cur;
       }
-      for (int64_t e = lane; e < d; e += 64) a.F[a.tgt[o + e]] = 1;
     }
-    if (!a.async_mode) queue_moves(moved && lane == 0, v, cstar, a);
+    if (moved && lane == 0) a.chg[v] = 1;
     if (lane == 0) {
       my_edges += (unsigned long long)d;
       my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-  flush_stats(my_edges, my_changed, a.st);
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
 }
 
 // ---- one workgroup per vertex, LDS table per workgroup ---------------------
@@ -239,7 +231,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __syncthreads();
   const uint32_t count = a.st->active[a.cls];
-  unsigned long long my_edges = 0;
+  unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0;
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const int32_t v = a.active[item];
@@ -284,27 +276,22 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     for (int q = 1; q < BT / 64; ++q) best = umax64(best, red[q]);
     uint32_t cstar = 0;
     const bool moved = decide(best, cur, a.pl, &cstar);
-    if (moved) {
-      if (tid == 0) {
-        if (a.async_mode) {
-          a.C[v] = (int32_t)cstar;
-        } else {
-          const unsigned long long pos = atomicAdd(&a.st->pending, 1ull);
-          a.pend_v[pos] = v;
-          a.pend_c[pos] = (int32_t)cstar;
-        }
+    if (tid == 0) {
+      if (a.async_mode) {
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : cur;
       }
-      if (a.async_mode) __threadfence();
-      __syncthreads();
-      for (int64_t e = tid; e < d; e += BT) a.F[a.tgt[o + e]] = 1;
     }
+    if (moved && tid == 0) a.chg[v] = 1;
     if (tid == 0) {
       my_edges += (unsigned long long)d;
       my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
     }
     __syncthreads();
   }
-  flush_stats(my_edges, my_changed, a.st);
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
 }
 
 // ---- hubs: slices reduced in LDS, merged in a global table -----------------
@@ -342,16 +329,26 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
     float* gv = a.gvals + a.hub_tab[h];
     int32_t* rec = a.rec + (int64_t)it * a.chunk;
     unsigned long long best = 0;
-    for (uint32_t s = tid; s < p1c; s += BT) {
-      const uint32_t kk = keys[s];
+    // every lane walks the same number of rounds so the wave can vote
+    for (uint32_t s0 = 0; s0 < p1c; s0 += BT) {
+      const uint32_t s = s0 + tid;
+      int32_t slot_out = -1;
+      const uint32_t kk = (s < p1c) ? keys[s] : kEmpty;
       if (kk != kEmpty) {
         float after;
         const uint32_t gs = global_accumulate(gk, gv, p1g, kk, vals[s], a.max_retries, &after);
         best = umax64(best, pack_key(after, kk));
-        const uint32_t r = atomicAdd(&nrec, 1u);
-        rec[r] = (int32_t)gs;
         keys[s] = kEmpty;
         vals[s] = 0.0f;
+        slot_out = (int32_t)gs;
+      }
+      // record the global slots touched by this slice, one LDS atomic per wave
+      const unsigned long long mask = __ballot(slot_out >= 0);
+      if (mask) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&nrec, (uint32_t)__popcll(mask));
+        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+        if (slot_out >= 0) rec[base + lane_rank(mask)] = slot_out;
       }
     }
     best = wave_max_u64(best);
@@ -362,13 +359,14 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
       for (int q = 1; q < BT / 64; ++q) b = umax64(b, red[q]);
       if (b) atomicMax(&a.hub_best[h], b);
       a.nrec[it] = (int32_t)nrec;
+      atomicAdd(&a.hub_nrec[h], (int32_t)nrec);
       nrec = 0;
       my_edges += (unsigned long long)n;
     }
     __syncthreads();
   }
   const unsigned long long e = wave_sum_u64(my_edges);
-  if (tid == 0 && e) atomicAdd(&a.st->edges, e);
+  if (tid == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
 }
 
 template <typename OffT, int BT>
@@ -394,18 +392,31 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
           a.pend_v[pos] = v;
           a.pend_c[pos] = (int32_t)cstar;
         }
-        atomicAdd(&a.st->changed, 1ull);
+        atomicAdd(&a.st->changed[kClassHub], 1ull);
       }
-      for (int64_t e = tid; e < n; e += BT) a.F[a.tgt[o + e0 + e]] = 1;
+      if (tid == 0) atomicAdd(&a.st->flagw[kClassHub], (unsigned long long)n);
+      if (c == 0 && tid == 0) a.chg[v] = 1;
     }
     uint32_t* gk = a.gkeys + a.hub_tab[h];
     float* gv = a.gvals + a.hub_tab[h];
-    const int32_t* rec = a.rec + (int64_t)it * a.chunk;
-    const int32_t nr = a.nrec[it];
-    for (int32_t r = tid; r < nr; r += BT) {
-      const int32_t s = rec[r];
-      gk[s] = kEmpty;
-      gv[s] = 0.0f;
+    const int64_t p1g = table_p1((uint32_t)d);
+    if (4ll * a.hub_nrec[h] >= p1g) {
+      // most of the table was touched: the hub's slices clear it in
+      // contiguous stripes
+      const int64_t ns = (d + a.chunk - 1) / a.chunk;
+      const int64_t s0 = p1g * c / ns, s1 = p1g * (c + 1) / ns;
+      for (int64_t s = s0 + tid; s < s1; s += BT) {
+        gk[s] = kEmpty;
+        gv[s] = 0.0f;
+      }
+    } else {
+      const int32_t* rec = a.rec + (int64_t)it * a.chunk;
+      const int32_t nr = a.nrec[it];
+      for (int32_t r = tid; r < nr; r += BT) {
+        const int32_t s = rec[r];
+        gk[s] = kEmpty;
+        gv[s] = 0.0f;
+      }
     }
   }
 }

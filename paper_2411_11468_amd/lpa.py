@@ -25,6 +25,9 @@ MODE_DETERMINISTIC = 0
 MODE_ASYNC = 1
 INDEX_I32 = 0
 INDEX_I64 = 1
+FLAGS_AUTO = 0
+FLAGS_PUSH = 1
+FLAGS_PULL = 2
 CLASS_NAMES = ("degree0", "small4", "small16", "wave", "block", "hub")
 
 
@@ -52,7 +55,14 @@ class lpa_tuning(ctypes.Structure):
 class lpa_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
                 ("tolerance", ctypes.c_double), ("pl_period", ctypes.c_int32),
-                ("prune", ctypes.c_int32), ("initial_labels", ctypes.c_void_p)]
+                ("prune", ctypes.c_int32), ("initial_labels", ctypes.c_void_p),
+                ("profile", ctypes.c_int32), ("flag_mode", ctypes.c_int32)]
+
+
+class lpa_kernel_profile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("edges", ctypes.c_int64), ("vertices", ctypes.c_int64)]
 
 
 class lpa_iter_stats(ctypes.Structure):
@@ -63,8 +73,8 @@ class lpa_iter_stats(ctypes.Structure):
 
 
 EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run",
-            "lpa_modularity", "lpa_graph_classes", "lpa_get_flags", "lpa_destroy",
-            "lpa_status_string", "lpa_last_error")
+            "lpa_modularity", "lpa_graph_classes", "lpa_get_flags", "lpa_profile",
+            "lpa_profile_reset", "lpa_destroy", "lpa_status_string", "lpa_last_error")
 
 _lib = None
 
@@ -96,6 +106,11 @@ def load_library(path: str = LIB_PATH):
     lib.lpa_graph_classes.restype = ctypes.c_int
     lib.lpa_get_flags.argtypes = [vp, vp]
     lib.lpa_get_flags.restype = ctypes.c_int
+    lib.lpa_profile.argtypes = [vp, ctypes.POINTER(lpa_kernel_profile), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int32)]
+    lib.lpa_profile.restype = ctypes.c_int
+    lib.lpa_profile_reset.argtypes = [vp]
+    lib.lpa_profile_reset.restype = ctypes.c_int
     lib.lpa_destroy.argtypes = [vp]
     lib.lpa_destroy.restype = None
     lib.lpa_status_string.argtypes = [ctypes.c_int]
@@ -185,7 +200,7 @@ def lpa_create(offsets, targets, weights=None, *, validate: bool = True,
 
 def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
             max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
-            initial_labels=None):
+            initial_labels=None, profile: bool = False, flag_mode: int = FLAGS_AUTO):
     """Run to termination; labels is a preallocated int32 torch tensor or numpy
     array of N entries.  Returns (iterations, list of stats dicts)."""
     lib = load_library()
@@ -196,6 +211,8 @@ def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
     o.pl_period = int(pl_period)
     o.prune = int(bool(prune))
     o.initial_labels = _addr(initial_labels)
+    o.profile = int(bool(profile))
+    o.flag_mode = int(flag_mode)
     cap = max(int(max_iterations), 1)
     st = (lpa_iter_stats * cap)()
     it = ctypes.c_int32(0)
@@ -216,6 +233,22 @@ def lpa_graph_classes(handle) -> dict:
     c = (ctypes.c_int64 * 6)()
     _check(load_library().lpa_graph_classes(handle, c))
     return dict(zip(CLASS_NAMES, list(c)))
+
+
+def lpa_profile(handle) -> list:
+    """Accumulated per-kernel records of the runs made with profile=True."""
+    lib = load_library()
+    cap = 32
+    arr = (lpa_kernel_profile * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(lib.lpa_profile(handle, arr, cap, ctypes.byref(cnt)))
+    return [dict(name=r.name.decode(), launches=r.launches, total_ms=r.total_ms,
+                 bytes=r.bytes, edges=r.edges, vertices=r.vertices)
+            for r in arr[:min(cnt.value, cap)]]
+
+
+def lpa_profile_reset(handle) -> None:
+    _check(load_library().lpa_profile_reset(handle))
 
 
 def lpa_get_flags(handle, out) -> None:
@@ -269,6 +302,12 @@ class LpaGraph:
 
     def classes(self) -> dict:
         return lpa_graph_classes(self.handle)
+
+    def profile(self) -> list:
+        return lpa_profile(self.handle)
+
+    def profile_reset(self) -> None:
+        lpa_profile_reset(self.handle)
 
     def flags(self) -> np.ndarray:
         out = np.empty(self.num_vertices, dtype=np.uint8)

@@ -46,12 +46,13 @@ def _tuning(**kw):
 SMALL_TUNING = dict(small4=2, small16=8, wave=40, block=100, hub_chunk=64)
 
 
-def assert_det_parity(g, tuning=None, on_device=True, weights=True, initial=None, **kw):
+def assert_det_parity(g, tuning=None, on_device=True, weights=True, initial=None,
+                      flag_mode=lpa.FLAGS_AUTO, **kw):
     ref = oracle.lpa_sync(g.offsets, g.targets, g.weights if weights else None,
                           initial_labels=initial, **kw)
     G = _graph_on_gpu(g, tuning, on_device, weights)
     init = None if initial is None else (_dev(initial) if on_device else initial)
-    res = G.run("det", initial_labels=init, **kw)
+    res = G.run("det", initial_labels=init, flag_mode=flag_mode, **kw)
     labels = res.labels.cpu().numpy() if on_device else res.labels
     assert res.iterations == ref.iterations
     for s_gpu, s_ref in zip(res.stats, ref.stats):
@@ -149,6 +150,18 @@ def test_det_options():
     assert_det_parity(g, tuning=t, initial=init, on_device=False)
 
 
+@pytest.mark.parametrize("flag_mode", [lpa.FLAGS_PUSH, lpa.FLAGS_PULL])
+def test_det_flag_modes(flag_mode):
+    # neighbour flags pushed by changed vertices or pulled by every vertex:
+    # the same flags, hence the same run, on a symmetric graph
+    assert_det_parity(graphgen.planted_partition_10k(1), flag_mode=flag_mode)
+    assert_det_parity(graphgen.rmat_graph(14, 3, "int8"), flag_mode=flag_mode)
+    assert_det_parity(graphgen.rmat_graph(12, 6, "int8"), tuning=_tuning(**SMALL_TUNING),
+                      flag_mode=flag_mode)
+    assert_det_parity(graphgen.from_edges(5, [(0, 1), (1, 1), (2, 3)]), flag_mode=flag_mode,
+                      pl_period=0)
+
+
 def test_edge_cases():
     # empty graph
     G = lpa.LpaGraph(_dev(np.zeros(1, np.int32)), _dev(np.zeros(0, np.int32)))
@@ -185,8 +198,8 @@ def test_modularity_matches_oracle():
 
 def _async_invariant(g, tuning=None, seed_runs=2):
     G = _graph_on_gpu(g, tuning)
-    for _ in range(seed_runs):
-        res = G.run("async", pl_period=0)
+    for r in range(seed_runs):
+        res = G.run("async", pl_period=0, flag_mode=(lpa.FLAGS_PUSH, lpa.FLAGS_PULL)[r % 2])
         lab = res.labels.cpu().numpy()
         flags = G.flags().astype(bool)
         ok = oracle.local_optimal(g.offsets, g.targets, g.weights, lab)
@@ -198,7 +211,7 @@ def _async_invariant(g, tuning=None, seed_runs=2):
 
 
 def test_async_local_optimality_invariant():
-    _async_invariant(graphgen.planted_partition_10k(1))
+    _async_invariant(graphgen.planted_partition_10k(1), seed_runs=4)
     _async_invariant(graphgen.rmat_graph(14, 5, "int8"))
     _async_invariant(graphgen.rmat_graph(12, 6, "int8"), _tuning(**SMALL_TUNING))
 
