@@ -107,6 +107,9 @@ typedef struct lpa_graph_s* lpa_graph;
  * Every hashtable holding D keys has 2^m - 1 >= 2D - 1 slots (load <= 1/2).
  * hub_chunk: edges per workgroup slice for the largest rows (default 8192).
  * max_retries: hybrid probes before the linear continuation (default 32).
+ * xcd_local: 1 = merge each hub's slices on one XCD with its table atomics
+ *   in that XCD's L2, any slice left over merged afterwards with device-wide
+ *   atomics; 0 = device-wide atomics only (default 1; same results).
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -115,7 +118,8 @@ typedef struct lpa_tuning {
   int32_t block;
   int32_t hub_chunk;
   int32_t max_retries;
-  int32_t reserved[2];
+  int32_t xcd_local;
+  int32_t reserved;
 } lpa_tuning;
 
 /*

@@ -21,12 +21,13 @@ namespace {
 // kernel ids of the optional profile
 constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubAcc = 2, kKidSweep0 = 2,
               kKidHubFin = 11, kKidApply = 12, kKidPull = 13, kKidPullHubs = 14,
-              kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kNumKids = 18;
+              kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kKidHubRest = 18,
+              kNumKids = 19;
 const char* const kKidNames[kNumKids] = {
     "hub_plan", "frontier", "hub_acc", "sweep_small4", "sweep_small16", "sweep_wave127",
     "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
     "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
-    "push_hubs", "flag_decide"};
+    "push_hubs", "flag_decide", "hub_acc_rest"};
 
 thread_local std::string g_err;
 
@@ -88,6 +89,9 @@ struct lpa_graph_s {
   int32_t* rec = nullptr;
   int32_t* nrec = nullptr;
   int32_t* hub_nrec = nullptr;
+  int32_t* hub_xcd = nullptr;
+  int32_t* hub_nch = nullptr;
+  int32_t* done = nullptr;
   int64_t max_items = 0;
   double* mod_sig = nullptr;
   double* mod_acc = nullptr;
@@ -192,7 +196,7 @@ struct lpa_graph_s {
     a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
     a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
     a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.rec = rec; a.nrec = nrec;
-    a.hub_nrec = hub_nrec;
+    a.hub_nrec = hub_nrec; a.hub_xcd = hub_xcd; a.hub_nch = hub_nch; a.done = done;
     a.H = H; a.chunk = tun.hub_chunk; a.pl = pl; a.async_mode = async_mode;
     a.max_retries = tun.max_retries;
     return a;
@@ -231,6 +235,7 @@ void lpa_tuning_default(lpa_tuning* t) {
   t->block = 8192;
   t->hub_chunk = 8192;
   t->max_retries = 32;
+  t->xcd_local = 1;
 }
 
 const char* lpa_status_string(lpa_status s) {
@@ -396,6 +401,23 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->max_items = items;
     if (lpa_status e = G->dalloc(&G->hub_tab, G->H)) return e;
     LPA_HIP(hipMemcpyAsync(G->hub_tab, tab.data(), sizeof(int64_t) * G->H, hipMemcpyHostToDevice, s));
+    // each hub's table lives in one XCD's L2: longest-processing-time-first
+    // assignment of hubs to XCDs by degree
+    std::vector<int32_t> order(G->H), xcd(G->H);
+    for (int32_t h = 0; h < G->H; ++h) order[h] = h;
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return hd[x] > hd[y]; });
+    int64_t load[kXcds] = {0};
+    for (int32_t h : order) {
+      int best = 0;
+      for (int q = 1; q < kXcds; ++q)
+        if (load[q] < load[best]) best = q;
+      xcd[h] = best;
+      load[best] += hd[h];
+    }
+    if (lpa_status e = G->dalloc(&G->hub_xcd, G->H)) return e;
+    LPA_HIP(hipMemcpyAsync(G->hub_xcd, xcd.data(), sizeof(int32_t) * G->H, hipMemcpyHostToDevice, s));
+    if (lpa_status e = G->dalloc(&G->hub_nch, G->H)) return e;
+    if (lpa_status e = G->dalloc(&G->done, items)) return e;
     if (lpa_status e = G->dalloc(&G->hub_best, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->hub_old, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->hub_nrec, G->H)) return e;
@@ -406,7 +428,9 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     if (lpa_status e = G->dalloc(&G->items, 2 * items)) return e;
     if (lpa_status e = G->dalloc(&G->rec, items * (int64_t)t.hub_chunk)) return e;
     if (lpa_status e = G->dalloc(&G->nrec, items)) return e;
-    G->hub_acc_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, hub_max_resident()));
+    // one resident workgroup per CU: every XCD gets workgroups to drain its
+    // segment (the fallback pass covers any segment left undone)
+    G->hub_acc_grid = hub_max_resident();
     G->hub_fin_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, 256 * 8));
     LPA_HIP(hipStreamSynchronize(s));
   }
@@ -525,8 +549,12 @@ lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
     if (lpa_status e = mark(kKidFrontier)) return e;
     LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
     if (g->H > 0) {
-      if (lpa_status e = mark(kKidHubAcc)) return e;
-      LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
+      if (g->tun.xcd_local) {
+        if (lpa_status e = mark(kKidHubAcc)) return e;
+        LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
+      }
+      if (lpa_status e = mark(kKidHubRest)) return e;
+      LPA_HIP(launch_hub_acc_rest(g->off64, ha, g->hub_fin_grid, s));
     }
     SweepArgs a;
     a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;

@@ -169,7 +169,9 @@ hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s) {
 }
 
 // ---- hub plan: reset the iteration counters, take the flagged hubs, queue
-// their slices.  One workgroup of 1024 threads. ----------------------------------
+// their slices grouped by the XCD each hub is assigned to (segment x of the
+// slice list holds the slices of XCD x's hubs).  One workgroup of 1024
+// threads. ------------------------------------------------------------------------
 template <typename OffT>
 __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_t* F) {
   __shared__ uint32_t scan[1024];
@@ -179,51 +181,62 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
   DevStats* st = a.st;
   if (tid == 0) {
     st->processed = 0; st->pending = 0;
+    st->pull_scanned = 0; st->pull_mode = 0;
     running = 0; nproc = 0;
   }
-  if (tid == 0) { st->pull_scanned = 0; st->pull_mode = 0; }
   if (tid < kNumClasses) {
     st->active[tid] = 0;
     st->edges[tid] = 0;
     st->changed[tid] = 0;
     st->flagw[tid] = 0;
   }
+  if (tid < kXcds) st->hub_head[tid] = 0;
   __syncthreads();
   const OffT* off = reinterpret_cast<const OffT*>(a.off);
-  for (int32_t tile = 0; tile < a.H; tile += 1024) {
-    const int32_t h = tile + tid;
-    uint32_t nch = 0;
-    if (h < a.H) {
-      const int32_t v = a.hub_vid[h];
-      a.hub_best[h] = 0ull;
-      a.hub_nrec[h] = 0;
-      if (F[v]) {
-        F[v] = 0;
-        a.hub_old[h] = C[v];
-        const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
-        nch = (uint32_t)((d + a.chunk - 1) / a.chunk);
-        atomicAdd(&nproc, 1u);
+  // take the flagged hubs
+  for (int32_t h = tid; h < a.H; h += 1024) {
+    const int32_t v = a.hub_vid[h];
+    a.hub_best[h] = 0ull;
+    a.hub_nrec[h] = 0;
+    int32_t nch = 0;
+    if (F[v]) {
+      F[v] = 0;
+      a.hub_old[h] = C[v];
+      const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+      nch = (int32_t)((d + a.chunk - 1) / a.chunk);
+      atomicAdd(&nproc, 1u);
+    }
+    a.hub_nch[h] = nch;
+  }
+  __syncthreads();
+  // queue the slices, XCD by XCD
+  for (int x = 0; x < kXcds; ++x) {
+    if (tid == 0) st->hub_seg[x] = running;
+    for (int32_t tile = 0; tile < a.H; tile += 1024) {
+      const int32_t h = tile + tid;
+      const uint32_t nch = (h < a.H && a.hub_xcd[h] == x) ? (uint32_t)a.hub_nch[h] : 0u;
+      // inclusive Hillis-Steele scan of nch over the workgroup
+      scan[tid] = nch;
+      __syncthreads();
+      for (int ofs = 1; ofs < 1024; ofs <<= 1) {
+        const uint32_t add = tid >= ofs ? scan[tid - ofs] : 0u;
+        __syncthreads();
+        scan[tid] += add;
+        __syncthreads();
       }
-    }
-    // inclusive Hillis-Steele scan of nch over the workgroup
-    scan[tid] = nch;
-    __syncthreads();
-    for (int ofs = 1; ofs < 1024; ofs <<= 1) {
-      const uint32_t add = tid >= ofs ? scan[tid - ofs] : 0u;
+      const uint32_t first = running + scan[tid] - nch;
+      for (uint32_t c = 0; c < nch; ++c) {
+        a.items[2 * (uint64_t)(first + c)] = (uint32_t)h;
+        a.items[2 * (uint64_t)(first + c) + 1] = c;
+        a.done[first + c] = 0;
+      }
       __syncthreads();
-      scan[tid] += add;
+      if (tid == 0) running += scan[1023];
       __syncthreads();
     }
-    const uint32_t first = running + scan[tid] - nch;
-    for (uint32_t c = 0; c < nch; ++c) {
-      a.items[2 * (uint64_t)(first + c)] = (uint32_t)h;
-      a.items[2 * (uint64_t)(first + c) + 1] = c;
-    }
-    __syncthreads();
-    if (tid == 0) running += scan[1023];
-    __syncthreads();
   }
   if (tid == 0) {
+    st->hub_seg[kXcds] = running;
     st->hub_items = running;
     st->processed = nproc;
   }

@@ -144,7 +144,10 @@ __device__ __forceinline__ void lds_accumulate(uint32_t* keys, float* vals, uint
 
 // Accumulate (k, v) into a global-memory table; returns the slot and the
 // value the slot holds after this add (values only grow, so the largest value
-// ever returned for a key is its final sum).
+// ever returned for a key is its final sum).  SCOPE is the atomics' memory
+// scope: agent when workgroups on several XCDs share the table, workgroup when
+// every access comes from one XCD (the atomics then resolve in its L2).
+template <int SCOPE>
 __device__ __forceinline__ uint32_t global_accumulate(uint32_t* keys, float* vals,
                                                       uint32_t p1, uint32_t k, float v,
                                                       int max_retries, float* after) {
@@ -153,21 +156,27 @@ __device__ __forceinline__ uint32_t global_accumulate(uint32_t* keys, float* val
   uint32_t step = 1u % p1;
   const uint32_t r = (k % p2) % p1;
   for (int t = 0;; ++t) {
-    uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, SCOPE);
     if (cur == kEmpty) {
       uint32_t expected = kEmpty;
       __hip_atomic_compare_exchange_strong(&keys[s], &expected, k, __ATOMIC_RELAXED,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                           __ATOMIC_RELAXED, SCOPE);
       cur = (expected == kEmpty) ? k : expected;
     }
     if (cur == k) {
-      const float old = __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+      const float old = __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED, SCOPE);
       *after = old + v;
       return s;
     }
     probe_next(s, step, r, p1, t, max_retries);
   }
+}
+
+// Index of the accelerator complex die (XCD) this wave runs on.
+__device__ __forceinline__ uint32_t xcc_id() {
+  uint32_t x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & (uint32_t)(kXcds - 1);
 }
 
 template <typename OffT>

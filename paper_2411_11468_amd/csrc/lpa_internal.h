@@ -16,6 +16,7 @@ namespace lpa {
 constexpr int kNumClasses = 10;
 constexpr int kClassHub = 9;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hashtable key
+constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
 
 // Per-iteration device counters.  Reset at the start of every iteration by
 // the hub-plan kernel, read back by the host after the iteration.
@@ -29,6 +30,8 @@ struct DevStats {
   unsigned int pull_mode;                       // 1: flags of this iteration pulled
   unsigned int active[kNumClasses];             // vertices appended per class
   unsigned int hub_items;                       // hub slices queued this iteration
+  unsigned int hub_seg[kXcds + 1];              // slice list segment of each XCD
+  unsigned int hub_head[kXcds];                 // next slice of each segment
   unsigned int error;                           // sticky error bits (validation, labels)
 };
 
@@ -70,6 +73,9 @@ struct HubArgs {
   int32_t* rec;                    // per slice: recorded global slots
   int32_t* nrec;                   // per slice: number of recorded slots
   int32_t* hub_nrec;               // per hub: slots recorded by all its slices
+  const int32_t* hub_xcd;          // per hub: XCD whose L2 holds its table
+  int32_t* hub_nch;                // per hub: slices queued this iteration
+  int32_t* done;                   // per slice: merged by the XCD-local pass
   int32_t H;
   int32_t chunk;                   // edges per slice
   int pl;
@@ -117,6 +123,7 @@ hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t
 hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid,
                         hipStream_t s);
 hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_hub_acc_rest(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_fin(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt,
                              const float* w, int64_t n, int64_t m,

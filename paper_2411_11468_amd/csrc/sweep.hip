@@ -295,20 +295,41 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
 }
 
 // ---- hubs: slices reduced in LDS, merged in a global table -----------------
-template <typename OffT, int SLOTS, int BT>
+// LOCAL: the XCD-local pass.  Each workgroup reads the XCD it runs on and
+// takes only slices of hubs assigned to that XCD, so every access to a hub's
+// table comes from one XCD and the table atomics run at workgroup scope in
+// that XCD's L2.  Merged slices are marked done.  !LOCAL: the fallback pass
+// after it (a kernel boundary writes the L2s back) merges any slice left
+// undone with agent-scope atomics; it normally finds none.
+template <typename OffT, int SLOTS, int BT, bool LOCAL>
 __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
   __shared__ uint32_t keys[SLOTS];
   __shared__ float vals[SLOTS];
   __shared__ unsigned long long red[BT / 64];
   __shared__ uint32_t nrec;
+  __shared__ uint32_t next;
+  constexpr int kScope = LOCAL ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
   if (tid == 0) nrec = 0;
   __syncthreads();
-  const uint32_t nitems = a.st->hub_items;
+  const uint32_t x = LOCAL ? xcc_id() : 0u;
+  const uint32_t seg0 = a.st->hub_seg[x];
+  const uint32_t seg_n = LOCAL ? a.st->hub_seg[x + 1] - seg0 : a.st->hub_items;
   unsigned long long my_edges = 0;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  uint32_t k = blockIdx.x;
+  for (;;) {
+    if (LOCAL) {
+      if (tid == 0) next = atomicAdd(&a.st->hub_head[x], 1u);
+      __syncthreads();
+      k = next;
+      __syncthreads();
+    }
+    if (k >= seg_n) break;
+    const uint32_t it = LOCAL ? seg0 + k : k;
+    if (!LOCAL) k += gridDim.x;
+    if (!LOCAL && a.done[it]) continue;
     const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
     const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
     const int32_t v = a.hub_vid[h];
@@ -336,7 +357,8 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
       const uint32_t kk = (s < p1c) ? keys[s] : kEmpty;
       if (kk != kEmpty) {
         float after;
-        const uint32_t gs = global_accumulate(gk, gv, p1g, kk, vals[s], a.max_retries, &after);
+        const uint32_t gs =
+            global_accumulate<kScope>(gk, gv, p1g, kk, vals[s], a.max_retries, &after);
         best = umax64(best, pack_key(after, kk));
         keys[s] = kEmpty;
         vals[s] = 0.0f;
@@ -360,6 +382,7 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
       if (b) atomicMax(&a.hub_best[h], b);
       a.nrec[it] = (int32_t)nrec;
       atomicAdd(&a.hub_nrec[h], (int32_t)nrec);
+      if (LOCAL) a.done[it] = 1;
       nrec = 0;
       my_edges += (unsigned long long)n;
     }
@@ -487,9 +510,18 @@ hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, hipSt
 hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s) {
   if (a.chunk > (kHubSlots + 1) / 2) return hipErrorInvalidValue;
   if (off64)
-    hipLaunchKernelGGL((k_hub_acc<int64_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
+    hipLaunchKernelGGL((k_hub_acc<int64_t, kHubSlots, kHubThreads, true>), dim3(grid), dim3(kHubThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((k_hub_acc<int32_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
+    hipLaunchKernelGGL((k_hub_acc<int32_t, kHubSlots, kHubThreads, true>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hub_acc_rest(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+  if (a.chunk > (kHubSlots + 1) / 2) return hipErrorInvalidValue;
+  if (off64)
+    hipLaunchKernelGGL((k_hub_acc<int64_t, kHubSlots, kHubThreads, false>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hub_acc<int32_t, kHubSlots, kHubThreads, false>), dim3(grid), dim3(kHubThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -115,6 +115,16 @@ def test_det_every_class_small_thresholds():
     assert_det_parity(r, tuning=t)
 
 
+@pytest.mark.parametrize("xcd_local", [0, 1])
+def test_det_hub_merge_paths(xcd_local):
+    # hub slices merged on one XCD with L2-local atomics, or device-wide only
+    t = _tuning(**SMALL_TUNING, xcd_local=xcd_local)
+    assert_det_parity(graphgen.random_graph(1500, 0.25, seed=5, wmax=8), tuning=t)
+    assert_det_parity(graphgen.rmat_graph(13, 8, "int8"), tuning=t)
+    t2 = _tuning(block=1024, hub_chunk=256, xcd_local=xcd_local)
+    assert_det_parity(graphgen.rmat_graph(16, 16, "int8"), tuning=t2)
+
+
 def test_det_rmat_default_tuning():
     g = graphgen.rmat_graph(15, 15, "int8")
     G = _graph_on_gpu(g)
