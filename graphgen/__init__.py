@@ -55,6 +55,10 @@ def _load():
         lib.gg_pair_weights.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_uint64,
                                         ctypes.c_int32, vp]
         lib.gg_fill_f32.argtypes = [ctypes.c_int64, ctypes.c_float, vp]
+        lib.gg_sbm_batch.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_int32, vp, ctypes.POINTER(_GG)]
         lib.gg_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -229,6 +233,44 @@ def complete_bipartite(n: int) -> Graph:
     return from_edges(2 * n, [(x, n + y) for x in range(n) for y in range(n)])
 
 
+def planted_partition_batch(num_graphs: int, seed: int, n_range=(256, 65536),
+                            d_range=(8.0, 32.0), mu_range=(0.1, 0.4),
+                            block_range=(32, 256)) -> tuple[Graph, np.ndarray]:
+    """num_graphs planted-partition graphs packed into one CSR (int64
+    offsets, global target ids, unit weights) and their vertex offsets
+    v_off (num_graphs + 1).  Per graph: vertex count log-uniform in n_range,
+    expected degree uniform in d_range, mixing uniform in mu_range, block
+    sizes uniform in block_range."""
+    v_off = np.zeros(num_graphs + 1, dtype=np.int64)
+    gg = _GG()
+    rc = _load().gg_sbm_batch(int(num_graphs), int(seed), float(n_range[0]), float(n_range[1]),
+                              float(d_range[0]), float(d_range[1]), float(mu_range[0]),
+                              float(mu_range[1]), int(block_range[0]), int(block_range[1]),
+                              _ptr(v_off), ctypes.byref(gg))
+    if rc != 0:
+        raise RuntimeError(f"gg_sbm_batch failed ({rc})")
+    off, tgt = _take(gg, np.int64)
+    return Graph(off, tgt, unit_weights(tgt.shape[0]), f"batch{num_graphs}"), v_off
+
+
+def pack_graphs(graphs) -> tuple[Graph, np.ndarray]:
+    """Concatenate graphs into one CSR with global target ids (int64
+    offsets); returns the packed graph and v_off."""
+    v_off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    offs, tgts, ws = [np.zeros(1, dtype=np.int64)], [], []
+    e0 = 0
+    for q, g in enumerate(graphs):
+        v_off[q + 1] = v_off[q] + g.num_vertices
+        o = g.offsets.astype(np.int64)
+        offs.append(o[1:] + e0)
+        tgts.append(g.targets.astype(np.int64) + v_off[q])
+        ws.append(g.weights if g.weights is not None else np.ones(g.num_edges, np.float32))
+        e0 += g.num_edges
+    tgt = np.concatenate(tgts).astype(np.int32) if tgts else np.zeros(0, np.int32)
+    w = np.concatenate(ws).astype(np.float32) if ws else np.zeros(0, np.float32)
+    return Graph(np.concatenate(offs), tgt, w, "packed"), v_off
+
+
 def max_threads() -> int:
     return int(_load().gg_max_threads())
 
@@ -236,4 +278,4 @@ def max_threads() -> int:
 __all__ = ["Graph", "build", "sbm", "rmat", "pair_weights", "unit_weights",
            "planted_partition_10k", "rmat_graph", "random_graph", "from_edges",
            "ring_of_cliques", "disjoint_cliques", "complete_bipartite",
-           "philox4x32_10", "max_threads"]
+           "philox4x32_10", "max_threads", "planted_partition_batch", "pack_graphs"]

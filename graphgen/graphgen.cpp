@@ -366,6 +366,95 @@ int gg_rmat(int32_t scale, int64_t edge_factor, double a, double b, double c,
   return 0;
 }
 
+// Many independent planted-partition graphs packed into one CSR.  Graph q
+// draws (Philox counter (q, k, 0, tag)) its vertex count n log-uniformly in
+// [nmin, nmax], its expected degree d uniformly in [dmin, dmax], its mixing
+// mu uniformly in [mumin, mumax], and block sizes uniformly in [bmin, bmax]
+// until they cover n (the last block takes the remainder).  Pairs inside a
+// block of size b are edges with probability (1 - mu) d / (b - 1), pairs
+// across blocks with probability mu d / (n - n/blocks).  Graph q occupies
+// global vertices v_off[q] .. v_off[q+1]-1; targets are global ids.
+int gg_sbm_batch(int32_t G, uint64_t seed, double nmin, double nmax, double dmin,
+                 double dmax, double mumin, double mumax, int32_t bmin, int32_t bmax,
+                 int64_t* v_off, gg_graph* out) {
+  memset(out, 0, sizeof(*out));
+  if (G <= 0 || nmin < 1 || nmax < nmin || bmin < 1 || bmax < bmin) return -1;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x42544348u;
+  std::vector<int64_t> n(G);
+  std::vector<double> d(G), mu(G);
+  std::vector<std::vector<int64_t>> blocks(G);
+  for (int32_t q = 0; q < G; ++q) {
+    const P4 x = philox((uint32_t)q, 0u, 0u, 0x50415241u, k0, k1);
+    const P4 y = philox((uint32_t)q, 1u, 0u, 0x50415241u, k0, k1);
+    const double ln = std::log(nmin) + u01(x.v[0], x.v[1]) * (std::log(nmax) - std::log(nmin));
+    n[q] = std::min<int64_t>((int64_t)nmax, std::max<int64_t>((int64_t)nmin, (int64_t)std::floor(std::exp(ln))));
+    d[q] = dmin + u01(x.v[2], x.v[3]) * (dmax - dmin);
+    mu[q] = mumin + u01(y.v[0], y.v[1]) * (mumax - mumin);
+    int64_t cov = 0;
+    for (uint32_t k = 2; cov < n[q]; ++k) {
+      const P4 z = philox((uint32_t)q, k, 0u, 0x424C4B53u, k0, k1);
+      int64_t b = bmin + (int64_t)(u01(z.v[0], z.v[1]) * (double)(bmax - bmin + 1));
+      if (b > bmax) b = bmax;
+      if (cov + b > n[q]) b = n[q] - cov;
+      blocks[q].push_back(b);
+      cov += b;
+    }
+  }
+  v_off[0] = 0;
+  for (int32_t q = 0; q < G; ++q) v_off[q + 1] = v_off[q] + n[q];
+  if (v_off[G] > INT32_MAX) return -1;
+  std::vector<Csr> part(G);
+  std::vector<int32_t> order(G);
+  for (int32_t q = 0; q < G; ++q) order[q] = q;
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
+  bool ok = true;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t oi = 0; oi < G; ++oi) {
+    const int32_t q = order[oi];
+    const std::vector<int64_t>& bs = blocks[q];
+    const int32_t nb = (int32_t)bs.size();
+    std::vector<int64_t> start(nb + 1, 0);
+    for (int32_t b = 0; b < nb; ++b) start[b + 1] = start[b] + bs[b];
+    const double mean_b = (double)n[q] / nb;
+    const double p_out = (n[q] - mean_b > 0.0) ? std::min(1.0, mu[q] * d[q] / ((double)n[q] - mean_b)) : 0.0;
+    std::vector<Pair> pairs;
+    for (int32_t a = 0; a < nb; ++a) {
+      const double p_in = bs[a] > 1 ? std::min(1.0, (1.0 - mu[q]) * d[q] / (double)(bs[a] - 1)) : 0.0;
+      sbm_region(start[a], bs[a], start[a], bs[a], true, p_in, (uint32_t)a, (uint32_t)q, k0, k1,
+                 &pairs);
+      for (int32_t b = a + 1; b < nb; ++b)
+        sbm_region(start[a], bs[a], start[b], bs[b], false, p_out,
+                   (uint32_t)(nb + (int64_t)a * nb + b), (uint32_t)q, k0, k1, &pairs);
+    }
+    if (!csr_from_pairs(n[q], pairs, &part[q])) ok = false;
+  }
+  if (!ok) {
+    for (Csr& c : part) { free(c.off); free(c.tgt); }
+    return -2;
+  }
+  const int64_t N = v_off[G];
+  std::vector<int64_t> e_off(G + 1, 0);
+  for (int32_t q = 0; q < G; ++q) e_off[q + 1] = e_off[q] + part[q].m;
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N + 1));
+  int32_t* tgt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(e_off[G] > 0 ? e_off[G] : 1));
+  if (!off || !tgt) {
+    free(off); free(tgt);
+    for (Csr& c : part) { free(c.off); free(c.tgt); }
+    return -2;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t q = 0; q < G; ++q) {
+    const Csr& c = part[q];
+    for (int64_t i = 0; i < c.n; ++i) off[v_off[q] + i] = e_off[q] + c.off[i];
+    const int32_t base = (int32_t)v_off[q];
+    for (int64_t e = 0; e < c.m; ++e) tgt[e_off[q] + e] = c.tgt[e] + base;
+  }
+  off[N] = e_off[G];
+  for (Csr& c : part) { free(c.off); free(c.tgt); }
+  out->n = N; out->m = e_off[G]; out->off = off; out->tgt = tgt;
+  return 0;
+}
+
 // Symmetric integer weights: w(u,v) = 1 + (h(min(u,v), max(u,v)) mod wmax)
 // where h is the first Philox word of counter (min, max) under the seed.
 void gg_pair_weights(int64_t n, const int64_t* off, const int32_t* tgt,

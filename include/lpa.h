@@ -136,6 +136,7 @@ typedef struct lpa_tuning {
  *   profile         1: bracket every kernel launch with HIP events and add its
  *                   duration and algorithmic bytes to the per-kernel profile
  *                   read by lpa_profile (default 0)
+ *   launch          lpa_launch (default LPA_LAUNCH_EAGER)
  *   flag_mode       how the neighbours of the vertices changed in an
  *                   iteration are flagged after its sweep (the flags are
  *                   identical on a symmetric graph):
@@ -154,6 +155,16 @@ typedef enum lpa_flag_mode {
   LPA_FLAGS_PULL = 2
 } lpa_flag_mode;
 
+typedef enum lpa_launch {
+  /* one host round trip per iteration: per-iteration GPU time in the stats,
+   * per-kernel profile available */
+  LPA_LAUNCH_EAGER = 0,
+  /* one iteration captured once as a HIP graph and replayed max_iterations
+   * times without host round trips; the kernels of iterations after the stop
+   * return at once; stats carry no per-iteration time; profile ignored */
+  LPA_LAUNCH_GRAPH = 1
+} lpa_launch;
+
 typedef struct lpa_options {
   int32_t mode;
   int32_t max_iterations;
@@ -163,6 +174,8 @@ typedef struct lpa_options {
   const int32_t* initial_labels;
   int32_t profile;
   int32_t flag_mode;
+  int32_t launch;
+  int32_t reserved;
 } lpa_options;
 
 /* Statistics of one iteration. */
@@ -224,6 +237,34 @@ lpa_status lpa_create(const lpa_csr* g, void* stream, const lpa_tuning* tuning,
 lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
                    lpa_iter_stats* stats, int32_t stats_cap,
                    int32_t* iters_done);
+
+/*
+ * Batched label propagation over many independent graphs packed into one CSR.
+ * Graph q owns vertices v_off[q] .. v_off[q+1]-1 (v_off: num_graphs + 1 host
+ * int64, from 0 to csr->num_vertices); every CSR entry of a row of graph q
+ * must point into graph q (checked when csr->validate = 1).  Vertex ids and
+ * labels are global: a graph's initial labels are its global vertex ids, so
+ * ties among them order as in a solo run of the graph.
+ * lpa_run_batched runs Algorithm 1 on every graph at once with one iteration
+ * counter: each graph stops after its own first iteration that is not
+ * Pick-Less and in which fewer than tolerance * (its vertex count) of its
+ * vertices changed, or at the cap; a stopped graph's vertices are no longer
+ * processed.  The result for each graph equals a solo lpa_run of that graph
+ * (exactly in deterministic mode), labels offset by v_off[q].
+ *   labels                  N int32, host or device
+ *   iters_per_graph         num_graphs host int32 (may be NULL): iterations
+ *                           graph q performed
+ *   changed_last_per_graph  num_graphs host int64 (may be NULL): vertices of
+ *                           graph q changed in its last iteration
+ *   iters_done              host int32 (may be NULL): iterations of the batch
+ * lpa_run, lpa_modularity and the other calls accept a batched handle too
+ * (lpa_run then reports statistics summed over the graphs).
+ */
+lpa_status lpa_create_batched(int32_t num_graphs, const int64_t* v_off, const lpa_csr* csr,
+                              void* stream, const lpa_tuning* tuning, lpa_graph* out);
+lpa_status lpa_run_batched(lpa_graph g, const lpa_options* opt, int32_t* labels,
+                           int32_t* iters_per_graph, int64_t* changed_last_per_graph,
+                           int32_t* iters_done);
 
 /*
  * Modularity of a labelling, Eq. 1, in fp64:

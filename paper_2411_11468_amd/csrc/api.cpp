@@ -22,12 +22,12 @@ namespace {
 constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubAcc = 2, kKidSweep0 = 2,
               kKidHubFin = 11, kKidApply = 12, kKidPull = 13, kKidPullHubs = 14,
               kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kKidHubRest = 18,
-              kNumKids = 19;
+              kKidBatch = 19, kNumKids = 20;
 const char* const kKidNames[kNumKids] = {
     "hub_plan", "frontier", "hub_acc", "sweep_small4", "sweep_small16", "sweep_wave127",
     "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
     "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
-    "push_hubs", "flag_decide", "hub_acc_rest"};
+    "push_hubs", "flag_decide", "hub_acc_rest", "batch_step"};
 
 thread_local std::string g_err;
 
@@ -161,6 +161,8 @@ struct lpa_graph_s {
         edges = (int64_t)fw;
         bytes = 5.0 * (double)listed + (off64 ? 16.0 : 8.0) * (double)ch + 5.0 * (double)fw;
       }
+    } else if (kid == kKidBatch) {
+      bytes = 2.0 * n;  // change byte read, flag cleared at most once
     } else if (kid == kKidApply) {
       unsigned long long listed = 0;
       for (int c = 1; c < kClassHub; ++c) listed += h.active[c];
@@ -190,19 +192,52 @@ struct lpa_graph_s {
     return LPA_OK;
   }
 
-  HubArgs hub_args(int pl, int async_mode) const {
+  // device history of per-iteration statistics
+  DevIterStats* hist = nullptr;
+  int32_t hist_cap = 0;
+  // batched runs
+  int32_t G = 0;
+  const int64_t* b_voff = nullptr;
+  uint8_t* b_done = nullptr;
+  int32_t* b_iters = nullptr;
+  long long* b_changed = nullptr;
+  // captured iterations, one executable graph per launch configuration
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec[12] = {};
+
+  BatchArgs batch_args() const {
+    BatchArgs b;
+    b.G = G; b.v_off = b_voff; b.done = b_done; b.iters = b_iters; b.changed_last = b_changed;
+    return b;
+  }
+
+  lpa_status ensure_history(int32_t cap) {
+    if (cap <= hist_cap && hist) return LPA_OK;
+    DevIterStats* h = nullptr;
+    if (lpa_status e = dalloc(&h, std::max(cap, 32))) return e;
+    hist = h;  // the old buffer stays in dev_allocs until destroy
+    hist_cap = std::max(cap, 32);
+    return LPA_OK;
+  }
+
+  lpa_status iteration_graph(const lpa_options& o, hipGraphExec_t* out);
+
+  HubArgs hub_args(int async_mode) const {
     HubArgs a;
     a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F; a.chg = chg;
     a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
     a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
     a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.rec = rec; a.nrec = nrec;
     a.hub_nrec = hub_nrec; a.hub_xcd = hub_xcd; a.hub_nch = hub_nch; a.done = done;
-    a.H = H; a.chunk = tun.hub_chunk; a.pl = pl; a.async_mode = async_mode;
+    a.H = H; a.chunk = tun.hub_chunk; a.async_mode = async_mode;
     a.max_retries = tun.max_retries;
     return a;
   }
 
   ~lpa_graph_s() {
+    for (hipGraphExec_t x : graph_exec)
+      if (x) (void)hipGraphExecDestroy(x);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : dev_allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
@@ -224,6 +259,7 @@ void lpa_options_default(lpa_options* opt) {
   opt->initial_labels = nullptr;
   opt->profile = 0;
   opt->flag_mode = LPA_FLAGS_AUTO;
+  opt->launch = LPA_LAUNCH_EAGER;
 }
 
 void lpa_tuning_default(lpa_tuning* t) {
@@ -491,8 +527,108 @@ static lpa_status stage_labels(lpa_graph g, const int32_t* src, int32_t* dst) {
   return LPA_OK;
 }
 
-lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
-                   lpa_iter_stats* stats, int32_t stats_cap, int32_t* iters_done) {
+}  // extern "C"
+
+// Enqueue one iteration of Algorithm 1 on stream s.  Every kernel reads the
+// iteration's Pick-Less flag and the stop flag from device memory, so the
+// sequence can be replayed without the host (eagerly or as a captured graph).
+// mark(kid) brackets launches for the optional per-kernel profile.
+template <typename Mark>
+static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, hipStream_t s,
+                                    Mark&& mark) {
+  const int64_t n = g->n;
+  const int async_mode = o.mode == LPA_MODE_ASYNC;
+  // without pruning every vertex is processed in every iteration
+  if (!o.prune) LPA_HIP(launch_arm_flags(g->F, n, g->st, s));
+  const HubArgs ha = g->hub_args(async_mode);
+  if (lpa_status e = mark(kKidPlan)) return e;
+  LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
+  if (lpa_status e = mark(kKidFrontier)) return e;
+  LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
+  if (g->H > 0) {
+    if (g->tun.xcd_local) {
+      if (lpa_status e = mark(kKidHubAcc)) return e;
+      LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
+    }
+    if (lpa_status e = mark(kKidHubRest)) return e;
+    LPA_HIP(launch_hub_acc_rest(g->off64, ha, g->hub_fin_grid, s));
+  }
+  SweepArgs a;
+  a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;
+  a.chg = g->chg; a.st = g->st;
+  a.async_mode = async_mode;
+  a.max_retries = g->tun.max_retries;
+  for (int c = kClassHub - 1; c >= 1; --c) {
+    if (g->cls_count[c] == 0) continue;
+    a.cls = c;
+    a.active = g->lists[c];
+    if (lpa_status e = mark(kKidSweep0 + c)) return e;
+    LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], s));
+  }
+  if (g->H > 0) {
+    if (lpa_status e = mark(kKidHubFin)) return e;
+    LPA_HIP(launch_hub_fin(g->off64, ha, g->hub_fin_grid, s));
+  }
+  if (!async_mode) {
+    if (lpa_status e = mark(kKidApply)) return e;
+    LPA_HIP(launch_apply(g->st, g->lists, g->Cn, g->pend_v, g->pend_c, g->C, g->apply_grid, s));
+  }
+  // flag the neighbours of the changed vertices: the decide kernel picks
+  // push or pull from this iteration's counters, the other kernels return
+  if (lpa_status e = mark(kKidDecide)) return e;
+  LPA_HIP(launch_flag_decide(g->st, g->m, o.flag_mode, s));
+  if (lpa_status e = mark(kKidPush)) return e;
+  LPA_HIP(launch_push_lists(g->off64, g->off, g->tgt, g->lists, g->chg, g->F, g->st,
+                            g->push_grid, s));
+  if (g->H > 0) {
+    if (lpa_status e = mark(kKidPushHubs)) return e;
+    LPA_HIP(launch_push_hubs(g->off64, ha, g->hub_fin_grid, s));
+  }
+  if (lpa_status e = mark(kKidPull)) return e;
+  LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, n, g->cls, g->chg, g->F, g->st,
+                            g->pull_grid, s));
+  if (g->H > 0) {
+    if (lpa_status e = mark(kKidPullHubs)) return e;
+    LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg, g->F,
+                             g->st, s));
+  }
+  if (g->G > 0) {
+    if (lpa_status e = mark(kKidBatch)) return e;
+    LPA_HIP(launch_batch_step(g->batch_args(), g->chg, g->F, g->st, s));
+  }
+  if (lpa_status e = mark(-1)) return e;
+  LPA_HIP(launch_iter_end(g->st, g->hist, n, s));
+  return LPA_OK;
+}
+
+lpa_status lpa_graph_s::iteration_graph(const lpa_options& o, hipGraphExec_t* out) {
+  const int key = (o.mode == LPA_MODE_ASYNC ? 6 : 0) + (o.prune ? 3 : 0) + o.flag_mode;
+  if (graph_exec[key]) {
+    *out = graph_exec[key];
+    return LPA_OK;
+  }
+  if (!cap_stream) LPA_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  LPA_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+  auto nomark = [](int) -> lpa_status { return LPA_OK; };
+  const lpa_status st = enqueue_iteration(this, o, cap_stream, nomark);
+  hipGraph_t graph = nullptr;
+  const hipError_t end = hipStreamEndCapture(cap_stream, &graph);
+  if (st != LPA_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (end != hipSuccess) return fail(LPA_ERR_HIP, "hipStreamEndCapture failed");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (inst != hipSuccess) return fail(LPA_ERR_HIP, "hipGraphInstantiate failed");
+  graph_exec[key] = exec;
+  *out = exec;
+  return LPA_OK;
+}
+
+static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
+                           lpa_iter_stats* stats, int32_t stats_cap, int32_t* iters_done) {
   if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
   lpa_options o;
   if (opt) o = *opt; else lpa_options_default(&o);
@@ -502,6 +638,8 @@ lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
   if (o.pl_period < 0) return fail(LPA_ERR_INVALID, "pl_period < 0");
   if (o.flag_mode < LPA_FLAGS_AUTO || o.flag_mode > LPA_FLAGS_PULL)
     return fail(LPA_ERR_INVALID, "flag_mode must be LPA_FLAGS_AUTO, _PUSH or _PULL");
+  if (o.launch != LPA_LAUNCH_EAGER && o.launch != LPA_LAUNCH_GRAPH)
+    return fail(LPA_ERR_INVALID, "launch must be LPA_LAUNCH_EAGER or LPA_LAUNCH_GRAPH");
   if (stats_cap < 0 || (stats_cap > 0 && !stats))
     return fail(LPA_ERR_INVALID, "stats_cap < 0 or stats is NULL");
   if (g->n > 0 && !labels) return fail(LPA_ERR_INVALID, "labels is NULL");
@@ -509,10 +647,11 @@ lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
   const int64_t n = g->n;
   if (n == 0) return LPA_OK;
   hipStream_t s = g->stream;
-  const int async_mode = o.mode == LPA_MODE_ASYNC;
+  if (lpa_status e = g->ensure_history(o.max_iterations)) return e;
 
-  LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(g->st), 0u,
-                          sizeof(DevStats) / sizeof(uint32_t), s));
+  LPA_HIP(launch_run_begin(g->st, o.tolerance, o.max_iterations, o.pl_period, g->G > 0,
+                           g->G, s));
+  if (g->G > 0) LPA_HIP(launch_batch_reset(g->batch_args(), s));
   const int32_t* init = nullptr;
   if (o.initial_labels) {
     if (lpa_status e = stage_labels(g, o.initial_labels, g->pend_v)) return e;
@@ -525,113 +664,149 @@ lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
     if (g->st_host->error & 4u)
       return fail(LPA_ERR_INVALID, "initial_labels must lie in [0, N)");
   }
-  int32_t done = 0;
-  const bool prof = o.profile != 0;
-  for (int32_t l = 0; l < o.max_iterations; ++l) {
-    const int pl = (o.pl_period > 0) && (l % o.pl_period == 0);
 
-    int nev = 0;
-    // launch bracketing for the optional per-kernel profile
-    auto mark = [&](int kid) -> lpa_status {
-      if (!prof) return LPA_OK;
-      if (lpa_status e = g->ensure_events(nev + 1)) return e;
-      g->ev_kid[nev] = kid;
-      LPA_HIP(hipEventRecord(g->ev_pool[nev], s));
-      ++nev;
-      return LPA_OK;
-    };
-    LPA_HIP(hipEventRecord(g->ev0, s));
-    // without pruning every vertex is processed in every iteration
-    if (!o.prune && l > 0) LPA_HIP(launch_fill_u8(g->F, 1, n, s));
-    const HubArgs ha = g->hub_args(pl, async_mode);
-    if (lpa_status e = mark(kKidPlan)) return e;
-    LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
-    if (lpa_status e = mark(kKidFrontier)) return e;
-    LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
-    if (g->H > 0) {
-      if (g->tun.xcd_local) {
-        if (lpa_status e = mark(kKidHubAcc)) return e;
-        LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
-      }
-      if (lpa_status e = mark(kKidHubRest)) return e;
-      LPA_HIP(launch_hub_acc_rest(g->off64, ha, g->hub_fin_grid, s));
-    }
-    SweepArgs a;
-    a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;
-    a.chg = g->chg; a.st = g->st;
-    a.pl = pl; a.async_mode = async_mode;
-    a.max_retries = g->tun.max_retries;
-    for (int c = kClassHub - 1; c >= 1; --c) {
-      if (g->cls_count[c] == 0) continue;
-      a.cls = c;
-      a.active = g->lists[c];
-      if (lpa_status e = mark(kKidSweep0 + c)) return e;
-      LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], s));
-    }
-    if (g->H > 0) {
-      if (lpa_status e = mark(kKidHubFin)) return e;
-      LPA_HIP(launch_hub_fin(g->off64, ha, g->hub_fin_grid, s));
-    }
-    if (!async_mode) {
-      if (lpa_status e = mark(kKidApply)) return e;
-      LPA_HIP(launch_apply(g->st, g->lists, g->Cn, g->pend_v, g->pend_c, g->C, g->apply_grid,
-                           s));
-    }
-    // flag the neighbours of the changed vertices: the decide kernel picks
-    // push or pull from this iteration's counters, the other kernels return
-    if (lpa_status e = mark(kKidDecide)) return e;
-    LPA_HIP(launch_flag_decide(g->st, g->m, o.flag_mode, s));
-    if (lpa_status e = mark(kKidPush)) return e;
-    LPA_HIP(launch_push_lists(g->off64, g->off, g->tgt, g->lists, g->chg, g->F, g->st,
-                              g->push_grid, s));
-    if (g->H > 0) {
-      if (lpa_status e = mark(kKidPushHubs)) return e;
-      LPA_HIP(launch_push_hubs(g->off64, ha, g->hub_fin_grid, s));
-    }
-    if (lpa_status e = mark(kKidPull)) return e;
-    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, n, g->cls, g->chg, g->F, g->st,
-                              g->pull_grid, s));
-    if (g->H > 0) {
-      if (lpa_status e = mark(kKidPullHubs)) return e;
-      LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg, g->F,
-                               g->st, s));
-    }
-    if (lpa_status e = mark(-1)) return e;
-    LPA_HIP(hipEventRecord(g->ev1, s));
+  int32_t done = 0;
+  const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile;
+  if (graph_mode) {
+    // capture one iteration on the private stream, replay it max_iterations
+    // times on the handle's stream; the kernels of iterations after the stop
+    // return at once
+    hipGraphExec_t exec = nullptr;
+    if (lpa_status e = g->iteration_graph(o, &exec)) return e;
+    for (int32_t l = 0; l < o.max_iterations; ++l) LPA_HIP(hipGraphLaunch(exec, s));
     LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
     LPA_HIP(hipStreamSynchronize(s));
-    float ms = 0.0f;
-    LPA_HIP(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-    const DevStats& h = *g->st_host;
-    unsigned long long changed = 0, edges = 0;
-    for (int c = 0; c < kNumClasses; ++c) {
-      changed += h.changed[c];
-      edges += h.edges[c];
-    }
-    if (prof) {
-      for (int q = 0; q + 1 < nev; ++q) {
-        float kms = 0.0f;
-        LPA_HIP(hipEventElapsedTime(&kms, g->ev_pool[q], g->ev_pool[q + 1]));
-        g->account(g->ev_kid[q], kms, h, async_mode != 0, h.pull_mode != 0);
+    done = g->st_host->iter;
+    const int32_t k = std::min(done, stats_cap);
+    if (k > 0) {
+      std::vector<DevIterStats> h(k);
+      LPA_HIP(hipMemcpyAsync(h.data(), g->hist, sizeof(DevIterStats) * k,
+                             hipMemcpyDeviceToHost, s));
+      LPA_HIP(hipStreamSynchronize(s));
+      for (int32_t l = 0; l < k; ++l) {
+        std::memset(&stats[l], 0, sizeof(stats[l]));
+        stats[l].iteration = h[l].iteration;
+        stats[l].pick_less = h[l].pick_less;
+        stats[l].changed = h[l].changed;
+        stats[l].processed = h[l].processed;
+        stats[l].edges_scanned = h[l].edges;
       }
     }
-    if (l < stats_cap) {
-      lpa_iter_stats& r = stats[l];
-      std::memset(&r, 0, sizeof(r));
-      r.iteration = l;
-      r.pick_less = pl;
-      r.changed = (int64_t)changed;
-      r.processed = (int64_t)h.processed;
-      r.edges_scanned = (int64_t)edges;
-      r.ms = ms;
+  } else {
+    const bool prof = o.profile != 0;
+    for (int32_t l = 0; l < o.max_iterations; ++l) {
+      int nev = 0;
+      auto mark = [&](int kid) -> lpa_status {
+        if (!prof) return LPA_OK;
+        if (lpa_status e = g->ensure_events(nev + 1)) return e;
+        g->ev_kid[nev] = kid;
+        LPA_HIP(hipEventRecord(g->ev_pool[nev], s));
+        ++nev;
+        return LPA_OK;
+      };
+      LPA_HIP(hipEventRecord(g->ev0, s));
+      if (lpa_status e = enqueue_iteration(g, o, s, mark)) return e;
+      LPA_HIP(hipEventRecord(g->ev1, s));
+      LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+      LPA_HIP(hipStreamSynchronize(s));
+      float ms = 0.0f;
+      LPA_HIP(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+      const DevStats& h = *g->st_host;
+      unsigned long long changed = 0, edges = 0;
+      for (int c = 0; c < kNumClasses; ++c) {
+        changed += h.changed[c];
+        edges += h.edges[c];
+      }
+      if (prof) {
+        for (int q = 0; q + 1 < nev; ++q) {
+          float kms = 0.0f;
+          LPA_HIP(hipEventElapsedTime(&kms, g->ev_pool[q], g->ev_pool[q + 1]));
+          g->account(g->ev_kid[q], kms, h, o.mode == LPA_MODE_ASYNC, h.pull_mode != 0);
+        }
+      }
+      if (l < stats_cap) {
+        lpa_iter_stats& r = stats[l];
+        std::memset(&r, 0, sizeof(r));
+        r.iteration = l;
+        r.pick_less = h.pl;
+        r.changed = (int64_t)changed;
+        r.processed = (int64_t)h.processed;
+        r.edges_scanned = (int64_t)edges;
+        r.ms = ms;
+      }
+      done = l + 1;
+      if (h.stop) break;
     }
-    done = l + 1;
-    if (!pl && (double)changed < o.tolerance * (double)n) break;
   }
   if (iters_done) *iters_done = done;
   const hipMemcpyKind kind = is_device_ptr(labels) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   LPA_HIP(hipMemcpyAsync(labels, g->C, sizeof(int32_t) * (size_t)n, kind, s));
   LPA_HIP(hipStreamSynchronize(s));
+  return LPA_OK;
+}
+
+extern "C" {
+
+lpa_status lpa_run(lpa_graph g, const lpa_options* opt, int32_t* labels,
+                   lpa_iter_stats* stats, int32_t stats_cap, int32_t* iters_done) {
+  return run_impl(g, opt, labels, stats, stats_cap, iters_done);
+}
+
+lpa_status lpa_run_batched(lpa_graph g, const lpa_options* opt, int32_t* labels,
+                           int32_t* iters_per_graph, int64_t* changed_last_per_graph,
+                           int32_t* iters_done) {
+  if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
+  if (g->G <= 0) return fail(LPA_ERR_STATE, "handle was not made by lpa_create_batched");
+  if (lpa_status e = run_impl(g, opt, labels, nullptr, 0, iters_done)) return e;
+  if (g->n == 0) return LPA_OK;
+  if (iters_per_graph)
+    LPA_HIP(hipMemcpyAsync(iters_per_graph, g->b_iters, sizeof(int32_t) * g->G,
+                           hipMemcpyDeviceToHost, g->stream));
+  if (changed_last_per_graph)
+    LPA_HIP(hipMemcpyAsync(changed_last_per_graph, g->b_changed, sizeof(int64_t) * g->G,
+                           hipMemcpyDeviceToHost, g->stream));
+  LPA_HIP(hipStreamSynchronize(g->stream));
+  return LPA_OK;
+}
+
+lpa_status lpa_create_batched(int32_t num_graphs, const int64_t* v_off, const lpa_csr* csr,
+                              void* stream, const lpa_tuning* tuning, lpa_graph* out) {
+  if (!out) return fail(LPA_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (num_graphs <= 0 || !v_off || !csr)
+    return fail(LPA_ERR_INVALID, "num_graphs must be positive; v_off and csr non-NULL");
+  if (v_off[0] != 0 || v_off[num_graphs] != csr->num_vertices)
+    return fail(LPA_ERR_INVALID, "v_off must run from 0 to num_vertices");
+  for (int32_t q = 0; q < num_graphs; ++q)
+    if (v_off[q + 1] < v_off[q]) return fail(LPA_ERR_INVALID, "v_off must be non-decreasing");
+  lpa_graph g = nullptr;
+  if (lpa_status e = lpa_create(csr, stream, tuning, &g)) return e;
+  hipStream_t s = g->stream;
+  auto cleanup = [&](lpa_status e) { lpa_destroy(g); return e; };
+  g->G = num_graphs;
+  int64_t* dv = nullptr;
+  if (lpa_status e = g->dalloc(&dv, num_graphs + 1)) return cleanup(e);
+  g->b_voff = dv;
+  if (lpa_status e = g->dalloc(&g->b_done, num_graphs)) return cleanup(e);
+  if (lpa_status e = g->dalloc(&g->b_iters, num_graphs)) return cleanup(e);
+  if (lpa_status e = g->dalloc(&g->b_changed, num_graphs)) return cleanup(e);
+  if (hipMemcpyAsync(dv, v_off, sizeof(int64_t) * (num_graphs + 1), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return cleanup(fail(LPA_ERR_HIP, "copying v_off failed"));
+  if (csr->validate) {
+    if (launch_fill_u32(reinterpret_cast<uint32_t*>(g->st), 0u,
+                        sizeof(DevStats) / sizeof(uint32_t), s) != hipSuccess ||
+        launch_batch_validate(g->off64, g->off, g->tgt, g->batch_args(), g->n, g->st, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return cleanup(fail(LPA_ERR_HIP, "batched validation failed to run"));
+    if (g->st_host->error & 16u)
+      return cleanup(fail(LPA_ERR_INVALID, "a CSR entry points outside its own graph"));
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(LPA_ERR_HIP, "sync failed"));
+  *out = g;
   return LPA_OK;
 }
 

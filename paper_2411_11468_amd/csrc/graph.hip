@@ -47,6 +47,164 @@ hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
   return hipGetLastError();
 }
 
+// ---- run control ---------------------------------------------------------------
+// k_run_begin zeroes the counters and stores the run's parameters; every
+// per-iteration kernel returns at once when stop is set; k_iter_end records
+// the iteration's statistics and applies the stop rule of Algorithm 1 (after
+// an iteration that is not Pick-Less with changed < tolerance * N), or, in a
+// batched run, stops when every graph has stopped.
+__global__ void k_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
+                            int graphs) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(st);
+  for (uint32_t i = threadIdx.x; i < sizeof(DevStats) / sizeof(uint32_t); i += blockDim.x)
+    w[i] = 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->tol = tol;
+    st->cap = cap;
+    st->rho = rho;
+    st->iter = 0;
+    st->stop = cap <= 0 ? 1 : 0;
+    st->batched = batched;
+    st->graphs_left = (unsigned int)graphs;
+  }
+}
+
+hipError_t launch_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
+                            int graphs, hipStream_t s) {
+  hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, s, st, tol, cap, rho, batched, graphs);
+  return hipGetLastError();
+}
+
+__global__ void k_arm_flags(uint8_t* F, int64_t n, const DevStats* st) {
+  if (st->stop) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    F[i] = 1;
+}
+
+hipError_t launch_arm_flags(uint8_t* F, int64_t n, const DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_arm_flags, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, F, n, st);
+  return hipGetLastError();
+}
+
+__global__ void k_iter_end(DevStats* st, DevIterStats* hist, int64_t n) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop) return;
+  unsigned long long changed = 0, edges = 0;
+  for (int c = 0; c < kNumClasses; ++c) {
+    changed += st->changed[c];
+    edges += st->edges[c];
+  }
+  const int l = st->iter;
+  DevIterStats& h = hist[l];
+  h.iteration = l;
+  h.pick_less = st->pl;
+  h.changed = (long long)changed;
+  h.processed = (long long)st->processed;
+  h.edges = (long long)edges;
+  int stop = 0;
+  if (st->batched) stop = st->graphs_left == 0u;
+  else stop = !st->pl && (double)changed < st->tol * (double)n;
+  st->iter = l + 1;
+  st->stop = (stop || l + 1 >= st->cap) ? 1 : 0;
+}
+
+hipError_t launch_iter_end(DevStats* st, DevIterStats* hist, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, s, st, hist, n);
+  return hipGetLastError();
+}
+
+// ---- batched runs: per-graph stop rule ------------------------------------------
+// One workgroup per graph: count the graph's changed vertices, apply Algorithm
+// 1's stop test with the graph's own vertex count, and clear the flags of a
+// graph that stops so that none of its vertices is processed again.  All
+// graphs share the iteration counter, so each follows its solo schedule.
+__global__ __launch_bounds__(kBT) void k_batch_step(BatchArgs b, const uint8_t* chg,
+                                                    uint8_t* F, DevStats* st) {
+  __shared__ unsigned int cnt[kBT / 64];
+  __shared__ int fin;
+  if (st->stop) return;
+  for (int32_t g = blockIdx.x; g < b.G; g += gridDim.x) {
+    if (b.done[g]) continue;
+    const int64_t v0 = b.v_off[g], v1 = b.v_off[g + 1];
+    unsigned int c = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kBT) c += chg[v];
+    for (int ofs = 32; ofs > 0; ofs >>= 1) c += __shfl_xor(c, ofs);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int q = 0; q < kBT / 64; ++q) t += cnt[q];
+      b.changed_last[g] = (long long)t;
+      const int l = st->iter;
+      const bool f = (!st->pl && (double)t < st->tol * (double)(v1 - v0)) || l + 1 >= st->cap;
+      if (f) {
+        b.done[g] = 1;
+        b.iters[g] = l + 1;
+      } else {
+        atomicAdd(&st->graphs_left, 1u);
+      }
+      fin = f;
+    }
+    __syncthreads();
+    if (fin)
+      for (int64_t v = v0 + threadIdx.x; v < v1; v += kBT) F[v] = 0;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batch_step(const BatchArgs& b, const uint8_t* chg, uint8_t* F, DevStats* st,
+                             hipStream_t s) {
+  const int g = b.G < 8192 ? (b.G > 0 ? b.G : 1) : 8192;
+  hipLaunchKernelGGL(k_batch_step, dim3(g), dim3(kBT), 0, s, b, chg, F, st);
+  return hipGetLastError();
+}
+
+__global__ void k_batch_reset(BatchArgs b) {
+  for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < b.G; g += gridDim.x * blockDim.x) {
+    b.done[g] = b.v_off[g + 1] == b.v_off[g];  // an empty graph performs no iteration
+    b.iters[g] = 0;
+    b.changed_last[g] = 0;
+  }
+}
+
+hipError_t launch_batch_reset(const BatchArgs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(grid_for(b.G, kBT, 1024)), dim3(kBT), 0, s, b);
+  return hipGetLastError();
+}
+
+// every CSR entry of graph g must point into graph g (error bit 16)
+template <typename OffT>
+__global__ void k_batch_validate(const OffT* off, const int32_t* tgt, BatchArgs b, int64_t n,
+                                 DevStats* st) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = b.G - 1;  // graph holding v: largest g with v_off[g] <= v
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (b.v_off[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    const int64_t a0 = b.v_off[lo], a1 = b.v_off[lo + 1];
+    for (int64_t e = (int64_t)off[v]; e < (int64_t)off[v + 1]; ++e)
+      if ((int64_t)tgt[e] < a0 || (int64_t)tgt[e] >= a1) {
+        set_error(st, 16u);
+        break;
+      }
+  }
+}
+
+hipError_t launch_batch_validate(bool off64, const void* off, const int32_t* tgt,
+                                 const BatchArgs& b, int64_t n, DevStats* st, hipStream_t s) {
+  const int g = grid_for(n, kBT, 8192);
+  if (off64)
+    hipLaunchKernelGGL(k_batch_validate<int64_t>, dim3(g), dim3(kBT), 0, s,
+                       (const int64_t*)off, tgt, b, n, st);
+  else
+    hipLaunchKernelGGL(k_batch_validate<int32_t>, dim3(g), dim3(kBT), 0, s,
+                       (const int32_t*)off, tgt, b, n, st);
+  return hipGetLastError();
+}
+
 // ---- validation (error bits: 1 offsets, 2 targets, 8 weights) ----------------
 template <typename OffT>
 __global__ void k_validate(const OffT* off, const int32_t* tgt, const float* w,
@@ -179,9 +337,13 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
   __shared__ uint32_t nproc;
   const int tid = threadIdx.x;
   DevStats* st = a.st;
+  if (st->stop) return;
   if (tid == 0) {
     st->processed = 0; st->pending = 0;
     st->pull_scanned = 0; st->pull_mode = 0;
+    st->graphs_left = 0;
+    // Pick-Less in iterations l with l mod rho == 0, counting from 0
+    st->pl = (st->rho > 0 && st->iter % st->rho == 0) ? 1 : 0;
     running = 0; nproc = 0;
   }
   if (tid < kNumClasses) {
@@ -259,6 +421,7 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
                                                   DevStats* st) {
   __shared__ uint32_t cnt[kNumClasses];
   __shared__ uint32_t base[kNumClasses];
+  if (st->stop) return;
   const int tid = threadIdx.x;
   uint32_t proc = 0;
   for (int64_t chunk = (int64_t)blockIdx.x * kBT * 4; chunk < n;
@@ -318,7 +481,7 @@ hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
 // vertices find a changed neighbour within a few entries), push otherwise;
 // the kernels of the other way return at once.
 __global__ void k_flag_decide(DevStats* st, int64_t m, int force) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop) return;
   unsigned long long fw = 0;
   for (int c = 0; c < kNumClasses; ++c) fw += st->flagw[c];
   st->pull_mode = force == 2 ? 1u : force == 1 ? 0u : (2ull * fw >= (unsigned long long)m ? 1u : 0u);
@@ -335,7 +498,7 @@ template <typename OffT>
 __global__ __launch_bounds__(kBT) void k_push_lists(const OffT* off, const int32_t* tgt,
                                                     ListPtrs lists, const uint8_t* chg,
                                                     uint8_t* F, DevStats* st) {
-  if (st->pull_mode) return;
+  if (st->stop || st->pull_mode) return;
   const int lane = threadIdx.x & 63;
   const int k = lane & 7;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -380,7 +543,7 @@ hipError_t launch_push_lists(bool off64, const void* off, const int32_t* tgt,
 
 template <typename OffT>
 __global__ __launch_bounds__(kBT) void k_push_hubs(HubArgs a) {
-  if (a.st->pull_mode) return;
+  if (a.st->stop || a.st->pull_mode) return;
   const uint32_t nitems = a.st->hub_items;
   const OffT* off = reinterpret_cast<const OffT*>(a.off);
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -419,7 +582,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
                                                     int64_t n, const uint8_t* cls,
                                                     const uint8_t* chg, uint8_t* F,
                                                     DevStats* st) {
-  if (!st->pull_mode) return;
+  if (st->stop || !st->pull_mode) return;
   const int lane = threadIdx.x & 63;
   const int k = lane & 7;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -460,7 +623,7 @@ __global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_
                                                    const uint8_t* chg, uint8_t* F,
                                                    DevStats* st) {
   __shared__ int any;
-  if (!st->pull_mode) return;
+  if (st->stop || !st->pull_mode) return;
   unsigned long long scanned = 0;
   for (int32_t h = blockIdx.x; h < H; h += gridDim.x) {
     const int32_t v = hub_vid[h];
@@ -513,6 +676,7 @@ hipError_t launch_pull_hubs(bool off64, const void* off, const int32_t* tgt,
 // queued their moves.  Copy both into C.
 __global__ void k_apply(const DevStats* st, ListPtrs lists, const int32_t* Cn,
                         const int32_t* pv, const int32_t* pc, int32_t* C) {
+  if (st->stop) return;
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
   const unsigned long long t0 = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
   const unsigned long long nq = st->pending;

@@ -32,6 +32,16 @@ struct DevStats {
   unsigned int hub_items;                       // hub slices queued this iteration
   unsigned int hub_seg[kXcds + 1];              // slice list segment of each XCD
   unsigned int hub_head[kXcds];                 // next slice of each segment
+  // run control, resident on the device so that iterations can be launched
+  // back to back (or replayed from a captured graph) without the host
+  double tol;                                   // stop tolerance
+  int cap;                                      // iteration cap
+  int rho;                                      // Pick-Less period (0: off)
+  int iter;                                     // index of the iteration being run
+  int stop;                                     // 1: run ended, kernels return at once
+  int pl;                                       // Pick-Less in this iteration
+  int batched;                                  // per-graph stop rule
+  unsigned int graphs_left;                     // batched: graphs still running
   unsigned int error;                           // sticky error bits (validation, labels)
 };
 
@@ -48,7 +58,6 @@ struct SweepArgs {
   const int32_t* active;  // active vertex list of this class
   DevStats* st;
   int cls;                // class index (selects st->active[cls])
-  int pl;                 // Pick-Less on in this iteration
   int async_mode;         // 1: write labels in place, 0: queue them
   int max_retries;        // hybrid probes before the linear continuation
 };
@@ -78,14 +87,41 @@ struct HubArgs {
   int32_t* done;                   // per slice: merged by the XCD-local pass
   int32_t H;
   int32_t chunk;                   // edges per slice
-  int pl;
   int async_mode;
   int max_retries;
+};
+
+// Statistics of one iteration as recorded on the device (same layout as the
+// leading fields of lpa_iter_stats).
+struct DevIterStats {
+  int32_t iteration;
+  int32_t pick_less;
+  long long changed;
+  long long processed;
+  long long edges;
+};
+
+// Per-graph state of a batched run.
+struct BatchArgs {
+  int32_t G;
+  const int64_t* v_off;            // G + 1 vertex offsets
+  uint8_t* done;                   // 1 once the graph has stopped
+  int32_t* iters;                  // iterations the graph performed
+  long long* changed_last;         // changed vertices in its last iteration
 };
 
 // ---- launch wrappers (defined in the .hip files) ----------------------------
 hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
                        DevStats* st, hipStream_t s);
+hipError_t launch_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
+                            int graphs, hipStream_t s);
+hipError_t launch_arm_flags(uint8_t* F, int64_t n, const DevStats* st, hipStream_t s);
+hipError_t launch_iter_end(DevStats* st, DevIterStats* hist, int64_t n, hipStream_t s);
+hipError_t launch_batch_step(const BatchArgs& b, const uint8_t* chg, uint8_t* F, DevStats* st,
+                             hipStream_t s);
+hipError_t launch_batch_reset(const BatchArgs& b, hipStream_t s);
+hipError_t launch_batch_validate(bool off64, const void* off, const int32_t* tgt,
+                                 const BatchArgs& b, int64_t n, DevStats* st, hipStream_t s);
 hipError_t launch_validate(bool off64, const void* off, const int32_t* tgt,
                            const float* w, int64_t n, int64_t m, DevStats* st,
                            hipStream_t s);

@@ -92,6 +92,7 @@ __device__ __forceinline__ void rot4_accum(uint32_t lab, float wt, float& sum) {
 // ---- small rows: G lanes per vertex, registers only -------------------------
 template <typename OffT, int G>
 __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
+  if (a.st->stop) return;
   const int lane = threadIdx.x & 63;
   const int k = lane & (G - 1);
   const uint32_t count = a.st->active[a.cls];
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
         (G == 16) ? row16_max_u64(packed) : quad_max_u64(packed);
     uint32_t cstar = 0;
     const int32_t cur = valid ? a.C[v] : 0;
-    const bool moved = valid && decide(best, cur, a.pl, &cstar);
+    const bool moved = valid && decide(best, cur, a.st->pl, &cstar);
     const bool leader = valid && k == 0;
     if (leader) {
       if (a.async_mode) {
@@ -157,6 +158,7 @@ template <typename OffT, int SLOTS, int WAVES, int U>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   __shared__ uint32_t keys_all[WAVES][SLOTS];
   __shared__ float vals_all[WAVES][SLOTS];
+  if (a.st->stop) return;
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   uint32_t* keys = keys_all[wv];
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     }
     best = wave_max_u64(best);
     uint32_t cstar = 0;
-    const bool moved = decide(best, cur, a.pl, &cstar);
+    const bool moved = decide(best, cur, a.st->pl, &cstar);
     if (lane == 0) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -226,6 +228,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
   __shared__ uint32_t keys[SLOTS];
   __shared__ float vals[SLOTS];
   __shared__ unsigned long long red[BT / 64];
+  if (a.st->stop) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
 #pragma unroll
     for (int q = 1; q < BT / 64; ++q) best = umax64(best, red[q]);
     uint32_t cstar = 0;
-    const bool moved = decide(best, cur, a.pl, &cstar);
+    const bool moved = decide(best, cur, a.st->pl, &cstar);
     if (tid == 0) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -309,6 +312,7 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
   __shared__ uint32_t nrec;
   __shared__ uint32_t next;
   constexpr int kScope = LOCAL ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
+  if (a.st->stop) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
@@ -394,6 +398,7 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
 
 template <typename OffT, int BT>
 __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
+  if (a.st->stop) return;
   const int tid = threadIdx.x;
   const uint32_t nitems = a.st->hub_items;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -405,7 +410,7 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
     const int64_t e0 = (int64_t)c * a.chunk;
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
     uint32_t cstar = 0;
-    const bool moved = decide(a.hub_best[h], a.hub_old[h], a.pl, &cstar);
+    const bool moved = decide(a.hub_best[h], a.hub_old[h], a.st->pl, &cstar);
     if (moved) {
       if (c == 0 && tid == 0) {
         if (a.async_mode) {

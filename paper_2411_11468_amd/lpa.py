@@ -28,6 +28,8 @@ INDEX_I64 = 1
 FLAGS_AUTO = 0
 FLAGS_PUSH = 1
 FLAGS_PULL = 2
+LAUNCH_EAGER = 0
+LAUNCH_GRAPH = 1
 CLASS_NAMES = ("degree0", "small4", "small16", "wave", "block", "hub")
 
 
@@ -56,7 +58,8 @@ class lpa_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
                 ("tolerance", ctypes.c_double), ("pl_period", ctypes.c_int32),
                 ("prune", ctypes.c_int32), ("initial_labels", ctypes.c_void_p),
-                ("profile", ctypes.c_int32), ("flag_mode", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("flag_mode", ctypes.c_int32),
+                ("launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lpa_kernel_profile(ctypes.Structure):
@@ -74,7 +77,8 @@ class lpa_iter_stats(ctypes.Structure):
 
 EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run",
             "lpa_modularity", "lpa_graph_classes", "lpa_get_flags", "lpa_profile",
-            "lpa_profile_reset", "lpa_destroy", "lpa_status_string", "lpa_last_error")
+            "lpa_profile_reset", "lpa_destroy", "lpa_status_string", "lpa_last_error",
+            "lpa_create_batched", "lpa_run_batched")
 
 _lib = None
 
@@ -111,6 +115,12 @@ def load_library(path: str = LIB_PATH):
     lib.lpa_profile.restype = ctypes.c_int
     lib.lpa_profile_reset.argtypes = [vp]
     lib.lpa_profile_reset.restype = ctypes.c_int
+    lib.lpa_create_batched.argtypes = [ctypes.c_int32, vp, ctypes.POINTER(lpa_csr), vp,
+                                       ctypes.POINTER(lpa_tuning), ctypes.POINTER(vp)]
+    lib.lpa_create_batched.restype = ctypes.c_int
+    lib.lpa_run_batched.argtypes = [vp, ctypes.POINTER(lpa_options), vp, vp, vp,
+                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.lpa_run_batched.restype = ctypes.c_int
     lib.lpa_destroy.argtypes = [vp]
     lib.lpa_destroy.restype = None
     lib.lpa_status_string.argtypes = [ctypes.c_int]
@@ -162,11 +172,7 @@ def default_options() -> lpa_options:
 
 # ---- thin wrappers with the C names ---------------------------------------------
 
-def lpa_create(offsets, targets, weights=None, *, validate: bool = True,
-               tuning: lpa_tuning | None = None, stream=None):
-    """Create a graph handle.  torch CUDA tensors are borrowed (keep them alive);
-    numpy arrays are copied to the device.  Returns an opaque handle."""
-    lib = load_library()
+def _csr_struct(offsets, targets, weights, validate):
     on_dev = _is_torch(offsets) and offsets.is_cuda
     if on_dev:
         import torch
@@ -191,6 +197,15 @@ def lpa_create(offsets, targets, weights=None, *, validate: bool = True,
     g.targets = _addr(targets)
     g.weights = _addr(weights)
     g.validate = int(validate)
+    return g, on_dev, (offsets, targets, weights)
+
+
+def lpa_create(offsets, targets, weights=None, *, validate: bool = True,
+               tuning: lpa_tuning | None = None, stream=None):
+    """Create a graph handle.  torch CUDA tensors are borrowed (keep them alive);
+    numpy arrays are copied to the device.  Returns an opaque handle."""
+    lib = load_library()
+    g, on_dev, _keep = _csr_struct(offsets, targets, weights, validate)
     h = ctypes.c_void_p()
     s = stream if stream is not None else _current_stream(on_dev)
     _check(lib.lpa_create(ctypes.byref(g), s, ctypes.byref(tuning) if tuning else None,
@@ -198,12 +213,22 @@ def lpa_create(offsets, targets, weights=None, *, validate: bool = True,
     return h
 
 
-def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
-            max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
-            initial_labels=None, profile: bool = False, flag_mode: int = FLAGS_AUTO):
-    """Run to termination; labels is a preallocated int32 torch tensor or numpy
-    array of N entries.  Returns (iterations, list of stats dicts)."""
+def lpa_create_batched(v_off, offsets, targets, weights=None, *, validate: bool = True,
+                       tuning: lpa_tuning | None = None, stream=None):
+    """Handle over graphs packed in one CSR; v_off (host, G + 1 int64) gives
+    each graph's vertex range."""
     lib = load_library()
+    vo = np.ascontiguousarray(v_off, dtype=np.int64)
+    g, on_dev, _keep = _csr_struct(offsets, targets, weights, validate)
+    h = ctypes.c_void_p()
+    s = stream if stream is not None else _current_stream(on_dev)
+    _check(lib.lpa_create_batched(int(vo.shape[0] - 1), _addr(vo), ctypes.byref(g), s,
+                                  ctypes.byref(tuning) if tuning else None, ctypes.byref(h)))
+    return h
+
+
+def _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, profile,
+             flag_mode, launch):
     o = default_options()
     o.mode = int(mode)
     o.tolerance = float(tolerance)
@@ -213,6 +238,36 @@ def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
     o.initial_labels = _addr(initial_labels)
     o.profile = int(bool(profile))
     o.flag_mode = int(flag_mode)
+    o.launch = int(launch)
+    return o
+
+
+def lpa_run_batched(handle, labels, num_graphs: int, *, mode: int = MODE_ASYNC,
+                    tolerance: float = 0.05, max_iterations: int = 20, pl_period: int = 4,
+                    prune: bool = True, initial_labels=None, flag_mode: int = FLAGS_AUTO,
+                    launch: int = LAUNCH_GRAPH):
+    """Returns (batch iterations, per-graph iterations, per-graph changed in
+    the last iteration)."""
+    lib = load_library()
+    o = _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, False,
+                 flag_mode, launch)
+    iters = np.zeros(num_graphs, dtype=np.int32)
+    last = np.zeros(num_graphs, dtype=np.int64)
+    it = ctypes.c_int32(0)
+    _check(lib.lpa_run_batched(handle, ctypes.byref(o), _addr(labels), _addr(iters),
+                               _addr(last), ctypes.byref(it)))
+    return int(it.value), iters, last
+
+
+def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
+            max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
+            initial_labels=None, profile: bool = False, flag_mode: int = FLAGS_AUTO,
+            launch: int = LAUNCH_EAGER):
+    """Run to termination; labels is a preallocated int32 torch tensor or numpy
+    array of N entries.  Returns (iterations, list of stats dicts)."""
+    lib = load_library()
+    o = _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, profile,
+                 flag_mode, launch)
     cap = max(int(max_iterations), 1)
     st = (lpa_iter_stats * cap)()
     it = ctypes.c_int32(0)
@@ -285,6 +340,8 @@ class LpaGraph:
         self.handle = lpa_create(offsets, targets, weights, validate=validate, tuning=tuning)
 
     def run(self, mode: str | int = "async", out=None, **kw) -> RunResult:
+        """lpa_run; keyword options as lpa_run (launch=LAUNCH_GRAPH replays a
+        captured iteration)."""
         m = {"async": MODE_ASYNC, "det": MODE_DETERMINISTIC,
              "deterministic": MODE_DETERMINISTIC}.get(mode, mode)
         if out is None:
@@ -324,3 +381,39 @@ class LpaGraph:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class BatchResult:
+    labels: object
+    iterations: int            # iterations of the batch (the longest graph)
+    iters_per_graph: np.ndarray
+    changed_last: np.ndarray
+
+
+class LpaBatch(LpaGraph):
+    """Many graphs packed in one CSR (see lpa_create_batched)."""
+
+    def __init__(self, v_off, offsets, targets, weights=None, *, validate: bool = True,
+                 tuning: lpa_tuning | None = None):
+        self._keep = (offsets, targets, weights)
+        self.on_device = _is_torch(offsets) and offsets.is_cuda
+        self.num_vertices = int(offsets.shape[0]) - 1
+        self.num_edges = int(targets.shape[0])
+        self.v_off = np.ascontiguousarray(v_off, dtype=np.int64)
+        self.num_graphs = int(self.v_off.shape[0] - 1)
+        self.handle = lpa_create_batched(self.v_off, offsets, targets, weights,
+                                         validate=validate, tuning=tuning)
+
+    def run_batched(self, mode: str | int = "async", out=None, **kw) -> BatchResult:
+        m = {"async": MODE_ASYNC, "det": MODE_DETERMINISTIC,
+             "deterministic": MODE_DETERMINISTIC}.get(mode, mode)
+        if out is None:
+            if self.on_device:
+                import torch
+                out = torch.empty(self.num_vertices, dtype=torch.int32,
+                                  device=self._keep[0].device)
+            else:
+                out = np.empty(self.num_vertices, dtype=np.int32)
+        it, per, last = lpa_run_batched(self.handle, out, self.num_graphs, mode=m, **kw)
+        return BatchResult(out, it, per, last)
