@@ -96,6 +96,9 @@ def main() -> int:
     ap.add_argument("--mode", default=None, choices=["async", "det"])
     ap.add_argument("--cpu-budget-edges", type=int, default=300_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy a 2 GiB device buffer three times "
+                         "(reference kernel for the HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -152,6 +155,27 @@ def main() -> int:
                for p in prof}
     log(f"dominant kernel {dom['name']}: {achieved:.0f} GB/s algorithmic; kernels {kernels}")
 
+    traffic, traffic_note = None, "no counter summary for these kernel sources"
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}-{mode}.json")
+    if os.path.exists(tpath):
+        from paper_2411_11468_amd import profiling
+        with open(tpath) as f:
+            tj = json.load(f)
+        if tj.get("sources") == profiling.source_hash() and dom["name"] in tj["kernels"]:
+            traffic = tj["kernels"][dom["name"]]["bytes_per_dispatch"]
+            traffic_note = (f"FETCH_SIZE+WRITE_SIZE per dispatch, scaled by a "
+                            f"{tj['copy_bytes'] / 2**30:.0f} GiB copy ({os.path.basename(tpath)})")
+        else:
+            traffic_note = "kernel sources changed since the counters were taken"
+
+    if args.calibrate_copy:
+        src = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
@@ -179,7 +203,10 @@ def main() -> int:
                    "seed": wl["seed"]},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None},
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+                     "avg_launch_us": 1e3 * dom["total_ms"] / dom["launches"],
+                     "traffic_note": traffic_note},
         "cpu_baseline": cpu,
         "iterations": iters,
         "time_to_termination_ms": float(np.median([1e3 * wall / args.steps])),

@@ -55,6 +55,9 @@ def _load():
         lib.gg_pair_weights.argtypes = [ctypes.c_int64, vp, vp, ctypes.c_uint64,
                                         ctypes.c_int32, vp]
         lib.gg_fill_f32.argtypes = [ctypes.c_int64, ctypes.c_float, vp]
+        lib.gg_lfr.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(_GG)]
         lib.gg_sbm_batch.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32,
@@ -253,6 +256,28 @@ def planted_partition_batch(num_graphs: int, seed: int, n_range=(256, 65536),
     return Graph(off, tgt, unit_weights(tgt.shape[0]), f"batch{num_graphs}"), v_off
 
 
+def lfr_graph(n: int, seed: int, mu: float | None = None, tau1: float = 2.5,
+              mean_deg: float = 20.0, kmax: float = 1000.0, tau2: float = 2.0,
+              cmin: float = 20.0, cmax: float = 5000.0) -> tuple[Graph, np.ndarray]:
+    """LFR-like graph (power-law degrees and community sizes, mixing mu) with
+    unit weights and int32 offsets; also returns the planted communities.
+    mu defaults to a draw from U[0.1, 0.5] keyed by the seed."""
+    if mu is None:
+        x = philox4x32_10([seed & 0xFFFFFFFF, 0, 0, 0x4D55], [7, 7])
+        mu = 0.1 + 0.4 * (int(x[0]) / 2.0 ** 32)
+    comm = np.empty(n, dtype=np.int32)
+    gg = _GG()
+    rc = _load().gg_lfr(int(n), int(seed), float(tau1), float(mean_deg), float(kmax),
+                        float(tau2), float(cmin), float(cmax), float(mu), _ptr(comm),
+                        ctypes.byref(gg))
+    if rc != 0:
+        raise RuntimeError(f"gg_lfr failed ({rc})")
+    off, tgt = _take(gg, np.int32)
+    g = Graph(off, tgt, unit_weights(tgt.shape[0]), f"lfr{n}")
+    g.mu = mu
+    return g, comm
+
+
 def pack_graphs(graphs) -> tuple[Graph, np.ndarray]:
     """Concatenate graphs into one CSR with global target ids (int64
     offsets); returns the packed graph and v_off."""
@@ -278,4 +303,5 @@ def max_threads() -> int:
 __all__ = ["Graph", "build", "sbm", "rmat", "pair_weights", "unit_weights",
            "planted_partition_10k", "rmat_graph", "random_graph", "from_edges",
            "ring_of_cliques", "disjoint_cliques", "complete_bipartite",
-           "philox4x32_10", "max_threads", "planted_partition_batch", "pack_graphs"]
+           "philox4x32_10", "max_threads", "planted_partition_batch", "pack_graphs",
+           "lfr_graph"]

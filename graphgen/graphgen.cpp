@@ -455,6 +455,126 @@ int gg_sbm_batch(int32_t G, uint64_t seed, double nmin, double nmax, double dmin
   return 0;
 }
 
+// LFR-like benchmark graph (after Lancichinetti, Fortunato & Radicchi 2008,
+// simplified): degrees from a power law of exponent tau1 on [kmin, kmax] with
+// kmin chosen for the requested mean degree; community sizes from a power law
+// of exponent tau2 on [cmin, cmax] until they cover n; vertices placed, in
+// order of decreasing degree, into a random community large enough for their
+// (1 - mu) k intra-community stubs; intra stubs paired uniformly inside each
+// community, the remaining mu k stubs paired uniformly across the graph
+// (configuration model); self-loops, duplicate pairs and cross stubs that
+// land in one community are dropped.  comm_out (n entries, may be NULL)
+// receives the planted community of each vertex.
+namespace {
+double pl_sample(double u, double lo, double hi, double tau) {
+  const double a = std::pow(lo, 1.0 - tau), b = std::pow(hi, 1.0 - tau);
+  return std::pow(a + u * (b - a), 1.0 / (1.0 - tau));
+}
+double pl_mean(double lo, double hi, double tau) {
+  // mean of the continuous power law on [lo, hi]
+  const double z = (std::pow(hi, 1.0 - tau) - std::pow(lo, 1.0 - tau)) / (1.0 - tau);
+  const double m = (std::pow(hi, 2.0 - tau) - std::pow(lo, 2.0 - tau)) / (2.0 - tau);
+  return m / z;
+}
+// Fisher-Yates shuffle driven by Philox counters (stream, i).
+void shuffle32(std::vector<int32_t>& a, uint32_t stream, uint32_t k0, uint32_t k1) {
+  for (int64_t i = (int64_t)a.size() - 1; i > 0; --i) {
+    const P4 x = philox(stream, (uint32_t)i, (uint32_t)(i >> 32), 0x53484655u, k0, k1);
+    const uint64_t r = ((uint64_t)x.v[0] << 32 | x.v[1]) % (uint64_t)(i + 1);
+    std::swap(a[i], a[(int64_t)r]);
+  }
+}
+}  // namespace
+
+int gg_lfr(int64_t n, uint64_t seed, double tau1, double mean_deg, double kmax, double tau2,
+           double cmin, double cmax, double mu, int32_t* comm_out, gg_graph* out) {
+  memset(out, 0, sizeof(*out));
+  if (n < 2 || n > INT32_MAX || mean_deg <= 1.0 || kmax <= mean_deg || mu < 0.0 || mu > 1.0)
+    return -1;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x4C465231u;
+  // kmin for the requested mean (bisection on the continuous mean)
+  double lo = 1.0, hi = mean_deg;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (pl_mean(mid, kmax, tau1) < mean_deg) lo = mid; else hi = mid;
+  }
+  const double kmin = 0.5 * (lo + hi);
+  std::vector<int32_t> deg(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const P4 x = philox((uint32_t)i, (uint32_t)(i >> 32), 1u, 0x44454721u, k0, k1);
+    deg[i] = (int32_t)std::lround(pl_sample(u01(x.v[0], x.v[1]), kmin, kmax, tau1));
+  }
+  // community sizes
+  std::vector<int64_t> csize;
+  int64_t cov = 0;
+  for (uint32_t k = 0; cov < n; ++k) {
+    const P4 x = philox(k, 0u, 2u, 0x434F4D4Du, k0, k1);
+    int64_t c = (int64_t)std::lround(pl_sample(u01(x.v[0], x.v[1]), cmin, cmax, tau2));
+    if (cov + c > n) c = n - cov;
+    csize.push_back(c);
+    cov += c;
+  }
+  const int32_t nc = (int32_t)csize.size();
+  // place vertices by decreasing intra degree into communities with room
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return deg[a] != deg[b] ? deg[a] > deg[b] : a < b;
+  });
+  std::vector<int64_t> room(csize);
+  std::vector<int32_t> comm(n, -1);
+  std::vector<int32_t> by_size(nc);
+  for (int32_t c = 0; c < nc; ++c) by_size[c] = c;
+  std::sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) {
+    return csize[a] != csize[b] ? csize[a] > csize[b] : a < b;
+  });
+  int32_t nfit = 0;  // communities big enough: a prefix of by_size that only grows
+  for (int64_t t = 0; t < n; ++t) {
+    const int32_t v = order[t];
+    const int64_t kin = (int64_t)std::lround((1.0 - mu) * deg[v]);
+    while (nfit < nc && csize[by_size[nfit]] - 1 >= kin) ++nfit;
+    const int32_t nbig = nfit > 0 ? nfit : 1;
+    int32_t pick = -1;
+    for (uint32_t tries = 0; tries < 16 && pick < 0; ++tries) {
+      const P4 x = philox((uint32_t)v, tries, 3u, 0x504C4143u, k0, k1);
+      const int32_t c = by_size[x.v[0] % (uint32_t)nbig];
+      if (room[c] > 0) pick = c;
+    }
+    if (pick < 0) {  // fall back to the community with the most room
+      int32_t best = 0;
+      for (int32_t c = 1; c < nc; ++c) if (room[c] > room[best]) best = c;
+      pick = best;
+    }
+    comm[v] = pick;
+    --room[pick];
+  }
+  // stubs
+  std::vector<std::vector<int32_t>> intra(nc);
+  std::vector<int32_t> inter;
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t kin = (int32_t)std::lround((1.0 - mu) * deg[v]);
+    for (int32_t q = 0; q < kin; ++q) intra[comm[v]].push_back((int32_t)v);
+    for (int32_t q = kin; q < deg[v]; ++q) inter.push_back((int32_t)v);
+  }
+  std::vector<std::vector<Pair>> parts(nc + 1);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t c = 0; c < nc; ++c) {
+    shuffle32(intra[c], (uint32_t)c, k0, k1);
+    for (size_t q = 0; q + 1 < intra[c].size(); q += 2)
+      if (intra[c][q] != intra[c][q + 1]) parts[c].push_back(Pair{intra[c][q], intra[c][q + 1]});
+  }
+  shuffle32(inter, 0xFFFFFFFFu, k0, k1);
+  for (size_t q = 0; q + 1 < inter.size(); q += 2)
+    if (comm[inter[q]] != comm[inter[q + 1]]) parts[nc].push_back(Pair{inter[q], inter[q + 1]});
+  std::vector<Pair> all;
+  for (auto& p : parts) all.insert(all.end(), p.begin(), p.end());
+  Csr g;
+  if (!csr_from_pairs(n, all, &g)) return -2;
+  if (comm_out) for (int64_t v = 0; v < n; ++v) comm_out[v] = comm[v];
+  out->n = g.n; out->m = g.m; out->off = g.off; out->tgt = g.tgt;
+  return 0;
+}
+
 // Symmetric integer weights: w(u,v) = 1 + (h(min(u,v), max(u,v)) mod wmax)
 // where h is the first Philox word of counter (min, max) under the seed.
 void gg_pair_weights(int64_t n, const int64_t* off, const int32_t* tgt,

@@ -267,6 +267,48 @@ lpa_status lpa_run_batched(lpa_graph g, const lpa_options* opt, int32_t* labels,
                            int32_t* iters_done);
 
 /*
+ * Change predictor (a project addition, not in the paper): a perceptron
+ * 12 -> 64 -> 64 -> 1 (ReLU, sigmoid output) that estimates, from a flagged
+ * vertex's features, the probability that processing it changes its label.
+ * Parameters: LPA_PREDICTOR_PARAMS fp32 values in the order W1[12][64],
+ * b1[64], W2[64][64], b2[64], W3[64], b3 (W[k][j] maps input k to unit j);
+ * the network computes with bf16 weights and inputs and fp32 accumulation.
+ * Samples X are n rows of 12 fp32 features, labels y are 0/1 fp32; both host
+ * or device memory.  The loss is the mean binary cross-entropy with the
+ * positive class weighted by pos_weight; the optimiser is Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected).
+ */
+#define LPA_PREDICTOR_PARAMS 5057
+typedef struct lpa_predictor_s* lpa_predictor;
+
+typedef struct lpa_train_options {
+  int32_t epochs;
+  int32_t batch;       /* samples per Adam step */
+  float lr;
+  float pos_weight;
+  uint64_t seed;       /* sample order */
+} lpa_train_options;
+
+/* New predictor with He-uniform weights drawn from seed, zero biases. */
+lpa_status lpa_predictor_create(uint64_t seed, void* stream, lpa_predictor* out);
+void lpa_predictor_destroy(lpa_predictor p);
+/* Replace / read the fp32 parameters (host arrays); set also resets Adam. */
+lpa_status lpa_predictor_set_params(lpa_predictor p, const float* params);
+lpa_status lpa_predictor_get_params(lpa_predictor p, float* params);
+/* Gradient of the loss over the n samples (grad: host, may be NULL; loss:
+ * host mean loss, may be NULL). */
+lpa_status lpa_predictor_gradient(lpa_predictor p, const float* X, const float* y, int64_t n,
+                                  float pos_weight, float* grad, double* loss);
+/* One Adam step with the given host gradient (NULL: the last computed one). */
+lpa_status lpa_predictor_adam(lpa_predictor p, const float* grad, float lr);
+/* Minibatch training; final_loss (host, may be NULL): mean loss of the last
+ * epoch. */
+lpa_status lpa_predictor_train(lpa_predictor p, const float* X, const float* y, int64_t n,
+                               const lpa_train_options* opt, float* final_loss);
+/* Probabilities for n samples (prob: host or device). */
+lpa_status lpa_predictor_predict(lpa_predictor p, const float* X, int64_t n, float* prob);
+
+/*
  * Modularity of a labelling, Eq. 1, in fp64:
  *   Q = sum_c [ sigma_c / 2m - (Sigma_c / 2m)^2 ]
  * with 2m the total CSR weight, Sigma_c the summed weighted degree of the

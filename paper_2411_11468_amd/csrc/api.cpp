@@ -12,9 +12,32 @@
 #include <vector>
 
 #include "../../include/lpa.h"
+#include "host_common.h"
 #include "lpa_internal.h"
 
 using namespace lpa;
+
+namespace lpa {
+
+thread_local std::string g_err;
+
+lpa_status fail(lpa_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+}  // namespace lpa
 
 namespace {
 
@@ -28,31 +51,6 @@ const char* const kKidNames[kNumKids] = {
     "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
     "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
     "push_hubs", "flag_decide", "hub_acc_rest", "batch_step"};
-
-thread_local std::string g_err;
-
-lpa_status fail(lpa_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define LPA_HIP(call)                                                        \
-  do {                                                                       \
-    hipError_t e_ = (call);                                                  \
-    if (e_ != hipSuccess)                                                    \
-      return fail(LPA_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-bool is_device_ptr(const void* p) {
-  if (!p) return false;
-  hipPointerAttribute_t at;
-  std::memset(&at, 0, sizeof(at));
-  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
-}
 
 }  // namespace
 

@@ -1,0 +1,94 @@
+// lpa_mlp.h -- change-predictor network: parameter layout, bfloat16 helpers
+// and the one-wave MFMA inference routine shared by mlp.hip and the frontier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpa {
+
+constexpr int kMlpIn = 12;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
+                           kMlpHidden + kMlpHidden + 1;  // 5,057
+
+// bfloat16 = the upper 16 bits of an IEEE binary32; round to nearest, ties to
+// even (NaN kept quiet).
+__host__ __device__ inline uint16_t bf16_bits(float x) {
+  union { float f; uint32_t u; } c;
+  c.f = x;
+  if ((c.u & 0x7F800000u) == 0x7F800000u && (c.u & 0x007FFFFFu))
+    return (uint16_t)((c.u >> 16) | 0x0040u);
+  c.u += 0x7FFFu + ((c.u >> 16) & 1u);
+  return (uint16_t)(c.u >> 16);
+}
+__host__ __device__ inline float bf16_round(float x) {
+  union { float f; uint32_t u; } c;
+  c.u = (uint32_t)bf16_bits(x) << 16;
+  return c.f;
+}
+
+// MFMA operand tiles of the bf16 weights (see k_mlp_pack) and fp32 biases.
+struct MlpTiles {
+  uint16_t w1t[4][64][4];
+  uint16_t w2t[4][4][64][4];
+  float b1[kMlpHidden];
+  float b2[kMlpHidden];
+  float w3[kMlpHidden];
+  float b3;
+};
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Logit for 16 samples, one wave: lane l holds features 4 (l/16) .. 4 (l/16)+3
+// of sample l % 16 in f (zero beyond feature 11); every lane returns the logit
+// of its sample.  All 64 lanes must be active.
+__device__ inline float mlp_infer16(const MlpTiles& t, const float f[4]) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  bf16x4_t xb;
+  for (int j = 0; j < 4; ++j) xb[j] = (short)bf16_bits(f[j]);
+  bf16x4_t h1[4];
+  const f32x4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(t.w1t[m][lane]);
+    const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, zero, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float v = fmaxf(acc[i] + t.b1[16 * m + 4 * g + i], 0.0f);
+      h1[m][i] = (short)bf16_bits(v);
+    }
+  }
+  float part = 0.0f;
+#pragma unroll
+  for (int mo = 0; mo < 4; ++mo) {
+    f32x4_t acc = zero;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(t.w2t[mo][kb][lane]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[kb], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u = 16 * mo + 4 * g + i;
+      part += fmaxf(acc[i] + t.b2[u], 0.0f) * t.w3[u];
+    }
+  }
+  part += __shfl_xor(part, 16);
+  part += __shfl_xor(part, 32);
+  return part + t.b3;
+}
+
+hipError_t launch_mlp_grad(const float* p, const float* X, const float* y, int64_t B,
+                           float pos_weight, float* grad, double* loss, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int t, float lr,
+                       double beta1, double beta2, float eps, hipStream_t s);
+hipError_t launch_mlp_pack(const float* p, MlpTiles* t, hipStream_t s);
+hipError_t launch_mlp_gather(const float* X, const float* y, const int32_t* idx, int64_t n,
+                             float* sX, float* sy, hipStream_t s);
+hipError_t launch_mlp_infer(const MlpTiles* t, const float* X, int64_t B, float* out,
+                            hipStream_t s);
+
+}  // namespace lpa

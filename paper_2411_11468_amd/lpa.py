@@ -68,6 +68,11 @@ class lpa_kernel_profile(ctypes.Structure):
                 ("edges", ctypes.c_int64), ("vertices", ctypes.c_int64)]
 
 
+class lpa_train_options(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("pos_weight", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
 class lpa_iter_stats(ctypes.Structure):
     _fields_ = [("iteration", ctypes.c_int32), ("pick_less", ctypes.c_int32),
                 ("changed", ctypes.c_int64), ("processed", ctypes.c_int64),
@@ -78,7 +83,10 @@ class lpa_iter_stats(ctypes.Structure):
 EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run",
             "lpa_modularity", "lpa_graph_classes", "lpa_get_flags", "lpa_profile",
             "lpa_profile_reset", "lpa_destroy", "lpa_status_string", "lpa_last_error",
-            "lpa_create_batched", "lpa_run_batched")
+            "lpa_create_batched", "lpa_run_batched", "lpa_predictor_create",
+            "lpa_predictor_destroy", "lpa_predictor_set_params", "lpa_predictor_get_params",
+            "lpa_predictor_gradient", "lpa_predictor_adam", "lpa_predictor_train",
+            "lpa_predictor_predict")
 
 _lib = None
 
@@ -123,6 +131,25 @@ def load_library(path: str = LIB_PATH):
     lib.lpa_run_batched.restype = ctypes.c_int
     lib.lpa_destroy.argtypes = [vp]
     lib.lpa_destroy.restype = None
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.lpa_predictor_create.argtypes = [ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+    lib.lpa_predictor_create.restype = ctypes.c_int
+    lib.lpa_predictor_destroy.argtypes = [vp]
+    lib.lpa_predictor_destroy.restype = None
+    lib.lpa_predictor_set_params.argtypes = [vp, vp]
+    lib.lpa_predictor_set_params.restype = ctypes.c_int
+    lib.lpa_predictor_get_params.argtypes = [vp, vp]
+    lib.lpa_predictor_get_params.restype = ctypes.c_int
+    lib.lpa_predictor_gradient.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, vp,
+                                           ctypes.POINTER(ctypes.c_double)]
+    lib.lpa_predictor_gradient.restype = ctypes.c_int
+    lib.lpa_predictor_adam.argtypes = [vp, vp, ctypes.c_float]
+    lib.lpa_predictor_adam.restype = ctypes.c_int
+    lib.lpa_predictor_train.argtypes = [vp, vp, vp, ctypes.c_int64,
+                                        ctypes.POINTER(lpa_train_options), fp]
+    lib.lpa_predictor_train.restype = ctypes.c_int
+    lib.lpa_predictor_predict.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.lpa_predictor_predict.restype = ctypes.c_int
     lib.lpa_status_string.argtypes = [ctypes.c_int]
     lib.lpa_status_string.restype = ctypes.c_char_p
     lib.lpa_last_error.argtypes = []
@@ -417,3 +444,86 @@ class LpaBatch(LpaGraph):
                 out = np.empty(self.num_vertices, dtype=np.int32)
         it, per, last = lpa_run_batched(self.handle, out, self.num_graphs, mode=m, **kw)
         return BatchResult(out, it, per, last)
+
+
+PREDICTOR_PARAMS = 5057
+PREDICTOR_FEATURES = 12
+
+
+def _f32(x):
+    """fp32 contiguous view: torch tensors stay where they are, the rest
+    becomes a numpy array."""
+    if _is_torch(x):
+        import torch
+        return x.detach().to(torch.float32).contiguous()
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+class Predictor:
+    """Owns an lpa_predictor handle (the change-predictor network)."""
+
+    def __init__(self, seed: int = 0, params=None, device_stream: bool = True):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.lpa_predictor_create(seed, _current_stream(device_stream), ctypes.byref(h)))
+        self.handle = h
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.shape[0] != PREDICTOR_PARAMS:
+            raise ValueError(f"expected {PREDICTOR_PARAMS} parameters")
+        _check(load_library().lpa_predictor_set_params(self.handle, _addr(p)))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(PREDICTOR_PARAMS, dtype=np.float32)
+        _check(load_library().lpa_predictor_get_params(self.handle, _addr(out)))
+        return out
+
+    def gradient(self, X, y, pos_weight: float = 1.0):
+        X, y = _f32(X), _f32(y)
+        g = np.empty(PREDICTOR_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(load_library().lpa_predictor_gradient(self.handle, _addr(X), _addr(y),
+                                                     int(y.shape[0]), pos_weight, _addr(g),
+                                                     ctypes.byref(loss)))
+        return g, loss.value
+
+    def adam(self, grad=None, lr: float = 1e-3) -> None:
+        g = None if grad is None else np.ascontiguousarray(grad, dtype=np.float32)
+        _check(load_library().lpa_predictor_adam(self.handle, _addr(g), lr))
+
+    def train(self, X, y, *, epochs: int = 1, batch: int = 1024, lr: float = 1e-3,
+              pos_weight: float = 1.0, seed: int = 0) -> float:
+        X, y = _f32(X), _f32(y)
+        o = lpa_train_options(epochs=epochs, batch=batch, lr=lr, pos_weight=pos_weight,
+                              seed=seed)
+        loss = ctypes.c_float()
+        _check(load_library().lpa_predictor_train(self.handle, _addr(X), _addr(y),
+                                                  int(y.shape[0]), ctypes.byref(o),
+                                                  ctypes.byref(loss)))
+        return loss.value
+
+    def predict(self, X, out=None):
+        X = _f32(X)
+        n = int(X.shape[0])
+        if out is None:
+            if _is_torch(X) and X.is_cuda:
+                import torch
+                out = torch.empty(n, dtype=torch.float32, device=X.device)
+            else:
+                out = np.empty(n, dtype=np.float32)
+        _check(load_library().lpa_predictor_predict(self.handle, _addr(X), n, _addr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().lpa_predictor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -47,6 +47,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lpa.lpa_options) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(lpa.lpa_kernel_profile) == 24 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lpa.lpa_iter_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(lpa.lpa_train_options) == 4 + 4 + 4 + 4 + 8
 
 
 def test_defaults(lib):
