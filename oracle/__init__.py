@@ -12,7 +12,10 @@ Functions and the passages they follow (paper arXiv 2411.11468):
   modularity        Eq. 1, community form.
   modularity_pairs  Eq. 1, pair form over all vertex pairs (tiny graphs).
   local_optimal     Eq. 3 attained by the current label, per vertex.
-  mlp_*             the change-predictor network (fp64 on bf16-rounded data).
+  lpa_learned       Algorithm 1 with the learned change predictor: per-vertex
+                    state records, features, skipping schedule, guard and
+                    fallback, traces (learned_oracle.c; a project addition).
+  mlp (module)      the change-predictor network (fp64 on bf16-rounded data).
 """
 from __future__ import annotations
 
@@ -24,7 +27,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "lpa_oracle.c")
+_SRCS = [os.path.join(_HERE, "lpa_oracle.c"), os.path.join(_HERE, "learned_oracle.c")]
 _LIB = os.path.join(_HERE, "liblpa_oracle.so")
 _lib = None
 
@@ -40,7 +43,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                               _SRC, "-o", tmp, "-lm"])
+                               *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -61,6 +64,20 @@ def _load():
             f.restype = ctypes.c_double
         lib.oracle_local_optimal.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp]
         lib.oracle_local_optimal.restype = ctypes.c_int64
+        lib.oracle_lpa_learned.argtypes = [
+            ctypes.c_int64, vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_double,
+            ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int64,
+            vp, vp, vp, vp, ctypes.c_int32, vp, vp]
+        lib.oracle_lpa_learned.restype = ctypes.c_int
+        lib.oracle_mlp_logit.argtypes = [vp, vp]
+        lib.oracle_mlp_logit.restype = ctypes.c_double
+        lib.oracle_features.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+        lib.oracle_features.restype = ctypes.c_int
+        lib.oracle_lq.argtypes = [ctypes.c_uint64, ctypes.c_float, vp]
+        lib.oracle_lq.restype = ctypes.c_int
+        lib.oracle_sample_draw.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64]
+        lib.oracle_sample_draw.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -126,3 +143,91 @@ def local_optimal(offsets, targets, weights, labels) -> np.ndarray:
     if bad < 0:
         raise MemoryError("oracle_local_optimal")
     return out.astype(bool)
+
+
+class LearnedStats(ctypes.Structure):
+    _fields_ = [("iteration", ctypes.c_int32), ("pick_less", ctypes.c_int32),
+                ("changed", ctypes.c_int64), ("processed", ctypes.c_int64),
+                ("edges_scanned", ctypes.c_int64), ("skipped", ctypes.c_int64),
+                ("predicted", ctypes.c_int64), ("false_neg", ctypes.c_int64),
+                ("skipping", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+
+
+@dataclass
+class LearnedResult:
+    labels: np.ndarray
+    stats: list
+    iterations: int
+    records: np.ndarray        # uint8 [n, 8]
+    min_margin: float          # smallest |z - z_theta| over all predictions
+    trace: dict | None         # X [k, 12], y [k], v [k], l [k] (k = samples kept)
+    trace_total: int           # samples drawn (may exceed the capacity)
+
+
+def lpa_learned(offsets, targets, weights=None, *, params=None, z_theta: float = 0.0,
+                tolerance: float = 0.05, max_iterations: int = 20, pl_period: int = 4,
+                prune: bool = True, guard: int = 4, max_pred_degree: int = 8192,
+                fn_bound: float = 0.02, sample_rate: float = 0.0, seed: int = 0,
+                trace_cap: int = 0) -> LearnedResult:
+    """Synchronous LPA with the learned change predictor (learned_oracle.c).
+    params: 5,057 fp32 network parameters or None (plain schedule)."""
+    off, tgt, w = _csr(offsets, targets, weights)
+    n = off.shape[0] - 1
+    labels = np.empty(max(n, 0), dtype=np.int32)
+    rec = np.empty((max(n, 0), 8), dtype=np.uint8)
+    cap = max(int(max_iterations), 0)
+    stats = (LearnedStats * max(cap, 1))()
+    iters = ctypes.c_int32(0)
+    margin = ctypes.c_double(0.0)
+    P = None if params is None else np.ascontiguousarray(params, dtype=np.float32).ravel()
+    if P is not None and P.shape[0] != 5057:
+        raise ValueError("params must hold 5057 values")
+    tc = max(int(trace_cap), 0)
+    tX = np.zeros((max(tc, 1), 12), dtype=np.float32) if tc else None
+    ty = np.zeros(max(tc, 1), dtype=np.float32) if tc else None
+    tv = np.zeros(max(tc, 1), dtype=np.int32) if tc else None
+    tl = np.zeros(max(tc, 1), dtype=np.int32) if tc else None
+    tcount = ctypes.c_int64(0)
+    rc = _load().oracle_lpa_learned(
+        n, _p(off), _p(tgt), _p(w), float(tolerance), cap, int(pl_period), int(bool(prune)),
+        int(guard), int(max_pred_degree), _p(P), float(z_theta), float(fn_bound),
+        float(sample_rate), int(seed) & 0xFFFFFFFFFFFFFFFF, _p(tX), _p(ty), _p(tv), _p(tl),
+        tc, ctypes.cast(ctypes.byref(tcount), ctypes.c_void_p), _p(labels), _p(rec),
+        ctypes.cast(stats, ctypes.c_void_p), cap,
+        ctypes.cast(ctypes.byref(iters), ctypes.c_void_p),
+        ctypes.cast(ctypes.byref(margin), ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError("oracle_lpa_learned rejected its arguments")
+    k = int(iters.value)
+    st = [{f: getattr(s, f) for f, _ in LearnedStats._fields_} for s in stats[:k]]
+    trace = None
+    if tc:
+        kept = min(int(tcount.value), tc)
+        trace = dict(X=tX[:kept].copy(), y=ty[:kept].copy(), v=tv[:kept].copy(),
+                     l=tl[:kept].copy())
+    return LearnedResult(labels, st, k, rec, float(margin.value), trace, int(tcount.value))
+
+
+def mlp_logit(params, features) -> float:
+    P = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    f = np.ascontiguousarray(features, dtype=np.float32).ravel()
+    return float(_load().oracle_mlp_logit(_p(P), _p(f)))
+
+
+def record_features(record, iteration: int, cap: int, pl_period: int) -> np.ndarray:
+    r = np.ascontiguousarray(record, dtype=np.uint8).ravel()
+    f = np.zeros(12, dtype=np.float32)
+    _load().oracle_features(_p(r), int(iteration), int(cap), int(pl_period), _p(f))
+    return f
+
+
+def log_quant(u: int, x: float) -> tuple:
+    """(lq of the integer u >= 1, lq of the fp32 value x >= 1)."""
+    out = np.zeros(2, dtype=np.uint8)
+    _load().oracle_lq(int(u), float(x), _p(out))
+    return int(out[0]), int(out[1])
+
+
+def sample_draw(seed: int, iteration: int, v: int) -> float:
+    return float(_load().oracle_sample_draw(int(seed) & 0xFFFFFFFFFFFFFFFF, int(iteration),
+                                            int(v)))

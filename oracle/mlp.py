@@ -56,23 +56,23 @@ def _w(a, exact):
     return np.asarray(a, dtype=np.float64) if exact else bf16_round(a).astype(np.float64)
 
 
-def forward(p: dict, X: np.ndarray, round_hidden: bool = False, exact: bool = False):
+def forward(p: dict, X: np.ndarray, bf16_h1: bool = False, exact: bool = False):
     """Logits z (shape [B]) and hidden activations (h1, h2), fp64.  Weights and
-    inputs are taken at bf16 precision (exact=True: at their full value); with
-    round_hidden the hidden activations are also rounded to bf16 before the
-    next layer.  Biases stay fp32."""
+    inputs are taken at bf16 precision (exact=True: at their full value).  With
+    bf16_h1 the first hidden layer's output, an operand of the second matrix
+    product, is rounded to bf16 (through fp32) as in bf16 inference; the
+    second hidden layer feeds only the final fp32 dot product and is never
+    rounded.  Biases stay fp32."""
     W1, b1 = _w(p["W1"], exact), np.asarray(p["b1"], dtype=np.float64)
     W2, b2 = _w(p["W2"], exact), np.asarray(p["b2"], dtype=np.float64)
     W3, b3 = _w(p["W3"], exact), np.asarray(p["b3"], dtype=np.float64)
     x = _w(X, exact)
     a1 = x @ W1 + b1
     h1 = np.maximum(a1, 0.0)
-    if round_hidden:
+    if bf16_h1:
         h1 = bf16_round(h1.astype(np.float32)).astype(np.float64)
     a2 = h1 @ W2 + b2
     h2 = np.maximum(a2, 0.0)
-    if round_hidden:
-        h2 = bf16_round(h2.astype(np.float32)).astype(np.float64)
     z = (h2 @ W3 + b3)[:, 0]
     return z, (x, a1, h1, a2, h2)
 
@@ -91,10 +91,10 @@ def bce_loss(z: np.ndarray, y: np.ndarray, pos_weight: float = 1.0) -> float:
 
 
 def backward(p: dict, X: np.ndarray, y: np.ndarray, pos_weight: float = 1.0,
-             round_hidden: bool = False, exact: bool = False) -> dict:
+             bf16_h1: bool = False, exact: bool = False) -> dict:
     """Gradients of bce_loss(forward(p, X)) w.r.t. the parameters (chain rule
     through the layers; the bf16 rounding is treated as identity)."""
-    z, (x, a1, h1, a2, h2) = forward(p, X, round_hidden, exact)
+    z, (x, a1, h1, a2, h2) = forward(p, X, bf16_h1, exact)
     y = np.asarray(y, dtype=np.float64)
     B = z.shape[0]
     s = sigmoid(z)

@@ -5,10 +5,10 @@ Tolerances follow from the arithmetic.  The training kernel computes in fp32
 on the same bf16-rounded weights and inputs as the oracle, so logits and
 gradients agree to fp32 summation error (relative 1e-4 of the largest term,
 with slack for atomics' order).  Inference runs on MFMA with bf16 hidden
-activations; a fp32 accumulation landing on the other side of a bf16 rounding
-boundary moves one hidden value by one bf16 ulp (2^-8 relative), so logits
-are compared against the oracle with bf16 hidden rounding at 2e-2 absolute +
-1e-2 relative, and on average far tighter.  Adam is elementwise fp32 against
+first-layer activations; a fp32 accumulation landing on the other side of a
+bf16 rounding boundary moves one hidden value by one bf16 ulp (2^-8
+relative), so logits are compared against the oracle with bf16 first-layer
+rounding at 2e-2 absolute + 1e-2 relative, and on average far tighter.  Adam is elementwise fp32 against
 fp64, so one fp32 ulp of the parameter.
 """
 import numpy as np
@@ -107,7 +107,7 @@ def test_predict_matches_oracle(n):
     X, _ = _samples(n, 22, scale=2.0)
     pr = lpa.Predictor(params=mlp.flatten(p))
     prob = pr.predict(X)
-    z, _ = mlp.forward(p, X, round_hidden=True)
+    z, _ = mlp.forward(p, X, bf16_h1=True)
     zg = np.log(prob.astype(np.float64)) - np.log1p(-prob.astype(np.float64))
     ok = np.abs(prob - mlp.sigmoid(z)) < 1e-6     # saturated probabilities
     err = np.abs(zg - z)
