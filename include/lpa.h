@@ -148,6 +148,9 @@ typedef struct lpa_tuning {
  *                                   at least half of the CSR entries, push
  *                                   otherwise, decided on the GPU per
  *                                   iteration (default)
+ *   learned         1: skip the vertices that the predictor attached with
+ *                   lpa_set_predictor marks unchanged (see there; a project
+ *                   addition, not in the paper); 0: plain run (default)
  */
 typedef enum lpa_flag_mode {
   LPA_FLAGS_AUTO = 0,
@@ -175,7 +178,7 @@ typedef struct lpa_options {
   int32_t profile;
   int32_t flag_mode;
   int32_t launch;
-  int32_t reserved;
+  int32_t learned;
 } lpa_options;
 
 /* Statistics of one iteration. */
@@ -185,8 +188,8 @@ typedef struct lpa_iter_stats {
   int64_t changed;        /* vertices whose label changed */
   int64_t processed;      /* vertices processed (flagged at the start) */
   int64_t edges_scanned;  /* CSR entries read by the label scan */
-  float ms;               /* GPU time of the iteration */
-  int32_t reserved;
+  float ms;               /* GPU time of the iteration (eager launch) */
+  int32_t skipped;        /* learned runs: flagged vertices left unprocessed */
 } lpa_iter_stats;
 
 /*
@@ -307,6 +310,75 @@ lpa_status lpa_predictor_train(lpa_predictor p, const float* X, const float* y, 
                                const lpa_train_options* opt, float* final_loss);
 /* Probabilities for n samples (prob: host or device). */
 lpa_status lpa_predictor_predict(lpa_predictor p, const float* X, int64_t n, float* prob);
+
+/*
+ * Learned skipping (a project addition, not in the paper).  A graph with a
+ * predictor attached runs, when lpa_options.learned = 1, Algorithm 1 with
+ * these changes:
+ *  - every evaluated vertex of degree 1 .. lpa_tuning.block (the vertices of
+ *    the non-hub classes) keeps an 8-byte state record (label shares of its
+ *    last evaluation, log-quantised degrees, change history, iteration);
+ *  - from iteration 1 on, the frontier computes 12 features from the record
+ *    of each flagged such vertex and runs the predictor on them (bf16 MFMA);
+ *    in a skipping iteration a vertex whose probability of change is below
+ *    threshold is not processed and keeps its flag;
+ *  - iteration l skips unless l % guard_period == 0 or the previous
+ *    iteration changed fewer than tolerance * N labels (guard_period 0: no
+ *    periodic guard); the other iterations are plain sweeps that still
+ *    predict, and if more than fn_bound of the vertices predicted unchanged
+ *    in such a sweep change, skipping is off for the rest of the run;
+ *  - the stop test of Algorithm 1 is taken only after an iteration that
+ *    skipped no vertex.
+ * Features, in order: log-quantised degree and weighted degree (/ 64), own
+ * label share, best-second margin, best-own gain (/ 255 of the total
+ * weight), changed in l-1, l-2, l-3, l / cap, Pick-Less in l, iterations
+ * since the last evaluation / cap, distinct labels per entry.
+ */
+typedef struct lpa_learned_options {
+  float threshold;        /* skip when P(change) < threshold (default 0.1) */
+  float fn_bound;         /* fallback bound on false negatives (default 0.02) */
+  int32_t guard_period;   /* plain guard sweep every guard_period (default 4) */
+  int32_t reserved;
+} lpa_learned_options;
+
+typedef struct lpa_learned_iter {
+  int32_t iteration;
+  int32_t skipping;         /* 1 if the iteration skipped predicted vertices */
+  int32_t fallback;         /* skipping switched off after this iteration */
+  int32_t reserved;
+  int64_t skipped;          /* flagged vertices left unprocessed */
+  int64_t predicted;        /* vertices predicted unchanged */
+  int64_t false_negatives;  /* plain iterations: of those, changed */
+} lpa_learned_iter;
+
+void lpa_learned_options_default(lpa_learned_options* o);
+/* Attach p (NULL detaches) with options lo (NULL: defaults).  The graph
+ * reads p's parameters at every run; p must outlive its use by g.
+ * Errors: LPA_ERR_INVALID (threshold outside (0, 1), fn_bound < 0,
+ * guard_period < 0); LPA_ERR_UNSUPPORTED (batched handle). */
+lpa_status lpa_set_predictor(lpa_graph g, lpa_predictor p, const lpa_learned_options* lo);
+/* Per-iteration skipping statistics of the last learned run (count: host,
+ * iterations written, at most cap). */
+lpa_status lpa_learned_history(lpa_graph g, lpa_learned_iter* out, int32_t cap,
+                               int32_t* count);
+/* The N state records after the last learned or traced run (8 N bytes, host
+ * or device).  Errors: LPA_ERR_STATE before any such run. */
+lpa_status lpa_get_records(lpa_graph g, uint64_t* out);
+/*
+ * Training traces: run Algorithm 1 as lpa_run with opt (learned skipping if
+ * opt->learned, eager launch) and, in every iteration l >= 1, sample each
+ * processed vertex of a non-hub class with probability sample_rate: the
+ * draw is u = (SplitMix64 output of state seed + 0x9E3779B97F4A7C15 *
+ * (1 + (l << 32 | v))) >> 11, taken when u * 2^-53 < sample_rate.  A sample
+ * is its 12 features at the start of the iteration (X, row-major), 1 if the
+ * vertex then changed label else 0 (y), the vertex and the iteration.  X, y,
+ * vertex, iteration: cap entries each (12 cap for X), host or device; vertex
+ * and iteration may be NULL.  Samples beyond cap are drawn but dropped;
+ * *count (host) receives the number drawn; their order is unspecified.
+ */
+lpa_status lpa_trace(lpa_graph g, const lpa_options* opt, double sample_rate, uint64_t seed,
+                     float* X, float* y, int32_t* vertex, int32_t* iteration, int64_t cap,
+                     int64_t* count);
 
 /*
  * Modularity of a labelling, Eq. 1, in fp64:

@@ -14,6 +14,7 @@
 #include "../../include/lpa.h"
 #include "host_common.h"
 #include "lpa_internal.h"
+#include "lpa_mlp.h"
 
 using namespace lpa;
 
@@ -53,6 +54,8 @@ const char* const kKidNames[kNumKids] = {
     "push_hubs", "flag_decide", "hub_acc_rest", "batch_step"};
 
 }  // namespace
+
+struct RunCtx;
 
 struct lpa_graph_s {
   hipStream_t stream = nullptr;
@@ -132,6 +135,7 @@ struct lpa_graph_s {
       verts = (int64_t)h.active[c];
       bytes = eb * edges + (4.0 + ob + 4.0) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
+      if (acct_feat) bytes += 16.0 * verts;  // state record read and written
     } else if (kid == kKidHubAcc) {
       edges = (int64_t)h.edges[kClassHub];
       bytes = eb * edges;
@@ -142,6 +146,8 @@ struct lpa_graph_s {
       // flag, class and change byte per vertex; flag clear + list id per
       // taken vertex
       bytes = 3.0 * n + 5.0 * (double)h.processed;
+      // learned frontier: the record of every predicted or traced vertex
+      if (acct_feat) bytes += 8.0 * (double)(h.processed + h.skipped);
     } else if (kid == kKidPull || kid == kKidPullHubs) {
       // row offsets and class per vertex, target + change byte per entry
       // read, flag byte per vertex; the two kernels share one counter, so
@@ -201,7 +207,16 @@ struct lpa_graph_s {
   long long* b_changed = nullptr;
   // captured iterations, one executable graph per launch configuration
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph_exec[12] = {};
+  hipGraphExec_t graph_exec[24] = {};
+  const MlpTiles* graph_tiles[24] = {};
+  // learned skipping: attached predictor and options, per-vertex records
+  lpa_predictor pred = nullptr;
+  lpa_learned_options lopt{};
+  unsigned long long* lrec = nullptr;
+  bool lrec_valid = false;
+  int learn_grid = 1;
+  int32_t learned_iters = 0;   // iterations of the last learned run
+  bool acct_feat = false;      // profile: the run keeps records
 
   BatchArgs batch_args() const {
     BatchArgs b;
@@ -218,7 +233,7 @@ struct lpa_graph_s {
     return LPA_OK;
   }
 
-  lpa_status iteration_graph(const lpa_options& o, hipGraphExec_t* out);
+  lpa_status iteration_graph(const lpa_options& o, const RunCtx& rc, hipGraphExec_t* out);
 
   HubArgs hub_args(int async_mode) const {
     HubArgs a;
@@ -270,6 +285,14 @@ void lpa_tuning_default(lpa_tuning* t) {
   t->hub_chunk = 8192;
   t->max_retries = 32;
   t->xcd_local = 1;
+}
+
+void lpa_learned_options_default(lpa_learned_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->threshold = 0.1f;
+  o->fn_bound = 0.02f;
+  o->guard_period = 4;
 }
 
 const char* lpa_status_string(lpa_status s) {
@@ -402,6 +425,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->grid[c] = (int)std::max<int64_t>(1, std::min<int64_t>(need, sweep_max_resident(c)));
   }
   G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 256 * 8));
+  G->learn_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
   G->apply_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256 * 8));
   G->pull_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 31) / 32, 256 * 8));
   G->push_grid = 256 * 8;
@@ -531,9 +555,17 @@ static lpa_status stage_labels(lpa_graph g, const int32_t* src, int32_t* dst) {
 // iteration's Pick-Less flag and the stop flag from device memory, so the
 // sequence can be replayed without the host (eagerly or as a captured graph).
 // mark(kid) brackets launches for the optional per-kernel profile.
+// Learned-variant context of a run: records kept (feat), predictor tiles
+// (NULL: no predictions) and trace buffers (X NULL: no trace).
+struct RunCtx {
+  bool feat = false;
+  const MlpTiles* tiles = nullptr;
+  TraceArgs tr{};
+};
+
 template <typename Mark>
-static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, hipStream_t s,
-                                    Mark&& mark) {
+static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const RunCtx& rc,
+                                    hipStream_t s, Mark&& mark) {
   const int64_t n = g->n;
   const int async_mode = o.mode == LPA_MODE_ASYNC;
   // without pruning every vertex is processed in every iteration
@@ -542,7 +574,11 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, hipStream
   if (lpa_status e = mark(kKidPlan)) return e;
   LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
   if (lpa_status e = mark(kKidFrontier)) return e;
-  LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
+  if (rc.feat)
+    LPA_HIP(launch_frontier_learned(n, g->F, g->cls, g->lists, g->chg, g->st, g->lrec, rc.tiles,
+                                    rc.tr, g->learn_grid, s));
+  else
+    LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
   if (g->H > 0) {
     if (g->tun.xcd_local) {
       if (lpa_status e = mark(kKidHubAcc)) return e;
@@ -556,12 +592,13 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, hipStream
   a.chg = g->chg; a.st = g->st;
   a.async_mode = async_mode;
   a.max_retries = g->tun.max_retries;
+  a.rec = g->lrec;
   for (int c = kClassHub - 1; c >= 1; --c) {
     if (g->cls_count[c] == 0) continue;
     a.cls = c;
     a.active = g->lists[c];
     if (lpa_status e = mark(kKidSweep0 + c)) return e;
-    LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], s));
+    LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], rc.feat, s));
   }
   if (g->H > 0) {
     if (lpa_status e = mark(kKidHubFin)) return e;
@@ -594,13 +631,26 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, hipStream
     if (lpa_status e = mark(kKidBatch)) return e;
     LPA_HIP(launch_batch_step(g->batch_args(), g->chg, g->F, g->st, s));
   }
+  if (rc.tr.X) {
+    if (lpa_status e = mark(-1)) return e;
+    LPA_HIP(launch_trace_label(g->st, g->chg, rc.tr, s));
+  }
   if (lpa_status e = mark(-1)) return e;
   LPA_HIP(launch_iter_end(g->st, g->hist, n, s));
   return LPA_OK;
 }
 
-lpa_status lpa_graph_s::iteration_graph(const lpa_options& o, hipGraphExec_t* out) {
-  const int key = (o.mode == LPA_MODE_ASYNC ? 6 : 0) + (o.prune ? 3 : 0) + o.flag_mode;
+lpa_status lpa_graph_s::iteration_graph(const lpa_options& o, const RunCtx& rc,
+                                        hipGraphExec_t* out) {
+  // a captured learned iteration holds the predictor's tile address: rebuild
+  // it when another predictor is attached
+  const int key = (o.mode == LPA_MODE_ASYNC ? 6 : 0) + (o.prune ? 3 : 0) + o.flag_mode +
+                  (rc.feat ? 12 : 0);
+  if (graph_exec[key] && graph_tiles[key] != rc.tiles) {
+    (void)hipGraphExecDestroy(graph_exec[key]);
+    graph_exec[key] = nullptr;
+  }
+  graph_tiles[key] = rc.tiles;
   if (graph_exec[key]) {
     *out = graph_exec[key];
     return LPA_OK;
@@ -608,7 +658,7 @@ lpa_status lpa_graph_s::iteration_graph(const lpa_options& o, hipGraphExec_t* ou
   if (!cap_stream) LPA_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
   LPA_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
   auto nomark = [](int) -> lpa_status { return LPA_OK; };
-  const lpa_status st = enqueue_iteration(this, o, cap_stream, nomark);
+  const lpa_status st = enqueue_iteration(this, o, rc, cap_stream, nomark);
   hipGraph_t graph = nullptr;
   const hipError_t end = hipStreamEndCapture(cap_stream, &graph);
   if (st != LPA_OK) {
@@ -625,8 +675,17 @@ lpa_status lpa_graph_s::iteration_graph(const lpa_options& o, hipGraphExec_t* ou
   return LPA_OK;
 }
 
+// Trace request of lpa_trace (device buffers).
+struct TraceReq {
+  TraceArgs tr;
+  double rate;
+  uint64_t seed;
+  int64_t cap;
+};
+
 static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
-                           lpa_iter_stats* stats, int32_t stats_cap, int32_t* iters_done) {
+                           lpa_iter_stats* stats, int32_t stats_cap, int32_t* iters_done,
+                           const TraceReq* trace = nullptr) {
   if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
   lpa_options o;
   if (opt) o = *opt; else lpa_options_default(&o);
@@ -641,14 +700,46 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   if (stats_cap < 0 || (stats_cap > 0 && !stats))
     return fail(LPA_ERR_INVALID, "stats_cap < 0 or stats is NULL");
   if (g->n > 0 && !labels) return fail(LPA_ERR_INVALID, "labels is NULL");
+  if (o.learned != 0 && o.learned != 1) return fail(LPA_ERR_INVALID, "learned must be 0 or 1");
+  if (o.learned && !g->pred)
+    return fail(LPA_ERR_STATE, "learned run without a predictor (lpa_set_predictor)");
+  if ((o.learned || trace) && g->G > 0)
+    return fail(LPA_ERR_UNSUPPORTED, "learned skipping and traces need a single graph");
   if (iters_done) *iters_done = 0;
   const int64_t n = g->n;
   if (n == 0) return LPA_OK;
   hipStream_t s = g->stream;
   if (lpa_status e = g->ensure_history(o.max_iterations)) return e;
 
+  RunCtx rc;
+  LearnParams lp{};
+  rc.feat = o.learned || trace;
+  if (rc.feat) {
+    if (!g->lrec) {
+      if (lpa_status e = g->dalloc(&g->lrec, n)) return e;
+    }
+    LPA_HIP(launch_fill_u64(g->lrec, kRecordInit, n, s));
+    g->lrec_valid = true;
+  }
+  if (o.learned) {
+    rc.tiles = predictor_tiles(g->pred);
+    if (!rc.tiles) return fail(LPA_ERR_HIP, "packing the predictor's parameters failed");
+    const double th = g->lopt.threshold;
+    lp.learn = 1;
+    lp.guard = g->lopt.guard_period;
+    lp.z_theta = (float)std::log(th / (1.0 - th));
+    lp.fn_bound = g->lopt.fn_bound;
+  }
+  if (trace) {
+    rc.tr = trace->tr;
+    lp.trace = 1;
+    lp.trace_rate = trace->rate;
+    lp.trace_seed = trace->seed;
+    lp.trace_cap = (unsigned long long)trace->cap;
+  }
+  g->acct_feat = rc.feat;
   LPA_HIP(launch_run_begin(g->st, o.tolerance, o.max_iterations, o.pl_period, g->G > 0,
-                           g->G, s));
+                           g->G, lp, s));
   if (g->G > 0) LPA_HIP(launch_batch_reset(g->batch_args(), s));
   const int32_t* init = nullptr;
   if (o.initial_labels) {
@@ -664,13 +755,13 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   }
 
   int32_t done = 0;
-  const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile;
+  const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {
     // capture one iteration on the private stream, replay it max_iterations
     // times on the handle's stream; the kernels of iterations after the stop
     // return at once
     hipGraphExec_t exec = nullptr;
-    if (lpa_status e = g->iteration_graph(o, &exec)) return e;
+    if (lpa_status e = g->iteration_graph(o, rc, &exec)) return e;
     for (int32_t l = 0; l < o.max_iterations; ++l) LPA_HIP(hipGraphLaunch(exec, s));
     LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
     LPA_HIP(hipStreamSynchronize(s));
@@ -688,6 +779,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         stats[l].changed = h[l].changed;
         stats[l].processed = h[l].processed;
         stats[l].edges_scanned = h[l].edges;
+        stats[l].skipped = (int32_t)h[l].skipped;
       }
     }
   } else {
@@ -703,7 +795,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         return LPA_OK;
       };
       LPA_HIP(hipEventRecord(g->ev0, s));
-      if (lpa_status e = enqueue_iteration(g, o, s, mark)) return e;
+      if (lpa_status e = enqueue_iteration(g, o, rc, s, mark)) return e;
       LPA_HIP(hipEventRecord(g->ev1, s));
       LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
       LPA_HIP(hipStreamSynchronize(s));
@@ -731,12 +823,14 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         r.processed = (int64_t)h.processed;
         r.edges_scanned = (int64_t)edges;
         r.ms = ms;
+        r.skipped = (int32_t)h.skipped;
       }
       done = l + 1;
       if (h.stop) break;
     }
   }
   if (iters_done) *iters_done = done;
+  g->learned_iters = o.learned ? done : 0;
   const hipMemcpyKind kind = is_device_ptr(labels) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   LPA_HIP(hipMemcpyAsync(labels, g->C, sizeof(int32_t) * (size_t)n, kind, s));
   LPA_HIP(hipStreamSynchronize(s));
@@ -826,6 +920,113 @@ lpa_status lpa_profile(lpa_graph g, lpa_kernel_profile* out, int32_t cap, int32_
 lpa_status lpa_profile_reset(lpa_graph g) {
   if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
   for (int q = 0; q < kNumKids; ++q) g->prof[q] = lpa_kernel_profile{};
+  return LPA_OK;
+}
+
+lpa_status lpa_set_predictor(lpa_graph g, lpa_predictor p, const lpa_learned_options* lo) {
+  if (!g) return fail(LPA_ERR_INVALID, "graph is NULL");
+  if (g->G > 0) return fail(LPA_ERR_UNSUPPORTED, "learned skipping needs a single graph");
+  lpa_learned_options o;
+  if (lo) o = *lo; else lpa_learned_options_default(&o);
+  if (!(o.threshold > 0.0f && o.threshold < 1.0f))
+    return fail(LPA_ERR_INVALID, "threshold must lie in (0, 1)");
+  if (!(o.fn_bound >= 0.0f)) return fail(LPA_ERR_INVALID, "fn_bound must be >= 0");
+  if (o.guard_period < 0) return fail(LPA_ERR_INVALID, "guard_period must be >= 0");
+  g->pred = p;
+  g->lopt = o;
+  return LPA_OK;
+}
+
+lpa_status lpa_learned_history(lpa_graph g, lpa_learned_iter* out, int32_t cap,
+                               int32_t* count) {
+  if (!g || !count || cap < 0 || (cap > 0 && !out))
+    return fail(LPA_ERR_INVALID, "bad argument");
+  *count = 0;
+  const int32_t k = std::min(g->learned_iters, cap);
+  if (k <= 0) return LPA_OK;
+  std::vector<DevIterStats> h(k);
+  LPA_HIP(hipMemcpyAsync(h.data(), g->hist, sizeof(DevIterStats) * k, hipMemcpyDeviceToHost,
+                         g->stream));
+  LPA_HIP(hipStreamSynchronize(g->stream));
+  for (int32_t l = 0; l < k; ++l) {
+    std::memset(&out[l], 0, sizeof(out[l]));
+    out[l].iteration = h[l].iteration;
+    out[l].skipping = h[l].skipping;
+    out[l].fallback = h[l].fallback;
+    out[l].skipped = h[l].skipped;
+    out[l].predicted = h[l].npred;
+    out[l].false_negatives = h[l].fneg;
+  }
+  *count = k;
+  return LPA_OK;
+}
+
+lpa_status lpa_get_records(lpa_graph g, uint64_t* out) {
+  if (!g || (g->n > 0 && !out)) return fail(LPA_ERR_INVALID, "NULL argument");
+  if (g->n == 0) return LPA_OK;
+  if (!g->lrec_valid) return fail(LPA_ERR_STATE, "no learned or traced run yet");
+  const hipMemcpyKind kind = is_device_ptr(out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  LPA_HIP(hipMemcpyAsync(out, g->lrec, sizeof(uint64_t) * (size_t)g->n, kind, g->stream));
+  LPA_HIP(hipStreamSynchronize(g->stream));
+  return LPA_OK;
+}
+
+lpa_status lpa_trace(lpa_graph g, const lpa_options* opt, double sample_rate, uint64_t seed,
+                     float* X, float* y, int32_t* vertex, int32_t* iteration, int64_t cap,
+                     int64_t* count) {
+  if (!g || !count) return fail(LPA_ERR_INVALID, "NULL argument");
+  if (cap < 0 || (cap > 0 && (!X || !y))) return fail(LPA_ERR_INVALID, "bad trace buffers");
+  if (!(sample_rate >= 0.0 && sample_rate <= 1.0))
+    return fail(LPA_ERR_INVALID, "sample_rate must lie in [0, 1]");
+  *count = 0;
+  if (g->n == 0) return LPA_OK;
+  hipStream_t s = g->stream;
+  // device buffers: the caller's when they are device memory, else staging
+  std::vector<void*> staged;
+  struct Free {
+    std::vector<void*>* v;
+    ~Free() { for (void* q : *v) (void)hipFree(q); }
+  } guard{&staged};
+  auto dev = [&](void* user, size_t bytes, void** out) -> lpa_status {
+    if (user && is_device_ptr(user)) { *out = user; return LPA_OK; }
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(bytes, 4)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LPA_ERR_OOM, "hipMalloc failed for trace staging");
+    }
+    staged.push_back(q);
+    *out = q;
+    return LPA_OK;
+  };
+  const size_t c = (size_t)cap;
+  void *dX, *dy, *dv, *dl;
+  if (lpa_status e = dev(X, sizeof(float) * 12 * c, &dX)) return e;
+  if (lpa_status e = dev(y, sizeof(float) * c, &dy)) return e;
+  if (lpa_status e = dev(vertex, sizeof(int32_t) * c, &dv)) return e;
+  if (lpa_status e = dev(iteration, sizeof(int32_t) * c, &dl)) return e;
+  TraceReq req;
+  req.tr.X = static_cast<float*>(dX);
+  req.tr.y = static_cast<float*>(dy);
+  req.tr.v = static_cast<int32_t*>(dv);
+  req.tr.l = static_cast<int32_t*>(dl);
+  req.rate = sample_rate;
+  req.seed = seed;
+  req.cap = cap;
+  std::vector<int32_t> labels((size_t)g->n);
+  if (lpa_status e = run_impl(g, opt, labels.data(), nullptr, 0, nullptr, &req)) return e;
+  const int64_t drawn = (int64_t)g->st_host->trace_n;
+  *count = drawn;
+  const size_t kept = (size_t)std::min<int64_t>(drawn, cap);
+  auto back = [&](void* user, void* d, size_t bytes) -> lpa_status {
+    if (!user || user == d || bytes == 0) return LPA_OK;
+    LPA_HIP(hipMemcpyAsync(user, d, bytes, hipMemcpyDeviceToHost, s));
+    return LPA_OK;
+  };
+  if (lpa_status e = back(X, dX, sizeof(float) * 12 * kept)) return e;
+  if (lpa_status e = back(y, dy, sizeof(float) * kept)) return e;
+  if (lpa_status e = back(vertex, dv, sizeof(int32_t) * kept)) return e;
+  if (lpa_status e = back(iteration, dl, sizeof(int32_t) * kept)) return e;
+  LPA_HIP(hipStreamSynchronize(s));
   return LPA_OK;
 }
 

@@ -4,6 +4,8 @@
 // vertices ("for all unprocessed i ... mark i processed"), the hub slice plan,
 // the deterministic-mode label apply, and fp64 modularity (Eq. 1).
 #include "lpa_device.h"
+#include "lpa_mlp.h"
+#include "lpa_record.h"
 
 namespace lpa {
 
@@ -54,7 +56,7 @@ hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
 // an iteration that is not Pick-Less with changed < tolerance * N), or, in a
 // batched run, stops when every graph has stopped.
 __global__ void k_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
-                            int graphs) {
+                            int graphs, LearnParams lp) {
   uint32_t* w = reinterpret_cast<uint32_t*>(st);
   for (uint32_t i = threadIdx.x; i < sizeof(DevStats) / sizeof(uint32_t); i += blockDim.x)
     w[i] = 0u;
@@ -67,12 +69,22 @@ __global__ void k_run_begin(DevStats* st, double tol, int cap, int rho, int batc
     st->stop = cap <= 0 ? 1 : 0;
     st->batched = batched;
     st->graphs_left = (unsigned int)graphs;
+    st->learn = lp.learn;
+    st->guard = lp.guard;
+    st->trace = lp.trace;
+    st->z_theta = lp.z_theta;
+    st->fn_bound = lp.fn_bound;
+    st->trace_rate = lp.trace_rate;
+    st->trace_seed = lp.trace_seed;
+    st->trace_cap = lp.trace_cap;
+    st->cand = 1;
   }
 }
 
 hipError_t launch_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
-                            int graphs, hipStream_t s) {
-  hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, s, st, tol, cap, rho, batched, graphs);
+                            int graphs, const LearnParams& lp, hipStream_t s) {
+  hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(256), 0, s, st, tol, cap, rho, batched, graphs,
+                     lp);
   return hipGetLastError();
 }
 
@@ -96,15 +108,29 @@ __global__ void k_iter_end(DevStats* st, DevIterStats* hist, int64_t n) {
     edges += st->edges[c];
   }
   const int l = st->iter;
+  const bool few = (double)changed < st->tol * (double)n;
+  // learned skipping: a plain iteration with predictions checks the vertices
+  // predicted unchanged; too many of them changing turns skipping off
+  if (st->predict && !st->skipping && st->npred > 0 &&
+      (double)st->fneg > st->fn_bound * (double)st->npred)
+    st->fallback = 1;
   DevIterStats& h = hist[l];
   h.iteration = l;
   h.pick_less = st->pl;
   h.changed = (long long)changed;
   h.processed = (long long)st->processed;
   h.edges = (long long)edges;
+  h.skipped = (long long)st->skipped;
+  h.npred = (long long)st->npred;
+  h.fneg = st->skipping ? 0ll : (long long)st->fneg;
+  h.skipping = st->skipping;
+  h.fallback = st->fallback;
   int stop = 0;
   if (st->batched) stop = st->graphs_left == 0u;
-  else stop = !st->pl && (double)changed < st->tol * (double)n;
+  // Algorithm 1's test, taken only after an iteration that left no flagged
+  // vertex unprocessed
+  else stop = st->skipped == 0ull && !st->pl && few;
+  st->cand = few ? 1 : 0;
   st->iter = l + 1;
   st->stop = (stop || l + 1 >= st->cap) ? 1 : 0;
 }
@@ -325,6 +351,12 @@ hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0, s, p, v, count);
   return hipGetLastError();
 }
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0,
+                     s, p, v, count);
+  return hipGetLastError();
+}
 
 // ---- hub plan: reset the iteration counters, take the flagged hubs, queue
 // their slices grouped by the XCD each hub is assigned to (segment x of the
@@ -344,6 +376,13 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     st->graphs_left = 0;
     // Pick-Less in iterations l with l mod rho == 0, counting from 0
     st->pl = (st->rho > 0 && st->iter % st->rho == 0) ? 1 : 0;
+    // learned skipping: predictions from iteration 1 on until a fallback;
+    // skip unless this is a guard iteration or the last one changed few
+    const int l = st->iter;
+    st->predict = (st->learn && !st->fallback && l >= 1) ? 1 : 0;
+    st->skipping = (st->predict && (st->guard == 0 || l % st->guard != 0) && !st->cand) ? 1 : 0;
+    st->skipped = 0; st->npred = 0; st->fneg = 0;
+    st->trace_first = st->trace_n;
     running = 0; nproc = 0;
   }
   if (tid < kNumClasses) {
@@ -465,6 +504,163 @@ hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
   ListPtrs lp;
   for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
   hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kBT), 0, s, n, F, cls, lp, chg_clear, st);
+  return hipGetLastError();
+}
+
+// ---- frontier with the change predictor (learned variant) ------------------------
+// One wave per 64 consecutive vertices.  The flagged vertices of classes 1..8
+// are compacted within the wave and, when this iteration predicts, run through
+// the network 16 at a time (one MFMA tile of samples, operands held in
+// registers for the whole kernel).  In a skipping iteration a vertex whose
+// logit is below z_theta keeps its flag and is not listed; in a plain one it
+// is listed and marked (record byte 6, bit 7) so that the sweep counts it if
+// it changes.  Trace samples (features of a listed vertex) are appended here;
+// their targets are filled in after the sweep.
+namespace {
+
+__device__ __forceinline__ double sample_draw(unsigned long long seed, int l, int64_t v) {
+  unsigned long long z = seed + 0x9E3779B97F4A7C15ull *
+                                    (1ull + (((unsigned long long)(uint32_t)l << 32) |
+                                             (unsigned long long)v));
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace
+
+constexpr int kLearnWaves = 4;
+
+__global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
+    int64_t n, uint8_t* F, const uint8_t* cls, ListPtrs lists, uint8_t* chg_clear,
+    DevStats* st, unsigned long long* rec, const MlpTiles* tiles, TraceArgs tr) {
+  __shared__ uint8_t lst_all[kLearnWaves][64];
+  __shared__ uint8_t dec_all[kLearnWaves][64];
+  __shared__ unsigned long long slot_all[kLearnWaves][16];
+  if (st->stop) return;
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  uint8_t* lst = lst_all[wv];
+  uint8_t* dec = dec_all[wv];
+  unsigned long long* slot = slot_all[wv];
+  const int l = st->iter;
+  const int cap = st->cap, rho = st->rho;
+  const bool predict = st->predict != 0;
+  const bool skipping = st->skipping != 0;
+  const bool tracing = st->trace != 0 && l >= 1 && tr.X != nullptr;
+  const float z_theta = st->z_theta;
+  const double rate = st->trace_rate;
+  const unsigned long long seed = st->trace_seed, tcap = st->trace_cap;
+  MlpLane W;
+  if (predict) mlp_load(*tiles, W);
+  uint32_t proc = 0, skipped = 0, npred = 0;
+  const int64_t wave = (int64_t)blockIdx.x * kLearnWaves + wv;
+  const int64_t nwaves = (int64_t)gridDim.x * kLearnWaves;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t v = base + lane;
+    const bool valid = v < n;
+    uint8_t f = 0, c = 0;
+    if (valid) {
+      chg_clear[v] = 0;
+      f = F[v];
+      c = cls[v];
+    }
+    const bool cand = f && c >= 1 && c < kClassHub && (predict || tracing);
+    const unsigned long long cm = __ballot(cand);
+    const uint32_t cnt = __popcll(cm);
+    if (cand) lst[lane_rank(cm)] = (uint8_t)lane;
+    dec[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t r0 = 0; r0 < cnt; r0 += 16) {  // uniform trip count
+      const uint32_t si = r0 + (uint32_t)(lane & 15);
+      const bool has = si < cnt;
+      const int src = has ? lst[si] : 0;
+      const int64_t u = base + src;
+      const unsigned long long rr = has ? rec[u] : kRecordInit;
+      float x[4];
+      rec_features(rr, l, cap, rho, g, x);
+      bool pred = false;
+      if (predict) {
+        const float z = mlp_logit16(W, x);
+        pred = has && z < z_theta;
+      }
+      const bool skip = pred && skipping;
+      if (lane < 16 && has) dec[src] = (uint8_t)((pred ? 1 : 0) | (skip ? 2 : 0));
+      if (tracing) {
+        const bool take = has && !skip && sample_draw(seed, l, u) < rate;
+        if (lane < 16) slot[lane] = take ? atomicAdd(&st->trace_n, 1ull) : ~0ull;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const unsigned long long q = slot[lane & 15];
+        if (take && q < tcap && g < 3) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) tr.X[q * kMlpIn + 4 * g + j] = x[j];
+          if (g == 0) {
+            tr.v[q] = (int32_t)u;
+            tr.l[q] = l;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint8_t dd = dec[lane];
+    const bool skip = (dd & 2) != 0;
+    const bool keep = f && !skip;
+    if (dd & 1) {
+      ++npred;
+      // plain iteration: mark for the false-negative count of the sweep
+      if (!skip) rec[v] |= 0x80ull << 48;
+    }
+    if (skip) ++skipped;
+    if (keep) {
+      F[v] = 0;
+      ++proc;
+    }
+    // append the listed vertices of classes 1..8, one atomic per class and wave
+    for (int q = 1; q < kClassHub; ++q) {
+      const unsigned long long m = __ballot(keep && c == q);
+      if (!m) continue;
+      uint32_t b = 0;
+      if (lane == 0) b = atomicAdd(&st->active[q], (uint32_t)__popcll(m));
+      b = (uint32_t)__shfl(b, 0);
+      if (keep && c == q) lists.p[q][b + lane_rank(m)] = (int32_t)v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  const uint32_t tp = wave_sum_u32(proc), ts = wave_sum_u32(skipped), tn = wave_sum_u32(npred);
+  if (lane == 0) {
+    if (tp) atomicAdd(&st->processed, (unsigned long long)tp);
+    if (ts) atomicAdd(&st->skipped, (unsigned long long)ts);
+    if (tn) atomicAdd(&st->npred, (unsigned long long)tn);
+  }
+}
+
+hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
+                                   int32_t* const* lists, uint8_t* chg_clear, DevStats* st,
+                                   unsigned long long* rec, const MlpTiles* tiles,
+                                   const TraceArgs& tr, int grid, hipStream_t s) {
+  ListPtrs lp;
+  for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
+  hipLaunchKernelGGL(k_frontier_learned, dim3(grid), dim3(kLearnWaves * 64), 0, s, n, F, cls,
+                     lp, chg_clear, st, rec, tiles, tr);
+  return hipGetLastError();
+}
+
+// Targets of this iteration's trace samples: 1 if the vertex changed label.
+__global__ void k_trace_label(const DevStats* st, const uint8_t* chg, TraceArgs tr) {
+  if (st->stop || !st->trace) return;
+  const unsigned long long end = st->trace_n < st->trace_cap ? st->trace_n : st->trace_cap;
+  for (unsigned long long i = st->trace_first + blockIdx.x * (unsigned long long)blockDim.x +
+                              threadIdx.x;
+       i < end; i += (unsigned long long)gridDim.x * blockDim.x)
+    tr.y[i] = chg[tr.v[i]] ? 1.0f : 0.0f;
+}
+
+hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const TraceArgs& tr,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_trace_label, dim3(256), dim3(256), 0, s, st, chg, tr);
   return hipGetLastError();
 }
 

@@ -10,6 +10,10 @@ namespace lpa {
 lpa_status fail(lpa_status s, const std::string& msg);
 // True for device or managed memory of the current device.
 bool is_device_ptr(const void* p);
+// Packed bf16 operand tiles of a predictor's current parameters (packed on
+// first use after a change and synchronised); NULL on error.
+struct MlpTiles;
+const MlpTiles* predictor_tiles(lpa_predictor p);
 }  // namespace lpa
 
 #define LPA_HIP(call)                                                                 \

@@ -86,6 +86,12 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
+// Lane rank among the lanes of the wave whose bit is set in mask.
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 // Max within each 16-lane row, result in every lane of the row.
 __device__ __forceinline__ unsigned long long row16_max_u64(unsigned long long x) {
   x = umax64(x, dpp64<0x128>(x));  // row_ror:8

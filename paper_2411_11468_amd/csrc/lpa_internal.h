@@ -43,6 +43,53 @@ struct DevStats {
   int batched;                                  // per-graph stop rule
   unsigned int graphs_left;                     // batched: graphs still running
   unsigned int error;                           // sticky error bits (validation, labels)
+  // learned skipping (a project addition): run parameters ...
+  int learn;                                    // 1: predictions are made
+  int guard;                                    // guard period (0: none)
+  int trace;                                    // 1: record trace samples
+  float z_theta;                                // predicted unchanged: logit < z_theta
+  double fn_bound;                              // fallback bound on false negatives
+  double trace_rate;                            // sampling rate of the trace
+  unsigned long long trace_seed;
+  unsigned long long trace_cap;
+  // ... and state
+  int predict;                                  // this iteration evaluates the predictor
+  int skipping;                                 // this iteration skips predicted vertices
+  int fallback;                                 // skipping off for the rest of the run
+  int cand;                                     // last iteration changed < tol * N
+  unsigned long long skipped;                   // flagged vertices left unprocessed
+  unsigned long long npred;                     // vertices predicted unchanged
+  unsigned long long fneg;                      // of those, processed and changed
+  unsigned long long trace_n;                   // samples drawn so far
+  unsigned long long trace_first;               // trace_n when the iteration began
+};
+
+// Learned-skipping parameters of a run (zero: plain run).
+struct LearnParams {
+  int learn;
+  int guard;
+  int trace;
+  float z_theta;
+  double fn_bound;
+  double trace_rate;
+  unsigned long long trace_seed;
+  unsigned long long trace_cap;
+};
+
+// Per-vertex state record of the learned variant, 8 bytes (byte i = bits
+// 8i..8i+7): 0 own-label share, 1 best-second margin, 2 best-own gain (each
+// floor(255 x / K)), 3 distinct labels per entry, 4 log-quantised degree,
+// 5 log-quantised weighted degree, 6 change history (bit 7: predicted
+// unchanged in this plain iteration), 7 iteration of the evaluation (255:
+// never).
+constexpr unsigned long long kRecordInit = 0xFFull << 56;
+
+// Trace output of a run (device pointers; X may be NULL: no trace).
+struct TraceArgs {
+  float* X;               // [cap][12] features
+  float* y;               // [cap] 1 if the vertex changed label
+  int32_t* v;             // [cap] vertex
+  int32_t* l;             // [cap] iteration
 };
 
 // Everything a sweep kernel needs, passed by value.
@@ -60,6 +107,7 @@ struct SweepArgs {
   int cls;                // class index (selects st->active[cls])
   int async_mode;         // 1: write labels in place, 0: queue them
   int max_retries;        // hybrid probes before the linear continuation
+  unsigned long long* rec;  // learned variant: per-vertex state records
 };
 
 struct HubArgs {
@@ -99,6 +147,11 @@ struct DevIterStats {
   long long changed;
   long long processed;
   long long edges;
+  long long skipped;
+  long long npred;
+  long long fneg;
+  int32_t skipping;
+  int32_t fallback;
 };
 
 // Per-graph state of a batched run.
@@ -114,7 +167,7 @@ struct BatchArgs {
 hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
                        DevStats* st, hipStream_t s);
 hipError_t launch_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
-                            int graphs, hipStream_t s);
+                            int graphs, const LearnParams& lp, hipStream_t s);
 hipError_t launch_arm_flags(uint8_t* F, int64_t n, const DevStats* st, hipStream_t s);
 hipError_t launch_iter_end(DevStats* st, DevIterStats* hist, int64_t n, hipStream_t s);
 hipError_t launch_batch_step(const BatchArgs& b, const uint8_t* chg, uint8_t* F, DevStats* st,
@@ -137,11 +190,20 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t count,
+                           hipStream_t s);
 hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
                            hipStream_t s);
 hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
                            int32_t* const* lists_dev, uint8_t* chg_clear, DevStats* st,
                            int grid, hipStream_t s);
+struct MlpTiles;
+hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
+                                   int32_t* const* lists, uint8_t* chg_clear, DevStats* st,
+                                   unsigned long long* rec, const MlpTiles* tiles,
+                                   const TraceArgs& tr, int grid, hipStream_t s);
+hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const TraceArgs& tr,
+                              hipStream_t s);
 hipError_t launch_flag_decide(DevStats* st, int64_t m, int force, hipStream_t s);
 hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
                              const uint8_t* cls, const uint8_t* chg, uint8_t* F,
@@ -156,7 +218,7 @@ hipError_t launch_pull_hubs(bool off64, const void* off, const int32_t* tgt,
 hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t* Cn,
                         const int32_t* pv, const int32_t* pc, int32_t* C, int grid,
                         hipStream_t s);
-hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid,
+hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, bool feat,
                         hipStream_t s);
 hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_acc_rest(bool off64, const HubArgs& a, int grid, hipStream_t s);

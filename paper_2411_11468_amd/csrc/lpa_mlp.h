@@ -41,44 +41,67 @@ struct MlpTiles {
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-// Logit for 16 samples, one wave: lane l holds features 4 (l/16) .. 4 (l/16)+3
-// of sample l % 16 in f (zero beyond feature 11); every lane returns the logit
-// of its sample.  All 64 lanes must be active.
-__device__ inline float mlp_infer16(const MlpTiles& t, const float f[4]) {
+// The operands one lane needs, held in registers across many calls: the
+// layer-1 and layer-2 A tiles, and the biases / output weights of the hidden
+// units u = 16 m + 4 (lane / 16) + i that the lane's accumulator rows hold.
+struct MlpLane {
+  bf16x4_t w1[4];
+  bf16x4_t w2[4][4];
+  float b1[16], b2[16], w3[16];  // index 4 m + i
+  float b3;
+};
+
+__device__ inline void mlp_load(const MlpTiles& t, MlpLane& r) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    r.w1[m] = *reinterpret_cast<const bf16x4_t*>(t.w1t[m][lane]);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+      r.w2[m][kb] = *reinterpret_cast<const bf16x4_t*>(t.w2t[m][kb][lane]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u = 16 * m + 4 * g + i;
+      r.b1[4 * m + i] = t.b1[u];
+      r.b2[4 * m + i] = t.b2[u];
+      r.w3[4 * m + i] = t.w3[u];
+    }
+  }
+  r.b3 = t.b3;
+}
+
+// Logit for 16 samples, one wave: lane l holds features 4 (l/16) .. 4 (l/16)+3
+// of sample l % 16 in f (zero beyond feature 11); every lane returns the logit
+// of its sample.  Layer 1 and 2 run on v_mfma_f32_16x16x16_bf16 with the
+// weights as the A operand and the 16 samples as the columns, so the output
+// tile of layer 1 (after bias, ReLU and bf16 rounding) is the B operand of
+// layer 2 as it stands.  Layer 3 is a fp32 dot product.  All 64 lanes must be
+// active.
+__device__ inline float mlp_logit16(const MlpLane& r, const float f[4]) {
   bf16x4_t xb;
   for (int j = 0; j < 4; ++j) xb[j] = (short)bf16_bits(f[j]);
   bf16x4_t h1[4];
   const f32x4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(t.w1t[m][lane]);
-    const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb, zero, 0, 0, 0);
+    const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w1[m], xb, zero, 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float v = fmaxf(acc[i] + t.b1[16 * m + 4 * g + i], 0.0f);
-      h1[m][i] = (short)bf16_bits(v);
-    }
+    for (int i = 0; i < 4; ++i) h1[m][i] = (short)bf16_bits(fmaxf(acc[i] + r.b1[4 * m + i], 0.0f));
   }
   float part = 0.0f;
 #pragma unroll
   for (int mo = 0; mo < 4; ++mo) {
     f32x4_t acc = zero;
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const bf16x4_t a = *reinterpret_cast<const bf16x4_t*>(t.w2t[mo][kb][lane]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, h1[kb], acc, 0, 0, 0);
-    }
+    for (int kb = 0; kb < 4; ++kb)
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w2[mo][kb], h1[kb], acc, 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u = 16 * mo + 4 * g + i;
-      part += fmaxf(acc[i] + t.b2[u], 0.0f) * t.w3[u];
-    }
+    for (int i = 0; i < 4; ++i) part += fmaxf(acc[i] + r.b2[4 * mo + i], 0.0f) * r.w3[4 * mo + i];
   }
   part += __shfl_xor(part, 16);
   part += __shfl_xor(part, 32);
-  return part + t.b3;
+  return part + r.b3;
 }
 
 hipError_t launch_mlp_grad(const float* p, const float* X, const float* y, int64_t B,

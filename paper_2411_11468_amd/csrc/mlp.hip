@@ -12,7 +12,7 @@
 //                 samples, activations in LDS)
 //   k_adam        one Adam step (Kingma & Ba 2015) with bias correction
 //   k_mlp_pack    fp32 masters -> bf16 MFMA operand tiles
-//   mlp_infer16   inference of 16 samples by one wave with
+//   mlp_logit16   inference of 16 samples by one wave with
 //                 v_mfma_f32_16x16x16_bf16: every layer is computed
 //                 transposed (weights as the A operand, samples as the 16
 //                 columns), so a layer's output tile, after bias, ReLU and
@@ -208,6 +208,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpTiles* t, const floa
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  MlpLane r;
+  mlp_load(*t, r);
   for (int64_t s0 = wave * 16; s0 < B; s0 += nw * 16) {
     const int64_t s = s0 + (lane & 15);
     float f[4];
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const MlpTiles* t, const floa
       const int k = 4 * (lane >> 4) + j;
       f[j] = (s < B && k < kIn) ? X[s * kIn + k] : 0.0f;
     }
-    const float z = mlp_infer16(*t, f);
+    const float z = mlp_logit16(r, f);
     if (lane < 16 && s < B) out[s] = 1.0f / (1.0f + __expf(-z));
   }
 }

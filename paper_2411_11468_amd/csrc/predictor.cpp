@@ -79,7 +79,11 @@ lpa_status pack(lpa_predictor p) {
 
 namespace lpa {
 const MlpTiles* predictor_tiles(lpa_predictor p) {
-  return (p && pack(p) == LPA_OK) ? p->tiles : nullptr;
+  if (!p) return nullptr;
+  if (!p->tiles_ok) {
+    if (pack(p) != LPA_OK || hipStreamSynchronize(p->stream) != hipSuccess) return nullptr;
+  }
+  return p->tiles;
 }
 }  // namespace lpa
 

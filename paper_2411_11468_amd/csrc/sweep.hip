@@ -30,6 +30,7 @@
 //                     global-memory table with atomics; the merge also
 //                     maintains the packed maximum, since sums only grow.
 #include "lpa_device.h"
+#include "lpa_record.h"
 
 namespace lpa {
 
@@ -47,11 +48,6 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Lane rank among the lanes of the wave whose bit is set in mask.
-__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 __device__ __forceinline__ void flush_stats(unsigned long long edges, uint32_t changed,
                                             unsigned long long flagw, DevStats* st,
@@ -74,33 +70,94 @@ __device__ __forceinline__ bool decide(unsigned long long best, int32_t cur, int
   return (int32_t)c != cur && (!pl || (int32_t)c < cur);
 }
 
-template <int R>
-__device__ __forceinline__ void rot16_accum(uint32_t lab, float wt, float& sum) {
+// One rotation step of the per-label sums inside a 16-lane row (R) or a quad
+// (quad_perm Q): add the other lane's weight if it holds the same label.
+// FEAT: also note whether that lane, of lower index in the group, does.
+template <int R, bool FEAT>
+__device__ __forceinline__ void rot16_accum(uint32_t lab, float wt, int k, float& sum,
+                                            bool& dup) {
   const uint32_t ol = dpp32<0x120 + R, 0xF, 0xF, false>(lab);
   const float ow = __uint_as_float(dpp32<0x120 + R, 0xF, 0xF, false>(__float_as_uint(wt)));
   if (ol == lab) sum += ow;
+  if constexpr (FEAT) {
+    const int ok = (int)dpp32<0x120 + R, 0xF, 0xF, false>((uint32_t)k);
+    if (ol == lab && ok < k) dup = true;
+  }
 }
-template <int Q>
-__device__ __forceinline__ void rot4_accum(uint32_t lab, float wt, float& sum) {
+template <int Q, bool FEAT>
+__device__ __forceinline__ void rot4_accum(uint32_t lab, float wt, int k, float& sum,
+                                           bool& dup) {
   const uint32_t ol = dpp32<Q, 0xF, 0xF, false>(lab);
   const float ow = __uint_as_float(dpp32<Q, 0xF, 0xF, false>(__float_as_uint(wt)));
   if (ol == lab) sum += ow;
+  if constexpr (FEAT) {
+    const int ok = (int)dpp32<Q, 0xF, 0xF, false>((uint32_t)k);
+    if (ol == lab && ok < k) dup = true;
+  }
+}
+
+// Reductions over a group of G = 4 (quad) or 16 (row) lanes, result in every
+// lane of the group.
+template <int G>
+__device__ __forceinline__ unsigned long long group_max(unsigned long long x) {
+  if constexpr (G == 16) return row16_max_u64(x);
+  else return quad_max_u64(x);
+}
+template <int G>
+__device__ __forceinline__ float group_sum_f32(float x) {
+  if constexpr (G == 16) {
+    x += dppf<0x128>(x);  // row_ror:8
+    x += dppf<0x124>(x);
+    x += dppf<0x122>(x);
+    x += dppf<0x121>(x);
+  } else {
+    x += dppf<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dppf<0x4E>(x);   // quad_perm [2,3,0,1]
+  }
+  return x;
+}
+template <int G>
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t x) {
+  if constexpr (G == 16) {
+    x += dpp32<0x128>(x);
+    x += dpp32<0x124>(x);
+    x += dpp32<0x122>(x);
+    x += dpp32<0x121>(x);
+  } else {
+    x += dpp32<0xB1>(x);
+    x += dpp32<0x4E>(x);
+  }
+  return x;
+}
+
+// fp32 sum over the wave (uniform result).
+__device__ __forceinline__ float wave_sum_f32(float x) {
+  for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
+  return x;
+}
+
+__device__ __forceinline__ void flush_fneg(uint32_t fneg, DevStats* st) {
+  const uint32_t f = wave_sum_u32(fneg);
+  if ((threadIdx.x & 63) == 0 && f) atomicAdd(&st->fneg, (unsigned long long)f);
 }
 
 }  // namespace
 
 // ---- small rows: G lanes per vertex, registers only -------------------------
-template <typename OffT, int G>
+// FEAT: the learned variant, which also rewrites the state record of every
+// vertex it evaluates (lpa_record.h).
+template <typename OffT, int G, bool FEAT>
 __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   if (a.st->stop) return;
   const int lane = threadIdx.x & 63;
   const int k = lane & (G - 1);
   const uint32_t count = a.st->active[a.cls];
+  const int l = a.st->iter;
   constexpr uint32_t kVpw = 64 / G;
   const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   unsigned long long my_edges = 0, my_flagw = 0;
-  uint32_t my_changed = 0;
+  uint32_t my_changed = 0, my_fneg = 0;
   for (uint64_t base = (uint64_t)wave_id * kVpw; base < count;
        base += (uint64_t)nwaves * kVpw) {
     const uint64_t idx = base + (uint32_t)lane / G;
@@ -113,29 +170,44 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     const float wt = has ? edge_weight(a.w, o + k) : 0.0f;
     const uint32_t lab = (has && j != v) ? (uint32_t)a.C[j] : kEmpty;
     // Per-label sum seen from this lane: its own weight plus every other lane
-    // of the group holding the same label.
+    // of the group holding the same label.  FEAT: dup = a lane of lower index
+    // holds the same label.
     float sum = wt;
+    bool dup = false;
     if constexpr (G == 16) {
-      rot16_accum<1>(lab, wt, sum);  rot16_accum<2>(lab, wt, sum);
-      rot16_accum<3>(lab, wt, sum);  rot16_accum<4>(lab, wt, sum);
-      rot16_accum<5>(lab, wt, sum);  rot16_accum<6>(lab, wt, sum);
-      rot16_accum<7>(lab, wt, sum);  rot16_accum<8>(lab, wt, sum);
-      rot16_accum<9>(lab, wt, sum);  rot16_accum<10>(lab, wt, sum);
-      rot16_accum<11>(lab, wt, sum); rot16_accum<12>(lab, wt, sum);
-      rot16_accum<13>(lab, wt, sum); rot16_accum<14>(lab, wt, sum);
-      rot16_accum<15>(lab, wt, sum);
+      rot16_accum<1, FEAT>(lab, wt, k, sum, dup);  rot16_accum<2, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<3, FEAT>(lab, wt, k, sum, dup);  rot16_accum<4, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<5, FEAT>(lab, wt, k, sum, dup);  rot16_accum<6, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<7, FEAT>(lab, wt, k, sum, dup);  rot16_accum<8, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<9, FEAT>(lab, wt, k, sum, dup);  rot16_accum<10, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<11, FEAT>(lab, wt, k, sum, dup); rot16_accum<12, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<13, FEAT>(lab, wt, k, sum, dup); rot16_accum<14, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<15, FEAT>(lab, wt, k, sum, dup);
     } else {
-      rot4_accum<0x39>(lab, wt, sum);  // quad_perm [1,2,3,0]
-      rot4_accum<0x4E>(lab, wt, sum);  // quad_perm [2,3,0,1]
-      rot4_accum<0x93>(lab, wt, sum);  // quad_perm [3,0,1,2]
+      rot4_accum<0x39, FEAT>(lab, wt, k, sum, dup);  // quad_perm [1,2,3,0]
+      rot4_accum<0x4E, FEAT>(lab, wt, k, sum, dup);  // quad_perm [2,3,0,1]
+      rot4_accum<0x93, FEAT>(lab, wt, k, sum, dup);  // quad_perm [3,0,1,2]
     }
     const unsigned long long packed = (lab != kEmpty) ? pack_key(sum, lab) : 0ull;
-    const unsigned long long best =
-        (G == 16) ? row16_max_u64(packed) : quad_max_u64(packed);
+    const unsigned long long best = group_max<G>(packed);
     uint32_t cstar = 0;
     const int32_t cur = valid ? a.C[v] : 0;
     const bool moved = valid && decide(best, cur, a.st->pl, &cstar);
     const bool leader = valid && k == 0;
+    if constexpr (FEAT) {
+      // every lane takes part in the group reductions
+      const float K = group_sum_f32<G>(lab != kEmpty ? wt : 0.0f);
+      const unsigned long long ownk =
+          (lab != kEmpty && (int32_t)lab == cur) ? (unsigned long long)__float_as_uint(sum) : 0ull;
+      const float own = __uint_as_float((uint32_t)group_max<G>(ownk));
+      const uint32_t bl = best ? unpack_label(best) : kEmpty;
+      const unsigned long long sk = (lab != kEmpty && lab != bl) ? pack_key(sum, lab) : 0ull;
+      const float second = __uint_as_float((uint32_t)(group_max<G>(sk) >> 32));
+      const float bw = __uint_as_float((uint32_t)(best >> 32));
+      const uint32_t distinct = group_sum_u32<G>((lab != kEmpty && !dup) ? 1u : 0u);
+      if (leader && d >= 1)
+        my_fneg += rec_write(a.rec, v, l, K, own, bw, second, distinct, (uint32_t)d, moved);
+    }
     if (leader) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -151,29 +223,47 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     }
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
+// Learned variant, table kernels: per-lane partials of the record quantities
+// gathered while the table is read back (each slot holds one label).
+struct RecPartial {
+  unsigned long long b1 = 0, b2 = 0;  // two largest packed keys of the lane
+  float own = 0.0f;                   // weight of the vertex's own label
+  float K = 0.0f;                     // lane's share of the total weight
+  uint32_t distinct = 0;              // occupied slots read by the lane
+  __device__ __forceinline__ void slot(unsigned long long pk, uint32_t key, float val,
+                                       int32_t cur) {
+    if (pk > b1) { b2 = b1; b1 = pk; } else if (pk > b2) { b2 = pk; }
+    if ((int32_t)key == cur) own = val;
+    ++distinct;
+  }
+};
+
 // ---- one wave per vertex, LDS table per wave -------------------------------
-template <typename OffT, int SLOTS, int WAVES, int U>
+template <typename OffT, int SLOTS, int WAVES, int U, bool FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   __shared__ uint32_t keys_all[WAVES][SLOTS];
   __shared__ float vals_all[WAVES][SLOTS];
   if (a.st->stop) return;
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  const int l = a.st->iter;
   uint32_t* keys = keys_all[wv];
   float* vals = vals_all[wv];
   for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
-  uint32_t my_changed = 0;
+  uint32_t my_changed = 0, my_fneg = 0;
   for (uint32_t item = blockIdx.x * WAVES + wv; item < count; item += gridDim.x * WAVES) {
     const int32_t v = a.active[item];
     int64_t o, d;
     row_of<OffT>(a.off, v, &o, &d);
     const int32_t cur = a.C[v];
     const uint32_t p1 = table_p1((uint32_t)d);
+    RecPartial rp;
     for (int64_t base = 0; base < d; base += 64 * U) {
       int32_t j[U];
       float wt[U];
@@ -189,14 +279,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
       for (int u = 0; u < U; ++u) lab[u] = (j[u] != v) ? (uint32_t)a.C[j[u]] : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+        if (lab[u] != kEmpty) {
+          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+          if constexpr (FEAT) rp.K += wt[u];
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     unsigned long long best = 0;
     for (uint32_t s = lane; s < p1; s += 64) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
-        best = umax64(best, pack_key(vals[s], kk));
+        const unsigned long long pk = pack_key(vals[s], kk);
+        if constexpr (FEAT) rp.slot(pk, kk, vals[s], cur);
+        best = umax64(best, pk);
         keys[s] = kEmpty;
         vals[s] = 0.0f;
       }
@@ -204,6 +299,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     best = wave_max_u64(best);
     uint32_t cstar = 0;
     const bool moved = decide(best, cur, a.st->pl, &cstar);
+    if constexpr (FEAT) {
+      const float second =
+          __uint_as_float((uint32_t)(wave_max_u64(rp.b1 == best ? rp.b2 : rp.b1) >> 32));
+      const float own = __uint_as_float((uint32_t)wave_max_u64(__float_as_uint(rp.own)));
+      const uint32_t distinct = wave_sum_u32(rp.distinct);
+      const float K = wave_sum_f32(rp.K);
+      if (lane == 0)
+        my_fneg += rec_write(a.rec, v, l, K, own, __uint_as_float((uint32_t)(best >> 32)),
+                             second, distinct, (uint32_t)d, moved);
+    }
     if (lane == 0) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -220,22 +325,28 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
 // ---- one workgroup per vertex, LDS table per workgroup ---------------------
-template <typename OffT, int SLOTS, int BT, int U>
+template <typename OffT, int SLOTS, int BT, int U, bool FEAT>
 __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
+  constexpr int NW = BT / 64;
   __shared__ uint32_t keys[SLOTS];
   __shared__ float vals[SLOTS];
-  __shared__ unsigned long long red[BT / 64];
+  __shared__ unsigned long long red[NW];
+  __shared__ unsigned long long red2[FEAT ? NW : 1], redo[FEAT ? NW : 1];
+  __shared__ uint32_t redc[FEAT ? NW : 1];
+  __shared__ float redk[FEAT ? NW : 1];
   if (a.st->stop) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const int l = a.st->iter;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __syncthreads();
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
-  uint32_t my_changed = 0;
+  uint32_t my_changed = 0, my_fneg = 0;
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const int32_t v = a.active[item];
     int64_t o, d;
@@ -244,6 +355,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     // overwrites it, and every thread must reach the same move decision.
     const int32_t cur = a.C[v];
     const uint32_t p1 = table_p1((uint32_t)d);
+    RecPartial rp;
     for (int64_t base = 0; base < d; base += (int64_t)BT * U) {
       int32_t j[U];
       float wt[U];
@@ -259,14 +371,19 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
       for (int u = 0; u < U; ++u) lab[u] = (j[u] != v) ? (uint32_t)a.C[j[u]] : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+        if (lab[u] != kEmpty) {
+          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+          if constexpr (FEAT) rp.K += wt[u];
+        }
     }
     __syncthreads();
     unsigned long long best = 0;
     for (uint32_t s = tid; s < p1; s += BT) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
-        best = umax64(best, pack_key(vals[s], kk));
+        const unsigned long long pk = pack_key(vals[s], kk);
+        if constexpr (FEAT) rp.slot(pk, kk, vals[s], cur);
+        best = umax64(best, pk);
         keys[s] = kEmpty;
         vals[s] = 0.0f;
       }
@@ -276,9 +393,37 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     __syncthreads();
     best = red[0];
 #pragma unroll
-    for (int q = 1; q < BT / 64; ++q) best = umax64(best, red[q]);
+    for (int q = 1; q < NW; ++q) best = umax64(best, red[q]);
     uint32_t cstar = 0;
     const bool moved = decide(best, cur, a.st->pl, &cstar);
+    if constexpr (FEAT) {
+      const unsigned long long ws = wave_max_u64(rp.b1 == best ? rp.b2 : rp.b1);
+      const unsigned long long wo = wave_max_u64(__float_as_uint(rp.own));
+      const uint32_t wc = wave_sum_u32(rp.distinct);
+      const float wk = wave_sum_f32(rp.K);
+      if (lane == 0) {
+        red2[tid >> 6] = ws;
+        redo[tid >> 6] = wo;
+        redc[tid >> 6] = wc;
+        redk[tid >> 6] = wk;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        unsigned long long sec = red2[0], ow = redo[0];
+        uint32_t distinct = redc[0];
+        float K = redk[0];
+        for (int q = 1; q < NW; ++q) {
+          sec = umax64(sec, red2[q]);
+          ow = umax64(ow, redo[q]);
+          distinct += redc[q];
+          K += redk[q];
+        }
+        my_fneg += rec_write(a.rec, v, l, K, __uint_as_float((uint32_t)ow),
+                             __uint_as_float((uint32_t)(best >> 32)),
+                             __uint_as_float((uint32_t)(sec >> 32)), distinct, (uint32_t)d,
+                             moved);
+      }
+    }
     if (tid == 0) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -295,6 +440,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     __syncthreads();
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
 // ---- hubs: slices reduced in LDS, merged in a global table -----------------
@@ -492,24 +638,27 @@ int sweep_max_resident(int cls) {
 int hub_block_threads() { return kHubThreads; }
 int hub_max_resident() { return 256; }
 
-template <typename OffT>
+template <typename OffT, bool FEAT>
 static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
-    case 1: hipLaunchKernelGGL((k_sweep_small<OffT, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16>), dim3(grid), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_sweep_wave<OffT, 127, kWaveWaves, 1>), dim3(grid), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_sweep_wave<OffT, 1023, kWaveWaves, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4>), dim3(grid), dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4>), dim3(grid), dim3(kBlockMid), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_sweep_block<OffT, 16383, kBlockBig, 4>), dim3(grid), dim3(kBlockBig), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_sweep_small<OffT, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_sweep_wave<OffT, 127, kWaveWaves, 1, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sweep_wave<OffT, 1023, kWaveWaves, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4, FEAT>), dim3(grid), dim3(kBlockMid), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep_block<OffT, 16383, kBlockBig, 4, FEAT>), dim3(grid), dim3(kBlockBig), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, hipStream_t s) {
-  return off64 ? sweep_t<int64_t>(cls, a, grid, s) : sweep_t<int32_t>(cls, a, grid, s);
+hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, bool feat,
+                        hipStream_t s) {
+  if (feat && !a.rec) return hipErrorInvalidValue;
+  if (off64) return feat ? sweep_t<int64_t, true>(cls, a, grid, s) : sweep_t<int64_t, false>(cls, a, grid, s);
+  return feat ? sweep_t<int32_t, true>(cls, a, grid, s) : sweep_t<int32_t, false>(cls, a, grid, s);
 }
 
 hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s) {

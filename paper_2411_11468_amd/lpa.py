@@ -59,7 +59,19 @@ class lpa_options(ctypes.Structure):
                 ("tolerance", ctypes.c_double), ("pl_period", ctypes.c_int32),
                 ("prune", ctypes.c_int32), ("initial_labels", ctypes.c_void_p),
                 ("profile", ctypes.c_int32), ("flag_mode", ctypes.c_int32),
-                ("launch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("launch", ctypes.c_int32), ("learned", ctypes.c_int32)]
+
+
+class lpa_learned_options(ctypes.Structure):
+    _fields_ = [("threshold", ctypes.c_float), ("fn_bound", ctypes.c_float),
+                ("guard_period", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lpa_learned_iter(ctypes.Structure):
+    _fields_ = [("iteration", ctypes.c_int32), ("skipping", ctypes.c_int32),
+                ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("skipped", ctypes.c_int64), ("predicted", ctypes.c_int64),
+                ("false_negatives", ctypes.c_int64)]
 
 
 class lpa_kernel_profile(ctypes.Structure):
@@ -77,7 +89,7 @@ class lpa_iter_stats(ctypes.Structure):
     _fields_ = [("iteration", ctypes.c_int32), ("pick_less", ctypes.c_int32),
                 ("changed", ctypes.c_int64), ("processed", ctypes.c_int64),
                 ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float),
-                ("reserved", ctypes.c_int32)]
+                ("skipped", ctypes.c_int32)]
 
 
 EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run",
@@ -86,7 +98,8 @@ EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run"
             "lpa_create_batched", "lpa_run_batched", "lpa_predictor_create",
             "lpa_predictor_destroy", "lpa_predictor_set_params", "lpa_predictor_get_params",
             "lpa_predictor_gradient", "lpa_predictor_adam", "lpa_predictor_train",
-            "lpa_predictor_predict")
+            "lpa_predictor_predict", "lpa_learned_options_default", "lpa_set_predictor",
+            "lpa_learned_history", "lpa_get_records", "lpa_trace")
 
 _lib = None
 
@@ -150,6 +163,18 @@ def load_library(path: str = LIB_PATH):
     lib.lpa_predictor_train.restype = ctypes.c_int
     lib.lpa_predictor_predict.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.lpa_predictor_predict.restype = ctypes.c_int
+    lib.lpa_learned_options_default.argtypes = [ctypes.POINTER(lpa_learned_options)]
+    lib.lpa_learned_options_default.restype = None
+    lib.lpa_set_predictor.argtypes = [vp, vp, ctypes.POINTER(lpa_learned_options)]
+    lib.lpa_set_predictor.restype = ctypes.c_int
+    lib.lpa_learned_history.argtypes = [vp, ctypes.POINTER(lpa_learned_iter), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.lpa_learned_history.restype = ctypes.c_int
+    lib.lpa_get_records.argtypes = [vp, vp]
+    lib.lpa_get_records.restype = ctypes.c_int
+    lib.lpa_trace.argtypes = [vp, ctypes.POINTER(lpa_options), ctypes.c_double, ctypes.c_uint64,
+                              vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.lpa_trace.restype = ctypes.c_int
     lib.lpa_status_string.argtypes = [ctypes.c_int]
     lib.lpa_status_string.restype = ctypes.c_char_p
     lib.lpa_last_error.argtypes = []
@@ -255,8 +280,9 @@ def lpa_create_batched(v_off, offsets, targets, weights=None, *, validate: bool 
 
 
 def _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, profile,
-             flag_mode, launch):
+             flag_mode, launch, learned=False):
     o = default_options()
+    o.learned = int(bool(learned))
     o.mode = int(mode)
     o.tolerance = float(tolerance)
     o.max_iterations = int(max_iterations)
@@ -289,20 +315,79 @@ def lpa_run_batched(handle, labels, num_graphs: int, *, mode: int = MODE_ASYNC,
 def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
             max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
             initial_labels=None, profile: bool = False, flag_mode: int = FLAGS_AUTO,
-            launch: int = LAUNCH_EAGER):
+            launch: int = LAUNCH_EAGER, learned: bool = False):
     """Run to termination; labels is a preallocated int32 torch tensor or numpy
     array of N entries.  Returns (iterations, list of stats dicts)."""
     lib = load_library()
     o = _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, profile,
-                 flag_mode, launch)
+                 flag_mode, launch, learned)
     cap = max(int(max_iterations), 1)
     st = (lpa_iter_stats * cap)()
     it = ctypes.c_int32(0)
     _check(lib.lpa_run(handle, ctypes.byref(o), _addr(labels), st, cap, ctypes.byref(it)))
     stats = [dict(iteration=s.iteration, pick_less=s.pick_less, changed=s.changed,
-                  processed=s.processed, edges_scanned=s.edges_scanned, ms=s.ms)
+                  processed=s.processed, edges_scanned=s.edges_scanned, ms=s.ms,
+                  skipped=s.skipped)
              for s in st[:it.value]]
     return int(it.value), stats
+
+
+def learned_options(threshold: float = 0.1, fn_bound: float = 0.02,
+                    guard_period: int = 4) -> lpa_learned_options:
+    o = lpa_learned_options()
+    load_library().lpa_learned_options_default(ctypes.byref(o))
+    o.threshold, o.fn_bound, o.guard_period = threshold, fn_bound, guard_period
+    return o
+
+
+def lpa_set_predictor(handle, predictor, *, threshold: float = 0.1, fn_bound: float = 0.02,
+                      guard_period: int = 4) -> None:
+    o = learned_options(threshold, fn_bound, guard_period)
+    ph = None if predictor is None else predictor.handle
+    _check(load_library().lpa_set_predictor(handle, ph, ctypes.byref(o)))
+
+
+def lpa_learned_history(handle, cap: int = 64) -> list:
+    arr = (lpa_learned_iter * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(load_library().lpa_learned_history(handle, arr, cap, ctypes.byref(cnt)))
+    return [{f: getattr(r, f) for f, _ in lpa_learned_iter._fields_ if f != "reserved"}
+            for r in arr[:cnt.value]]
+
+
+def lpa_get_records(handle, n: int) -> np.ndarray:
+    out = np.empty((n, 8), dtype=np.uint8)
+    _check(load_library().lpa_get_records(handle, _addr(out)))
+    return out
+
+
+def lpa_trace(handle, *, sample_rate: float, seed: int = 0, cap: int = 1 << 20,
+              mode: int = MODE_DETERMINISTIC, tolerance: float = 0.05,
+              max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
+              learned: bool = False, device=None):
+    """Training trace of one run (see lpa_trace in the header).  With device
+    (a torch device) the buffers are torch tensors there, else numpy arrays.
+    Returns (X, y, vertex, iteration, drawn) cut to the samples kept."""
+    lib = load_library()
+    o = _options(mode, tolerance, max_iterations, pl_period, prune, None, False, FLAGS_AUTO,
+                 LAUNCH_EAGER, learned)
+    if device is not None:
+        import torch
+        X = torch.empty((cap, 12), dtype=torch.float32, device=device)
+        y = torch.empty(cap, dtype=torch.float32, device=device)
+        v = torch.empty(cap, dtype=torch.int32, device=device)
+        it = torch.empty(cap, dtype=torch.int32, device=device)
+    else:
+        X = np.empty((cap, 12), dtype=np.float32)
+        y = np.empty(cap, dtype=np.float32)
+        v = np.empty(cap, dtype=np.int32)
+        it = np.empty(cap, dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    _check(lib.lpa_trace(handle, ctypes.byref(o), float(sample_rate),
+                         int(seed) & 0xFFFFFFFFFFFFFFFF, _addr(X), _addr(y), _addr(v),
+                         _addr(it), int(cap), ctypes.byref(cnt)))
+    k = min(int(cnt.value), cap)
+    return X[:k], y[:k], v[:k], it[:k], int(cnt.value)
 
 
 def lpa_modularity(handle, labels) -> float:
@@ -383,6 +468,20 @@ class LpaGraph:
 
     def modularity(self, labels) -> float:
         return lpa_modularity(self.handle, labels)
+
+    def set_predictor(self, predictor, **kw) -> None:
+        """Attach a Predictor (None detaches) for runs with learned=True."""
+        lpa_set_predictor(self.handle, predictor, **kw)
+        self._pred = predictor     # keep it alive while attached
+
+    def learned_history(self) -> list:
+        return lpa_learned_history(self.handle)
+
+    def records(self) -> np.ndarray:
+        return lpa_get_records(self.handle, self.num_vertices)
+
+    def trace(self, **kw):
+        return lpa_trace(self.handle, **kw)
 
     def classes(self) -> dict:
         return lpa_graph_classes(self.handle)

@@ -4,10 +4,11 @@
       per-kernel call count, total and average duration (kernel-trace --stats)
   python -m paper_2411_11468_amd.profiling traffic --fetch <counter_collection.csv>
       --write <counter_collection.csv> --copy-bytes B --command CMD --out F.json
-      per-kernel FETCH_SIZE and WRITE_SIZE per dispatch (KiB), each scaled by
-      the ratio the same counter shows for a plain device copy of B bytes
-      (the largest copy kernel in the same files), and the hash of the kernel
-      sources the counters were taken with.
+      per-kernel FETCH_SIZE and WRITE_SIZE per dispatch (KiB, averaged over the
+      kernel's dispatches), each scaled by the ratio the same counter shows
+      for plain device copies of B bytes (the largest copy dispatches in the
+      same files), and the hash of the kernel sources the counters were
+      taken with.
 
 The traffic summary is read by bench.py, which reports it only while the
 kernel sources still hash to the recorded value.
@@ -29,8 +30,8 @@ CSRC = os.path.join(HERE, "csrc")
 
 # rocprofv3 kernel names -> the names used by lpa_profile
 _NAME_RULES = [
-    (r"k_sweep_small<[^,]+, 4>", "sweep_small4"),
-    (r"k_sweep_small<[^,]+, 16>", "sweep_small16"),
+    (r"k_sweep_small<[^,]+, 4[,>]", "sweep_small4"),
+    (r"k_sweep_small<[^,]+, 16[,>]", "sweep_small16"),
     (r"k_sweep_wave<[^,]+, 127,", "sweep_wave127"),
     (r"k_sweep_wave<[^,]+, 1023,", "sweep_wave1023"),
     (r"k_sweep_block<[^,]+, 2047,", "sweep_block2047"),
@@ -41,7 +42,12 @@ _NAME_RULES = [
     (r"k_hub_acc<[^>]*false>", "hub_acc_rest"),
     (r"k_hub_fin<", "hub_fin"),
     (r"k_hub_plan<", "hub_plan"),
+    (r"k_frontier_learned", "frontier_learned"),
     (r"k_frontier", "frontier"),
+    (r"k_trace_label", "trace_label"),
+    (r"k_mlp_infer", "mlp_infer"),
+    (r"k_mlp_grad", "mlp_grad"),
+    (r"k_adam", "adam"),
     (r"k_apply", "apply"),
     (r"k_pull_flags<", "pull_flags"),
     (r"k_pull_hubs<", "pull_hubs"),
@@ -87,40 +93,45 @@ def kernel_stats_md(csv_path: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
-def _counter_means(csv_path: str, counter: str) -> dict:
-    """Average counter value per dispatch for every kernel name."""
+def _counter_rows(csv_path: str, counter: str) -> list:
+    """(kernel name, value) per dispatch; rocprofv3 writes one row per
+    dispatch and counter, values in KiB for FETCH_SIZE / WRITE_SIZE."""
+    return [(r["Kernel_Name"], float(r["Counter_Value"]))
+            for r in csv.DictReader(open(csv_path)) if r.get("Counter_Name") == counter]
+
+
+def _calibration(rows: list, copy_kib: float) -> tuple:
+    """Scale that maps the counter of the largest device copies (the
+    reference copies of copy_kib KiB each) onto their true size."""
+    copies = [v for k, v in rows if "copy" in k.lower()]
+    if not copies:
+        raise SystemExit("no copy kernel in the counter run")
+    big = [v for v in copies if v >= 0.5 * max(copies)]
+    mean = sum(big) / len(big)
+    return copy_kib / mean, len(big)
+
+
+def _means_by_kernel(rows: list) -> dict:
     acc = defaultdict(list)
-    for r in csv.DictReader(open(csv_path)):
-        if r.get("Counter_Name") != counter:
-            continue
-        acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+    for k, v in rows:
+        acc[short_name(k)].append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
 def traffic_json(fetch_csv: str, write_csv: str, copy_bytes: float, command: str) -> dict:
-    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
-    write = _counter_means(write_csv, "WRITE_SIZE")
-    copies = [k for k in fetch if "copy" in k.lower()]
-    if not copies:
-        raise SystemExit("no copy kernel in the FETCH_SIZE run")
-    ck = max(copies, key=lambda k: fetch[k])
+    frows = _counter_rows(fetch_csv, "FETCH_SIZE")
+    wrows = _counter_rows(write_csv, "WRITE_SIZE")
     kib = copy_bytes / 1024.0
-    f_scale = kib / fetch[ck]
-    w_scale = kib / write.get(ck, fetch[ck]) if write.get(ck) else 1.0
+    f_scale, nf = _calibration(frows, kib)
+    w_scale, nw = _calibration(wrows, kib)
+    fm, wm = _means_by_kernel(frows), _means_by_kernel(wrows)
     kernels = {}
-    for k in fetch:
-        s = short_name(k)
-        kernels.setdefault(s, {"fetch_kib": 0.0, "write_kib": 0.0, "n": 0})
-        kernels[s]["fetch_kib"] += fetch[k]
-        kernels[s]["write_kib"] += write.get(k, 0.0)
-        kernels[s]["n"] += 1
-    for s, v in kernels.items():
-        v["fetch_kib"] /= v["n"]
-        v["write_kib"] /= v["n"]
-        v["bytes_per_dispatch"] = 1024.0 * (v["fetch_kib"] * f_scale + v["write_kib"] * w_scale)
-        del v["n"]
-    return {"command": command, "sources": source_hash(), "copy_kernel": ck,
-            "copy_bytes": copy_bytes, "fetch_scale": f_scale, "write_scale": w_scale,
+    for s, (f, n) in fm.items():
+        w = wm.get(s, (0.0, 0))[0]
+        kernels[s] = {"dispatches": n, "fetch_kib": f, "write_kib": w,
+                      "bytes_per_dispatch": 1024.0 * (f * f_scale + w * w_scale)}
+    return {"command": command, "sources": source_hash(), "copy_bytes": copy_bytes,
+            "copy_dispatches": [nf, nw], "fetch_scale": f_scale, "write_scale": w_scale,
             "kernels": kernels}
 
 

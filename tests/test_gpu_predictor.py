@@ -112,7 +112,10 @@ def test_predict_matches_oracle(n):
     ok = np.abs(prob - mlp.sigmoid(z)) < 1e-6     # saturated probabilities
     err = np.abs(zg - z)
     assert np.all(ok | (err <= 2e-2 + 1e-2 * np.abs(z)))
-    assert np.mean(err[~ok]) < 2e-3 if (~ok).any() else True
+    # a bf16 rounding flip of a first-layer activation is rare: nearly every
+    # logit agrees to fp32 summation error
+    if (~ok).any():
+        assert np.mean(err[~ok] > 1e-4) <= max(0.05, 1.0 / n)
     # device in, device out
     pd = pr.predict(torch.from_numpy(X).cuda())
     np.testing.assert_array_equal(pd.cpu().numpy(), prob)
