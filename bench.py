@@ -14,6 +14,15 @@ paper's large web graphs.
 
 Prints one JSON line on stdout; progress goes to stderr.
   python bench.py [--steps K] [--warmup W] [--workload rmat26|rmat22|sbm10k]
+
+Two variant workloads compare against the plain run on the same GPU by time
+to termination:
+  --workload batch8k   8,192 planted-partition graphs packed in one CSR, one
+                       batched run (hipGraph-captured iterations) against
+                       per-graph runs of the same graphs
+  --workload lfr1m     learned skipping with the trained predictor
+                       (paper_2411_11468_amd/predictor_lfr.npz) against the
+                       plain run, on held-out LFR-like graphs of 10^6 vertices
 """
 from __future__ import annotations
 
@@ -42,6 +51,14 @@ WORKLOADS = {
     "sbm10k": dict(scale=None, seed=1, weights="unit", offsets=np.int32, mode="det",
                    desc="planted partition, 10,000 vertices in 100 blocks of 100, "
                         "16 intra + 4 inter expected neighbours"),
+    "batch8k": dict(scale=None, seed=5, weights="unit", offsets=np.int64, mode="async",
+                    desc="8,192 planted-partition graphs, vertex counts log-uniform in "
+                         "[256, 65536], mean degree U[8, 32], mixing U[0.1, 0.4], blocks "
+                         "U[32, 256], unit weights, packed in one CSR"),
+    "lfr1m": dict(scale=None, seed=2000, weights="unit", offsets=np.int32, mode="det",
+                  desc="LFR-like planted partitions, 10^6 vertices, power-law degrees "
+                       "(exponent 2.5, mean 20, max 1000), power-law communities "
+                       "(exponent 2, 20..5000), mixing U[0.1, 0.5], held-out seeds"),
 }
 
 
@@ -87,6 +104,117 @@ def cpu_baseline(g, budget_edges: int) -> dict:
                        f"{dt:.1f} s on one host core")}
 
 
+def run_batched(args, wl) -> int:
+    """Batched LPA over 8,192 packed graphs against per-graph runs."""
+    import torch
+    import graphgen
+    from paper_2411_11468_amd import lpa
+    mode = args.mode or wl["mode"]
+    m_id = lpa.MODE_ASYNC if mode == "async" else lpa.MODE_DETERMINISTIC
+    t0 = time.perf_counter()
+    g, v_off = graphgen.planted_partition_batch(8192, wl["seed"])
+    gen_s = time.perf_counter() - t0
+    n, m = g.num_vertices, g.num_edges
+    log(f"batch: {len(v_off) - 1} graphs, N={n} M={m}, generated in {gen_s:.1f}s")
+    dev = torch.device("cuda:0")
+    d_off = torch.from_numpy(g.offsets).to(dev)
+    d_tgt = torch.from_numpy(g.targets).to(dev)
+    d_w = torch.from_numpy(g.weights).to(dev)
+    B = lpa.LpaBatch(v_off, d_off, d_tgt, d_w)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        B.run_batched(mode, out=labels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        br = B.run_batched(mode, out=labels)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    e_per = np.diff(g.offsets[v_off])           # CSR entries per graph
+    edge_iters = float(np.sum(e_per * br.iters_per_graph))
+    log(f"batched: {t_batch * 1e3:.1f} ms per run, {br.iterations} iterations, "
+        f"{edge_iters / t_batch / 1e9:.2f} G edge-iterations/s")
+    # per-graph runs of the same graphs (pre-uploaded, one handle each)
+    t0 = time.perf_counter()
+    handles = []
+    for q in range(len(v_off) - 1):
+        a, b = int(v_off[q]), int(v_off[q + 1])
+        ea, eb = int(g.offsets[a]), int(g.offsets[b])
+        o = torch.from_numpy((g.offsets[a:b + 1] - ea).astype(np.int32)).to(dev)
+        t = torch.from_numpy((g.targets[ea:eb] - a).astype(np.int32)).to(dev)
+        w = d_w[ea:eb]
+        handles.append((lpa.LpaGraph(o, t, w, validate=False), torch.empty(b - a, dtype=torch.int32, device=dev)))
+    torch.cuda.synchronize()
+    log(f"per-graph handles built in {time.perf_counter() - t0:.1f}s")
+    best = None
+    for launch, lname in ((lpa.LAUNCH_EAGER, "eager"), (lpa.LAUNCH_GRAPH, "graph")):
+        for G, out in handles[:64]:
+            G.run(mode, out=out, launch=launch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters_solo = np.zeros(len(handles), dtype=np.int64)
+        for q, (G, out) in enumerate(handles):
+            iters_solo[q] = G.run(mode, out=out, launch=launch).iterations
+        torch.cuda.synchronize()
+        t_solo = time.perf_counter() - t0
+        log(f"per-graph ({lname} launch): {t_solo * 1e3:.1f} ms")
+        if best is None or t_solo < best[0]:
+            best = (t_solo, lname, iters_solo)
+    t_solo, lname, iters_solo = best
+    same_iters = bool(np.array_equal(iters_solo, br.iters_per_graph))
+    q_b = B.modularity(labels)
+    for G, _ in handles:
+        G.close()
+    out = {
+        "metric": "LPA edges/s (sum over graphs of |E_g|*iters_g / s), batched vs per-graph",
+        "value": edge_iters / t_batch, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch8k-{mode}", "graph": wl["desc"], "graphs": len(v_off) - 1,
+                   "vertices": n, "edges": m, "mode": mode, "seed": wl["seed"]},
+        "per_graph": {"value": float(np.sum(e_per * iters_solo)) / t_solo,
+                      "ms": 1e3 * t_solo, "launch": lname},
+        "speedup": t_solo / t_batch,
+        "iterations_equal_to_solo": same_iters,
+        "batch_iterations": br.iterations,
+        "modularity_packed": q_b,
+        "gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
+    return 0
+
+
+def run_learned(args, wl) -> int:
+    """Learned skipping against the plain run on held-out LFR-like graphs."""
+    from paper_2411_11468_amd import learned
+    path = os.path.join(ROOT, "paper_2411_11468_amd", "predictor_lfr.npz")
+    pred, info = learned.load(path)
+    mode = args.mode or info["mode"]
+    graphs = [(f"lfr1m-s{s}", learned.lfr(1_000_000, s))
+              for s in range(wl["seed"], wl["seed"] + max(1, args.steps))]
+    res = learned.evaluate(pred, info["threshold"], graphs, mode, reps=3)
+    sp = float(np.exp(np.mean([np.log(r["speedup"]) for r in res])))
+    m = sum(r["edges"] * r["plain_iters"] for r in res)
+    t_l = sum(r["learned_ms"] for r in res) / 1e3
+    t_p = sum(r["plain_ms"] for r in res) / 1e3
+    out = {
+        "metric": "LPA edges/s at the plain iteration count (|E|*iters_plain / t), learned "
+                  "vs plain",
+        "value": m / t_l, "unit": "edges/s", "n_gpus": 1, "steps": len(res), "warmup": 1,
+        "ms_per_step": 1e3 * t_l / len(res), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/bf16", "data": "synthetic",
+        "config": {"workload": f"lfr1m-learned-{mode}", "graph": wl["desc"],
+                   "threshold": info["threshold"], "guard_period": 4, "fn_bound": 0.02,
+                   "trained_on": {k: info[k] for k in ("graphs", "n", "samples", "mode")}},
+        "plain_value": m / t_p, "speedup_geomean": sp,
+        "worst_dq_rel": float(max(r["dq_rel"] for r in res)),
+        "runs": res,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +238,10 @@ def main() -> int:
     from paper_2411_11468_amd import LpaGraph
 
     wl = WORKLOADS[args.workload]
+    if args.workload == "batch8k":
+        return run_batched(args, wl)
+    if args.workload == "lfr1m":
+        return run_learned(args, wl)
     mode = args.mode or wl["mode"]
     t0 = time.perf_counter()
     g = make_graph(wl)

@@ -381,6 +381,33 @@ lpa_status lpa_trace(lpa_graph g, const lpa_options* opt, double sample_rate, ui
                      int64_t* count);
 
 /*
+ * Autotuner: pick lpa_tuning for a graph (num_graphs = 0) or a packed batch
+ * (num_graphs, v_off as for lpa_create_batched) by successive halving over a
+ * grid of class thresholds (small4 2/4, small16 8/16, wave 128/256/512,
+ * block 2048/4096/8192) and slice sizes (4096/8192), the defaults included.
+ * Each candidate is a fresh handle timed on complete runs with opt (NULL:
+ * defaults; profile and learned are turned off); each round keeps the
+ * fastest third and doubles the timed runs.  The search stops early when
+ * budget_ms of wall time is spent (the best measured so far is returned).
+ * The graph is validated once, on the first handle.  Device-resident arrays
+ * avoid a copy per candidate.
+ * Errors: as lpa_create / lpa_run; LPA_ERR_INVALID for budget_ms <= 0.
+ */
+typedef struct lpa_tune_report {
+  int32_t candidates;   /* grid size */
+  int32_t runs;         /* lpa_run calls made */
+  int32_t rounds;
+  int32_t reserved;
+  double best_ms;       /* median run time of the chosen tuning, last round */
+  double default_ms;    /* median run time of the defaults, first round */
+  double elapsed_ms;    /* wall time of the search */
+} lpa_tune_report;
+
+lpa_status lpa_autotune(const lpa_csr* csr, int32_t num_graphs, const int64_t* v_off,
+                        void* stream, const lpa_options* opt, double budget_ms,
+                        lpa_tuning* best, lpa_tune_report* report);
+
+/*
  * Modularity of a labelling, Eq. 1, in fp64:
  *   Q = sum_c [ sigma_c / 2m - (Sigma_c / 2m)^2 ]
  * with 2m the total CSR weight, Sigma_c the summed weighted degree of the

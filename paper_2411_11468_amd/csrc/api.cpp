@@ -43,15 +43,15 @@ bool is_device_ptr(const void* p) {
 namespace {
 
 // kernel ids of the optional profile
-constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubAcc = 2, kKidSweep0 = 2,
+constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubPart = 2, kKidSweep0 = 2,
               kKidHubFin = 11, kKidApply = 12, kKidPull = 13, kKidPullHubs = 14,
-              kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kKidHubRest = 18,
-              kKidBatch = 19, kNumKids = 20;
+              kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kKidHubReduce = 18,
+              kKidBatch = 19, kKidHubSpill = 20, kNumKids = 21;
 const char* const kKidNames[kNumKids] = {
-    "hub_plan", "frontier", "hub_acc", "sweep_small4", "sweep_small16", "sweep_wave127",
+    "hub_plan", "frontier", "hub_part", "sweep_small4", "sweep_small16", "sweep_wave127",
     "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
     "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
-    "push_hubs", "flag_decide", "hub_acc_rest", "batch_step"};
+    "push_hubs", "flag_decide", "hub_reduce", "batch_step", "hub_spill"};
 
 }  // namespace
 
@@ -87,13 +87,17 @@ struct lpa_graph_s {
   uint32_t* gkeys = nullptr;
   float* gvals = nullptr;
   uint32_t* items = nullptr;
-  int32_t* rec = nullptr;
-  int32_t* nrec = nullptr;
-  int32_t* hub_nrec = nullptr;
-  int32_t* hub_xcd = nullptr;
+  uint32_t* bitems = nullptr;
+  uint32_t* part_keys = nullptr;
+  float* part_vals = nullptr;
+  uint32_t* boff = nullptr;
   int32_t* hub_nch = nullptr;
-  int32_t* done = nullptr;
-  int64_t max_items = 0;
+  int32_t* hub_ovf = nullptr;
+  int32_t* hub_lgb = nullptr;
+  int64_t* hub_slice0 = nullptr;
+  int64_t* hub_boff0 = nullptr;
+  int64_t max_items = 0, max_bitems = 0;
+  int hub_reduce_grid = 8;
   double* mod_sig = nullptr;
   double* mod_acc = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -136,7 +140,7 @@ struct lpa_graph_s {
       bytes = eb * edges + (4.0 + ob + 4.0) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
       if (acct_feat) bytes += 16.0 * verts;  // state record read and written
-    } else if (kid == kKidHubAcc) {
+    } else if (kid == kKidHubPart) {
       edges = (int64_t)h.edges[kClassHub];
       bytes = eb * edges;
     } else if (kid == kKidHubFin) {
@@ -240,10 +244,13 @@ struct lpa_graph_s {
     a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F; a.chg = chg;
     a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
     a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
-    a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.rec = rec; a.nrec = nrec;
-    a.hub_nrec = hub_nrec; a.hub_xcd = hub_xcd; a.hub_nch = hub_nch; a.done = done;
+    a.hub_nch = hub_nch; a.hub_ovf = hub_ovf; a.hub_lgb = hub_lgb;
+    a.hub_slice0 = hub_slice0; a.hub_boff0 = hub_boff0;
+    a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.bitems = bitems;
+    a.part_keys = part_keys; a.part_vals = part_vals; a.boff = boff;
     a.H = H; a.chunk = tun.hub_chunk; a.async_mode = async_mode;
     a.max_retries = tun.max_retries;
+    a.xcd_map = tun.xcd_local;
     return a;
   }
 
@@ -445,50 +452,53 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     LPA_HIP(launch_gather_degrees(G->off64, G->off, G->hub_vid, G->H, ddeg, s));
     LPA_HIP(hipMemcpyAsync(hd.data(), ddeg, sizeof(int64_t) * G->H, hipMemcpyDeviceToHost, s));
     LPA_HIP(hipStreamSynchronize(s));
-    std::vector<int64_t> tab(G->H);
-    int64_t slots = 0, items = 0;
+    std::vector<int64_t> tab(G->H), slice0(G->H), boff0(G->H);
+    std::vector<int32_t> lgb(G->H);
+    int64_t slots = 0, items = 0, bitems = 0, boffs = 0;
     for (int32_t h = 0; h < G->H; ++h) {
       if (hd[h] > (int64_t)INT32_MAX / 2)
         return fail(LPA_ERR_INVALID, "a vertex degree exceeds 2^30");
       int64_t p = 1;
-      while (p < 2 * hd[h]) p <<= 1;  // capacity: smallest 2^m >= 2D, minus one
+      while (p < 2 * hd[h]) p <<= 1;  // spill table: smallest 2^m >= 2D, minus one
       tab[h] = slots;
       slots += p - 1;
-      items += (hd[h] + t.hub_chunk - 1) / t.hub_chunk;
+      const int64_t nch = (hd[h] + t.hub_chunk - 1) / t.hub_chunk;
+      lgb[h] = hub_bucket_log2(hd[h], t.hub_chunk);
+      slice0[h] = items;
+      boff0[h] = boffs;
+      items += nch;
+      bitems += (int64_t)1 << lgb[h];
+      boffs += nch * (((int64_t)1 << lgb[h]) + 1);
     }
     G->max_items = items;
-    if (lpa_status e = G->dalloc(&G->hub_tab, G->H)) return e;
-    LPA_HIP(hipMemcpyAsync(G->hub_tab, tab.data(), sizeof(int64_t) * G->H, hipMemcpyHostToDevice, s));
-    // each hub's table lives in one XCD's L2: longest-processing-time-first
-    // assignment of hubs to XCDs by degree
-    std::vector<int32_t> order(G->H), xcd(G->H);
-    for (int32_t h = 0; h < G->H; ++h) order[h] = h;
-    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return hd[x] > hd[y]; });
-    int64_t load[kXcds] = {0};
-    for (int32_t h : order) {
-      int best = 0;
-      for (int q = 1; q < kXcds; ++q)
-        if (load[q] < load[best]) best = q;
-      xcd[h] = best;
-      load[best] += hd[h];
-    }
-    if (lpa_status e = G->dalloc(&G->hub_xcd, G->H)) return e;
-    LPA_HIP(hipMemcpyAsync(G->hub_xcd, xcd.data(), sizeof(int32_t) * G->H, hipMemcpyHostToDevice, s));
+    G->max_bitems = bitems;
+    auto up64 = [&](int64_t** dst, const std::vector<int64_t>& v) -> lpa_status {
+      if (lpa_status e = G->dalloc(dst, G->H)) return e;
+      LPA_HIP(hipMemcpyAsync(*dst, v.data(), sizeof(int64_t) * G->H, hipMemcpyHostToDevice, s));
+      return LPA_OK;
+    };
+    if (lpa_status e = up64(&G->hub_tab, tab)) return e;
+    if (lpa_status e = up64(&G->hub_slice0, slice0)) return e;
+    if (lpa_status e = up64(&G->hub_boff0, boff0)) return e;
+    if (lpa_status e = G->dalloc(&G->hub_lgb, G->H)) return e;
+    LPA_HIP(hipMemcpyAsync(G->hub_lgb, lgb.data(), sizeof(int32_t) * G->H, hipMemcpyHostToDevice, s));
     if (lpa_status e = G->dalloc(&G->hub_nch, G->H)) return e;
-    if (lpa_status e = G->dalloc(&G->done, items)) return e;
+    if (lpa_status e = G->dalloc(&G->hub_ovf, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->hub_best, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->hub_old, G->H)) return e;
-    if (lpa_status e = G->dalloc(&G->hub_nrec, G->H)) return e;
     if (lpa_status e = G->dalloc(&G->gkeys, slots)) return e;
     if (lpa_status e = G->dalloc(&G->gvals, slots)) return e;
     LPA_HIP(launch_fill_u32(G->gkeys, kEmpty, slots, s));
     LPA_HIP(launch_fill_f32(G->gvals, 0.0f, slots, s));
     if (lpa_status e = G->dalloc(&G->items, 2 * items)) return e;
-    if (lpa_status e = G->dalloc(&G->rec, items * (int64_t)t.hub_chunk)) return e;
-    if (lpa_status e = G->dalloc(&G->nrec, items)) return e;
-    // one resident workgroup per CU: every XCD gets workgroups to drain its
-    // segment (the fallback pass covers any segment left undone)
-    G->hub_acc_grid = hub_max_resident();
+    if (lpa_status e = G->dalloc(&G->bitems, 2 * bitems)) return e;
+    if (lpa_status e = G->dalloc(&G->part_keys, items * (int64_t)t.hub_chunk)) return e;
+    if (lpa_status e = G->dalloc(&G->part_vals, items * (int64_t)t.hub_chunk)) return e;
+    if (lpa_status e = G->dalloc(&G->boff, boffs)) return e;
+    // one resident workgroup per CU for the two LDS-table kernels (a
+    // multiple of the 8 XCDs for the bucket mapping)
+    G->hub_acc_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, hub_max_resident()));
+    G->hub_reduce_grid = hub_max_resident();
     G->hub_fin_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, 256 * 8));
     LPA_HIP(hipStreamSynchronize(s));
   }
@@ -580,12 +590,12 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   else
     LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
   if (g->H > 0) {
-    if (g->tun.xcd_local) {
-      if (lpa_status e = mark(kKidHubAcc)) return e;
-      LPA_HIP(launch_hub_acc(g->off64, ha, g->hub_acc_grid, s));
-    }
-    if (lpa_status e = mark(kKidHubRest)) return e;
-    LPA_HIP(launch_hub_acc_rest(g->off64, ha, g->hub_fin_grid, s));
+    if (lpa_status e = mark(kKidHubPart)) return e;
+    LPA_HIP(launch_hub_part(g->off64, ha, g->hub_acc_grid, s));
+    if (lpa_status e = mark(kKidHubReduce)) return e;
+    LPA_HIP(launch_hub_reduce(g->off64, ha, g->hub_reduce_grid, s));
+    if (lpa_status e = mark(kKidHubSpill)) return e;
+    LPA_HIP(launch_hub_spill(g->off64, ha, g->hub_fin_grid, s));
   }
   SweepArgs a;
   a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;

@@ -359,13 +359,11 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 }
 
 // ---- hub plan: reset the iteration counters, take the flagged hubs, queue
-// their slices grouped by the XCD each hub is assigned to (segment x of the
-// slice list holds the slices of XCD x's hubs).  One workgroup of 1024
-// threads. ------------------------------------------------------------------------
+// their slices and their label buckets.  One workgroup of 1024 threads. -------
 template <typename OffT>
 __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_t* F) {
-  __shared__ uint32_t scan[1024];
-  __shared__ uint32_t running;
+  __shared__ uint32_t scan_s[1024], scan_b[1024];
+  __shared__ uint32_t run_s, run_b;
   __shared__ uint32_t nproc;
   const int tid = threadIdx.x;
   DevStats* st = a.st;
@@ -383,7 +381,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     st->skipping = (st->predict && (st->guard == 0 || l % st->guard != 0) && !st->cand) ? 1 : 0;
     st->skipped = 0; st->npred = 0; st->fneg = 0;
     st->trace_first = st->trace_n;
-    running = 0; nproc = 0;
+    run_s = 0; run_b = 0; nproc = 0;
   }
   if (tid < kNumClasses) {
     st->active[tid] = 0;
@@ -391,54 +389,58 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     st->changed[tid] = 0;
     st->flagw[tid] = 0;
   }
-  if (tid < kXcds) st->hub_head[tid] = 0;
   __syncthreads();
   const OffT* off = reinterpret_cast<const OffT*>(a.off);
-  // take the flagged hubs
-  for (int32_t h = tid; h < a.H; h += 1024) {
-    const int32_t v = a.hub_vid[h];
-    a.hub_best[h] = 0ull;
-    a.hub_nrec[h] = 0;
-    int32_t nch = 0;
-    if (F[v]) {
-      F[v] = 0;
-      a.hub_old[h] = C[v];
-      const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
-      nch = (int32_t)((d + a.chunk - 1) / a.chunk);
-      atomicAdd(&nproc, 1u);
+  // queue the flagged hubs' slices and buckets (inclusive Hillis-Steele scans
+  // of both counts over each tile of 1024 hubs)
+  for (int32_t tile = 0; tile < a.H; tile += 1024) {
+    const int32_t h = tile + tid;
+    uint32_t nch = 0, nbk = 0;
+    if (h < a.H) {
+      const int32_t v = a.hub_vid[h];
+      a.hub_best[h] = 0ull;
+      a.hub_ovf[h] = 0;
+      if (F[v]) {
+        F[v] = 0;
+        a.hub_old[h] = C[v];
+        const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+        nch = (uint32_t)((d + a.chunk - 1) / a.chunk);
+        nbk = 1u << a.hub_lgb[h];
+        atomicAdd(&nproc, 1u);
+      }
+      a.hub_nch[h] = (int32_t)nch;
     }
-    a.hub_nch[h] = nch;
-  }
-  __syncthreads();
-  // queue the slices, XCD by XCD
-  for (int x = 0; x < kXcds; ++x) {
-    if (tid == 0) st->hub_seg[x] = running;
-    for (int32_t tile = 0; tile < a.H; tile += 1024) {
-      const int32_t h = tile + tid;
-      const uint32_t nch = (h < a.H && a.hub_xcd[h] == x) ? (uint32_t)a.hub_nch[h] : 0u;
-      // inclusive Hillis-Steele scan of nch over the workgroup
-      scan[tid] = nch;
+    scan_s[tid] = nch;
+    scan_b[tid] = nbk;
+    __syncthreads();
+    for (int ofs = 1; ofs < 1024; ofs <<= 1) {
+      const uint32_t as = tid >= ofs ? scan_s[tid - ofs] : 0u;
+      const uint32_t ab = tid >= ofs ? scan_b[tid - ofs] : 0u;
       __syncthreads();
-      for (int ofs = 1; ofs < 1024; ofs <<= 1) {
-        const uint32_t add = tid >= ofs ? scan[tid - ofs] : 0u;
-        __syncthreads();
-        scan[tid] += add;
-        __syncthreads();
-      }
-      const uint32_t first = running + scan[tid] - nch;
-      for (uint32_t c = 0; c < nch; ++c) {
-        a.items[2 * (uint64_t)(first + c)] = (uint32_t)h;
-        a.items[2 * (uint64_t)(first + c) + 1] = c;
-        a.done[first + c] = 0;
-      }
-      __syncthreads();
-      if (tid == 0) running += scan[1023];
+      scan_s[tid] += as;
+      scan_b[tid] += ab;
       __syncthreads();
     }
+    const uint32_t fs = run_s + scan_s[tid] - nch;
+    const uint32_t fb = run_b + scan_b[tid] - nbk;
+    for (uint32_t c = 0; c < nch; ++c) {
+      a.items[2 * (uint64_t)(fs + c)] = (uint32_t)h;
+      a.items[2 * (uint64_t)(fs + c) + 1] = c;
+    }
+    for (uint32_t b = 0; b < nbk; ++b) {
+      a.bitems[2 * (uint64_t)(fb + b)] = (uint32_t)h;
+      a.bitems[2 * (uint64_t)(fb + b) + 1] = b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      run_s += scan_s[1023];
+      run_b += scan_b[1023];
+    }
+    __syncthreads();
   }
   if (tid == 0) {
-    st->hub_seg[kXcds] = running;
-    st->hub_items = running;
+    st->hub_items = run_s;
+    st->hub_bitems = run_b;
     st->processed = nproc;
   }
 }
@@ -897,13 +899,14 @@ hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t
 }
 
 // ---- modularity, Eq. 1 ------------------------------------------------------
-// Each thread owns a contiguous run of CSR entries, finds the row of its first
-// entry by binary search, and walks rows: K_i is gathered into a running sum
-// that is added into Sigma[C_i] when the label changes (and, across a wave,
-// once per label shared with the wave's first lane); entries with C_i = C_j
-// add to sigma.
+// Community form: Q = sigma / 2m - sum_c (Sigma_c / 2m)^2.  Edge-parallel: each
+// wave owns a contiguous range of CSR entries and takes 64 consecutive ones
+// per step (coalesced target and weight loads).  The row of each entry comes
+// from the 64 row ends that follow the wave's current row, searched across
+// lanes; an entry adds its weight to 2m, to sigma when both end labels agree,
+// and to Sigma of its row's label -- summed over each run of lanes whose rows
+// share a label, one fp64 atomic per run.
 namespace {
-constexpr int kModEpt = 64;
 
 __device__ __forceinline__ double block_sum_f64(double x, double* sh) {
   for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
@@ -916,6 +919,13 @@ __device__ __forceinline__ double block_sum_f64(double x, double* sh) {
   __syncthreads();
   return t;
 }
+
+__device__ __forceinline__ int64_t shfl_i64(int64_t x, int src) {
+  const int lo = __shfl((int)(uint32_t)x, src);
+  const int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 }  // namespace
 
 template <typename OffT>
@@ -924,52 +934,66 @@ __global__ __launch_bounds__(kBT) void k_mod_edges(const OffT* off, const int32_
                                                    const int32_t* C, double* sig,
                                                    double* acc) {
   __shared__ double sh[kBT / 64];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t S = (((m + nwaves - 1) / nwaves) + 63) & ~(int64_t)63;
+  const int64_t e_begin = wave * S;
+  const int64_t e_end = (e_begin + S < m) ? e_begin + S : m;
   double sigma = 0.0, two_m = 0.0;
-  const int64_t nchunks = (m + kModEpt - 1) / kModEpt;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // wave-uniform trip count: every lane takes part in the wave combine below
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nchunks;
-       base += stride) {
-    const int64_t t = base + (threadIdx.x & 63);
-    int32_t run_c = -1;   // label of the pending Sigma contribution
-    double run_k = 0.0;
-    if (t < nchunks) {
-      const int64_t e0 = t * kModEpt;
-      const int64_t e1 = (e0 + kModEpt < m) ? e0 + kModEpt : m;
-      // row containing e0: largest i with off[i] <= e0
-      int64_t lo = 0, hi = n - 1;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if ((int64_t)off[mid] <= e0) lo = mid; else hi = mid - 1;
-      }
-      int64_t i = lo;
-      int64_t row_end = (int64_t)off[i + 1];
-      int32_t ci = C[i];
-      run_c = ci;
-      for (int64_t e = e0; e < e1; ++e) {
-        while (e >= row_end) {
-          ++i;
-          row_end = (int64_t)off[i + 1];
-          ci = C[i];
-          if (ci != run_c) {
-            if (run_k != 0.0) atomicAdd(&sig[run_c], run_k);
-            run_c = ci;
-            run_k = 0.0;
-          }
+  if (e_begin < e_end) {  // uniform over the wave
+    // row of e_begin: the largest i with off[i] <= e_begin
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)off[mid] <= e_begin) lo = mid; else hi = mid - 1;
+    }
+    int64_t r0 = lo;
+    for (int64_t base = e_begin; base < e_end; base += 64) {
+      const int64_t e = base + lane;
+      const bool valid = e < e_end;
+      // row of e: r0 plus the number of row ends <= e, window by window
+      int64_t myrow = valid ? -1 : r0;
+      for (int64_t rb = r0;; rb += 64) {
+        const int64_t idx = rb + 1 + lane;
+        const int64_t end_k = idx <= n ? (int64_t)off[idx] : INT64_MAX;
+        int pos = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int64_t v = shfl_i64(end_k, pos + step - 1);
+          if (v <= e) pos += step;
         }
-        const double we = w ? (double)w[e] : 1.0;
-        run_k += we;
+        const int cnt = pos + (shfl_i64(end_k, pos) <= e ? 1 : 0);
+        if (myrow < 0 && cnt < 64) myrow = rb + cnt;
+        if (!__any(myrow < 0)) break;
+      }
+      int32_t ci = -1;
+      double we = 0.0;
+      if (valid) {
+        ci = C[myrow];
+        we = w ? (double)w[e] : 1.0;
         two_m += we;
         if (C[tgt[e]] == ci) sigma += we;
       }
+      // segmented sum of we over runs of equal labels, one atomic per run
+      const int32_t prev = __shfl_up(ci, 1);
+      const int32_t next = __shfl_down(ci, 1);
+      int f = (lane == 0 || prev != ci) ? 1 : 0;
+      double sm = we;
+#pragma unroll
+      for (int ofs = 1; ofs < 64; ofs <<= 1) {
+        const double ys = __shfl_up(sm, ofs);
+        const int yf = __shfl_up(f, ofs);
+        if (lane >= ofs && !f) {
+          sm += ys;
+          f |= yf;
+        }
+      }
+      const bool tail = lane == 63 || next != ci;
+      if (tail && ci >= 0 && sm != 0.0) atomicAdd(&sig[ci], sm);
+      const int last = (int)((e_end - 1 - base) < 63 ? (e_end - 1 - base) : 63);
+      r0 = shfl_i64(myrow, last);
     }
-    // lanes holding the same label as the first lane add it with one atomic
-    const int32_t lead = __builtin_amdgcn_readfirstlane(run_c);
-    const bool same = run_c == lead;
-    double part = same ? run_k : 0.0;
-    for (int ofs = 32; ofs > 0; ofs >>= 1) part += __shfl_xor(part, ofs);
-    if ((threadIdx.x & 63) == 0 && lead >= 0 && part != 0.0) atomicAdd(&sig[lead], part);
-    if (!same && run_c >= 0 && run_k != 0.0) atomicAdd(&sig[run_c], run_k);
   }
   const double s1 = block_sum_f64(sigma, sh);
   const double s2 = block_sum_f64(two_m, sh);
@@ -997,7 +1021,7 @@ hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt, co
   e = launch_fill_f64(acc, 0.0, 4, s);
   if (e != hipSuccess) return e;
   if (m > 0) {
-    const int g = grid_for((m + kModEpt - 1) / kModEpt, kBT, 16384);
+    const int g = grid_for((m + 63) / 64, kBT, 16384);
     if (off64)
       hipLaunchKernelGGL(k_mod_edges<int64_t>, dim3(g), dim3(kBT), 0, s, (const int64_t*)off,
                          tgt, w, n, m, C, sig, acc);

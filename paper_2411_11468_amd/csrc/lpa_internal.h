@@ -30,8 +30,7 @@ struct DevStats {
   unsigned int pull_mode;                       // 1: flags of this iteration pulled
   unsigned int active[kNumClasses];             // vertices appended per class
   unsigned int hub_items;                       // hub slices queued this iteration
-  unsigned int hub_seg[kXcds + 1];              // slice list segment of each XCD
-  unsigned int hub_head[kXcds];                 // next slice of each segment
+  unsigned int hub_bitems;                      // hub label buckets queued this iteration
   // run control, resident on the device so that iterations can be launched
   // back to back (or replayed from a captured graph) without the host
   double tol;                                   // stop tolerance
@@ -110,6 +109,13 @@ struct SweepArgs {
   unsigned long long* rec;  // learned variant: per-vertex state records
 };
 
+// Hubs (rows longer than the largest LDS table).  Each slice of chunk CSR
+// entries is reduced in an LDS table; its distinct (label, partial sum) pairs
+// are written out grouped by label bucket (a hash of the label, 2^lgb
+// buckets per hub, about chunk entries each).  Each bucket is then reduced in
+// LDS by one workgroup, which folds its maximum into the hub's packed best.
+// A bucket whose distinct labels overflow the LDS table spills the rest into
+// the hub's global-memory table, scanned afterwards.
 struct HubArgs {
   const void* off;
   const int32_t* tgt;
@@ -121,22 +127,26 @@ struct HubArgs {
   int32_t* pend_c;
   DevStats* st;
   const int32_t* hub_vid;          // H hub vertex ids
-  const int64_t* hub_tab;          // H offsets into the global table
+  const int64_t* hub_tab;          // H offsets into the overflow table
   unsigned long long* hub_best;    // H packed (weight, ~label) maxima
   int32_t* hub_old;                // H labels at iteration start
-  uint32_t* gkeys;                 // global table keys
-  float* gvals;                    // global table values
-  uint32_t* items;                 // queued slices: (hub index, slice index) word pairs
-  int32_t* rec;                    // per slice: recorded global slots
-  int32_t* nrec;                   // per slice: number of recorded slots
-  int32_t* hub_nrec;               // per hub: slots recorded by all its slices
-  const int32_t* hub_xcd;          // per hub: XCD whose L2 holds its table
   int32_t* hub_nch;                // per hub: slices queued this iteration
-  int32_t* done;                   // per slice: merged by the XCD-local pass
+  int32_t* hub_ovf;                // per hub: some bucket spilled this iteration
+  const int32_t* hub_lgb;          // per hub: log2 of its bucket count
+  const int64_t* hub_slice0;       // per hub: index of its first slice
+  const int64_t* hub_boff0;        // per hub: start of its bucket offsets
+  uint32_t* gkeys;                 // overflow table keys
+  float* gvals;                    // overflow table values
+  uint32_t* items;                 // queued slices: (hub, slice) word pairs
+  uint32_t* bitems;                // queued buckets: (hub, bucket) word pairs
+  uint32_t* part_keys;             // per slice: chunk entries, grouped by bucket
+  float* part_vals;
+  uint32_t* boff;                  // per slice: 2^lgb + 1 bucket offsets
   int32_t H;
   int32_t chunk;                   // edges per slice
   int async_mode;
   int max_retries;
+  int xcd_map;                     // 1: consecutive buckets on one XCD
 };
 
 // Statistics of one iteration as recorded on the device (same layout as the
@@ -220,9 +230,13 @@ hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t
                         hipStream_t s);
 hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, bool feat,
                         hipStream_t s);
-hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s);
-hipError_t launch_hub_acc_rest(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_hub_part(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_hub_reduce(bool off64, const HubArgs& a, int grid, hipStream_t s);
+hipError_t launch_hub_spill(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_fin(bool off64, const HubArgs& a, int grid, hipStream_t s);
+// Bucket count of a hub of degree d: 2^lgb buckets of about chunk entries.
+int hub_bucket_log2(int64_t d, int chunk);
+constexpr int kHubMaxBucketLog2 = 12;   // 4096 buckets (LDS histogram of k_hub_part)
 hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt,
                              const float* w, int64_t n, int64_t m,
                              const int32_t* C, double* sig, double* acc,

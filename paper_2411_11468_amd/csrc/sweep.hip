@@ -443,43 +443,112 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
-// ---- hubs: slices reduced in LDS, merged in a global table -----------------
-// LOCAL: the XCD-local pass.  Each workgroup reads the XCD it runs on and
-// takes only slices of hubs assigned to that XCD, so every access to a hub's
-// table comes from one XCD and the table atomics run at workgroup scope in
-// that XCD's L2.  Merged slices are marked done.  !LOCAL: the fallback pass
-// after it (a kernel boundary writes the L2s back) merges any slice left
-// undone with agent-scope atomics; it normally finds none.
-template <typename OffT, int SLOTS, int BT, bool LOCAL>
-__global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
+// ---- hubs: slices reduced in LDS, partitioned by label bucket, buckets
+// reduced in LDS ----------------------------------------------------------------
+// A hub row is cut into slices of chunk entries.  k_hub_part reduces a slice
+// in an LDS table and writes its distinct (label, partial sum) pairs grouped
+// by bucket (label hash >> (32 - lgb)), with the bucket offsets of the slice.
+// k_hub_reduce takes one (hub, bucket): it reads that bucket's run from every
+// slice of the hub, sums the runs in an LDS table and folds the bucket's
+// packed maximum into the hub's best.  Every label of a hub lies in exactly
+// one bucket, so the largest bucket maximum is the hub's Eq. 3 maximum.  The
+// pairs move through HBM once each way, coalesced; no global atomics are
+// made on label sums.  A bucket that finds its LDS table full spills the new
+// labels into the hub's global table (each such label wholly, since a full
+// table stays full), which k_hub_spill scans and clears.
+namespace {
+
+__device__ __forceinline__ uint32_t bucket_of(uint32_t label, int lgb) {
+  uint32_t x = label;  // MurmurHash3 32-bit finaliser
+  x ^= x >> 16;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  x *= 0xC2B2AE35u;
+  x ^= x >> 16;
+  return lgb == 0 ? 0u : (x >> (32 - lgb));
+}
+
+// In-place exclusive scan of a[0..n) (n <= BT * PER) by one workgroup;
+// returns the total.  Ends with a barrier.
+template <int BT, int PER>
+__device__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t n, uint32_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t v[PER];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const uint32_t i = (uint32_t)tid * PER + q;
+    v[q] = i < n ? a[i] : 0u;
+    mine += v[q];
+  }
+  // inclusive scan of the per-thread sums within the wave
+  uint32_t x = mine;
+#pragma unroll
+  for (int ofs = 1; ofs < 64; ofs <<= 1) {
+    const uint32_t y = __shfl_up(x, ofs);
+    if (lane >= ofs) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int q = 0; q < BT / 64; ++q) {
+    if (q < wv) before += wsum[q];
+    total += wsum[q];
+  }
+  uint32_t run = before + x - mine;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const uint32_t i = (uint32_t)tid * PER + q;
+    if (i < n) a[i] = run;
+    run += v[q];
+  }
+  __syncthreads();
+  return total;
+}
+
+// lds_accumulate that gives up (returns false) when the table holds neither
+// the key nor an empty slot: after max_retries hybrid probes the linear
+// continuation has visited every slot once.
+__device__ __forceinline__ bool lds_accumulate_bounded(uint32_t* keys, float* vals, uint32_t p1,
+                                                       uint32_t k, float v, int max_retries) {
+  const uint32_t p2 = 2u * p1 + 1u;
+  uint32_t s = k % p1;
+  uint32_t step = 1u % p1;
+  const uint32_t r = (k % p2) % p1;
+  const int limit = max_retries + (int)p1;
+  for (int t = 0; t < limit; ++t) {
+    uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == kEmpty) {
+      uint32_t expected = kEmpty;
+      __hip_atomic_compare_exchange_strong(&keys[s], &expected, k, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      cur = (expected == kEmpty) ? k : expected;
+    }
+    if (cur == k) {
+      __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return true;
+    }
+    probe_next(s, step, r, p1, t, max_retries);
+  }
+  return false;
+}
+
+}  // namespace
+
+template <typename OffT, int SLOTS, int BT>
+__global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
+  constexpr int kMaxB = 1 << kHubMaxBucketLog2;
   __shared__ uint32_t keys[SLOTS];
   __shared__ float vals[SLOTS];
-  __shared__ unsigned long long red[BT / 64];
-  __shared__ uint32_t nrec;
-  __shared__ uint32_t next;
-  constexpr int kScope = LOCAL ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
+  __shared__ uint32_t hist[kMaxB];
+  __shared__ uint32_t wsum[BT / 64];
   if (a.st->stop) return;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
-  if (tid == 0) nrec = 0;
   __syncthreads();
-  const uint32_t x = LOCAL ? xcc_id() : 0u;
-  const uint32_t seg0 = a.st->hub_seg[x];
-  const uint32_t seg_n = LOCAL ? a.st->hub_seg[x + 1] - seg0 : a.st->hub_items;
+  const uint32_t nitems = a.st->hub_items;
   unsigned long long my_edges = 0;
-  uint32_t k = blockIdx.x;
-  for (;;) {
-    if (LOCAL) {
-      if (tid == 0) next = atomicAdd(&a.st->hub_head[x], 1u);
-      __syncthreads();
-      k = next;
-      __syncthreads();
-    }
-    if (k >= seg_n) break;
-    const uint32_t it = LOCAL ? seg0 + k : k;
-    if (!LOCAL) k += gridDim.x;
-    if (!LOCAL && a.done[it]) continue;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
     const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
     const int32_t v = a.hub_vid[h];
@@ -487,6 +556,9 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
     row_of<OffT>(a.off, v, &o, &d);
     const int64_t e0 = (int64_t)c * a.chunk;
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
+    const int lgb = a.hub_lgb[h];
+    const uint32_t nb = 1u << lgb;
+    for (uint32_t b = tid; b < nb; b += BT) hist[b] = 0u;
     const uint32_t p1c = table_p1((uint32_t)n);
     for (int64_t e = tid; e < n; e += BT) {
       const int32_t j = a.tgt[o + e0 + e];
@@ -495,59 +567,170 @@ __global__ __launch_bounds__(BT) void k_hub_acc(HubArgs a) {
                        a.max_retries);
     }
     __syncthreads();
-    const uint32_t p1g = table_p1((uint32_t)d);
-    uint32_t* gk = a.gkeys + a.hub_tab[h];
-    float* gv = a.gvals + a.hub_tab[h];
-    int32_t* rec = a.rec + (int64_t)it * a.chunk;
-    unsigned long long best = 0;
-    // every lane walks the same number of rounds so the wave can vote
-    for (uint32_t s0 = 0; s0 < p1c; s0 += BT) {
-      const uint32_t s = s0 + tid;
-      int32_t slot_out = -1;
-      const uint32_t kk = (s < p1c) ? keys[s] : kEmpty;
+    for (uint32_t s = tid; s < p1c; s += BT) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) atomicAdd(&hist[bucket_of(kk, lgb)], 1u);
+    }
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan<BT, kMaxB / BT>(hist, nb, wsum);
+    uint32_t* bo = a.boff + a.hub_boff0[h] + (int64_t)c * (nb + 1);
+    for (uint32_t b = tid; b < nb; b += BT) bo[b] = hist[b];
+    if (tid == 0) bo[nb] = total;
+    const int64_t base = (a.hub_slice0[h] + c) * (int64_t)a.chunk;
+    for (uint32_t s = tid; s < p1c; s += BT) {
+      const uint32_t kk = keys[s];
       if (kk != kEmpty) {
-        float after;
-        const uint32_t gs =
-            global_accumulate<kScope>(gk, gv, p1g, kk, vals[s], a.max_retries, &after);
-        best = umax64(best, pack_key(after, kk));
+        const uint32_t pos = atomicAdd(&hist[bucket_of(kk, lgb)], 1u);
+        a.part_keys[base + pos] = kk;
+        a.part_vals[base + pos] = vals[s];
         keys[s] = kEmpty;
         vals[s] = 0.0f;
-        slot_out = (int32_t)gs;
       }
-      // record the global slots touched by this slice, one LDS atomic per wave
-      const unsigned long long mask = __ballot(slot_out >= 0);
-      if (mask) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&nrec, (uint32_t)__popcll(mask));
-        base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-        if (slot_out >= 0) rec[base + lane_rank(mask)] = slot_out;
+    }
+    if (tid == 0) my_edges += (unsigned long long)n;
+    __syncthreads();
+  }
+  const unsigned long long e = wave_sum_u64(my_edges);
+  if ((tid & 63) == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
+}
+
+template <typename OffT, int SLOTS, int BT>
+__global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
+  __shared__ uint32_t keys[SLOTS];
+  __shared__ float vals[SLOTS];
+  __shared__ unsigned long long red[BT / 64];
+  __shared__ uint32_t wcnt[BT / 64];
+  __shared__ int spilled;
+  if (a.st->stop) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  if (tid == 0) spilled = 0;
+  __syncthreads();
+  const uint32_t nitems = a.st->hub_bitems;
+  // xcd_map: workgroup w runs on XCD w % 8 (round-robin dispatch); give each
+  // XCD a contiguous range of buckets so that the runs of neighbouring
+  // buckets, which share cache lines, are read through one L2
+  const uint32_t nx = a.xcd_map ? (uint32_t)kXcds : 1u;
+  const uint32_t x = blockIdx.x % nx, lw = blockIdx.x / nx, nlw = gridDim.x / nx;
+  if (lw >= nlw) return;  // workgroups past the last full round of XCDs
+  const uint32_t per = (nitems + nx - 1) / nx;
+  for (uint32_t j = lw; j < per; j += nlw) {
+    const uint32_t it = x * per + j;
+    if (it >= nitems) break;
+    const int32_t h = (int32_t)a.bitems[2 * (uint64_t)it];
+    const uint32_t b = a.bitems[2 * (uint64_t)it + 1];
+    const int32_t v = a.hub_vid[h];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    const uint32_t nch = (uint32_t)((d + a.chunk - 1) / a.chunk);
+    const int lgb = a.hub_lgb[h];
+    const uint32_t nb1 = (1u << lgb) + 1u;
+    const uint32_t* bo = a.boff + a.hub_boff0[h];
+    // entries of this bucket over all slices: sizes the table
+    uint32_t cnt = 0;
+    for (uint32_t c = tid; c < nch; c += BT) cnt += bo[c * nb1 + b + 1] - bo[c * nb1 + b];
+    cnt = wave_sum_u32(cnt);
+    if (lane == 0) wcnt[tid >> 6] = cnt;
+    __syncthreads();
+    uint32_t E = 0;
+    for (int q = 0; q < BT / 64; ++q) E += wcnt[q];
+    const uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
+    // G lanes per slice run (a power of two), so that few slices still keep
+    // the workgroup busy
+    uint32_t G = 1;
+    while (G < 64 && G * 2 * nch <= (uint32_t)BT) G *= 2;
+    const int64_t slice0 = a.hub_slice0[h];
+    uint32_t* gk = a.gkeys + a.hub_tab[h];
+    float* gv = a.gvals + a.hub_tab[h];
+    const uint32_t p1g = table_p1((uint32_t)d);
+    bool my_spill = false;
+    for (uint32_t c = tid / G; c < nch; c += BT / G) {
+      const uint32_t lo = bo[c * nb1 + b], hi = bo[c * nb1 + b + 1];
+      const int64_t base = (slice0 + c) * (int64_t)a.chunk;
+      for (uint32_t e = lo + tid % G; e < hi; e += G) {
+        const uint32_t kk = a.part_keys[base + e];
+        const float vv = a.part_vals[base + e];
+        if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.max_retries)) {
+          float after;
+          (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, p1g, kk, vv, a.max_retries,
+                                                            &after);
+          my_spill = true;
+        }
+      }
+    }
+    if (my_spill) spilled = 1;
+    __syncthreads();
+    unsigned long long best = 0;
+    for (uint32_t s = tid; s < p1; s += BT) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(vals[s], kk));
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
       }
     }
     best = wave_max_u64(best);
     if (lane == 0) red[tid >> 6] = best;
     __syncthreads();
     if (tid == 0) {
-      unsigned long long b = red[0];
-      for (int q = 1; q < BT / 64; ++q) b = umax64(b, red[q]);
-      if (b) atomicMax(&a.hub_best[h], b);
-      a.nrec[it] = (int32_t)nrec;
-      atomicAdd(&a.hub_nrec[h], (int32_t)nrec);
-      if (LOCAL) a.done[it] = 1;
-      nrec = 0;
-      my_edges += (unsigned long long)n;
+      unsigned long long bb = red[0];
+      for (int q = 1; q < BT / 64; ++q) bb = umax64(bb, red[q]);
+      if (bb) atomicMax(&a.hub_best[h], bb);
+      if (spilled) a.hub_ovf[h] = 1;
+      spilled = 0;
     }
     __syncthreads();
   }
-  const unsigned long long e = wave_sum_u64(my_edges);
-  if (tid == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
 }
 
+// Labels spilled into a hub's global table: each slice of the hub scans a
+// stripe of the table, folds its maximum into the hub's best and clears it.
+template <typename OffT, int BT>
+__global__ __launch_bounds__(BT) void k_hub_spill(HubArgs a) {
+  __shared__ unsigned long long red[BT / 64];
+  if (a.st->stop) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t nitems = a.st->hub_items;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
+    if (!a.hub_ovf[h]) continue;  // uniform over the workgroup
+    const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    int64_t o, d;
+    row_of<OffT>(a.off, a.hub_vid[h], &o, &d);
+    const int64_t ns = (d + a.chunk - 1) / a.chunk;
+    const int64_t p1g = table_p1((uint32_t)d);
+    const int64_t s0 = p1g * c / ns, s1 = p1g * (c + 1) / ns;
+    uint32_t* gk = a.gkeys + a.hub_tab[h];
+    float* gv = a.gvals + a.hub_tab[h];
+    unsigned long long best = 0;
+    for (int64_t s = s0 + tid; s < s1; s += BT) {
+      const uint32_t kk = gk[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(gv[s], kk));
+        gk[s] = kEmpty;
+        gv[s] = 0.0f;
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) red[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long bb = red[0];
+      for (int q = 1; q < BT / 64; ++q) bb = umax64(bb, red[q]);
+      if (bb) atomicMax(&a.hub_best[h], bb);
+    }
+    __syncthreads();
+  }
+}
+
+// Move decision of each hub from its packed best (slice 0 of the hub writes
+// the label; every slice adds its entry count to the flag work).
 template <typename OffT, int BT>
 __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
   if (a.st->stop) return;
   const int tid = threadIdx.x;
   const uint32_t nitems = a.st->hub_items;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (uint32_t it = blockIdx.x * BT + tid; it < nitems; it += gridDim.x * BT) {
     const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
     const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
     const int32_t v = a.hub_vid[h];
@@ -557,41 +740,19 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
     uint32_t cstar = 0;
     const bool moved = decide(a.hub_best[h], a.hub_old[h], a.st->pl, &cstar);
-    if (moved) {
-      if (c == 0 && tid == 0) {
-        if (a.async_mode) {
-          a.C[v] = (int32_t)cstar;
-        } else {
-          const unsigned long long pos = atomicAdd(&a.st->pending, 1ull);
-          a.pend_v[pos] = v;
-          a.pend_c[pos] = (int32_t)cstar;
-        }
-        atomicAdd(&a.st->changed[kClassHub], 1ull);
+    if (!moved) continue;
+    if (c == 0) {
+      if (a.async_mode) {
+        a.C[v] = (int32_t)cstar;
+      } else {
+        const unsigned long long pos = atomicAdd(&a.st->pending, 1ull);
+        a.pend_v[pos] = v;
+        a.pend_c[pos] = (int32_t)cstar;
       }
-      if (tid == 0) atomicAdd(&a.st->flagw[kClassHub], (unsigned long long)n);
-      if (c == 0 && tid == 0) a.chg[v] = 1;
+      atomicAdd(&a.st->changed[kClassHub], 1ull);
+      a.chg[v] = 1;
     }
-    uint32_t* gk = a.gkeys + a.hub_tab[h];
-    float* gv = a.gvals + a.hub_tab[h];
-    const int64_t p1g = table_p1((uint32_t)d);
-    if (4ll * a.hub_nrec[h] >= p1g) {
-      // most of the table was touched: the hub's slices clear it in
-      // contiguous stripes
-      const int64_t ns = (d + a.chunk - 1) / a.chunk;
-      const int64_t s0 = p1g * c / ns, s1 = p1g * (c + 1) / ns;
-      for (int64_t s = s0 + tid; s < s1; s += BT) {
-        gk[s] = kEmpty;
-        gv[s] = 0.0f;
-      }
-    } else {
-      const int32_t* rec = a.rec + (int64_t)it * a.chunk;
-      const int32_t nr = a.nrec[it];
-      for (int32_t r = tid; r < nr; r += BT) {
-        const int32_t s = rec[r];
-        gk[s] = kEmpty;
-        gv[s] = 0.0f;
-      }
-    }
+    atomicAdd(&a.st->flagw[kClassHub], (unsigned long long)n);
   }
 }
 
@@ -661,21 +822,34 @@ hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, bool 
   return feat ? sweep_t<int32_t, true>(cls, a, grid, s) : sweep_t<int32_t, false>(cls, a, grid, s);
 }
 
-hipError_t launch_hub_acc(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+int hub_bucket_log2(int64_t d, int chunk) {
+  int lgb = 0;
+  while (lgb < kHubMaxBucketLog2 && ((int64_t)chunk << lgb) < d) ++lgb;
+  return lgb;
+}
+
+hipError_t launch_hub_part(bool off64, const HubArgs& a, int grid, hipStream_t s) {
   if (a.chunk > (kHubSlots + 1) / 2) return hipErrorInvalidValue;
   if (off64)
-    hipLaunchKernelGGL((k_hub_acc<int64_t, kHubSlots, kHubThreads, true>), dim3(grid), dim3(kHubThreads), 0, s, a);
+    hipLaunchKernelGGL((k_hub_part<int64_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((k_hub_acc<int32_t, kHubSlots, kHubThreads, true>), dim3(grid), dim3(kHubThreads), 0, s, a);
+    hipLaunchKernelGGL((k_hub_part<int32_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_hub_acc_rest(bool off64, const HubArgs& a, int grid, hipStream_t s) {
-  if (a.chunk > (kHubSlots + 1) / 2) return hipErrorInvalidValue;
+hipError_t launch_hub_reduce(bool off64, const HubArgs& a, int grid, hipStream_t s) {
   if (off64)
-    hipLaunchKernelGGL((k_hub_acc<int64_t, kHubSlots, kHubThreads, false>), dim3(grid), dim3(kHubThreads), 0, s, a);
+    hipLaunchKernelGGL((k_hub_reduce<int64_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((k_hub_acc<int32_t, kHubSlots, kHubThreads, false>), dim3(grid), dim3(kHubThreads), 0, s, a);
+    hipLaunchKernelGGL((k_hub_reduce<int32_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hub_spill(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL((k_hub_spill<int64_t, 256>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hub_spill<int32_t, 256>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -74,6 +74,13 @@ class lpa_learned_iter(ctypes.Structure):
                 ("false_negatives", ctypes.c_int64)]
 
 
+class lpa_tune_report(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("runs", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double)]
+
+
 class lpa_kernel_profile(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
@@ -99,7 +106,7 @@ EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run"
             "lpa_predictor_destroy", "lpa_predictor_set_params", "lpa_predictor_get_params",
             "lpa_predictor_gradient", "lpa_predictor_adam", "lpa_predictor_train",
             "lpa_predictor_predict", "lpa_learned_options_default", "lpa_set_predictor",
-            "lpa_learned_history", "lpa_get_records", "lpa_trace")
+            "lpa_learned_history", "lpa_get_records", "lpa_trace", "lpa_autotune")
 
 _lib = None
 
@@ -175,6 +182,10 @@ def load_library(path: str = LIB_PATH):
     lib.lpa_trace.argtypes = [vp, ctypes.POINTER(lpa_options), ctypes.c_double, ctypes.c_uint64,
                               vp, vp, vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.lpa_trace.restype = ctypes.c_int
+    lib.lpa_autotune.argtypes = [ctypes.POINTER(lpa_csr), ctypes.c_int32, vp, vp,
+                                 ctypes.POINTER(lpa_options), ctypes.c_double,
+                                 ctypes.POINTER(lpa_tuning), ctypes.POINTER(lpa_tune_report)]
+    lib.lpa_autotune.restype = ctypes.c_int
     lib.lpa_status_string.argtypes = [ctypes.c_int]
     lib.lpa_status_string.restype = ctypes.c_char_p
     lib.lpa_last_error.argtypes = []
@@ -388,6 +399,23 @@ def lpa_trace(handle, *, sample_rate: float, seed: int = 0, cap: int = 1 << 20,
                          _addr(it), int(cap), ctypes.byref(cnt)))
     k = min(int(cnt.value), cap)
     return X[:k], y[:k], v[:k], it[:k], int(cnt.value)
+
+
+def lpa_autotune(offsets, targets, weights=None, *, v_off=None, mode: int = MODE_ASYNC,
+                 budget_ms: float = 60_000.0, launch: int = LAUNCH_GRAPH, stream=None):
+    """Search lpa_tuning for this graph (or packed batch with v_off).
+    Returns (tuning, report dict)."""
+    lib = load_library()
+    g, on_dev, _keep = _csr_struct(offsets, targets, weights, True)
+    o = _options(mode, 0.05, 20, 4, True, None, False, FLAGS_AUTO, launch)
+    best = lpa_tuning()
+    rep = lpa_tune_report()
+    vo = None if v_off is None else np.ascontiguousarray(v_off, dtype=np.int64)
+    ng = 0 if vo is None else int(vo.shape[0] - 1)
+    s = stream if stream is not None else _current_stream(on_dev)
+    _check(lib.lpa_autotune(ctypes.byref(g), ng, _addr(vo), s, ctypes.byref(o),
+                            float(budget_ms), ctypes.byref(best), ctypes.byref(rep)))
+    return best, {f: getattr(rep, f) for f, _ in lpa_tune_report._fields_ if f != "reserved"}
 
 
 def lpa_modularity(handle, labels) -> float:
