@@ -904,8 +904,11 @@ hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t
 // per step (coalesced target and weight loads).  The row of each entry comes
 // from the 64 row ends that follow the wave's current row, searched across
 // lanes; an entry adds its weight to 2m, to sigma when both end labels agree,
-// and to Sigma of its row's label -- summed over each run of lanes whose rows
-// share a label, one fp64 atomic per run.
+// and to Sigma of its row's label.  Sigma is summed over each run of lanes
+// whose rows share a label, then gathered per wave in a small LDS table of
+// labels (a direct-mapped cache flushed with one fp64 atomic per label at the
+// end of the wave's range), so that a label shared by many rows -- a large
+// community -- costs few atomics on its one address.
 namespace {
 
 __device__ __forceinline__ double block_sum_f64(double x, double* sh) {
@@ -928,13 +931,22 @@ __device__ __forceinline__ int64_t shfl_i64(int64_t x, int src) {
 
 }  // namespace
 
+constexpr int kModCache = 64;  // label slots per wave
+
 template <typename OffT>
 __global__ __launch_bounds__(kBT) void k_mod_edges(const OffT* off, const int32_t* tgt,
                                                    const float* w, int64_t n, int64_t m,
                                                    const int32_t* C, double* sig,
                                                    double* acc) {
   __shared__ double sh[kBT / 64];
+  __shared__ int32_t ckey_all[kBT / 64][kModCache];
+  __shared__ double cval_all[kBT / 64][kModCache];
   const int lane = threadIdx.x & 63;
+  int32_t* ckey = ckey_all[threadIdx.x >> 6];
+  double* cval = cval_all[threadIdx.x >> 6];
+  ckey[lane] = -1;
+  cval[lane] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t S = (((m + nwaves - 1) / nwaves) + 63) & ~(int64_t)63;
@@ -990,11 +1002,26 @@ __global__ __launch_bounds__(kBT) void k_mod_edges(const OffT* off, const int32_
         }
       }
       const bool tail = lane == 63 || next != ci;
-      if (tail && ci >= 0 && sm != 0.0) atomicAdd(&sig[ci], sm);
+      if (tail && ci >= 0 && sm != 0.0) {
+        const int slot = (int)(((uint32_t)ci * 0x9E3779B1u) >> 26);  // 64 slots
+        int k = __hip_atomic_load(&ckey[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (k == -1) {
+          int expected = -1;
+          __hip_atomic_compare_exchange_strong(&ckey[slot], &expected, ci, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          k = expected == -1 ? ci : expected;
+        }
+        if (k == ci)
+          __hip_atomic_fetch_add(&cval[slot], sm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        else
+          atomicAdd(&sig[ci], sm);  // slot held by another label
+      }
       const int last = (int)((e_end - 1 - base) < 63 ? (e_end - 1 - base) : 63);
       r0 = shfl_i64(myrow, last);
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  if (ckey[lane] >= 0 && cval[lane] != 0.0) atomicAdd(&sig[ckey[lane]], cval[lane]);
   const double s1 = block_sum_f64(sigma, sh);
   const double s2 = block_sum_f64(two_m, sh);
   if (threadIdx.x == 0) {

@@ -596,10 +596,12 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
 
 template <typename OffT, int SLOTS, int BT>
 __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
+  constexpr int kRuns = 4 * BT;  // slice runs staged per pass
   __shared__ uint32_t keys[SLOTS];
   __shared__ float vals[SLOTS];
+  __shared__ uint32_t start[kRuns];
   __shared__ unsigned long long red[BT / 64];
-  __shared__ uint32_t wcnt[BT / 64];
+  __shared__ uint32_t wsum[BT / 64];
   __shared__ int spilled;
   if (a.st->stop) return;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -630,26 +632,39 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
     uint32_t cnt = 0;
     for (uint32_t c = tid; c < nch; c += BT) cnt += bo[c * nb1 + b + 1] - bo[c * nb1 + b];
     cnt = wave_sum_u32(cnt);
-    if (lane == 0) wcnt[tid >> 6] = cnt;
+    if (lane == 0) wsum[tid >> 6] = cnt;
     __syncthreads();
     uint32_t E = 0;
-    for (int q = 0; q < BT / 64; ++q) E += wcnt[q];
+    for (int q = 0; q < BT / 64; ++q) E += wsum[q];
+    __syncthreads();
     const uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
-    // G lanes per slice run (a power of two), so that few slices still keep
-    // the workgroup busy
-    uint32_t G = 1;
-    while (G < 64 && G * 2 * nch <= (uint32_t)BT) G *= 2;
     const int64_t slice0 = a.hub_slice0[h];
     uint32_t* gk = a.gkeys + a.hub_tab[h];
     float* gv = a.gvals + a.hub_tab[h];
     const uint32_t p1g = table_p1((uint32_t)d);
     bool my_spill = false;
-    for (uint32_t c = tid / G; c < nch; c += BT / G) {
-      const uint32_t lo = bo[c * nb1 + b], hi = bo[c * nb1 + b + 1];
-      const int64_t base = (slice0 + c) * (int64_t)a.chunk;
-      for (uint32_t e = lo + tid % G; e < hi; e += G) {
-        const uint32_t kk = a.part_keys[base + e];
-        const float vv = a.part_vals[base + e];
+    // the bucket's runs, kRuns slices at a time: their lengths are scanned
+    // into start[], and the workgroup's threads take the pass's entries
+    // evenly, each finding its slice by binary search in start[]
+    for (uint32_t c0 = 0; c0 < nch; c0 += kRuns) {
+      const uint32_t cn = (nch - c0 < (uint32_t)kRuns) ? nch - c0 : (uint32_t)kRuns;
+      for (uint32_t i = tid; i < cn; i += BT) {
+        const uint32_t c = c0 + i;
+        start[i] = bo[c * nb1 + b + 1] - bo[c * nb1 + b];
+      }
+      __syncthreads();
+      const uint32_t total = block_exclusive_scan<BT, kRuns / BT>(start, cn, wsum);
+      for (uint32_t g = tid; g < total; g += BT) {
+        uint32_t lo = 0, hi = cn - 1;  // largest i with start[i] <= g
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) >> 1;
+          if (start[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t c = c0 + lo;
+        const uint32_t e = bo[c * nb1 + b] + (g - start[lo]);
+        const int64_t idx = (slice0 + c) * (int64_t)a.chunk + e;
+        const uint32_t kk = a.part_keys[idx];
+        const float vv = a.part_vals[idx];
         if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.max_retries)) {
           float after;
           (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, p1g, kk, vv, a.max_retries,
@@ -657,6 +672,7 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
           my_spill = true;
         }
       }
+      __syncthreads();  // start[] is rewritten by the next pass
     }
     if (my_spill) spilled = 1;
     __syncthreads();

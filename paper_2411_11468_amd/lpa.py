@@ -111,11 +111,13 @@ EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run"
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load liblpa.so (raises if it has not been built)."""
+def load_library(path: str | None = None):
+    """Load liblpa.so (raises if it has not been built).  LPA_LIBRARY in the
+    environment names another build of the same ABI."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("LPA_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2411_11468_amd.build`")
