@@ -27,9 +27,11 @@ struct lpa_predictor_s {
   template <typename T>
   lpa_status alloc(T** out, size_t count) {
     void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    const hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(LPA_ERR_OOM, "hipMalloc failed for the predictor");
+      return fail(LPA_ERR_OOM, std::string("hipMalloc failed for the predictor: ") +
+                                   hipGetErrorString(e));
     }
     allocs.push_back(q);
     *out = static_cast<T*>(q);

@@ -118,6 +118,15 @@ def load_library(path: str | None = None):
     if _lib is not None:
         return _lib
     path = path or os.environ.get("LPA_LIBRARY") or LIB_PATH
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 with
+    # the same soname as ROCm's.  Importing torch first lets liblpa.so bind
+    # to the copy torch uses; loading liblpa.so first would map ROCm's copy
+    # as well, and torch's device memory would then belong to another
+    # runtime instance than the library's calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2411_11468_amd.build`")

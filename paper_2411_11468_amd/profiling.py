@@ -38,8 +38,9 @@ _NAME_RULES = [
     (r"k_sweep_block<[^,]+, 4095,", "sweep_block4095"),
     (r"k_sweep_block<[^,]+, 8191,", "sweep_block8191"),
     (r"k_sweep_block<[^,]+, 16383,", "sweep_block16383"),
-    (r"k_hub_acc<[^>]*true>", "hub_acc"),
-    (r"k_hub_acc<[^>]*false>", "hub_acc_rest"),
+    (r"k_hub_part<", "hub_part"),
+    (r"k_hub_reduce<", "hub_reduce"),
+    (r"k_hub_spill<", "hub_spill"),
     (r"k_hub_fin<", "hub_fin"),
     (r"k_hub_plan<", "hub_plan"),
     (r"k_frontier_learned", "frontier_learned"),

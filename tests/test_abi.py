@@ -96,3 +96,19 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.lower(), f
+
+
+def test_one_hip_runtime_per_process():
+    """liblpa.so must bind to the HIP runtime torch uses (same soname, two
+    copies on disk): loading it through the binding maps only one."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2411_11468_amd import lpa\n"
+            "lpa.load_library()\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'amdhip64' in l}))"
+            % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
