@@ -70,8 +70,11 @@ def short_name(kernel: str) -> str:
 
 
 def source_hash() -> str:
+    """Hash of the device code (the .hip kernels and the headers they
+    include); host-only .cpp files do not change what a kernel does."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(CSRC, "*"))):
+    files = glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h"))
+    for f in sorted(files):
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
