@@ -327,8 +327,8 @@ lpa_status lpa_predictor_predict(lpa_predictor p, const float* X, int64_t n, flo
  *    periodic guard); the other iterations are plain sweeps that still
  *    predict, and if more than fn_bound of the vertices predicted unchanged
  *    in such a sweep change, skipping is off for the rest of the run;
- *  - the stop test of Algorithm 1 is taken only after an iteration that
- *    skipped no vertex.
+ *  - the stop test of Algorithm 1 is applied to changed + skipped (an upper
+ *    bound on what the plain sweep of the iteration would have changed).
  * Features, in order: log-quantised degree and weighted degree (/ 64), own
  * label share, best-second margin, best-own gain (/ 255 of the total
  * weight), changed in l-1, l-2, l-3, l / cap, Pick-Less in l, iterations

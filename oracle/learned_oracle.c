@@ -54,10 +54,12 @@
  *     plain iteration with l >= 1 and the fallback off the predictions are
  *     still made, and if more than fn_bound of the vertices predicted
  *     unchanged do change, the fallback turns on for the rest of the run.
- *     The run stops after an iteration that left no flagged vertex
- *     unprocessed (every plain iteration, and a skipping one that skipped
- *     nothing), is not Pick-Less and has changed < tolerance * N, or at the
- *     cap.
+ *     The run stops after an iteration that is not Pick-Less and in which
+ *     changed + skipped < tolerance * N, or at the cap.  The skipped
+ *     vertices bound what the plain sweep of the same iteration could have
+ *     changed in addition (every other vertex reads the iteration-start
+ *     labels either way), so the test is Algorithm 1's, applied to an upper
+ *     bound of the plain count; with nothing skipped it is Algorithm 1's.
  *
  * Traces: in every iteration l >= 1, each processed vertex with
  * 1 <= D_i <= max_pred_degree whose sample draw falls below sample_rate
@@ -334,7 +336,7 @@ int oracle_lpa_learned(int64_t n, const int64_t* off, const int32_t* tgt, const 
     }
     *iters_done = l + 1;
     changed_prev = changed;
-    if (skipped == 0 && !pl && (double)changed < tol * (double)n) break;
+    if (!pl && (double)(changed + skipped) < tol * (double)n) break;
   }
   if (tcount) *tcount = nt_out;
   free(Cn); free(F); free(Fn); free(skip); free(pred); free(acc); free(seen); free(touched);

@@ -127,9 +127,9 @@ __global__ void k_iter_end(DevStats* st, DevIterStats* hist, int64_t n) {
   h.fallback = st->fallback;
   int stop = 0;
   if (st->batched) stop = st->graphs_left == 0u;
-  // Algorithm 1's test, taken only after an iteration that left no flagged
-  // vertex unprocessed
-  else stop = st->skipped == 0ull && !st->pl && few;
+  // Algorithm 1's test on changed + skipped: the skipped vertices bound what
+  // a plain sweep of this iteration could have changed in addition
+  else stop = !st->pl && (double)(changed + st->skipped) < st->tol * (double)n;
   st->cand = few ? 1 : 0;
   st->iter = l + 1;
   st->stop = (stop || l + 1 >= st->cap) ? 1 : 0;

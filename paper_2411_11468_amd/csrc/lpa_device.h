@@ -194,8 +194,10 @@ __device__ __forceinline__ void row_of(const void* off, int32_t v, int64_t* o, i
   *d = b - a;
 }
 
+// Targets and weights are read once per sweep: streaming (non-temporal)
+// loads keep them from displacing the gathered labels in the caches.
 __device__ __forceinline__ float edge_weight(const float* w, int64_t e) {
-  return w ? w[e] : 1.0f;
+  return w ? __builtin_nontemporal_load(&w[e]) : 1.0f;
 }
 
 }  // namespace lpa

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     int64_t o = 0, d = 0;
     if (valid) row_of<OffT>(a.off, v, &o, &d);
     const bool has = valid && k < d;
-    const int32_t j = has ? a.tgt[o + k] : -1;
+    const int32_t j = has ? __builtin_nontemporal_load(&a.tgt[o + k]) : -1;
     const float wt = has ? edge_weight(a.w, o + k) : 0.0f;
     const uint32_t lab = (has && j != v) ? (uint32_t)a.C[j] : kEmpty;
     // Per-label sum seen from this lane: its own weight plus every other lane
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
       for (int u = 0; u < U; ++u) {
         const int64_t e = base + u * 64 + lane;
         const bool has = e < d;
-        j[u] = has ? a.tgt[o + e] : v;
+        j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
         wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
       }
 #pragma unroll
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
       for (int u = 0; u < U; ++u) {
         const int64_t e = base + u * BT + tid;
         const bool has = e < d;
-        j[u] = has ? a.tgt[o + e] : v;
+        j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
         wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
       }
 #pragma unroll
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     for (uint32_t b = tid; b < nb; b += BT) hist[b] = 0u;
     const uint32_t p1c = table_p1((uint32_t)n);
     for (int64_t e = tid; e < n; e += BT) {
-      const int32_t j = a.tgt[o + e0 + e];
+      const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e0 + e]);
       if (j != v)
         lds_accumulate(keys, vals, p1c, (uint32_t)a.C[j], edge_weight(a.w, o + e0 + e),
                        a.max_retries);

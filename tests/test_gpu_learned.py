@@ -266,3 +266,14 @@ def test_learned_argument_errors():
     assert e.value.status == 5   # LPA_ERR_UNSUPPORTED
     B.close()
     pr.close()
+
+
+def test_stop_after_a_skip_iteration_matches_oracle():
+    K, L = 30, 20
+    edges = [(c, K + c * L + i) for c in range(K) for i in range(L)]
+    g = graphgen.from_edges(K + K * L, edges)
+    ref, G, pr, res = _learned_pair(g, None, P_ALWAYS, fn_bound=1.0)
+    assert ref.iterations == 2 and ref.stats[1]["skipping"] == 1
+    _assert_same(ref, G, res)
+    G.close()
+    pr.close()

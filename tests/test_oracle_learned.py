@@ -62,19 +62,31 @@ def test_plain_schedule_is_the_plain_run(name, g, rho, prune):
 
 
 @pytest.mark.parametrize("name,g", _graphs()[:2], ids=[n for n, _ in _graphs()[:2]])
-def test_always_unchanged_without_fallback(name, g):
-    want = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0)
+@pytest.mark.parametrize("tol", [0.05, 0.3])
+def test_always_unchanged_without_fallback(name, g, tol):
+    want = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0, tolerance=tol)
     assert want.iterations < 20
     got = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=_const_params(-50.0),
-                             pl_period=0, guard=4, fn_bound=1.0, max_iterations=40)
-    assert np.array_equal(got.labels, want.labels)
-    assert got.iterations == 2 * want.iterations - 1
+                             pl_period=0, guard=4, fn_bound=1.0, max_iterations=40,
+                             tolerance=tol)
     plain = [s for s in got.stats if not s["skipping"]]
     skips = [s for s in got.stats if s["skipping"]]
-    assert len(plain) == want.iterations
     for a, b in zip(plain, want.stats):
         for k in ("changed", "processed", "edges_scanned"):
             assert a[k] == b[k]
+    k = len(plain)
+    if got.stats[-1]["skipping"]:
+        # stopped on a skip iteration: its skipped vertices (the plain run's
+        # next frontier) were fewer than tolerance * N, so the plain run's
+        # next iteration is its last; the labels are those before it
+        assert got.stats[-1]["skipped"] < tol * g.num_vertices
+        assert k == want.iterations - 1 and got.iterations == 2 * k
+        before = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0,
+                                 max_iterations=k, tolerance=tol)
+        assert np.array_equal(got.labels, before.labels)
+    else:
+        assert k == want.iterations and got.iterations == 2 * k - 1
+        assert np.array_equal(got.labels, want.labels)
     for s in skips:
         # every flagged vertex with a neighbour is skipped and nothing moves
         assert s["changed"] == 0 and s["processed"] == 0
@@ -255,3 +267,22 @@ def test_trace_with_full_sampling():
                      for l, v in zip(tr["l"], tr["v"])])
     np.testing.assert_array_equal(h.trace["v"], tr["v"][keep])
     np.testing.assert_array_equal(h.trace["y"], tr["y"][keep])
+
+
+def test_stop_after_a_skip_iteration():
+    # 30 stars, centre ids 0..29 (the smallest), 20 leaves each: the Pick-Less
+    # iteration 0 moves every leaf to its centre's label and flags only the
+    # 30 centres; the next iteration skips them all (30 < 0.05 N) and the
+    # bound changed + skipped < tolerance N ends the run there -- the plain
+    # run ends at the same iteration, its centres keeping their labels
+    K, L = 30, 20
+    edges = [(c, K + c * L + i) for c in range(K) for i in range(L)]
+    g = graphgen.from_edges(K + K * L, edges)
+    want = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+    got = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=_const_params(-50.0),
+                             fn_bound=1.0)
+    assert want.iterations == 2 and want.stats[1]["changed"] == 0
+    assert got.iterations == 2
+    s = got.stats[1]
+    assert (s["skipping"], s["skipped"], s["processed"], s["changed"]) == (1, K, 0, 0)
+    assert np.array_equal(got.labels, want.labels)
