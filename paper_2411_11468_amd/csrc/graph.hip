@@ -533,6 +533,7 @@ __device__ __forceinline__ double sample_draw(unsigned long long seed, int l, in
 }  // namespace
 
 constexpr int kLearnWaves = 4;
+constexpr int kLearnChunks = 4;  // 64-vertex chunks per wave and block step
 
 __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
     int64_t n, uint8_t* F, const uint8_t* cls, ListPtrs lists, uint8_t* chg_clear,
@@ -540,9 +541,12 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   __shared__ uint8_t lst_all[kLearnWaves][64];
   __shared__ uint8_t dec_all[kLearnWaves][64];
   __shared__ unsigned long long slot_all[kLearnWaves][16];
+  __shared__ uint32_t cnt[kNumClasses];
+  __shared__ uint32_t cbase[kNumClasses];
   if (st->stop) return;
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6;
+  const int lane = tid & 63;
   const int g = lane >> 4;
   uint8_t* lst = lst_all[wv];
   uint8_t* dec = dec_all[wv];
@@ -558,78 +562,94 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   MlpLane W;
   if (predict) mlp_load(*tiles, W);
   uint32_t proc = 0, skipped = 0, npred = 0;
-  const int64_t wave = (int64_t)blockIdx.x * kLearnWaves + wv;
-  const int64_t nwaves = (int64_t)gridDim.x * kLearnWaves;
-  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-    const int64_t v = base + lane;
-    const bool valid = v < n;
-    uint8_t f = 0, c = 0;
-    if (valid) {
-      chg_clear[v] = 0;
-      f = F[v];
-      c = cls[v];
-    }
-    const bool cand = f && c >= 1 && c < kClassHub && (predict || tracing);
-    const unsigned long long cm = __ballot(cand);
-    const uint32_t cnt = __popcll(cm);
-    if (cand) lst[lane_rank(cm)] = (uint8_t)lane;
-    dec[lane] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    for (uint32_t r0 = 0; r0 < cnt; r0 += 16) {  // uniform trip count
-      const uint32_t si = r0 + (uint32_t)(lane & 15);
-      const bool has = si < cnt;
-      const int src = has ? lst[si] : 0;
-      const int64_t u = base + src;
-      const unsigned long long rr = has ? rec[u] : kRecordInit;
-      float x[4];
-      rec_features(rr, l, cap, rho, g, x);
-      bool pred = false;
-      if (predict) {
-        const float z = mlp_logit16(W, x);
-        pred = has && z < z_theta;
-      }
-      const bool skip = pred && skipping;
-      if (lane < 16 && has) dec[src] = (uint8_t)((pred ? 1 : 0) | (skip ? 2 : 0));
-      if (tracing) {
-        const bool take = has && !skip && sample_draw(seed, l, u) < rate;
-        if (lane < 16) slot[lane] = take ? atomicAdd(&st->trace_n, 1ull) : ~0ull;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const unsigned long long q = slot[lane & 15];
-        if (take && q < tcap && g < 3) {
+  constexpr int64_t kStep = (int64_t)kLearnWaves * kLearnChunks * 64;
+  // the whole workgroup walks the same steps of kStep vertices (barriers
+  // inside); the listed vertices of a step are appended with one atomic per
+  // class and workgroup, as in the plain frontier
+  for (int64_t step0 = (int64_t)blockIdx.x * kStep; step0 < n;
+       step0 += (int64_t)gridDim.x * kStep) {
+    if (tid < kNumClasses) cnt[tid] = 0;
+    __syncthreads();
+    int8_t cq[kLearnChunks];
+    uint32_t pos[kLearnChunks];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) tr.X[q * kMlpIn + 4 * g + j] = x[j];
-          if (g == 0) {
-            tr.v[q] = (int32_t)u;
-            tr.l[q] = l;
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int q = 0; q < kLearnChunks; ++q) {
+      const int64_t base = step0 + ((int64_t)wv * kLearnChunks + q) * 64;
+      const int64_t v = base + lane;
+      const bool valid = v < n;
+      uint8_t f = 0, c = 0;
+      if (valid) {
+        chg_clear[v] = 0;
+        f = F[v];
+        c = cls[v];
       }
+      const bool cand = f && c >= 1 && c < kClassHub && (predict || tracing);
+      const unsigned long long cm = __ballot(cand);
+      const uint32_t ncand = __popcll(cm);
+      if (cand) lst[lane_rank(cm)] = (uint8_t)lane;
+      dec[lane] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      for (uint32_t r0 = 0; r0 < ncand; r0 += 16) {  // uniform trip count
+        const uint32_t si = r0 + (uint32_t)(lane & 15);
+        const bool has = si < ncand;
+        const int src = has ? lst[si] : 0;
+        const int64_t u = base + src;
+        const unsigned long long rr = has ? rec[u] : kRecordInit;
+        float x[4];
+        rec_features(rr, l, cap, rho, g, x);
+        bool pred = false;
+        if (predict) {
+          const float z = mlp_logit16(W, x);
+          pred = has && z < z_theta;
+        }
+        const bool skip = pred && skipping;
+        if (lane < 16 && has) dec[src] = (uint8_t)((pred ? 1 : 0) | (skip ? 2 : 0));
+        if (tracing) {
+          const bool take = has && !skip && sample_draw(seed, l, u) < rate;
+          if (lane < 16) slot[lane] = take ? atomicAdd(&st->trace_n, 1ull) : ~0ull;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          const unsigned long long qq = slot[lane & 15];
+          if (take && qq < tcap && g < 3) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tr.X[qq * kMlpIn + 4 * g + j] = x[j];
+            if (g == 0) {
+              tr.v[qq] = (int32_t)u;
+              tr.l[qq] = l;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const uint8_t dd = dec[lane];
+      const bool skip = (dd & 2) != 0;
+      const bool keep = f && !skip;
+      if (dd & 1) {
+        ++npred;
+        // plain iteration: mark for the false-negative count of the sweep
+        if (!skip) rec[v] |= 0x80ull << 48;
+      }
+      if (skip) ++skipped;
+      cq[q] = -1;
+      if (keep) {
+        F[v] = 0;
+        ++proc;
+        if (c >= 1 && c < kClassHub) {
+          cq[q] = (int8_t)c;
+          pos[q] = atomicAdd(&cnt[c], 1u);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const uint8_t dd = dec[lane];
-    const bool skip = (dd & 2) != 0;
-    const bool keep = f && !skip;
-    if (dd & 1) {
-      ++npred;
-      // plain iteration: mark for the false-negative count of the sweep
-      if (!skip) rec[v] |= 0x80ull << 48;
-    }
-    if (skip) ++skipped;
-    if (keep) {
-      F[v] = 0;
-      ++proc;
-    }
-    // append the listed vertices of classes 1..8, one atomic per class and wave
-    for (int q = 1; q < kClassHub; ++q) {
-      const unsigned long long m = __ballot(keep && c == q);
-      if (!m) continue;
-      uint32_t b = 0;
-      if (lane == 0) b = atomicAdd(&st->active[q], (uint32_t)__popcll(m));
-      b = (uint32_t)__shfl(b, 0);
-      if (keep && c == q) lists.p[q][b + lane_rank(m)] = (int32_t)v;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __syncthreads();
+    if (tid < kNumClasses) cbase[tid] = cnt[tid] ? atomicAdd(&st->active[tid], cnt[tid]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kLearnChunks; ++q)
+      if (cq[q] >= 0)
+        lists.p[cq[q]][cbase[cq[q]] + pos[q]] =
+            (int32_t)(step0 + ((int64_t)wv * kLearnChunks + q) * 64 + lane);
+    __syncthreads();
   }
   const uint32_t tp = wave_sum_u32(proc), ts = wave_sum_u32(skipped), tn = wave_sum_u32(npred);
   if (lane == 0) {
