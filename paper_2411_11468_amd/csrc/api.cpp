@@ -128,7 +128,9 @@ struct lpa_graph_s {
   void account(int kid, float ms, const DevStats& h, bool async_mode, bool pull) {
     if (kid < 0 || kid >= kNumKids) return;
     lpa_kernel_profile& p = prof[kid];
-    const double eb = 8.0 + (w ? 4.0 : 0.0);
+    // first iteration from labels = ids: the neighbour labels are not gathered
+    const bool id0 = h.ident && h.iter == 1;
+    const double eb = (id0 ? 4.0 : 8.0) + (w ? 4.0 : 0.0);
     const double ob = off64 ? 16.0 : 8.0;
     const double chb = async_mode ? 4.0 : 8.0;
     double bytes = 0.0;

@@ -34,6 +34,7 @@ int grid_for(int64_t n, int per_block, int cap) {
 // ---- init ---------------------------------------------------------------------
 __global__ void k_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
                        DevStats* st) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->ident = init ? 0 : 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t c = init ? init[i] : (int32_t)i;

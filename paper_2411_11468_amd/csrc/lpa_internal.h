@@ -37,6 +37,7 @@ struct DevStats {
   int cap;                                      // iteration cap
   int rho;                                      // Pick-Less period (0: off)
   int iter;                                     // index of the iteration being run
+  int ident;                                    // the run started from labels = vertex ids
   int stop;                                     // 1: run ended, kernels return at once
   int pl;                                       // Pick-Less in this iteration
   int batched;                                  // per-graph stop rule

@@ -13,7 +13,11 @@
 //      (Sec. 4 item 4) after the sweep, by the flag kernels of graph.hip.
 // In asynchronous mode the new label is stored in place; in deterministic
 // mode it is queued and applied after the sweep, so every vertex reads the
-// iteration-start labels.  Flags are cleared only by the frontier kernel
+// iteration-start labels.  In the first iteration of a run that starts from
+// labels = vertex ids (Algorithm 1's initialisation) a neighbour's label is
+// its id and is not gathered: the deterministic result is unchanged, and in
+// asynchronous mode this is the read of the iteration-start value, which an
+// asynchronous sweep is free to make.  Flags are cleared only by the frontier kernel
 // before the sweep and set only after it, so a neighbour that read an old
 // label is always flagged for the next iteration and no fence is needed
 // between a label store and anything else.  (An agent-scope fence would
@@ -149,6 +153,7 @@ __device__ __forceinline__ void flush_fneg(uint32_t fneg, DevStats* st) {
 template <typename OffT, int G, bool FEAT>
 __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   if (a.st->stop) return;
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int lane = threadIdx.x & 63;
   const int k = lane & (G - 1);
   const uint32_t count = a.st->active[a.cls];
@@ -168,7 +173,8 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     const bool has = valid && k < d;
     const int32_t j = has ? __builtin_nontemporal_load(&a.tgt[o + k]) : -1;
     const float wt = has ? edge_weight(a.w, o + k) : 0.0f;
-    const uint32_t lab = (has && j != v) ? (uint32_t)a.C[j] : kEmpty;
+    uint32_t lab = kEmpty;
+    if (has && j != v) lab = id0 ? (uint32_t)j : (uint32_t)a.C[j];
     // Per-label sum seen from this lane: its own weight plus every other lane
     // of the group holding the same label.  FEAT: dup = a lane of lower index
     // holds the same label.
@@ -247,6 +253,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   __shared__ uint32_t keys_all[WAVES][SLOTS];
   __shared__ float vals_all[WAVES][SLOTS];
   if (a.st->stop) return;
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int l = a.st->iter;
@@ -276,7 +283,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
         wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) lab[u] = (j[u] != v) ? (uint32_t)a.C[j[u]] : kEmpty;
+      for (int u = 0; u < U; ++u)
+        lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
@@ -339,6 +347,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
   __shared__ uint32_t redc[FEAT ? NW : 1];
   __shared__ float redk[FEAT ? NW : 1];
   if (a.st->stop) return;
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int l = a.st->iter;
@@ -368,7 +377,8 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
         wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) lab[u] = (j[u] != v) ? (uint32_t)a.C[j[u]] : kEmpty;
+      for (int u = 0; u < U; ++u)
+        lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
@@ -543,6 +553,7 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   __shared__ uint32_t hist[kMaxB];
   __shared__ uint32_t wsum[BT / 64];
   if (a.st->stop) return;
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int tid = threadIdx.x;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __syncthreads();
@@ -563,7 +574,8 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     for (int64_t e = tid; e < n; e += BT) {
       const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e0 + e]);
       if (j != v)
-        lds_accumulate(keys, vals, p1c, (uint32_t)a.C[j], edge_weight(a.w, o + e0 + e),
+        lds_accumulate(keys, vals, p1c, id0 ? (uint32_t)j : (uint32_t)a.C[j],
+                       edge_weight(a.w, o + e0 + e),
                        a.max_retries);
     }
     __syncthreads();
