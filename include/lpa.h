@@ -145,7 +145,7 @@ typedef struct lpa_tuning {
  *                   LPA_FLAGS_PULL  every vertex reads its neighbours' change
  *                                   marks up to the first changed one;
  *                   LPA_FLAGS_AUTO  pull when the changed vertices' rows hold
- *                                   at least half of the CSR entries, push
+ *                                   at least 1/16 of the CSR entries, push
  *                                   otherwise, decided on the GPU per
  *                                   iteration (default)
  *   learned         1: skip the vertices that the predictor attached with
@@ -323,8 +323,8 @@ lpa_status lpa_predictor_predict(lpa_predictor p, const float* X, int64_t n, flo
  *    in a skipping iteration a vertex whose probability of change is below
  *    threshold is not processed and keeps its flag;
  *  - iteration l skips unless l % guard_period == 0 or the previous
- *    iteration changed fewer than tolerance * N labels (guard_period 0: no
- *    periodic guard); the other iterations are plain sweeps that still
+ *    iteration changed fewer than 2 * tolerance * N labels (guard_period 0:
+ *    no periodic guard); the other iterations are plain sweeps that still
  *    predict, and if more than fn_bound of the vertices predicted unchanged
  *    in such a sweep change, skipping is off for the rest of the run;
  *  - the stop test of Algorithm 1 is applied to changed + skipped (an upper

@@ -47,8 +47,9 @@
  *
  *  3. The schedule.  Iteration l "skips" when a predictor is given, l >= 1,
  *     l is not a multiple of the guard period (0: no periodic guard), the
- *     previous iteration changed at least tolerance * N labels, and the
- *     fallback is off.  In a skipping iteration a flagged vertex with
+ *     previous iteration changed at least 2 * tolerance * N labels (below
+ *     that the run is near its stop and the plain sweep is taken, so that
+ *     the stop comes where the plain run's would), and the fallback is off.  In a skipping iteration a flagged vertex with
  *     1 <= D_i <= max_pred_degree that is predicted unchanged is not
  *     processed and stays flagged.  Every other iteration is plain; in a
  *     plain iteration with l >= 1 and the fallback off the predictions are
@@ -228,7 +229,7 @@ int oracle_lpa_learned(int64_t n, const int64_t* off, const int32_t* tgt, const 
     const int pl = (rho > 0) && (l % rho == 0);
     const int predict = params && !fallback && l >= 1;
     const int skipping = predict && (guard == 0 || l % guard != 0) &&
-                         !((double)changed_prev < tol * (double)n);
+                         !((double)changed_prev < 2.0 * tol * (double)n);
     int64_t changed = 0, processed = 0, scanned = 0, skipped = 0, npred = 0, fneg = 0;
     /* predictions at the iteration start (the frontier) */
     for (int64_t i = 0; i < n; ++i) {

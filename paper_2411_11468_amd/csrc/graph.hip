@@ -109,7 +109,6 @@ __global__ void k_iter_end(DevStats* st, DevIterStats* hist, int64_t n) {
     edges += st->edges[c];
   }
   const int l = st->iter;
-  const bool few = (double)changed < st->tol * (double)n;
   // learned skipping: a plain iteration with predictions checks the vertices
   // predicted unchanged; too many of them changing turns skipping off
   if (st->predict && !st->skipping && st->npred > 0 &&
@@ -131,7 +130,8 @@ __global__ void k_iter_end(DevStats* st, DevIterStats* hist, int64_t n) {
   // Algorithm 1's test on changed + skipped: the skipped vertices bound what
   // a plain sweep of this iteration could have changed in addition
   else stop = !st->pl && (double)(changed + st->skipped) < st->tol * (double)n;
-  st->cand = few ? 1 : 0;
+  // near the stop (changed < 2 tol N) the next iteration is a plain sweep
+  st->cand = (double)changed < 2.0 * st->tol * (double)n ? 1 : 0;
   st->iter = l + 1;
   st->stop = (stop || l + 1 >= st->cap) ? 1 : 0;
 }
@@ -694,16 +694,18 @@ hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const Trac
 //   push: each changed vertex writes the flag byte of each neighbour;
 //   pull: each vertex reads the change bytes of its neighbours and stops at
 //         the first changed one.
-// Push costs one scattered byte store per entry of a changed row; pull costs
-// a read per entry up to the first changed neighbour.  k_flag_decide picks
-// pull when the changed rows hold at least half of the CSR entries (then most
-// vertices find a changed neighbour within a few entries), push otherwise;
-// the kernels of the other way return at once.
+// Push costs one scattered byte store (a line's read-modify-write) per entry
+// of a changed row; pull costs a read per entry up to the first changed
+// neighbour, about 1/p entries per vertex when the changed rows hold a share
+// p of the entries.  On R-MAT scale 26 the two cost the same near p = 1/16
+// (push of a quarter of the entries: 18.6 ms; pull at p near 1/2: 2.7 ms), so
+// k_flag_decide picks pull when the changed rows hold at least 1/16 of the CSR
+// entries, push otherwise; the kernels of the other way return at once.
 __global__ void k_flag_decide(DevStats* st, int64_t m, int force) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop) return;
   unsigned long long fw = 0;
   for (int c = 0; c < kNumClasses; ++c) fw += st->flagw[c];
-  st->pull_mode = force == 2 ? 1u : force == 1 ? 0u : (2ull * fw >= (unsigned long long)m ? 1u : 0u);
+  st->pull_mode = force == 2 ? 1u : force == 1 ? 0u : (16ull * fw >= (unsigned long long)m ? 1u : 0u);
 }
 
 hipError_t launch_flag_decide(DevStats* st, int64_t m, int force, hipStream_t s) {

@@ -76,27 +76,23 @@ __device__ __forceinline__ bool decide(unsigned long long best, int32_t cur, int
 
 // One rotation step of the per-label sums inside a 16-lane row (R) or a quad
 // (quad_perm Q): add the other lane's weight if it holds the same label.
-// FEAT: also note whether that lane, of lower index in the group, does.
+// FEAT: also count the lanes holding the lane's label (its multiplicity).
 template <int R, bool FEAT>
-__device__ __forceinline__ void rot16_accum(uint32_t lab, float wt, int k, float& sum,
-                                            bool& dup) {
+__device__ __forceinline__ void rot16_accum(uint32_t lab, float wt, float& sum, float& mult) {
   const uint32_t ol = dpp32<0x120 + R, 0xF, 0xF, false>(lab);
   const float ow = __uint_as_float(dpp32<0x120 + R, 0xF, 0xF, false>(__float_as_uint(wt)));
-  if (ol == lab) sum += ow;
-  if constexpr (FEAT) {
-    const int ok = (int)dpp32<0x120 + R, 0xF, 0xF, false>((uint32_t)k);
-    if (ol == lab && ok < k) dup = true;
+  if (ol == lab) {
+    sum += ow;
+    if constexpr (FEAT) mult += 1.0f;
   }
 }
 template <int Q, bool FEAT>
-__device__ __forceinline__ void rot4_accum(uint32_t lab, float wt, int k, float& sum,
-                                           bool& dup) {
+__device__ __forceinline__ void rot4_accum(uint32_t lab, float wt, float& sum, float& mult) {
   const uint32_t ol = dpp32<Q, 0xF, 0xF, false>(lab);
   const float ow = __uint_as_float(dpp32<Q, 0xF, 0xF, false>(__float_as_uint(wt)));
-  if (ol == lab) sum += ow;
-  if constexpr (FEAT) {
-    const int ok = (int)dpp32<Q, 0xF, 0xF, false>((uint32_t)k);
-    if (ol == lab && ok < k) dup = true;
+  if (ol == lab) {
+    sum += ow;
+    if constexpr (FEAT) mult += 1.0f;
   }
 }
 
@@ -176,23 +172,21 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     uint32_t lab = kEmpty;
     if (has && j != v) lab = id0 ? (uint32_t)j : (uint32_t)a.C[j];
     // Per-label sum seen from this lane: its own weight plus every other lane
-    // of the group holding the same label.  FEAT: dup = a lane of lower index
-    // holds the same label.
-    float sum = wt;
-    bool dup = false;
+    // of the group holding the same label.  FEAT: mult = lanes holding it.
+    float sum = wt, mult = 1.0f;
     if constexpr (G == 16) {
-      rot16_accum<1, FEAT>(lab, wt, k, sum, dup);  rot16_accum<2, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<3, FEAT>(lab, wt, k, sum, dup);  rot16_accum<4, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<5, FEAT>(lab, wt, k, sum, dup);  rot16_accum<6, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<7, FEAT>(lab, wt, k, sum, dup);  rot16_accum<8, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<9, FEAT>(lab, wt, k, sum, dup);  rot16_accum<10, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<11, FEAT>(lab, wt, k, sum, dup); rot16_accum<12, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<13, FEAT>(lab, wt, k, sum, dup); rot16_accum<14, FEAT>(lab, wt, k, sum, dup);
-      rot16_accum<15, FEAT>(lab, wt, k, sum, dup);
+      rot16_accum<1, FEAT>(lab, wt, sum, mult);  rot16_accum<2, FEAT>(lab, wt, sum, mult);
+      rot16_accum<3, FEAT>(lab, wt, sum, mult);  rot16_accum<4, FEAT>(lab, wt, sum, mult);
+      rot16_accum<5, FEAT>(lab, wt, sum, mult);  rot16_accum<6, FEAT>(lab, wt, sum, mult);
+      rot16_accum<7, FEAT>(lab, wt, sum, mult);  rot16_accum<8, FEAT>(lab, wt, sum, mult);
+      rot16_accum<9, FEAT>(lab, wt, sum, mult);  rot16_accum<10, FEAT>(lab, wt, sum, mult);
+      rot16_accum<11, FEAT>(lab, wt, sum, mult); rot16_accum<12, FEAT>(lab, wt, sum, mult);
+      rot16_accum<13, FEAT>(lab, wt, sum, mult); rot16_accum<14, FEAT>(lab, wt, sum, mult);
+      rot16_accum<15, FEAT>(lab, wt, sum, mult);
     } else {
-      rot4_accum<0x39, FEAT>(lab, wt, k, sum, dup);  // quad_perm [1,2,3,0]
-      rot4_accum<0x4E, FEAT>(lab, wt, k, sum, dup);  // quad_perm [2,3,0,1]
-      rot4_accum<0x93, FEAT>(lab, wt, k, sum, dup);  // quad_perm [3,0,1,2]
+      rot4_accum<0x39, FEAT>(lab, wt, sum, mult);  // quad_perm [1,2,3,0]
+      rot4_accum<0x4E, FEAT>(lab, wt, sum, mult);  // quad_perm [2,3,0,1]
+      rot4_accum<0x93, FEAT>(lab, wt, sum, mult);  // quad_perm [3,0,1,2]
     }
     const unsigned long long packed = (lab != kEmpty) ? pack_key(sum, lab) : 0ull;
     const unsigned long long best = group_max<G>(packed);
@@ -210,7 +204,10 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
       const unsigned long long sk = (lab != kEmpty && lab != bl) ? pack_key(sum, lab) : 0ull;
       const float second = __uint_as_float((uint32_t)(group_max<G>(sk) >> 32));
       const float bw = __uint_as_float((uint32_t)(best >> 32));
-      const uint32_t distinct = group_sum_u32<G>((lab != kEmpty && !dup) ? 1u : 0u);
+      // each label's lanes contribute 1/mult each: the group sum is the
+      // number of distinct labels up to rounding (at most 16 terms)
+      const uint32_t distinct =
+          (uint32_t)rintf(group_sum_f32<G>(lab != kEmpty ? 1.0f / mult : 0.0f));
       if (leader && d >= 1)
         my_fneg += rec_write(a.rec, v, l, K, own, bw, second, distinct, (uint32_t)d, moved);
     }
