@@ -293,6 +293,7 @@ def main() -> int:
     log(f"dominant kernel {dom['name']}: {achieved:.0f} GB/s algorithmic; kernels {kernels}")
 
     traffic, traffic_note = None, "no counter summary for these kernel sources"
+    tj = None
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}-{mode}.json")
     if os.path.exists(tpath):
         from paper_2411_11468_amd import profiling
@@ -304,6 +305,17 @@ def main() -> int:
                             f"{tj['copy_bytes'] / 2**30:.0f} GiB copy ({os.path.basename(tpath)})")
         else:
             traffic_note = "kernel sources changed since the counters were taken"
+            tj = None
+    # the whole label scan (class sweeps and hub kernels): algorithmic bytes
+    # and, when the counters match these sources, measured HBM bytes per second
+    scan = [p for p in prof if p["name"].startswith(("sweep", "hub_part", "hub_reduce"))]
+    scan_ms = sum(p["total_ms"] for p in scan)
+    scan_total = {"kernels": len(scan), "ms": scan_ms,
+                  "alg_GBps": sum(p["bytes"] for p in scan) / (scan_ms * 1e-3) / 1e9}
+    if tj is not None and all(p["name"] in tj["kernels"] for p in scan):
+        tb = sum(tj["kernels"][p["name"]]["bytes_per_dispatch"] * p["launches"] for p in scan)
+        scan_total["traffic_GBps"] = tb / (scan_ms * 1e-3) / 1e9
+        scan_total["traffic_frac"] = scan_total["traffic_GBps"] / HBM_PEAK_GBPS
 
     if args.calibrate_copy:
         src = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
@@ -343,7 +355,10 @@ def main() -> int:
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
                      "avg_launch_us": 1e3 * dom["total_ms"] / dom["launches"],
+                     "traffic_GBps": (None if traffic is None else
+                                      traffic / (dom["total_ms"] / dom["launches"] * 1e-3) / 1e9),
                      "traffic_note": traffic_note},
+        "scan_total": scan_total,
         "cpu_baseline": cpu,
         "iterations": iters,
         "time_to_termination_ms": float(np.median([1e3 * wall / args.steps])),
