@@ -102,14 +102,20 @@ typedef struct lpa_graph_s* lpa_graph;
  *                                                              at most 512)
  *   block    one workgroup per vertex, LDS hashtable up to 16383 slots
  *                                                 (default 8192, at most 8192)
- *   larger degrees: several workgroups per vertex, each with an LDS table for
- *   its slice of the row, merged in a global-memory hashtable.
+ *   larger degrees ("hubs"): the row is cut into slices, each reduced in an
+ *   LDS table by one workgroup; the slices' distinct (label, sum) pairs are
+ *   regrouped by a hash bucket of the label and each bucket is summed in an
+ *   LDS table by one workgroup; a bucket whose labels overflow its table
+ *   spills them into a global-memory hashtable of the hub.
  * Every hashtable holding D keys has 2^m - 1 >= 2D - 1 slots (load <= 1/2).
  * hub_chunk: edges per workgroup slice for the largest rows (default 8192).
  * max_retries: hybrid probes before the linear continuation (default 32).
- * xcd_local: 1 = merge each hub's slices on one XCD with its table atomics
- *   in that XCD's L2, any slice left over merged afterwards with device-wide
- *   atomics; 0 = device-wide atomics only (default 1; same results).
+ * xcd_local: 1 = the buckets of consecutive indices run on one XCD (their
+ *   pair runs share cache lines); 0 = plain round-robin (default 1; same
+ *   results).
+ * hub_table_cap: 0 (default) = bucket tables of up to 16383 slots; else at
+ *   most this many slots (rounded down to 2^m - 1), to exercise the spill
+ *   path in tests.
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -119,7 +125,7 @@ typedef struct lpa_tuning {
   int32_t hub_chunk;
   int32_t max_retries;
   int32_t xcd_local;
-  int32_t reserved;
+  int32_t hub_table_cap;
 } lpa_tuning;
 
 /*

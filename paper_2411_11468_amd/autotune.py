@@ -15,7 +15,8 @@ import numpy as np
 
 from . import lpa
 
-TUNING_FIELDS = ("small4", "small16", "wave", "block", "hub_chunk", "max_retries", "xcd_local")
+TUNING_FIELDS = ("small4", "small16", "wave", "block", "hub_chunk", "max_retries", "xcd_local",
+                 "hub_table_cap")
 
 
 def _round2(x: int) -> int:

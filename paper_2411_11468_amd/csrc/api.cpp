@@ -253,6 +253,12 @@ struct lpa_graph_s {
     a.H = H; a.chunk = tun.hub_chunk; a.async_mode = async_mode;
     a.max_retries = tun.max_retries;
     a.xcd_map = tun.xcd_local;
+    uint32_t cap = 16383u;
+    if (tun.hub_table_cap > 0) {
+      cap = 1u;
+      while (2u * cap + 1u <= (uint32_t)std::min(tun.hub_table_cap, 16383)) cap = 2u * cap + 1u;
+    }
+    a.table_cap = cap;
     return a;
   }
 
@@ -328,7 +334,8 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   const lpa_tuning& t = G->tun;
   if (!(0 <= t.small4 && t.small4 <= 4 && t.small4 <= t.small16 && t.small16 <= 16 &&
         t.small16 <= t.wave && t.wave <= 512 && t.wave <= t.block && t.block <= 8192 &&
-        t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0))
+        t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0 &&
+        t.hub_table_cap >= 0))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   hipStream_t s = G->stream;
   const int64_t n = G->n, m = G->m;

@@ -148,6 +148,7 @@ struct HubArgs {
   int async_mode;
   int max_retries;
   int xcd_map;                     // 1: consecutive buckets on one XCD
+  uint32_t table_cap;              // largest bucket table (2^m - 1 slots)
 };
 
 // Statistics of one iteration as recorded on the device (same layout as the

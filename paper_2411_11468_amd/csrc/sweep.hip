@@ -646,7 +646,8 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
     uint32_t E = 0;
     for (int q = 0; q < BT / 64; ++q) E += wsum[q];
     __syncthreads();
-    const uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
+    uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
+    if (p1 > a.table_cap) p1 = a.table_cap;
     const int64_t slice0 = a.hub_slice0[h];
     uint32_t* gk = a.gkeys + a.hub_tab[h];
     float* gv = a.gvals + a.hub_tab[h];

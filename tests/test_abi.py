@@ -56,8 +56,8 @@ def test_defaults(lib):
     assert (o.mode, o.max_iterations, o.tolerance, o.pl_period, o.prune) == \
         (lpa.MODE_ASYNC, 20, 0.05, 4, 1)
     t = lpa.default_tuning()
-    assert (t.small4, t.small16, t.wave, t.block, t.hub_chunk, t.max_retries, t.xcd_local) == \
-        (4, 16, 512, 8192, 8192, 32, 1)
+    assert (t.small4, t.small16, t.wave, t.block, t.hub_chunk, t.max_retries, t.xcd_local,
+            t.hub_table_cap) == (4, 16, 512, 8192, 8192, 32, 1, 0)
 
 
 def test_status_strings(lib):

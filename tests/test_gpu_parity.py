@@ -125,6 +125,17 @@ def test_det_hub_merge_paths(xcd_local):
     assert_det_parity(graphgen.rmat_graph(16, 16, "int8"), tuning=t2)
 
 
+@pytest.mark.parametrize("cap", [1, 7, 63])
+def test_det_hub_spill_path(cap):
+    # bucket tables capped far below the labels of a bucket: most labels
+    # spill into the hubs' global tables, which must give the same result
+    t = _tuning(**SMALL_TUNING, hub_table_cap=cap)
+    assert_det_parity(graphgen.random_graph(1500, 0.25, seed=5, wmax=8), tuning=t)
+    assert_det_parity(graphgen.rmat_graph(13, 8, "int8"), tuning=t)
+    t2 = _tuning(block=1024, hub_chunk=256, hub_table_cap=cap, xcd_local=0)
+    assert_det_parity(graphgen.rmat_graph(16, 16, "int8"), tuning=t2)
+
+
 def test_det_rmat_default_tuning():
     g = graphgen.rmat_graph(15, 15, "int8")
     G = _graph_on_gpu(g)
