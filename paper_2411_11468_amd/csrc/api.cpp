@@ -61,6 +61,7 @@ struct lpa_graph_s {
   hipStream_t stream = nullptr;
   int64_t n = 0, m = 0;
   bool off64 = false;
+  bool strict_rows = false;   // every row's targets strictly increase
   const void* off = nullptr;
   const int32_t* tgt = nullptr;
   const float* w = nullptr;
@@ -71,8 +72,9 @@ struct lpa_graph_s {
   int32_t* lists[kNumClasses] = {};
   int64_t cls_count[kNumClasses] = {};
   int grid[kNumClasses] = {};
+  int direct_grid[kNumClasses] = {};  // table-free first sweep
   int frontier_grid = 1, apply_grid = 1, hub_acc_grid = 1, hub_fin_grid = 1, pull_grid = 1,
-      push_grid = 1;
+      push_grid = 1, hub_direct_grid = 1;
   int32_t* pend_v = nullptr;
   int32_t* pend_c = nullptr;
   int32_t* Cn = nullptr;
@@ -139,7 +141,9 @@ struct lpa_graph_s {
       const int c = kid - kKidSweep0;
       edges = (int64_t)h.edges[c];
       verts = (int64_t)h.active[c];
-      bytes = eb * edges + (4.0 + ob + 4.0) * verts + (double)h.changed[c] +
+      // the table-free first sweep knows each vertex's own label (its id)
+      const double own = (id0 && strict_rows && !acct_feat) ? 0.0 : 4.0;
+      bytes = eb * edges + (4.0 + ob + own) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
       if (acct_feat) bytes += 16.0 * verts;  // state record read and written
     } else if (kid == kKidHubPart) {
@@ -396,6 +400,28 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
       return fail(LPA_ERR_INVALID, "malformed CSR:" + why);
     }
   }
+  // rows with strictly increasing targets: in the first sweep from identity
+  // labels every neighbour then carries its own label once, so the row's
+  // Eq. 3 maximum is the largest (weight, smallest id) entry -- no table
+  if (m > 1) {
+    uint8_t* mark = nullptr;
+    unsigned int* bad = nullptr;
+    if (hipMalloc(&mark, (size_t)m) != hipSuccess || hipMalloc(&bad, sizeof(unsigned)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (mark) (void)hipFree(mark);
+      return fail(LPA_ERR_OOM, "hipMalloc failed for the row check");
+    }
+    unsigned int hb = 1u;
+    hipError_t e = launch_rows_strict(G->off64, G->off, G->tgt, n, m, mark, bad, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(mark);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(LPA_ERR_HIP, std::string("row check: ") + hipGetErrorString(e));
+    G->strict_rows = hb == 0u;
+  } else {
+    G->strict_rows = true;
+  }
 
   // labels, flags, deterministic-mode queue
   if (lpa_status e = G->dalloc(&G->C, n)) return e;
@@ -439,6 +465,9 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     const int64_t per = sweep_items_per_block(c);
     const int64_t need = (G->cls_count[c] + per - 1) / per;
     G->grid[c] = (int)std::max<int64_t>(1, std::min<int64_t>(need, sweep_max_resident(c)));
+    const int64_t dper = sweep_direct_items_per_block(c);
+    G->direct_grid[c] =
+        (int)std::max<int64_t>(1, std::min<int64_t>((G->cls_count[c] + dper - 1) / dper, 256 * 8));
   }
   G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 256 * 8));
   G->learn_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 2048));
@@ -509,6 +538,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->hub_acc_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, hub_max_resident()));
     G->hub_reduce_grid = hub_max_resident();
     G->hub_fin_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, 256 * 8));
+    G->hub_direct_grid = G->hub_fin_grid;
     LPA_HIP(hipStreamSynchronize(s));
   }
   LPA_HIP(hipEventCreate(&G->ev0));
@@ -582,9 +612,11 @@ struct RunCtx {
   TraceArgs tr{};
 };
 
+// direct: the first sweep of a run from identity labels over rows with
+// strictly increasing targets, which takes the table-free kernels.
 template <typename Mark>
 static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const RunCtx& rc,
-                                    hipStream_t s, Mark&& mark) {
+                                    hipStream_t s, Mark&& mark, bool direct = false) {
   const int64_t n = g->n;
   const int async_mode = o.mode == LPA_MODE_ASYNC;
   // without pruning every vertex is processed in every iteration
@@ -598,7 +630,10 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
                                     rc.tr, g->learn_grid, s));
   else
     LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
-  if (g->H > 0) {
+  if (g->H > 0 && direct) {
+    if (lpa_status e = mark(kKidHubPart)) return e;
+    LPA_HIP(launch_hub_direct(g->off64, ha, g->hub_direct_grid, s));
+  } else if (g->H > 0) {
     if (lpa_status e = mark(kKidHubPart)) return e;
     LPA_HIP(launch_hub_part(g->off64, ha, g->hub_acc_grid, s));
     if (lpa_status e = mark(kKidHubReduce)) return e;
@@ -617,7 +652,10 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     a.cls = c;
     a.active = g->lists[c];
     if (lpa_status e = mark(kKidSweep0 + c)) return e;
-    LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], rc.feat, s));
+    if (direct)
+      LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c], s));
+    else
+      LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], rc.feat, s));
   }
   if (g->H > 0) {
     if (lpa_status e = mark(kKidHubFin)) return e;
@@ -773,6 +811,8 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
       return fail(LPA_ERR_INVALID, "initial_labels must lie in [0, N)");
   }
 
+  // a run from identity labels over strict rows: table-free first sweep
+  const bool first_direct = !init && g->strict_rows && !rc.feat;
   int32_t done = 0;
   const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {
@@ -781,7 +821,13 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     // return at once
     hipGraphExec_t exec = nullptr;
     if (lpa_status e = g->iteration_graph(o, rc, &exec)) return e;
-    for (int32_t l = 0; l < o.max_iterations; ++l) LPA_HIP(hipGraphLaunch(exec, s));
+    int32_t l0 = 0;
+    if (first_direct && o.max_iterations > 0) {
+      auto nomark = [](int) -> lpa_status { return LPA_OK; };
+      if (lpa_status e = enqueue_iteration(g, o, rc, s, nomark, true)) return e;
+      l0 = 1;
+    }
+    for (int32_t l = l0; l < o.max_iterations; ++l) LPA_HIP(hipGraphLaunch(exec, s));
     LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
     LPA_HIP(hipStreamSynchronize(s));
     done = g->st_host->iter;
@@ -814,7 +860,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         return LPA_OK;
       };
       LPA_HIP(hipEventRecord(g->ev0, s));
-      if (lpa_status e = enqueue_iteration(g, o, rc, s, mark)) return e;
+      if (lpa_status e = enqueue_iteration(g, o, rc, s, mark, first_direct && l == 0)) return e;
       LPA_HIP(hipEventRecord(g->ev1, s));
       LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
       LPA_HIP(hipStreamSynchronize(s));

@@ -265,6 +265,40 @@ hipError_t launch_validate(bool off64, const void* off, const int32_t* tgt,
   return hipGetLastError();
 }
 
+// Rows with strictly increasing targets (sorted, no repeated neighbour):
+// mark the first entry of every non-empty row, then flag any entry whose
+// successor in the same row is not larger.  bad receives 1 on a violation.
+template <typename OffT>
+__global__ void k_mark_row_starts(const OffT* off, int64_t n, uint8_t* mark) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (off[i] < off[i + 1]) mark[off[i]] = 1;
+}
+
+__global__ void k_rows_strict(const int32_t* tgt, const uint8_t* mark, int64_t m,
+                              unsigned int* bad) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e + 1 < m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    if (!mark[e + 1] && tgt[e] >= tgt[e + 1]) *bad = 1u;
+}
+
+hipError_t launch_rows_strict(bool off64, const void* off, const int32_t* tgt, int64_t n,
+                              int64_t m, uint8_t* mark, unsigned int* bad, hipStream_t s) {
+  hipError_t e = launch_fill_u8(mark, 0, m, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u32(bad, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  if (off64)
+    hipLaunchKernelGGL(k_mark_row_starts<int64_t>, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0,
+                       s, (const int64_t*)off, n, mark);
+  else
+    hipLaunchKernelGGL(k_mark_row_starts<int32_t>, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0,
+                       s, (const int32_t*)off, n, mark);
+  hipLaunchKernelGGL(k_rows_strict, dim3(grid_for(m, kBT, 16384)), dim3(kBT), 0, s, tgt, mark, m,
+                     bad);
+  return hipGetLastError();
+}
+
 __global__ void k_check_labels(int64_t n, const int32_t* lab, DevStats* st) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

@@ -192,6 +192,8 @@ hipError_t launch_validate(bool off64, const void* off, const int32_t* tgt,
                            hipStream_t s);
 hipError_t launch_check_labels(int64_t n, const int32_t* lab, DevStats* st,
                                hipStream_t s);
+hipError_t launch_rows_strict(bool off64, const void* off, const int32_t* tgt, int64_t n,
+                              int64_t m, uint8_t* mark, unsigned int* bad, hipStream_t s);
 hipError_t launch_classify(bool off64, const void* off, int64_t n,
                            const int32_t* bounds, uint8_t* cls,
                            unsigned long long* counts, int32_t* hub_out,
@@ -232,6 +234,11 @@ hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t
                         hipStream_t s);
 hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, bool feat,
                         hipStream_t s);
+// The first sweep from identity labels over rows with strictly increasing
+// targets: table-free kernels (every neighbour label occurs once per row).
+hipError_t launch_sweep_direct(bool off64, int cls, const SweepArgs& a, int grid,
+                               hipStream_t s);
+hipError_t launch_hub_direct(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_part(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_reduce(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_spill(bool off64, const HubArgs& a, int grid, hipStream_t s);
@@ -247,6 +254,7 @@ hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt,
 // Threads per workgroup of each sweep class and resident-workgroup estimate.
 int sweep_block_threads(int cls);
 int sweep_items_per_block(int cls);
+int sweep_direct_items_per_block(int cls);
 int sweep_max_resident(int cls);
 int hub_block_threads();
 int hub_max_resident();

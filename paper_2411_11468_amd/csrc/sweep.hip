@@ -17,7 +17,9 @@
 // labels = vertex ids (Algorithm 1's initialisation) a neighbour's label is
 // its id and is not gathered: the deterministic result is unchanged, and in
 // asynchronous mode this is the read of the iteration-start value, which an
-// asynchronous sweep is free to make.  Flags are cleared only by the frontier kernel
+// asynchronous sweep is free to make.  When, moreover, every row's targets
+// strictly increase (checked once at create), the host runs that first sweep
+// with k_sweep_direct / k_hub_direct, which need no table.  Flags are cleared only by the frontier kernel
 // before the sweep and set only after it, so a neighbour that read an old
 // label is always flagged for the next iteration and no fence is needed
 // between a label store and anything else.  (An agent-scope fence would
@@ -268,6 +270,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     const int32_t cur = a.C[v];
     const uint32_t p1 = table_p1((uint32_t)d);
     RecPartial rp;
+    unsigned long long best = 0;
     for (int64_t base = 0; base < d; base += 64 * U) {
       int32_t j[U];
       float wt[U];
@@ -290,7 +293,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    unsigned long long best = 0;
     for (uint32_t s = lane; s < p1; s += 64) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
@@ -362,6 +364,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     const int32_t cur = a.C[v];
     const uint32_t p1 = table_p1((uint32_t)d);
     RecPartial rp;
+    unsigned long long best = 0;
     for (int64_t base = 0; base < d; base += (int64_t)BT * U) {
       int32_t j[U];
       float wt[U];
@@ -384,7 +387,6 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
         }
     }
     __syncthreads();
-    unsigned long long best = 0;
     for (uint32_t s = tid; s < p1; s += BT) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
@@ -782,6 +784,94 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
   }
 }
 
+// ---- the first sweep from identity labels over strict rows ------------------
+// Every neighbour label occurs once in such a row and its sum is the entry's
+// weight, so the row's Eq. 3 maximum (ties to the smallest label) is the
+// largest packed (weight, target) entry: a streaming maximum, no table.  G
+// lanes per vertex (4, 16 or 64 for the wave-sized classes, a whole
+// workgroup of BT for the larger ones); hub slices fold their maximum into the
+// hub's best, decided by k_hub_fin as usual.
+template <typename OffT, int G, int BT>
+__global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
+  __shared__ unsigned long long red[BT / 64];
+  if (a.st->stop) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t count = a.st->active[a.cls];
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  constexpr int kPer = (G >= 64) ? 1 : 64 / G;        // vertices per wave step
+  const int k = (G >= 64) ? ((G == 64) ? lane : tid) : (lane & (G - 1));
+  const uint64_t nsteps_wave = (G > 64) ? 1 : (uint64_t)(BT / 64);
+  const uint64_t unit0 = (G > 64) ? blockIdx.x : (uint64_t)blockIdx.x * nsteps_wave + (tid >> 6);
+  const uint64_t nunits = (G > 64) ? gridDim.x : (uint64_t)gridDim.x * nsteps_wave;
+  for (uint64_t base = unit0 * kPer; base < count; base += nunits * kPer) {
+    const uint64_t idx = base + ((G >= 64) ? 0 : (uint32_t)lane / G);
+    const bool valid = idx < count;
+    const int32_t v = valid ? a.active[idx] : 0;
+    int64_t o = 0, d = 0;
+    if (valid) row_of<OffT>(a.off, v, &o, &d);
+    unsigned long long best = 0;
+    for (int64_t e = k; e < d; e += G) {
+      const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e]);
+      if (j != v) best = umax64(best, pack_key(edge_weight(a.w, o + e), (uint32_t)j));
+    }
+    if constexpr (G == 4) best = quad_max_u64(best);
+    else if constexpr (G == 16) best = row16_max_u64(best);
+    else best = wave_max_u64(best);
+    if constexpr (G > 64) {
+      if (lane == 0) red[tid >> 6] = best;
+      __syncthreads();
+      best = red[0];
+#pragma unroll
+      for (int q = 1; q < BT / 64; ++q) best = umax64(best, red[q]);
+      __syncthreads();
+    }
+    // the vertex's own label is its id in this sweep
+    uint32_t cstar = 0;
+    const bool moved = valid && decide(best, v, a.st->pl, &cstar);
+    const bool leader = valid && k == 0;
+    if (leader) {
+      if (a.async_mode) {
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : v;
+      }
+      if (moved) a.chg[v] = 1;
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
+    }
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
+template <typename OffT, int BT>
+__global__ __launch_bounds__(BT) void k_hub_direct(HubArgs a) {
+  if (a.st->stop) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t nitems = a.st->hub_items;
+  unsigned long long my_edges = 0;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
+    const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    const int32_t v = a.hub_vid[h];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    const int64_t e0 = (int64_t)c * a.chunk;
+    const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
+    unsigned long long best = 0;
+    for (int64_t e = tid; e < n; e += BT) {
+      const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e0 + e]);
+      if (j != v) best = umax64(best, pack_key(edge_weight(a.w, o + e0 + e), (uint32_t)j));
+    }
+    best = wave_max_u64(best);
+    if (lane == 0 && best) atomicMax(&a.hub_best[h], best);
+    if (tid == 0) my_edges += (unsigned long long)n;
+  }
+  const unsigned long long e = wave_sum_u64(my_edges);
+  if (lane == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
+}
+
 // ---- launch wrappers ----------------------------------------------------------
 namespace {
 constexpr int kWaveWaves = 4;
@@ -805,6 +895,14 @@ int sweep_items_per_block(int cls) {
     case 1: return 256 / 4;
     case 2: return 256 / 16;
     case 3: case 4: return kWaveWaves;
+    default: return 1;
+  }
+}
+int sweep_direct_items_per_block(int cls) {
+  switch (cls) {
+    case 1: return 256 / 4;
+    case 2: return 256 / 16;
+    case 3: case 4: return 256 / 64;
     default: return 1;
   }
 }
@@ -838,6 +936,32 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
     case 8: hipLaunchKernelGGL((k_sweep_block<OffT, 16383, kBlockBig, 4, FEAT>), dim3(grid), dim3(kBlockBig), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename OffT>
+static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
+  switch (cls) {
+    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256>), dim3(grid), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3: case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256>), dim3(grid), dim3(256), 0, s, a); break;
+    case 5: case 6: case 7: case 8:
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 256, 256>), dim3(grid), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_direct(bool off64, int cls, const SweepArgs& a, int grid,
+                               hipStream_t s) {
+  return off64 ? direct_t<int64_t>(cls, a, grid, s) : direct_t<int32_t>(cls, a, grid, s);
+}
+
+hipError_t launch_hub_direct(bool off64, const HubArgs& a, int grid, hipStream_t s) {
+  if (off64)
+    hipLaunchKernelGGL((k_hub_direct<int64_t, 256>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_hub_direct<int32_t, 256>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -136,6 +136,27 @@ def test_det_hub_spill_path(cap):
     assert_det_parity(graphgen.rmat_graph(16, 16, "int8"), tuning=t2)
 
 
+def _shuffle_rows(g, seed):
+    """The same graph with every row's entries in random order."""
+    rng = np.random.default_rng(seed)
+    off = g.offsets.astype(np.int64)
+    row = np.repeat(np.arange(g.num_vertices), np.diff(off))
+    order = np.lexsort((rng.random(g.num_edges), row))
+    return graphgen.Graph(g.offsets, g.targets[order].copy(), g.weights[order].copy())
+
+
+def test_det_unsorted_rows_and_repeated_entries():
+    # rows that are not strictly increasing take the table path in the first
+    # sweep too; repeated entries add their weights
+    t = _tuning(**SMALL_TUNING)
+    g = graphgen.rmat_graph(13, 8, "int8")
+    assert_det_parity(_shuffle_rows(g, 1))
+    assert_det_parity(_shuffle_rows(g, 2), tuning=t)
+    edges = [(i, (i * 7 + 3) % 300) for i in range(300)] * 3 + [(i, i + 1) for i in range(299)]
+    assert_det_parity(graphgen.from_edges(300, edges))
+    assert_det_parity(graphgen.from_edges(300, edges), tuning=t)
+
+
 def test_det_rmat_default_tuning():
     g = graphgen.rmat_graph(15, 15, "int8")
     G = _graph_on_gpu(g)
