@@ -116,6 +116,16 @@ typedef struct lpa_graph_s* lpa_graph;
  * hub_table_cap: 0 (default) = bucket tables of up to 16383 slots; else at
  *   most this many slots (rounded down to 2^m - 1), to exercise the spill
  *   path in tests.
+ * relabel: where the handle keeps each vertex's label and row.  1 = in an
+ *   internal order by degree, largest first (8 steps per octave, ties by
+ *   id), built once by lpa_create as a second copy of the CSR: the label
+ *   reads of every sweep then concentrate on few cache lines.  0 = in the
+ *   caller's order.  -1 (default) = automatic: internal order when N > 2^20
+ *   and fewer than half of the CSR entries of a row sample point within
+ *   2^16 ids of their row.  Label values, results and every array passed in
+ *   or out stay in the caller's numbering either way; a deterministic run
+ *   returns the same labels.  lpa_create_batched keeps the caller's order
+ *   (relabel = 1 there is LPA_ERR_UNSUPPORTED).
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -126,6 +136,7 @@ typedef struct lpa_tuning {
   int32_t max_retries;
   int32_t xcd_local;
   int32_t hub_table_cap;
+  int32_t relabel;
 } lpa_tuning;
 
 /*

@@ -16,7 +16,7 @@ import numpy as np
 from . import lpa
 
 TUNING_FIELDS = ("small4", "small16", "wave", "block", "hub_chunk", "max_retries", "xcd_local",
-                 "hub_table_cap")
+                 "hub_table_cap", "relabel")
 
 
 def _round2(x: int) -> int:
@@ -46,7 +46,8 @@ def tuning_to_dict(t) -> dict:
 def tuning_from_dict(d: dict):
     t = lpa.default_tuning()
     for f in TUNING_FIELDS:
-        setattr(t, f, int(d[f]))
+        if f in d:  # entries written before a field existed keep its default
+            setattr(t, f, int(d[f]))
     return t
 
 

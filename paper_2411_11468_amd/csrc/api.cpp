@@ -62,9 +62,16 @@ struct lpa_graph_s {
   int64_t n = 0, m = 0;
   bool off64 = false;
   bool strict_rows = false;   // every row's targets strictly increase
-  const void* off = nullptr;
-  const int32_t* tgt = nullptr;
+  const void* off = nullptr;     // CSR the kernels read: the internal order
+  const int32_t* tgt = nullptr;  // when relabeled, else the caller's arrays
   const float* w = nullptr;
+  const void* uoff = nullptr;    // the caller's CSR (uploaded or borrowed)
+  const int32_t* utgt = nullptr;
+  const float* uw = nullptr;
+  int32_t* perm = nullptr;       // caller id -> internal id; NULL: one order
+  int32_t* inv = nullptr;        // internal id -> caller id
+  uint8_t* stage8 = nullptr;     // n bytes, flags in the caller's order
+  unsigned long long* stage64 = nullptr;  // n records in the caller's order
   lpa_tuning tun{};
   uint8_t* cls = nullptr;
   int32_t* C = nullptr;
@@ -130,8 +137,10 @@ struct lpa_graph_s {
   void account(int kid, float ms, const DevStats& h, bool async_mode, bool pull) {
     if (kid < 0 || kid >= kNumKids) return;
     lpa_kernel_profile& p = prof[kid];
-    // first iteration from labels = ids: the neighbour labels are not gathered
-    const bool id0 = h.ident && h.iter == 1;
+    // first iteration from labels = ids: the neighbour labels are not
+    // gathered (the table-free sweep also knows each vertex's own label)
+    const bool first = h.iter == 1;
+    const bool id0 = first && (h.ident || acct_direct);
     const double eb = (id0 ? 4.0 : 8.0) + (w ? 4.0 : 0.0);
     const double ob = off64 ? 16.0 : 8.0;
     const double chb = async_mode ? 4.0 : 8.0;
@@ -142,7 +151,7 @@ struct lpa_graph_s {
       edges = (int64_t)h.edges[c];
       verts = (int64_t)h.active[c];
       // the table-free first sweep knows each vertex's own label (its id)
-      const double own = (id0 && strict_rows && !acct_feat) ? 0.0 : 4.0;
+      const double own = (first && acct_direct) ? 0.0 : 4.0;
       bytes = eb * edges + (4.0 + ob + own) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
       if (acct_feat) bytes += 16.0 * verts;  // state record read and written
@@ -227,6 +236,7 @@ struct lpa_graph_s {
   int learn_grid = 1;
   int32_t learned_iters = 0;   // iterations of the last learned run
   bool acct_feat = false;      // profile: the run keeps records
+  bool acct_direct = false;    // profile: the run's first sweep is table-free
 
   BatchArgs batch_args() const {
     BatchArgs b;
@@ -248,6 +258,7 @@ struct lpa_graph_s {
   HubArgs hub_args(int async_mode) const {
     HubArgs a;
     a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F; a.chg = chg;
+    a.uoff = uoff; a.utgt = utgt; a.uw = uw; a.inv = inv;
     a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
     a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
     a.hub_nch = hub_nch; a.hub_ovf = hub_ovf; a.hub_lgb = hub_lgb;
@@ -304,6 +315,7 @@ void lpa_tuning_default(lpa_tuning* t) {
   t->hub_chunk = 8192;
   t->max_retries = 32;
   t->xcd_local = 1;
+  t->relabel = -1;
 }
 
 void lpa_learned_options_default(lpa_learned_options* o) {
@@ -339,7 +351,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   if (!(0 <= t.small4 && t.small4 <= 4 && t.small4 <= t.small16 && t.small16 <= 16 &&
         t.small16 <= t.wave && t.wave <= 512 && t.wave <= t.block && t.block <= 8192 &&
         t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0 &&
-        t.hub_table_cap >= 0))
+        t.hub_table_cap >= 0 && t.relabel >= -1 && t.relabel <= 1))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   hipStream_t s = G->stream;
   const int64_t n = G->n, m = G->m;
@@ -377,6 +389,9 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->tgt = dtgt;
     G->w = dw;
   }
+  G->uoff = G->off;
+  G->utgt = G->tgt;
+  G->uw = G->w;
 
   // counters
   if (lpa_status e = G->dalloc(&G->st, 1)) return e;
@@ -421,6 +436,54 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->strict_rows = hb == 0u;
   } else {
     G->strict_rows = true;
+  }
+
+  // internal vertex order by degree (relabel.hip).  Automatic: when the
+  // labels outgrow one XCD's L2 (N > 2^20) and fewer than half of the
+  // sampled entries point within 2^16 ids of their row, i.e. the caller's
+  // order gives the label reads no locality of its own.
+  bool relabel = t.relabel == 1;
+  if (t.relabel < 0 && n > (int64_t)1 << 20) {
+    unsigned long long* acc = nullptr;
+    if (hipMalloc(&acc, 4 * sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LPA_ERR_OOM, "hipMalloc failed for the locality sample");
+    }
+    unsigned long long h[4] = {0, 0, 0, 0};
+    hipError_t e = relabel_locality(G->off64, G->off, G->tgt, n, acc, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(acc);
+    if (e != hipSuccess)
+      return fail(LPA_ERR_HIP, std::string("locality sample: ") + hipGetErrorString(e));
+    relabel = 2 * h[0] < h[1];
+  }
+  if (relabel && n > 0) {
+    if (lpa_status e = G->dalloc(&G->perm, n)) return e;
+    if (lpa_status e = G->dalloc(&G->inv, n)) return e;
+    void* noff = nullptr;
+    if (G->off64) {
+      int64_t* p; if (lpa_status e = G->dalloc(&p, n + 1)) return e; noff = p;
+    } else {
+      int32_t* p; if (lpa_status e = G->dalloc(&p, n + 1)) return e; noff = p;
+    }
+    int32_t* ntgt = nullptr;
+    float* nw = nullptr;
+    if (lpa_status e = G->dalloc(&ntgt, m)) return e;
+    if (G->uw) {
+      if (lpa_status e = G->dalloc(&nw, m)) return e;
+    }
+    const hipError_t e = relabel_build(G->off64, G->uoff, G->utgt, G->uw, n, G->perm, G->inv,
+                                       noff, ntgt, nw, s);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return fail(LPA_ERR_OOM, "hipMalloc failed while building the internal order");
+    }
+    if (e != hipSuccess)
+      return fail(LPA_ERR_HIP, std::string("internal order: ") + hipGetErrorString(e));
+    G->off = noff;
+    G->tgt = ntgt;
+    G->w = nw;
   }
 
   // labels, flags, deterministic-mode queue
@@ -644,6 +707,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   SweepArgs a;
   a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;
   a.chg = g->chg; a.st = g->st;
+  a.uoff = g->uoff; a.utgt = g->utgt; a.uw = g->uw; a.inv = g->inv;
   a.async_mode = async_mode;
   a.max_retries = g->tun.max_retries;
   a.rec = g->lrec;
@@ -787,8 +851,12 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     lp.z_theta = (float)std::log(th / (1.0 - th));
     lp.fn_bound = g->lopt.fn_bound;
   }
+  rc.tr.inv = g->inv;
+  rc.tr.perm = g->perm;
   if (trace) {
     rc.tr = trace->tr;
+    rc.tr.inv = g->inv;
+    rc.tr.perm = g->perm;
     lp.trace = 1;
     lp.trace_rate = trace->rate;
     lp.trace_seed = trace->seed;
@@ -803,7 +871,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     if (lpa_status e = stage_labels(g, o.initial_labels, g->pend_v)) return e;
     init = g->pend_v;
   }
-  LPA_HIP(launch_init(n, init, g->C, g->F, g->st, s));
+  LPA_HIP(launch_init(n, init, g->inv, g->C, g->F, g->st, s));
   if (init) {
     LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
     LPA_HIP(hipStreamSynchronize(s));
@@ -813,6 +881,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
 
   // a run from identity labels over strict rows: table-free first sweep
   const bool first_direct = !init && g->strict_rows && !rc.feat;
+  g->acct_direct = first_direct;
   int32_t done = 0;
   const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {
@@ -896,8 +965,17 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   }
   if (iters_done) *iters_done = done;
   g->learned_iters = o.learned ? done : 0;
-  const hipMemcpyKind kind = is_device_ptr(labels) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  LPA_HIP(hipMemcpyAsync(labels, g->C, sizeof(int32_t) * (size_t)n, kind, s));
+  const bool dev_out = is_device_ptr(labels);
+  if (g->perm) {
+    // labels in the caller's order (Cn is free once the run has ended)
+    int32_t* dst = dev_out ? labels : g->Cn;
+    LPA_HIP(launch_unpermute_i32(g->C, g->perm, n, dst, s));
+    if (!dev_out)
+      LPA_HIP(hipMemcpyAsync(labels, dst, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+  } else {
+    const hipMemcpyKind kind = dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    LPA_HIP(hipMemcpyAsync(labels, g->C, sizeof(int32_t) * (size_t)n, kind, s));
+  }
   LPA_HIP(hipStreamSynchronize(s));
   return LPA_OK;
 }
@@ -936,8 +1014,15 @@ lpa_status lpa_create_batched(int32_t num_graphs, const int64_t* v_off, const lp
     return fail(LPA_ERR_INVALID, "v_off must run from 0 to num_vertices");
   for (int32_t q = 0; q < num_graphs; ++q)
     if (v_off[q + 1] < v_off[q]) return fail(LPA_ERR_INVALID, "v_off must be non-decreasing");
+  // the packed graphs keep the caller's order (their stop test works on
+  // ranges of vertex ids)
+  lpa_tuning tb;
+  if (tuning) tb = *tuning; else lpa_tuning_default(&tb);
+  if (tb.relabel == 1)
+    return fail(LPA_ERR_UNSUPPORTED, "relabel = 1 needs a single graph (lpa_create)");
+  tb.relabel = 0;
   lpa_graph g = nullptr;
-  if (lpa_status e = lpa_create(csr, stream, tuning, &g)) return e;
+  if (lpa_status e = lpa_create(csr, stream, &tb, &g)) return e;
   hipStream_t s = g->stream;
   auto cleanup = [&](lpa_status e) { lpa_destroy(g); return e; };
   g->G = num_graphs;
@@ -1030,8 +1115,23 @@ lpa_status lpa_get_records(lpa_graph g, uint64_t* out) {
   if (!g || (g->n > 0 && !out)) return fail(LPA_ERR_INVALID, "NULL argument");
   if (g->n == 0) return LPA_OK;
   if (!g->lrec_valid) return fail(LPA_ERR_STATE, "no learned or traced run yet");
-  const hipMemcpyKind kind = is_device_ptr(out) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  LPA_HIP(hipMemcpyAsync(out, g->lrec, sizeof(uint64_t) * (size_t)g->n, kind, g->stream));
+  const bool dev_out = is_device_ptr(out);
+  const unsigned long long* src = g->lrec;
+  if (g->perm) {
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(out);
+    if (!dev_out) {
+      if (!g->stage64) {
+        if (lpa_status e = g->dalloc(&g->stage64, g->n)) return e;
+      }
+      dst = g->stage64;
+    }
+    LPA_HIP(launch_unpermute_u64(g->lrec, g->perm, g->n, dst, g->stream));
+    src = dst;
+  }
+  if (src != reinterpret_cast<const unsigned long long*>(out)) {
+    const hipMemcpyKind kind = dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    LPA_HIP(hipMemcpyAsync(out, src, sizeof(uint64_t) * (size_t)g->n, kind, g->stream));
+  }
   LPA_HIP(hipStreamSynchronize(g->stream));
   return LPA_OK;
 }
@@ -1098,8 +1198,23 @@ lpa_status lpa_trace(lpa_graph g, const lpa_options* opt, double sample_rate, ui
 lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags) {
   if (!g || (g->n > 0 && !flags)) return fail(LPA_ERR_INVALID, "NULL argument");
   if (g->n == 0) return LPA_OK;
-  const hipMemcpyKind kind = is_device_ptr(flags) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  LPA_HIP(hipMemcpyAsync(flags, g->F, (size_t)g->n, kind, g->stream));
+  const bool dev_out = is_device_ptr(flags);
+  const uint8_t* src = g->F;
+  if (g->perm) {
+    uint8_t* dst = flags;
+    if (!dev_out) {
+      if (!g->stage8) {
+        if (lpa_status e = g->dalloc(&g->stage8, g->n)) return e;
+      }
+      dst = g->stage8;
+    }
+    LPA_HIP(launch_unpermute_u8(g->F, g->perm, g->n, dst, g->stream));
+    src = dst;
+  }
+  if (src != flags) {
+    const hipMemcpyKind kind = dev_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    LPA_HIP(hipMemcpyAsync(flags, src, (size_t)g->n, kind, g->stream));
+  }
   LPA_HIP(hipStreamSynchronize(g->stream));
   return LPA_OK;
 }
@@ -1125,7 +1240,7 @@ lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q) {
   LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
   LPA_HIP(hipStreamSynchronize(s));
   if (g->st_host->error & 4u) return fail(LPA_ERR_INVALID, "labels must lie in [0, N)");
-  LPA_HIP(launch_modularity(g->off64, g->off, g->tgt, g->w, g->n, g->m, lab, g->mod_sig,
+  LPA_HIP(launch_modularity(g->off64, g->uoff, g->utgt, g->uw, g->n, g->m, lab, g->mod_sig,
                             g->mod_acc, s));
   double acc[4];
   LPA_HIP(hipMemcpyAsync(acc, g->mod_acc, sizeof(acc), hipMemcpyDeviceToHost, s));

@@ -32,21 +32,25 @@ int grid_for(int64_t n, int per_block, int cap) {
 }  // namespace
 
 // ---- init ---------------------------------------------------------------------
-__global__ void k_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
-                       DevStats* st) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->ident = init ? 0 : 1;
+__global__ void k_init(int64_t n, const int32_t* init, const int32_t* inv, int32_t* C,
+                       uint8_t* F, DevStats* st) {
+  // ident: every label equals its internal id, so the first sweep may take
+  // a neighbour's id for its label
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->ident = (init || inv) ? 0 : 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = init ? init[i] : (int32_t)i;
+    const int64_t u = inv ? (int64_t)inv[i] : i;
+    const int32_t c = init ? init[u] : (int32_t)u;
     if (c < 0 || (int64_t)c >= n) set_error(st, 4u);
     C[i] = c;
     F[i] = 1;
   }
 }
 
-hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
-                       DevStats* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, n, init, C, F, st);
+hipError_t launch_init(int64_t n, const int32_t* init, const int32_t* inv, int32_t* C,
+                       uint8_t* F, DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, n, init, inv, C, F,
+                     st);
   return hipGetLastError();
 }
 
@@ -640,7 +644,8 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
         const bool skip = pred && skipping;
         if (lane < 16 && has) dec[src] = (uint8_t)((pred ? 1 : 0) | (skip ? 2 : 0));
         if (tracing) {
-          const bool take = has && !skip && sample_draw(seed, l, u) < rate;
+          const int64_t uid = tr.inv ? (int64_t)tr.inv[u] : u;  // the caller's id
+          const bool take = has && !skip && sample_draw(seed, l, uid) < rate;
           if (lane < 16) slot[lane] = take ? atomicAdd(&st->trace_n, 1ull) : ~0ull;
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           const unsigned long long qq = slot[lane & 15];
@@ -648,7 +653,7 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
 #pragma unroll
             for (int j = 0; j < 4; ++j) tr.X[qq * kMlpIn + 4 * g + j] = x[j];
             if (g == 0) {
-              tr.v[qq] = (int32_t)u;
+              tr.v[qq] = (int32_t)uid;
               tr.l[qq] = l;
             }
           }
@@ -712,7 +717,7 @@ __global__ void k_trace_label(const DevStats* st, const uint8_t* chg, TraceArgs 
   for (unsigned long long i = st->trace_first + blockIdx.x * (unsigned long long)blockDim.x +
                               threadIdx.x;
        i < end; i += (unsigned long long)gridDim.x * blockDim.x)
-    tr.y[i] = chg[tr.v[i]] ? 1.0f : 0.0f;
+    tr.y[i] = chg[tr.perm ? tr.perm[tr.v[i]] : tr.v[i]] ? 1.0f : 0.0f;
 }
 
 hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const TraceArgs& tr,

@@ -88,8 +88,10 @@ constexpr unsigned long long kRecordInit = 0xFFull << 56;
 struct TraceArgs {
   float* X;               // [cap][12] features
   float* y;               // [cap] 1 if the vertex changed label
-  int32_t* v;             // [cap] vertex
+  int32_t* v;             // [cap] vertex (the caller's id)
   int32_t* l;             // [cap] iteration
+  const int32_t* inv;     // internal id -> caller id (NULL: one order)
+  const int32_t* perm;    // caller id -> internal id
 };
 
 // Everything a sweep kernel needs, passed by value.
@@ -108,6 +110,12 @@ struct SweepArgs {
   int async_mode;         // 1: write labels in place, 0: queue them
   int max_retries;        // hybrid probes before the linear continuation
   unsigned long long* rec;  // learned variant: per-vertex state records
+  // the caller's CSR and inv (internal id -> caller id; NULL when the two
+  // orders agree), read by the table-free first sweep
+  const void* uoff;
+  const int32_t* utgt;
+  const float* uw;
+  const int32_t* inv;
 };
 
 // Hubs (rows longer than the largest LDS table).  Each slice of chunk CSR
@@ -121,6 +129,10 @@ struct HubArgs {
   const void* off;
   const int32_t* tgt;
   const float* w;
+  const void* uoff;                // the caller's CSR and inv, as in SweepArgs
+  const int32_t* utgt;
+  const float* uw;
+  const int32_t* inv;
   int32_t* C;
   uint8_t* F;
   uint8_t* chg;
@@ -176,8 +188,10 @@ struct BatchArgs {
 };
 
 // ---- launch wrappers (defined in the .hip files) ----------------------------
-hipError_t launch_init(int64_t n, const int32_t* init, int32_t* C, uint8_t* F,
-                       DevStats* st, hipStream_t s);
+// C[v'] = initial label of the caller's vertex inv[v'] (its id when init is
+// NULL; inv NULL: one order).
+hipError_t launch_init(int64_t n, const int32_t* init, const int32_t* inv, int32_t* C,
+                       uint8_t* F, DevStats* st, hipStream_t s);
 hipError_t launch_run_begin(DevStats* st, double tol, int cap, int rho, int batched,
                             int graphs, const LearnParams& lp, hipStream_t s);
 hipError_t launch_arm_flags(uint8_t* F, int64_t n, const DevStats* st, hipStream_t s);
@@ -258,5 +272,18 @@ int sweep_direct_items_per_block(int cls);
 int sweep_max_resident(int cls);
 int hub_block_threads();
 int hub_max_resident();
+
+// Internal vertex order (relabel.hip).
+hipError_t relabel_build(bool off64, const void* uoff, const int32_t* utgt, const float* uw,
+                         int64_t n, int32_t* perm, int32_t* inv, void* noff, int32_t* ntgt,
+                         float* nw, hipStream_t s);
+hipError_t relabel_locality(bool off64, const void* off, const int32_t* tgt, int64_t n,
+                            unsigned long long* acc, hipStream_t s);
+hipError_t launch_unpermute_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,
+                                hipStream_t s);
+hipError_t launch_unpermute_u8(const uint8_t* in, const int32_t* perm, int64_t n, uint8_t* out,
+                               hipStream_t s);
+hipError_t launch_unpermute_u64(const unsigned long long* in, const int32_t* perm, int64_t n,
+                                unsigned long long* out, hipStream_t s);
 
 }  // namespace lpa

@@ -787,7 +787,9 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
 // ---- the first sweep from identity labels over strict rows ------------------
 // Every neighbour label occurs once in such a row and its sum is the entry's
 // weight, so the row's Eq. 3 maximum (ties to the smallest label) is the
-// largest packed (weight, target) entry: a streaming maximum, no table.  G
+// largest packed (weight, target) entry: a streaming maximum, no table.  The
+// rows are read in the caller's order and numbering (uoff/utgt/uw), where
+// the targets are the labels; results go to the internal slots.  G
 // lanes per vertex (4, 16 or 64 for the wave-sized classes, a whole
 // workgroup of BT for the larger ones); hub slices fold their maximum into the
 // hub's best, decided by k_hub_fin as usual.
@@ -807,13 +809,14 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
   for (uint64_t base = unit0 * kPer; base < count; base += nunits * kPer) {
     const uint64_t idx = base + ((G >= 64) ? 0 : (uint32_t)lane / G);
     const bool valid = idx < count;
-    const int32_t v = valid ? a.active[idx] : 0;
+    const int32_t vi = valid ? a.active[idx] : 0;       // internal id
+    const int32_t v = a.inv ? a.inv[vi] : vi;            // caller's id = its label
     int64_t o = 0, d = 0;
-    if (valid) row_of<OffT>(a.off, v, &o, &d);
+    if (valid) row_of<OffT>(a.uoff, v, &o, &d);
     unsigned long long best = 0;
     for (int64_t e = k; e < d; e += G) {
-      const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e]);
-      if (j != v) best = umax64(best, pack_key(edge_weight(a.w, o + e), (uint32_t)j));
+      const int32_t j = __builtin_nontemporal_load(&a.utgt[o + e]);
+      if (j != v) best = umax64(best, pack_key(edge_weight(a.uw, o + e), (uint32_t)j));
     }
     if constexpr (G == 4) best = quad_max_u64(best);
     else if constexpr (G == 16) best = row16_max_u64(best);
@@ -826,17 +829,17 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
       for (int q = 1; q < BT / 64; ++q) best = umax64(best, red[q]);
       __syncthreads();
     }
-    // the vertex's own label is its id in this sweep
+    // the vertex's own label is its caller id in this sweep
     uint32_t cstar = 0;
     const bool moved = valid && decide(best, v, a.st->pl, &cstar);
     const bool leader = valid && k == 0;
     if (leader) {
       if (a.async_mode) {
-        if (moved) a.C[v] = (int32_t)cstar;
+        if (moved) a.C[vi] = (int32_t)cstar;
       } else {
-        a.Cn[v] = moved ? (int32_t)cstar : v;
+        a.Cn[vi] = moved ? (int32_t)cstar : v;
       }
-      if (moved) a.chg[v] = 1;
+      if (moved) a.chg[vi] = 1;
       my_edges += (unsigned long long)d;
       my_changed += moved ? 1u : 0u;
       my_flagw += moved ? (unsigned long long)d : 0ull;
@@ -854,15 +857,16 @@ __global__ __launch_bounds__(BT) void k_hub_direct(HubArgs a) {
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
     const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
-    const int32_t v = a.hub_vid[h];
+    const int32_t vi = a.hub_vid[h];
+    const int32_t v = a.inv ? a.inv[vi] : vi;  // the caller's row, same length
     int64_t o, d;
-    row_of<OffT>(a.off, v, &o, &d);
+    row_of<OffT>(a.uoff, v, &o, &d);
     const int64_t e0 = (int64_t)c * a.chunk;
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
     unsigned long long best = 0;
     for (int64_t e = tid; e < n; e += BT) {
-      const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e0 + e]);
-      if (j != v) best = umax64(best, pack_key(edge_weight(a.w, o + e0 + e), (uint32_t)j));
+      const int32_t j = __builtin_nontemporal_load(&a.utgt[o + e0 + e]);
+      if (j != v) best = umax64(best, pack_key(edge_weight(a.uw, o + e0 + e), (uint32_t)j));
     }
     best = wave_max_u64(best);
     if (lane == 0 && best) atomicMax(&a.hub_best[h], best);
