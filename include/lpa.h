@@ -436,6 +436,17 @@ lpa_status lpa_autotune(const lpa_csr* csr, int32_t num_graphs, const int64_t* v
 lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q);
 
 /*
+ * Ceiling of the sweep kernels' memory side: the rate (CSR entries per
+ * second, into *reads_per_s) of a pass that does nothing but read every
+ * entry's target and then its neighbour's label, in the order and vertex
+ * numbering the sweeps use (the internal order when the handle has one),
+ * averaged over reps passes after one warm-up.  Resets the handle's labels
+ * to the plain start (labels = ids); a later lpa_run starts afresh anyway.
+ * Errors: LPA_ERR_INVALID (NULL, reps < 1), LPA_ERR_OOM, LPA_ERR_HIP.
+ */
+lpa_status lpa_label_read_rate(lpa_graph g, int32_t reps, double* reads_per_s);
+
+/*
  * Number of vertices in each degree class, in the order: degree 0, small4,
  * small16, wave, block (all LDS sizes), hub.  counts must hold 6 entries.
  */

@@ -46,12 +46,15 @@ namespace {
 constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubPart = 2, kKidSweep0 = 2,
               kKidHubFin = 11, kKidApply = 12, kKidPull = 13, kKidPullHubs = 14,
               kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kKidHubReduce = 18,
-              kKidBatch = 19, kKidHubSpill = 20, kNumKids = 21;
+              kKidBatch = 19, kKidHubSpill = 20, kKidDirect0 = 20, kKidHubDirect = 29,
+              kNumKids = 30;
 const char* const kKidNames[kNumKids] = {
     "hub_plan", "frontier", "hub_part", "sweep_small4", "sweep_small16", "sweep_wave127",
     "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
     "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
-    "push_hubs", "flag_decide", "hub_reduce", "batch_step", "hub_spill"};
+    "push_hubs", "flag_decide", "hub_reduce", "batch_step", "hub_spill", "direct_small4",
+    "direct_small16", "direct_wave127", "direct_wave1023", "direct_block2047",
+    "direct_block4095", "direct_block8191", "direct_block16383", "hub_direct"};
 
 }  // namespace
 
@@ -72,6 +75,7 @@ struct lpa_graph_s {
   int32_t* inv = nullptr;        // internal id -> caller id
   uint8_t* stage8 = nullptr;     // n bytes, flags in the caller's order
   unsigned long long* stage64 = nullptr;  // n records in the caller's order
+  uint32_t* probe_sink = nullptr;         // lpa_label_read_rate
   lpa_tuning tun{};
   uint8_t* cls = nullptr;
   int32_t* C = nullptr;
@@ -138,24 +142,26 @@ struct lpa_graph_s {
     if (kid < 0 || kid >= kNumKids) return;
     lpa_kernel_profile& p = prof[kid];
     // first iteration from labels = ids: the neighbour labels are not
-    // gathered (the table-free sweep also knows each vertex's own label)
-    const bool first = h.iter == 1;
-    const bool id0 = first && (h.ident || acct_direct);
-    const double eb = (id0 ? 4.0 : 8.0) + (w ? 4.0 : 0.0);
+    // gathered; the table-free kernels read the caller's rows, where the
+    // targets are the labels, and know each vertex's own label
+    const bool id0 = h.iter == 1 && h.ident;
+    const bool direct = (kid > kKidDirect0 && kid <= kKidDirect0 + 8) || kid == kKidHubDirect;
+    const double eb = ((id0 || direct) ? 4.0 : 8.0) + (w ? 4.0 : 0.0);
     const double ob = off64 ? 16.0 : 8.0;
     const double chb = async_mode ? 4.0 : 8.0;
     double bytes = 0.0;
     int64_t edges = 0, verts = 0;
-    if (kid >= kKidSweep0 + 1 && kid <= kKidSweep0 + 8) {
-      const int c = kid - kKidSweep0;
+    if ((kid >= kKidSweep0 + 1 && kid <= kKidSweep0 + 8) || (direct && kid != kKidHubDirect)) {
+      const int c = direct ? kid - kKidDirect0 : kid - kKidSweep0;
       edges = (int64_t)h.edges[c];
       verts = (int64_t)h.active[c];
-      // the table-free first sweep knows each vertex's own label (its id)
-      const double own = (first && acct_direct) ? 0.0 : 4.0;
+      // own label: read, or (table-free) the caller id through inv when
+      // the handle keeps an internal order
+      const double own = direct ? (perm ? 4.0 : 0.0) : 4.0;
       bytes = eb * edges + (4.0 + ob + own) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
       if (acct_feat) bytes += 16.0 * verts;  // state record read and written
-    } else if (kid == kKidHubPart) {
+    } else if (kid == kKidHubPart || kid == kKidHubDirect) {
       edges = (int64_t)h.edges[kClassHub];
       bytes = eb * edges;
     } else if (kid == kKidHubFin) {
@@ -236,7 +242,6 @@ struct lpa_graph_s {
   int learn_grid = 1;
   int32_t learned_iters = 0;   // iterations of the last learned run
   bool acct_feat = false;      // profile: the run keeps records
-  bool acct_direct = false;    // profile: the run's first sweep is table-free
 
   BatchArgs batch_args() const {
     BatchArgs b;
@@ -694,7 +699,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   else
     LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
   if (g->H > 0 && direct) {
-    if (lpa_status e = mark(kKidHubPart)) return e;
+    if (lpa_status e = mark(kKidHubDirect)) return e;
     LPA_HIP(launch_hub_direct(g->off64, ha, g->hub_direct_grid, s));
   } else if (g->H > 0) {
     if (lpa_status e = mark(kKidHubPart)) return e;
@@ -715,7 +720,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     if (g->cls_count[c] == 0) continue;
     a.cls = c;
     a.active = g->lists[c];
-    if (lpa_status e = mark(kKidSweep0 + c)) return e;
+    if (lpa_status e = mark((direct ? kKidDirect0 : kKidSweep0) + c)) return e;
     if (direct)
       LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c], s));
     else
@@ -881,7 +886,6 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
 
   // a run from identity labels over strict rows: table-free first sweep
   const bool first_direct = !init && g->strict_rows && !rc.feat;
-  g->acct_direct = first_direct;
   int32_t done = 0;
   const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {
@@ -1216,6 +1220,30 @@ lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags) {
     LPA_HIP(hipMemcpyAsync(flags, src, (size_t)g->n, kind, g->stream));
   }
   LPA_HIP(hipStreamSynchronize(g->stream));
+  return LPA_OK;
+}
+
+lpa_status lpa_label_read_rate(lpa_graph g, int32_t reps, double* reads_per_s) {
+  if (!g || !reads_per_s) return fail(LPA_ERR_INVALID, "NULL argument");
+  if (reps < 1) return fail(LPA_ERR_INVALID, "reps must be at least 1");
+  *reads_per_s = 0.0;
+  if (g->m == 0 || g->n == 0) return LPA_OK;
+  hipStream_t s = g->stream;
+  constexpr int kGrid = 256 * 16;
+  if (!g->probe_sink) {
+    if (lpa_status e = g->dalloc(&g->probe_sink, (int64_t)kGrid * 256)) return e;
+  }
+  // labels of a plain start, so that the reads see valid ids
+  LPA_HIP(launch_init(g->n, nullptr, g->inv, g->C, g->F, g->st, s));
+  LPA_HIP(launch_label_read_probe(g->tgt, g->m, g->C, g->probe_sink, kGrid, s));  // warm-up
+  LPA_HIP(hipEventRecord(g->ev0, s));
+  for (int32_t r = 0; r < reps; ++r)
+    LPA_HIP(launch_label_read_probe(g->tgt, g->m, g->C, g->probe_sink, kGrid, s));
+  LPA_HIP(hipEventRecord(g->ev1, s));
+  LPA_HIP(hipEventSynchronize(g->ev1));
+  float ms = 0.0f;
+  LPA_HIP(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+  *reads_per_s = ms > 0.0f ? (double)g->m * reps / (1e-3 * ms) : 0.0;
   return LPA_OK;
 }
 

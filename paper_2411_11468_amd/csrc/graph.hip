@@ -303,6 +303,33 @@ hipError_t launch_rows_strict(bool off64, const void* off, const int32_t* tgt, i
   return hipGetLastError();
 }
 
+// Label-read probe: one pass that only reads every CSR entry's target and
+// its neighbour's label, in the order the sweep kernels read them (8 entries
+// in flight per lane).  Its rate bounds any sweep that must read them.
+__global__ __launch_bounds__(256) void k_label_read_probe(const int32_t* tgt, int64_t m,
+                                                          const int32_t* C, uint32_t* sink) {
+  constexpr int U = 8;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t T = (int64_t)gridDim.x * 256;
+  uint32_t acc = 0;
+  int64_t e = t;
+  for (; e + (U - 1) * T < m; e += U * T) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = __builtin_nontemporal_load(&tgt[e + u * T]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += (uint32_t)C[j[u]];
+  }
+  for (; e < m; e += T) acc += (uint32_t)C[__builtin_nontemporal_load(&tgt[e])];
+  sink[t] = acc;
+}
+
+hipError_t launch_label_read_probe(const int32_t* tgt, int64_t m, const int32_t* C,
+                                   uint32_t* sink, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_label_read_probe, dim3(grid), dim3(256), 0, s, tgt, m, C, sink);
+  return hipGetLastError();
+}
+
 __global__ void k_check_labels(int64_t n, const int32_t* lab, DevStats* st) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)

@@ -273,6 +273,10 @@ int sweep_max_resident(int cls);
 int hub_block_threads();
 int hub_max_resident();
 
+// One pass reading every entry's target and neighbour label (sink: grid*256).
+hipError_t launch_label_read_probe(const int32_t* tgt, int64_t m, const int32_t* C,
+                                   uint32_t* sink, int grid, hipStream_t s);
+
 // Internal vertex order (relabel.hip).
 hipError_t relabel_build(bool off64, const void* uoff, const int32_t* utgt, const float* uw,
                          int64_t n, int32_t* perm, int32_t* inv, void* noff, int32_t* ntgt,

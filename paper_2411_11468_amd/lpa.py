@@ -107,7 +107,8 @@ EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run"
             "lpa_predictor_destroy", "lpa_predictor_set_params", "lpa_predictor_get_params",
             "lpa_predictor_gradient", "lpa_predictor_adam", "lpa_predictor_train",
             "lpa_predictor_predict", "lpa_learned_options_default", "lpa_set_predictor",
-            "lpa_learned_history", "lpa_get_records", "lpa_trace", "lpa_autotune")
+            "lpa_learned_history", "lpa_get_records", "lpa_trace", "lpa_autotune",
+            "lpa_label_read_rate")
 
 _lib = None
 
@@ -146,6 +147,8 @@ def load_library(path: str | None = None):
     lib.lpa_run.restype = ctypes.c_int
     lib.lpa_modularity.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     lib.lpa_modularity.restype = ctypes.c_int
+    lib.lpa_label_read_rate.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.lpa_label_read_rate.restype = ctypes.c_int
     lib.lpa_graph_classes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.lpa_graph_classes.restype = ctypes.c_int
     lib.lpa_get_flags.argtypes = [vp, vp]
@@ -436,6 +439,14 @@ def lpa_modularity(handle, labels) -> float:
     return float(q.value)
 
 
+def lpa_label_read_rate(handle, reps: int = 3) -> float:
+    """CSR entries per second of a pass that only reads each entry's target
+    and neighbour label (the sweeps' memory-side ceiling)."""
+    r = ctypes.c_double(0.0)
+    _check(load_library().lpa_label_read_rate(handle, int(reps), ctypes.byref(r)))
+    return float(r.value)
+
+
 def lpa_graph_classes(handle) -> dict:
     c = (ctypes.c_int64 * 6)()
     _check(load_library().lpa_graph_classes(handle, c))
@@ -525,6 +536,9 @@ class LpaGraph:
 
     def classes(self) -> dict:
         return lpa_graph_classes(self.handle)
+
+    def label_read_rate(self, reps: int = 3) -> float:
+        return lpa_label_read_rate(self.handle, reps)
 
     def profile(self) -> list:
         return lpa_profile(self.handle)

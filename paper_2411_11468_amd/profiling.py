@@ -38,6 +38,16 @@ _NAME_RULES = [
     (r"k_sweep_block<[^,]+, 4095,", "sweep_block4095"),
     (r"k_sweep_block<[^,]+, 8191,", "sweep_block8191"),
     (r"k_sweep_block<[^,]+, 16383,", "sweep_block16383"),
+    # the table-free first sweep: one instantiation per lane-group width, so
+    # lpa_profile's direct_wave127 + direct_wave1023 make "direct_wave" and
+    # its four direct_block classes "direct_block"
+    (r"k_sweep_direct<[^,]+, 4,", "direct_small4"),
+    (r"k_sweep_direct<[^,]+, 16,", "direct_small16"),
+    (r"k_sweep_direct<[^,]+, 64,", "direct_wave"),
+    (r"k_sweep_direct<[^,]+, 256,", "direct_block"),
+    (r"k_hub_direct<", "hub_direct"),
+    (r"k_rl_|k_scan_chunks|k_scan_add", "relabel_build"),
+    (r"k_unpermute<", "unpermute"),
     (r"k_hub_part<", "hub_part"),
     (r"k_hub_reduce<", "hub_reduce"),
     (r"k_hub_spill<", "hub_spill"),

@@ -306,3 +306,43 @@ def test_det_rmat_scale22_full_size():
     g = graphgen.rmat_graph(22, 22, "int8")
     assert int(g.weights.max()) * int(g.degrees().max()) < 2 ** 24
     assert_det_parity(g)
+
+
+def test_profile_books_each_kernel():
+    # every class kernel once per iteration; the table-free first sweep
+    # under its own names, once per run
+    g = graphgen.rmat_graph(12, 6, "int8")
+    G = _graph_on_gpu(g, _tuning(**SMALL_TUNING))
+    cls = G.classes()
+    G.profile_reset()
+    res = G.run("det", profile=True)
+    prof = {p["name"]: p for p in G.profile()}
+    it = res.iterations
+    assert it >= 3
+    assert prof["frontier"]["launches"] == it
+    assert prof["hub_direct"]["launches"] == 1
+    assert prof["hub_part"]["launches"] == it - 1
+    if cls["small4"]:
+        assert prof["direct_small4"]["launches"] == 1
+        assert prof["sweep_small4"]["launches"] == it - 1
+    for name in ("hub_direct", "hub_part", "direct_small16", "sweep_small16"):
+        p = prof[name]
+        assert p["total_ms"] > 0 and p["bytes"] > 0 and p["edges"] > 0, p
+    G.close()
+
+
+def test_label_read_rate():
+    g = graphgen.rmat_graph(14, 5, "int8")
+    for relabel in (0, 1):
+        G = _graph_on_gpu(g, _tuning(relabel=relabel))
+        r = G.label_read_rate(2)
+        assert r > 1e8, r
+        # the probe leaves no trace on later runs
+        ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+        assert np.array_equal(G.run("det").labels.cpu().numpy(), ref.labels)
+        with pytest.raises(lpa.LpaError):
+            G.label_read_rate(0)
+        G.close()
+    E = _graph_on_gpu(graphgen.from_edges(3, []))
+    assert E.label_read_rate(1) == 0.0
+    E.close()
