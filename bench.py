@@ -322,6 +322,7 @@ def main() -> int:
     achieved = dom["bytes"] / (dom["total_ms"] * 1e-3) / 1e9
     kernels = {p["name"]: {"launches": p["launches"],
                            "avg_us": round(1e3 * p["total_ms"] / p["launches"], 2),
+                           "entries": p["edges"], "vertices": p["vertices"],
                            "alg_GBps": round(p["bytes"] / max(p["total_ms"], 1e-9) / 1e6, 1),
                            "share": round(p["total_ms"] / sum(x["total_ms"] for x in prof), 3)}
                for p in prof}

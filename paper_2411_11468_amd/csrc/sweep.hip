@@ -570,12 +570,26 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     const uint32_t nb = 1u << lgb;
     for (uint32_t b = tid; b < nb; b += BT) hist[b] = 0u;
     const uint32_t p1c = table_p1((uint32_t)n);
-    for (int64_t e = tid; e < n; e += BT) {
-      const int32_t j = __builtin_nontemporal_load(&a.tgt[o + e0 + e]);
-      if (j != v)
-        lds_accumulate(keys, vals, p1c, id0 ? (uint32_t)j : (uint32_t)a.C[j],
-                       edge_weight(a.w, o + e0 + e),
-                       a.max_retries);
+    // U entries per thread in flight: targets, then their labels, then the
+    // table inserts
+    constexpr int U = 4;
+    for (int64_t base = 0; base < n; base += (int64_t)BT * U) {
+      int32_t j[U];
+      float wt[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * BT + tid;
+        const bool has = e < n;
+        j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e0 + e]) : v;
+        wt[u] = has ? edge_weight(a.w, o + e0 + e) : 0.0f;
+      }
+      uint32_t lab[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.max_retries);
     }
     __syncthreads();
     for (uint32_t s = tid; s < p1c; s += BT) {
