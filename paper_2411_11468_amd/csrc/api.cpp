@@ -722,7 +722,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     a.active = g->lists[c];
     if (lpa_status e = mark((direct ? kKidDirect0 : kKidSweep0) + c)) return e;
     if (direct)
-      LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c], s));
+      LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c], rc.feat, s));
     else
       LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], rc.feat, s));
   }
@@ -885,7 +885,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   }
 
   // a run from identity labels over strict rows: table-free first sweep
-  const bool first_direct = !init && g->strict_rows && !rc.feat;
+  const bool first_direct = !init && g->strict_rows;
   int32_t done = 0;
   const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {

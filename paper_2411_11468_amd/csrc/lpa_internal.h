@@ -250,7 +250,7 @@ hipError_t launch_sweep(bool off64, int cls, const SweepArgs& a, int grid, bool 
                         hipStream_t s);
 // The first sweep from identity labels over rows with strictly increasing
 // targets: table-free kernels (every neighbour label occurs once per row).
-hipError_t launch_sweep_direct(bool off64, int cls, const SweepArgs& a, int grid,
+hipError_t launch_sweep_direct(bool off64, int cls, const SweepArgs& a, int grid, bool feat,
                                hipStream_t s);
 hipError_t launch_hub_direct(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_part(bool off64, const HubArgs& a, int grid, hipStream_t s);

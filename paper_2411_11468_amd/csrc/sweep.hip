@@ -151,6 +151,7 @@ __device__ __forceinline__ void flush_fneg(uint32_t fneg, DevStats* st) {
 template <typename OffT, int G, bool FEAT>
 __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int lane = threadIdx.x & 63;
   const int k = lane & (G - 1);
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     const unsigned long long best = group_max<G>(packed);
     uint32_t cstar = 0;
     const int32_t cur = valid ? a.C[v] : 0;
-    const bool moved = valid && decide(best, cur, a.st->pl, &cstar);
+    const bool moved = valid && decide(best, cur, pl, &cstar);
     const bool leader = valid && k == 0;
     if constexpr (FEAT) {
       // every lane takes part in the group reductions
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   __shared__ uint32_t keys_all[WAVES][SLOTS];
   __shared__ float vals_all[WAVES][SLOTS];
   if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     }
     best = wave_max_u64(best);
     uint32_t cstar = 0;
-    const bool moved = decide(best, cur, a.st->pl, &cstar);
+    const bool moved = decide(best, cur, pl, &cstar);
     if constexpr (FEAT) {
       const float second =
           __uint_as_float((uint32_t)(wave_max_u64(rp.b1 == best ? rp.b2 : rp.b1) >> 32));
@@ -335,6 +337,192 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
+// ---- one wave per vertex, next row's head loaded during the table scan ------
+// Plain variant of k_sweep_wave for the rows of 65-512 entries: the wave
+// issues the loads of its next vertex (list entry, row offsets, first 64U
+// targets and weights) before it scans and clears the current vertex's
+// table, so that those loads are in flight while the scan runs.  Labels are
+// not prefetched: they are read when the row is accumulated, as before.
+template <typename OffT, int SLOTS, int WAVES, int U>
+__global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
+  __shared__ uint32_t keys_all[WAVES][SLOTS];
+  __shared__ float vals_all[WAVES][SLOTS];
+  if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  uint32_t* keys = keys_all[wv];
+  float* vals = vals_all[wv];
+  for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const uint32_t count = a.st->active[a.cls];
+  const uint32_t stride = gridDim.x * WAVES;
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  int32_t v = 0, j[U];
+  int64_t o = 0, d = 0;
+  float wt[U];
+  auto head = [&](uint32_t it, int32_t& hv, int64_t& ho, int64_t& hd, int32_t* hj,
+                  float* hw) {
+    hv = a.active[it];
+    row_of<OffT>(a.off, hv, &ho, &hd);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = u * 64 + lane;
+      const bool has = e < hd;
+      hj[u] = has ? __builtin_nontemporal_load(&a.tgt[ho + e]) : hv;
+      hw[u] = has ? edge_weight(a.w, ho + e) : 0.0f;
+    }
+  };
+  uint32_t item = blockIdx.x * WAVES + wv;
+  if (item < count) head(item, v, o, d, j, wt);
+  while (item < count) {
+    const int32_t cur = a.C[v];
+    const uint32_t p1 = table_p1((uint32_t)d);
+    uint32_t lab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+    for (int64_t base = 64 * U; base < d; base += 64 * U) {
+      int32_t jj[U];
+      float ww[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * 64 + lane;
+        const bool has = e < d;
+        jj[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
+        ww[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.max_retries);
+    }
+    // next vertex's head, in flight during the scan below
+    const uint32_t nitem = item + stride;
+    int32_t nv = 0, nj[U];
+    int64_t no = 0, nd = 0;
+    float nw[U];
+    if (nitem < count) head(nitem, nv, no, nd, nj, nw);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned long long best = 0;
+    for (uint32_t s = lane; s < p1; s += 64) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(vals[s], kk));
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
+      }
+    }
+    best = wave_max_u64(best);
+    uint32_t cstar = 0;
+    const bool moved = decide(best, cur, pl, &cstar);
+    if (lane == 0) {
+      if (a.async_mode) {
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : cur;
+      }
+      if (moved) a.chg[v] = 1;
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    item = nitem;
+    v = nv; o = no; d = nd;
+#pragma unroll
+    for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
+// ---- G lanes per vertex, LDS table per lane group ----------------------------
+// Rows of up to 4G entries: a wave takes 64/G vertices at once, each group of
+// G lanes with a table of its own, so that four rows' label reads are in
+// flight per wave where the one-wave-per-vertex kernel has one.  G = 16 is
+// one DPP row, whose reductions stay inside the group.  Plain variant only
+// (the learned variant keeps k_sweep_wave for this class).
+template <typename OffT, int SLOTS, int G>
+__global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
+  static_assert(G == 16, "group reductions are DPP-row wide");
+  constexpr int NG = 256 / G;
+  constexpr int U = 4;
+  __shared__ uint32_t keys_all[NG][SLOTS];
+  __shared__ float vals_all[NG][SLOTS];
+  if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
+  const int tid = threadIdx.x;
+  const int gi = tid / G, k = tid & (G - 1);
+  uint32_t* keys = keys_all[gi];
+  float* vals = vals_all[gi];
+  for (int s = k; s < SLOTS; s += G) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const uint32_t count = a.st->active[a.cls];
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  // the 16 lanes of a group are active or inactive together
+  for (uint64_t item = (uint64_t)blockIdx.x * NG + gi; item < count;
+       item += (uint64_t)gridDim.x * NG) {
+    const int32_t v = a.active[item];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    const int32_t cur = a.C[v];
+    const uint32_t p1 = table_p1((uint32_t)d);
+    for (int64_t base = 0; base < d; base += G * U) {
+      int32_t j[U];
+      float wt[U];
+      uint32_t lab[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * G + k;
+        const bool has = e < d;
+        j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
+        wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned long long best = 0;
+    for (uint32_t s = k; s < p1; s += G) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(vals[s], kk));
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
+      }
+    }
+    best = row16_max_u64(best);
+    uint32_t cstar = 0;
+    const bool moved = decide(best, cur, pl, &cstar);
+    if (k == 0) {
+      if (a.async_mode) {
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : cur;
+      }
+      if (moved) a.chg[v] = 1;
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
 // ---- one workgroup per vertex, LDS table per workgroup ---------------------
 template <typename OffT, int SLOTS, int BT, int U, bool FEAT>
 __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
@@ -346,6 +534,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
   __shared__ uint32_t redc[FEAT ? NW : 1];
   __shared__ float redk[FEAT ? NW : 1];
   if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -404,7 +593,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
 #pragma unroll
     for (int q = 1; q < NW; ++q) best = umax64(best, red[q]);
     uint32_t cstar = 0;
-    const bool moved = decide(best, cur, a.st->pl, &cstar);
+    const bool moved = decide(best, cur, pl, &cstar);
     if constexpr (FEAT) {
       const unsigned long long ws = wave_max_u64(rp.b1 == best ? rp.b2 : rp.b1);
       const unsigned long long wo = wave_max_u64(__float_as_uint(rp.own));
@@ -770,6 +959,7 @@ __global__ __launch_bounds__(BT) void k_hub_spill(HubArgs a) {
 template <typename OffT, int BT>
 __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
   if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
   const int tid = threadIdx.x;
   const uint32_t nitems = a.st->hub_items;
   for (uint32_t it = blockIdx.x * BT + tid; it < nitems; it += gridDim.x * BT) {
@@ -781,7 +971,7 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
     const int64_t e0 = (int64_t)c * a.chunk;
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
     uint32_t cstar = 0;
-    const bool moved = decide(a.hub_best[h], a.hub_old[h], a.st->pl, &cstar);
+    const bool moved = decide(a.hub_best[h], a.hub_old[h], pl, &cstar);
     if (!moved) continue;
     if (c == 0) {
       if (a.async_mode) {
@@ -807,14 +997,24 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
 // lanes per vertex (4, 16 or 64 for the wave-sized classes, a whole
 // workgroup of BT for the larger ones); hub slices fold their maximum into the
 // hub's best, decided by k_hub_fin as usual.
-template <typename OffT, int G, int BT>
+//
+// FEAT: the learned variant, which also writes each vertex's state record:
+// with every label of the row distinct and none equal to the vertex's own,
+// the record's label weights are entry weights — own label 0, best and
+// second best the two largest entries, distinct labels the non-self entries.
+template <typename OffT, int G, int BT, bool FEAT>
 __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
   __shared__ unsigned long long red[BT / 64];
+  __shared__ unsigned long long red2[FEAT ? BT / 64 : 1];
+  __shared__ float redk[FEAT ? BT / 64 : 1];
+  __shared__ uint32_t redc[FEAT ? BT / 64 : 1];
   if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const int l = a.st->iter;
   const int tid = threadIdx.x, lane = tid & 63;
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
-  uint32_t my_changed = 0;
+  uint32_t my_changed = 0, my_fneg = 0;
   constexpr int kPer = (G >= 64) ? 1 : 64 / G;        // vertices per wave step
   const int k = (G >= 64) ? ((G == 64) ? lane : tid) : (lane & (G - 1));
   const uint64_t nsteps_wave = (G > 64) ? 1 : (uint64_t)(BT / 64);
@@ -827,11 +1027,24 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     const int32_t v = a.inv ? a.inv[vi] : vi;            // caller's id = its label
     int64_t o = 0, d = 0;
     if (valid) row_of<OffT>(a.uoff, v, &o, &d);
-    unsigned long long best = 0;
+    unsigned long long best = 0, b2 = 0;  // this lane's two largest entries
+    float K = 0.0f;
+    uint32_t nd = 0;
     for (int64_t e = k; e < d; e += G) {
       const int32_t j = __builtin_nontemporal_load(&a.utgt[o + e]);
-      if (j != v) best = umax64(best, pack_key(edge_weight(a.uw, o + e), (uint32_t)j));
+      if (j != v) {
+        const float wj = edge_weight(a.uw, o + e);
+        const unsigned long long pk = pack_key(wj, (uint32_t)j);
+        if constexpr (FEAT) {
+          if (pk > best) { b2 = best; best = pk; } else if (pk > b2) { b2 = pk; }
+          K += wj;
+          ++nd;
+        } else {
+          best = umax64(best, pk);
+        }
+      }
     }
+    const unsigned long long mine = best;
     if constexpr (G == 4) best = quad_max_u64(best);
     else if constexpr (G == 16) best = row16_max_u64(best);
     else best = wave_max_u64(best);
@@ -845,8 +1058,29 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     }
     // the vertex's own label is its caller id in this sweep
     uint32_t cstar = 0;
-    const bool moved = valid && decide(best, v, a.st->pl, &cstar);
+    const bool moved = valid && decide(best, v, pl, &cstar);
     const bool leader = valid && k == 0;
+    if constexpr (FEAT) {
+      unsigned long long sc = (mine == best) ? b2 : mine;
+      if constexpr (G == 4) {
+        sc = quad_max_u64(sc); K = group_sum_f32<4>(K); nd = group_sum_u32<4>(nd);
+      } else if constexpr (G == 16) {
+        sc = row16_max_u64(sc); K = group_sum_f32<16>(K); nd = group_sum_u32<16>(nd);
+      } else {
+        sc = wave_max_u64(sc); K = wave_sum_f32(K); nd = wave_sum_u32(nd);
+      }
+      if constexpr (G > 64) {
+        if (lane == 0) { red2[tid >> 6] = sc; redk[tid >> 6] = K; redc[tid >> 6] = nd; }
+        __syncthreads();
+        sc = red2[0]; K = redk[0]; nd = redc[0];
+#pragma unroll
+        for (int q = 1; q < BT / 64; ++q) { sc = umax64(sc, red2[q]); K += redk[q]; nd += redc[q]; }
+        __syncthreads();
+      }
+      if (leader && d >= 1)
+        my_fneg += rec_write(a.rec, vi, l, K, 0.0f, __uint_as_float((uint32_t)(best >> 32)),
+                             __uint_as_float((uint32_t)(sc >> 32)), nd, (uint32_t)d, moved);
+    }
     if (leader) {
       if (a.async_mode) {
         if (moved) a.C[vi] = (int32_t)cstar;
@@ -860,6 +1094,7 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     }
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
 template <typename OffT, int BT>
@@ -911,16 +1146,16 @@ int sweep_block_threads(int cls) {
 int sweep_items_per_block(int cls) {
   switch (cls) {
     case 1: return 256 / 4;
-    case 2: return 256 / 16;
-    case 3: case 4: return kWaveWaves;
+    case 2: case 3: return 256 / 16;
+    case 4: return kWaveWaves;
     default: return 1;
   }
 }
 int sweep_direct_items_per_block(int cls) {
   switch (cls) {
     case 1: return 256 / 4;
-    case 2: return 256 / 16;
-    case 3: case 4: return 256 / 64;
+    case 2: case 3: return 256 / 16;
+    case 4: return 256 / 64;
     default: return 1;
   }
 }
@@ -929,7 +1164,7 @@ int sweep_direct_items_per_block(int cls) {
 int sweep_max_resident(int cls) {
   switch (cls) {
     case 1: case 2: return 256 * 8;   // 32 waves per CU
-    case 3: return 256 * 8;           // 4 KB LDS per workgroup
+    case 3: return 256 * 8;           // 16 KB LDS per workgroup (16 tables)
     case 4: return 256 * 4;           // 32 KB
     case 5: return 256 * 8;           // 16 KB
     case 6: return 256 * 4;           // 32 KB
@@ -946,8 +1181,18 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
   switch (cls) {
     case 1: hipLaunchKernelGGL((k_sweep_small<OffT, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_sweep_wave<OffT, 127, kWaveWaves, 1, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_sweep_wave<OffT, 1023, kWaveWaves, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3:
+      if constexpr (FEAT)
+        hipLaunchKernelGGL((k_sweep_wave<OffT, 127, kWaveWaves, 1, true>), dim3(grid), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sweep_group<OffT, 127, 16>), dim3(grid), dim3(256), 0, s, a);
+      break;
+    case 4:
+      if constexpr (FEAT)
+        hipLaunchKernelGGL((k_sweep_wave<OffT, 1023, kWaveWaves, 4, true>), dim3(grid), dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_sweep_wave_pipe<OffT, 1023, kWaveWaves, 4>), dim3(grid), dim3(256), 0, s, a);
+      break;
     case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     case 7: hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4, FEAT>), dim3(grid), dim3(kBlockMid), 0, s, a); break;
@@ -957,22 +1202,25 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
   return hipGetLastError();
 }
 
-template <typename OffT>
+template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
-    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256>), dim3(grid), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256>), dim3(grid), dim3(256), 0, s, a); break;
-    case 3: case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256>), dim3(grid), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 2: case 3:
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     case 5: case 6: case 7: case 8:
-      hipLaunchKernelGGL((k_sweep_direct<OffT, 256, 256>), dim3(grid), dim3(256), 0, s, a); break;
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 256, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_direct(bool off64, int cls, const SweepArgs& a, int grid,
+hipError_t launch_sweep_direct(bool off64, int cls, const SweepArgs& a, int grid, bool feat,
                                hipStream_t s) {
-  return off64 ? direct_t<int64_t>(cls, a, grid, s) : direct_t<int32_t>(cls, a, grid, s);
+  if (feat)
+    return off64 ? direct_t<int64_t, true>(cls, a, grid, s) : direct_t<int32_t, true>(cls, a, grid, s);
+  return off64 ? direct_t<int64_t, false>(cls, a, grid, s) : direct_t<int32_t, false>(cls, a, grid, s);
 }
 
 hipError_t launch_hub_direct(bool off64, const HubArgs& a, int grid, hipStream_t s) {

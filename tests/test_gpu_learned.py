@@ -277,3 +277,26 @@ def test_stop_after_a_skip_iteration_matches_oracle():
     _assert_same(ref, G, res)
     G.close()
     pr.close()
+
+
+def _shuffled(g, seed):
+    rng = np.random.default_rng(seed)
+    tgt, w = g.targets.copy(), g.weights.copy()
+    for v in range(g.num_vertices):
+        a, b = g.offsets[v], g.offsets[v + 1]
+        p = rng.permutation(b - a) + a
+        tgt[a:b], w[a:b] = tgt[p], w[p]
+    return graphgen.Graph(g.offsets.copy(), tgt, w, g.name + "-shuffled")
+
+
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_learned_first_sweep_records_both_paths(shuffle):
+    # sorted rows: the records of the first sweep come from the table-free
+    # kernels; shuffled rows: from the table kernels -- both equal the oracle
+    g = graphgen.rmat_graph(12, 6, "int8")
+    if shuffle:
+        g = _shuffled(g, 3)
+    ref, G, pr, res = _learned_pair(g, SMALL_TUNING, P_GAIN, fn_bound=1.0)
+    _assert_same(ref, G, res)
+    G.close()
+    pr.close()
