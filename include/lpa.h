@@ -441,7 +441,8 @@ lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q);
  * entry's target and then its neighbour's label, in the order and vertex
  * numbering the sweeps use (the internal order when the handle has one),
  * averaged over reps passes after one warm-up.  Resets the handle's labels
- * to the plain start (labels = ids); a later lpa_run starts afresh anyway.
+ * and flags to the plain start (labels = ids, all flagged); a later lpa_run
+ * starts afresh anyway.
  * Errors: LPA_ERR_INVALID (NULL, reps < 1), LPA_ERR_OOM, LPA_ERR_HIP.
  */
 lpa_status lpa_label_read_rate(lpa_graph g, int32_t reps, double* reads_per_s);
@@ -457,7 +458,10 @@ lpa_status lpa_graph_classes(lpa_graph g, int64_t* counts);
  * or device memory): 1 = the vertex was marked unprocessed by a neighbour's
  * change and would be processed in a further iteration, 0 = not flagged.
  * Used to check an asynchronous run: every vertex that is not flagged holds a
- * label of maximum weight (Eq. 3), unless Pick-Less refused its move.
+ * label of maximum weight (Eq. 3), unless Pick-Less refused its move.  A
+ * single-graph run does not flag after the iteration it stops on; the first
+ * lpa_get_flags after it sets those flags from the run's change marks (one
+ * pull pass), so the result is the same.
  */
 lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags);
 

@@ -76,6 +76,7 @@ struct lpa_graph_s {
   uint8_t* stage8 = nullptr;     // n bytes, flags in the caller's order
   unsigned long long* stage64 = nullptr;  // n records in the caller's order
   uint32_t* probe_sink = nullptr;         // lpa_label_read_rate
+  bool flags_pending = false;  // the last run left its final flags to chg
   lpa_tuning tun{};
   uint8_t* cls = nullptr;
   int32_t* C = nullptr;
@@ -138,7 +139,9 @@ struct lpa_graph_s {
   // deterministic mode its next label 4 B; per change: the new label 4 B in
   // asynchronous mode (a queued hub pair 8 B in deterministic mode) and one
   // flag byte per neighbour).
-  void account(int kid, float ms, const DevStats& h, bool async_mode, bool pull) {
+  // flag_mode: 0 pushed, 1 pulled, 2 deferred to lpa_get_flags
+  void account(int kid, float ms, const DevStats& h, bool async_mode, int flag_mode) {
+    const bool pull = flag_mode == 1, push = flag_mode == 0;
     if (kid < 0 || kid >= kNumKids) return;
     lpa_kernel_profile& p = prof[kid];
     // first iteration from labels = ids: the neighbour labels are not
@@ -183,7 +186,7 @@ struct lpa_graph_s {
       }
     } else if (kid == kKidPush || kid == kKidPushHubs) {
       // per changed row: its offsets and, per entry, target read + flag byte
-      if (kid == kKidPush && !pull) {
+      if (kid == kKidPush && push) {
         unsigned long long fw = 0, ch = 0, listed = 0;
         for (int c = 0; c < kNumClasses; ++c) { fw += h.flagw[c]; ch += h.changed[c]; }
         for (int c = 1; c < kClassHub; ++c) listed += h.active[c];
@@ -737,7 +740,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   // flag the neighbours of the changed vertices: the decide kernel picks
   // push or pull from this iteration's counters, the other kernels return
   if (lpa_status e = mark(kKidDecide)) return e;
-  LPA_HIP(launch_flag_decide(g->st, g->m, o.flag_mode, s));
+  LPA_HIP(launch_flag_decide(g->st, g->m, g->n, o.flag_mode, s));
   if (lpa_status e = mark(kKidPush)) return e;
   LPA_HIP(launch_push_lists(g->off64, g->off, g->tgt, g->lists, g->chg, g->F, g->st,
                             g->push_grid, s));
@@ -834,6 +837,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   if (iters_done) *iters_done = 0;
   const int64_t n = g->n;
   if (n == 0) return LPA_OK;
+  g->flags_pending = false;
   hipStream_t s = g->stream;
   if (lpa_status e = g->ensure_history(o.max_iterations)) return e;
 
@@ -949,7 +953,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         for (int q = 0; q + 1 < nev; ++q) {
           float kms = 0.0f;
           LPA_HIP(hipEventElapsedTime(&kms, g->ev_pool[q], g->ev_pool[q + 1]));
-          g->account(g->ev_kid[q], kms, h, o.mode == LPA_MODE_ASYNC, h.pull_mode != 0);
+          g->account(g->ev_kid[q], kms, h, o.mode == LPA_MODE_ASYNC, (int)h.pull_mode);
         }
       }
       if (l < stats_cap) {
@@ -968,6 +972,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     }
   }
   if (iters_done) *iters_done = done;
+  g->flags_pending = g->st_host->flags_deferred != 0;
   g->learned_iters = o.learned ? done : 0;
   const bool dev_out = is_device_ptr(labels);
   if (g->perm) {
@@ -1202,6 +1207,19 @@ lpa_status lpa_trace(lpa_graph g, const lpa_options* opt, double sample_rate, ui
 lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags) {
   if (!g || (g->n > 0 && !flags)) return fail(LPA_ERR_INVALID, "NULL argument");
   if (g->n == 0) return LPA_OK;
+  if (g->flags_pending) {
+    // the run skipped flagging after its final iteration: pull those flags
+    // from the change bytes it left (the frontier of a next run clears them)
+    hipStream_t s = g->stream;
+    LPA_HIP(launch_flags_resume(g->st, s));
+    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, g->n, g->cls, g->chg, g->F, g->st,
+                              g->pull_grid, s));
+    if (g->H > 0)
+      LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg, g->F,
+                               g->st, s));
+    LPA_HIP(launch_flags_done(g->st, s));
+    g->flags_pending = false;
+  }
   const bool dev_out = is_device_ptr(flags);
   const uint8_t* src = g->F;
   if (g->perm) {
@@ -1235,6 +1253,7 @@ lpa_status lpa_label_read_rate(lpa_graph g, int32_t reps, double* reads_per_s) {
   }
   // labels of a plain start, so that the reads see valid ids
   LPA_HIP(launch_init(g->n, nullptr, g->inv, g->C, g->F, g->st, s));
+  g->flags_pending = false;
   LPA_HIP(launch_label_read_probe(g->tgt, g->m, g->C, g->probe_sink, kGrid, s));  // warm-up
   LPA_HIP(hipEventRecord(g->ev0, s));
   for (int32_t r = 0; r < reps; ++r)

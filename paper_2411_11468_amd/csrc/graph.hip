@@ -767,15 +767,51 @@ hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const Trac
 // (push of a quarter of the entries: 18.6 ms; pull at p near 1/2: 2.7 ms), so
 // k_flag_decide picks pull when the changed rows hold at least 1/16 of the CSR
 // entries, push otherwise; the kernels of the other way return at once.
-__global__ void k_flag_decide(DevStats* st, int64_t m, int force) {
+__global__ void k_flag_decide(DevStats* st, int64_t m, int64_t n, int force) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop) return;
-  unsigned long long fw = 0;
-  for (int c = 0; c < kNumClasses; ++c) fw += st->flagw[c];
+  unsigned long long fw = 0, changed = 0;
+  for (int c = 0; c < kNumClasses; ++c) {
+    fw += st->flagw[c];
+    changed += st->changed[c];
+  }
+  // the run stops after this iteration (k_iter_end's test, same operands):
+  // its flags matter only to a later lpa_get_flags, which sets them then
+  if (!st->batched) {
+    const bool last = (!st->pl && (double)(changed + st->skipped) < st->tol * (double)n) ||
+                      st->iter + 1 >= st->cap;
+    if (last) {
+      st->pull_mode = 2u;
+      st->flags_deferred = 1u;
+      return;
+    }
+  }
   st->pull_mode = force == 2 ? 1u : force == 1 ? 0u : (16ull * fw >= (unsigned long long)m ? 1u : 0u);
 }
 
-hipError_t launch_flag_decide(DevStats* st, int64_t m, int force, hipStream_t s) {
-  hipLaunchKernelGGL(k_flag_decide, dim3(1), dim3(64), 0, s, st, m, force);
+hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_decide, dim3(1), dim3(64), 0, s, st, m, n, force);
+  return hipGetLastError();
+}
+
+__global__ void k_flags_resume(DevStats* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->stop = 0;
+    st->pull_mode = 1u;
+  }
+}
+__global__ void k_flags_done(DevStats* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->stop = 1;
+    st->pull_mode = 2u;
+    st->flags_deferred = 0u;
+  }
+}
+hipError_t launch_flags_resume(DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_flags_resume, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_flags_done(DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_flags_done, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 
@@ -869,7 +905,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
                                                     int64_t n, const uint8_t* cls,
                                                     const uint8_t* chg, uint8_t* F,
                                                     DevStats* st) {
-  if (st->stop || !st->pull_mode) return;
+  if (st->stop || st->pull_mode != 1u) return;
   const int lane = threadIdx.x & 63;
   const int k = lane & 7;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -910,7 +946,7 @@ __global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_
                                                    const uint8_t* chg, uint8_t* F,
                                                    DevStats* st) {
   __shared__ int any;
-  if (st->stop || !st->pull_mode) return;
+  if (st->stop || st->pull_mode != 1u) return;
   unsigned long long scanned = 0;
   for (int32_t h = blockIdx.x; h < H; h += gridDim.x) {
     const int32_t v = hub_vid[h];

@@ -27,7 +27,11 @@ struct DevStats {
   unsigned long long changed[kNumClasses];      // label changes, per class
   unsigned long long flagw[kNumClasses];        // sum of degrees of changed vertices
   unsigned long long pull_scanned;              // entries read by the pull-flag kernels
-  unsigned int pull_mode;                       // 1: flags of this iteration pulled
+  unsigned int pull_mode;                       // 0: flags of this iteration pushed,
+                                                // 1: pulled, 2: deferred (the run
+                                                // stops after this iteration)
+  unsigned int flags_deferred;                  // the last iteration's flags are
+                                                // still to be set from chg
   unsigned int active[kNumClasses];             // vertices appended per class
   unsigned int hub_items;                       // hub slices queued this iteration
   unsigned int hub_bitems;                      // hub label buckets queued this iteration
@@ -232,7 +236,11 @@ hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
                                    const TraceArgs& tr, int grid, hipStream_t s);
 hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const TraceArgs& tr,
                               hipStream_t s);
-hipError_t launch_flag_decide(DevStats* st, int64_t m, int force, hipStream_t s);
+hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, hipStream_t s);
+// Deferred flags of a finished run: re-open the run control for one pull
+// pass (resume), close it again (done).
+hipError_t launch_flags_resume(DevStats* st, hipStream_t s);
+hipError_t launch_flags_done(DevStats* st, hipStream_t s);
 hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
                              const uint8_t* cls, const uint8_t* chg, uint8_t* F,
                              DevStats* st, int grid, hipStream_t s);

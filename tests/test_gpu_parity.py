@@ -346,3 +346,26 @@ def test_label_read_rate():
     E = _graph_on_gpu(graphgen.from_edges(3, []))
     assert E.label_read_rate(1) == 0.0
     E.close()
+
+
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_final_flags_are_the_neighbours_of_the_last_changes(relabel):
+    # the stop iteration's flags are set on demand by lpa_get_flags; they must
+    # be exactly the neighbours of the vertices that iteration changed
+    g = graphgen.rmat_graph(13, 8, "int8")
+    G = _graph_on_gpu(g, _tuning(relabel=relabel, **SMALL_TUNING))
+    full = G.run("det")
+    flags = G.flags().astype(bool)
+    # a second call returns the same flags
+    np.testing.assert_array_equal(G.flags().astype(bool), flags)
+    k = full.iterations
+    assert k >= 2
+    before = G.run("det", max_iterations=k - 1).labels.cpu().numpy()
+    after = full.labels.cpu().numpy()
+    changed = before != after
+    assert changed.sum() == full.stats[-1]["changed"]
+    rows = np.repeat(np.arange(g.num_vertices), np.diff(g.offsets))
+    want = np.zeros(g.num_vertices, dtype=bool)
+    np.logical_or.at(want, rows, changed[g.targets])
+    np.testing.assert_array_equal(flags, want)
+    G.close()
