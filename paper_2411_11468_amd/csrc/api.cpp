@@ -105,6 +105,8 @@ struct lpa_graph_s {
   uint32_t* part_keys = nullptr;
   float* part_vals = nullptr;
   uint32_t* boff = nullptr;
+  uint32_t* bsize = nullptr;   // per queued bucket: pairs over all slices
+  int32_t* hub_bq = nullptr;   // per hub: queue index of its bucket 0
   int32_t* hub_nch = nullptr;
   int32_t* hub_ovf = nullptr;
   int32_t* hub_lgb = nullptr;
@@ -273,6 +275,7 @@ struct lpa_graph_s {
     a.hub_slice0 = hub_slice0; a.hub_boff0 = hub_boff0;
     a.gkeys = gkeys; a.gvals = gvals; a.items = items; a.bitems = bitems;
     a.part_keys = part_keys; a.part_vals = part_vals; a.boff = boff;
+    a.bsize = bsize; a.hub_bq = hub_bq;
     a.H = H; a.chunk = tun.hub_chunk; a.async_mode = async_mode;
     a.max_retries = tun.max_retries;
     a.xcd_map = tun.xcd_local;
@@ -604,6 +607,8 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     if (lpa_status e = G->dalloc(&G->part_keys, items * (int64_t)t.hub_chunk)) return e;
     if (lpa_status e = G->dalloc(&G->part_vals, items * (int64_t)t.hub_chunk)) return e;
     if (lpa_status e = G->dalloc(&G->boff, boffs)) return e;
+    if (lpa_status e = G->dalloc(&G->bsize, bitems)) return e;
+    if (lpa_status e = G->dalloc(&G->hub_bq, G->H)) return e;
     // one resident workgroup per CU for the two LDS-table kernels (a
     // multiple of the 8 XCDs for the bucket mapping)
     G->hub_acc_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, hub_max_resident()));

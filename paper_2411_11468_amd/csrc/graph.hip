@@ -496,7 +496,9 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     for (uint32_t b = 0; b < nbk; ++b) {
       a.bitems[2 * (uint64_t)(fb + b)] = (uint32_t)h;
       a.bitems[2 * (uint64_t)(fb + b) + 1] = b;
+      a.bsize[fb + b] = 0u;
     }
+    if (nbk) a.hub_bq[h] = (int32_t)fb;
     __syncthreads();
     if (tid == 0) {
       run_s += scan_s[1023];

@@ -159,6 +159,8 @@ struct HubArgs {
   uint32_t* part_keys;             // per slice: chunk entries, grouped by bucket
   float* part_vals;
   uint32_t* boff;                  // per slice: 2^lgb + 1 bucket offsets
+  uint32_t* bsize;                 // per queued bucket: its pairs over all slices
+  int32_t* hub_bq;                 // per hub: queue index of its bucket 0
   int32_t H;
   int32_t chunk;                   // edges per slice
   int async_mode;

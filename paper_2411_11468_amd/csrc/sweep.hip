@@ -786,6 +786,11 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
       if (kk != kEmpty) atomicAdd(&hist[bucket_of(kk, lgb)], 1u);
     }
     __syncthreads();
+    // the bucket totals over all slices, which size the reduction's tables
+    const int32_t bq = a.hub_bq[h];
+    for (uint32_t b = tid; b < nb; b += BT)
+      if (hist[b]) atomicAdd(&a.bsize[bq + b], hist[b]);
+    __syncthreads();
     const uint32_t total = block_exclusive_scan<BT, kMaxB / BT>(hist, nb, wsum);
     uint32_t* bo = a.boff + a.hub_boff0[h] + (int64_t)c * (nb + 1);
     for (uint32_t b = tid; b < nb; b += BT) bo[b] = hist[b];
@@ -808,7 +813,11 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   if ((tid & 63) == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
 }
 
-template <typename OffT, int SLOTS, int BT>
+// Two instantiations share the queued buckets: the small one (SLOTS 4095,
+// several workgroups per CU) takes the buckets of at most SMALL_E pairs, the
+// large one the rest; a bucket with no pairs is skipped by both.
+constexpr uint32_t kHubSmallE = 2048;
+template <typename OffT, int SLOTS, int BT, bool LARGE>
 __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
   constexpr int kRuns = 4 * BT;  // slice runs staged per pass
   __shared__ uint32_t keys[SLOTS];
@@ -842,15 +851,9 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
     const int lgb = a.hub_lgb[h];
     const uint32_t nb1 = (1u << lgb) + 1u;
     const uint32_t* bo = a.boff + a.hub_boff0[h];
-    // entries of this bucket over all slices: sizes the table
-    uint32_t cnt = 0;
-    for (uint32_t c = tid; c < nch; c += BT) cnt += bo[c * nb1 + b + 1] - bo[c * nb1 + b];
-    cnt = wave_sum_u32(cnt);
-    if (lane == 0) wsum[tid >> 6] = cnt;
-    __syncthreads();
-    uint32_t E = 0;
-    for (int q = 0; q < BT / 64; ++q) E += wsum[q];
-    __syncthreads();
+    // pairs of this bucket over all slices (counted by k_hub_part)
+    const uint32_t E = a.bsize[it];
+    if (E == 0 || (E > kHubSmallE) != LARGE) continue;  // uniform over the workgroup
     uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
     if (p1 > a.table_cap) p1 = a.table_cap;
     const int64_t slice0 = a.hub_slice0[h];
@@ -1253,11 +1256,16 @@ hipError_t launch_hub_part(bool off64, const HubArgs& a, int grid, hipStream_t s
   return hipGetLastError();
 }
 
+// grid: workgroups of the large instantiation (one per CU); the small one
+// runs four per CU.
 hipError_t launch_hub_reduce(bool off64, const HubArgs& a, int grid, hipStream_t s) {
-  if (off64)
-    hipLaunchKernelGGL((k_hub_reduce<int64_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_hub_reduce<int32_t, kHubSlots, kHubThreads>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  if (off64) {
+    hipLaunchKernelGGL((k_hub_reduce<int64_t, 4095, 256, false>), dim3(4 * grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_hub_reduce<int64_t, kHubSlots, kHubThreads, true>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_hub_reduce<int32_t, 4095, 256, false>), dim3(4 * grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_hub_reduce<int32_t, kHubSlots, kHubThreads, true>), dim3(grid), dim3(kHubThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 
