@@ -163,7 +163,10 @@ struct lpa_graph_s {
       // own label: read, or (table-free) the caller id through inv when
       // the handle keeps an internal order
       const double own = direct ? (perm ? 4.0 : 0.0) : 4.0;
-      bytes = eb * edges + (4.0 + ob + own) * verts + (double)h.changed[c] +
+      // table-free sweep of rows up to 4 entries: internal rows, each
+      // target's caller id read from inv
+      const double ebc = eb + ((direct && c == 1 && perm) ? 4.0 : 0.0);
+      bytes = ebc * edges + (4.0 + ob + own) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
       if (acct_feat) bytes += 16.0 * verts;  // state record read and written
     } else if (kid == kKidHubPart || kid == kKidHubDirect) {

@@ -1005,7 +1005,11 @@ __global__ __launch_bounds__(BT) void k_hub_fin(HubArgs a) {
 // with every label of the row distinct and none equal to the vertex's own,
 // the record's label weights are entry weights — own label 0, best and
 // second best the two largest entries, distinct labels the non-self entries.
-template <typename OffT, int G, int BT, bool FEAT>
+// INT: read the internal row instead and take each target's label from inv
+// (rows of at most 4 entries: such a row in the caller's order costs a cache
+// line of its own, while the internal rows of the class are contiguous; for
+// longer rows the inv reads cost more than they save, measured).
+template <typename OffT, int G, int BT, bool FEAT, bool INT>
 __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
   __shared__ unsigned long long red[BT / 64];
   __shared__ unsigned long long red2[FEAT ? BT / 64 : 1];
@@ -1029,14 +1033,23 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     const int32_t vi = valid ? a.active[idx] : 0;       // internal id
     const int32_t v = a.inv ? a.inv[vi] : vi;            // caller's id = its label
     int64_t o = 0, d = 0;
-    if (valid) row_of<OffT>(a.uoff, v, &o, &d);
+    if (valid) row_of<OffT>(INT ? a.off : a.uoff, INT ? vi : v, &o, &d);
     unsigned long long best = 0, b2 = 0;  // this lane's two largest entries
     float K = 0.0f;
     uint32_t nd = 0;
     for (int64_t e = k; e < d; e += G) {
-      const int32_t j = __builtin_nontemporal_load(&a.utgt[o + e]);
-      if (j != v) {
-        const float wj = edge_weight(a.uw, o + e);
+      int32_t j;
+      bool other;
+      if constexpr (INT) {
+        const int32_t ji = __builtin_nontemporal_load(&a.tgt[o + e]);
+        other = ji != vi;
+        j = a.inv ? a.inv[ji] : ji;
+      } else {
+        j = __builtin_nontemporal_load(&a.utgt[o + e]);
+        other = j != v;
+      }
+      if (other) {
+        const float wj = edge_weight(INT ? a.w : a.uw, o + e);
         const unsigned long long pk = pack_key(wj, (uint32_t)j);
         if constexpr (FEAT) {
           if (pk > best) { b2 = best; best = pk; } else if (pk > b2) { b2 = pk; }
@@ -1208,12 +1221,12 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
 template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
-    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
     case 2: case 3:
-      hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
     case 5: case 6: case 7: case 8:
-      hipLaunchKernelGGL((k_sweep_direct<OffT, 256, 256, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 256, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
