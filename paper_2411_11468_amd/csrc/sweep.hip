@@ -641,6 +641,117 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
+// ---- one workgroup per vertex, next row's head loaded during the scan -------
+// Plain variant of k_sweep_block: as k_sweep_wave_pipe, the workgroup issues
+// the loads of its next vertex's head (the first BT*U targets and weights)
+// before the barrier that ends the current row's accumulation, so that they
+// are in flight while the table is scanned and cleared (the barriers wait on
+// LDS traffic only).
+template <typename OffT, int SLOTS, int BT, int U>
+__global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
+  constexpr int NW = BT / 64;
+  __shared__ uint32_t keys[SLOTS];
+  __shared__ float vals[SLOTS];
+  __shared__ unsigned long long red[NW];
+  if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  __syncthreads();
+  const uint32_t count = a.st->active[a.cls];
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  int32_t v = 0, j[U];
+  int64_t o = 0, d = 0;
+  float wt[U];
+  auto head = [&](uint32_t it, int32_t& hv, int64_t& ho, int64_t& hd, int32_t* hj,
+                  float* hw) {
+    hv = a.active[it];
+    row_of<OffT>(a.off, hv, &ho, &hd);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = (int64_t)u * BT + tid;
+      const bool has = e < hd;
+      hj[u] = has ? __builtin_nontemporal_load(&a.tgt[ho + e]) : hv;
+      hw[u] = has ? edge_weight(a.w, ho + e) : 0.0f;
+    }
+  };
+  uint32_t item = blockIdx.x;
+  if (item < count) head(item, v, o, d, j, wt);
+  while (item < count) {
+    // own label, read before the barriers below: in asynchronous mode thread
+    // 0 overwrites it, and every thread must reach the same move decision
+    const int32_t cur = a.C[v];
+    const uint32_t p1 = table_p1((uint32_t)d);
+    uint32_t lab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+    for (int64_t base = (int64_t)BT * U; base < d; base += (int64_t)BT * U) {
+      int32_t jj[U];
+      float ww[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * BT + tid;
+        const bool has = e < d;
+        jj[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
+        ww[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.max_retries);
+    }
+    const uint32_t nitem = item + gridDim.x;
+    int32_t nv = 0, nj[U];
+    int64_t no = 0, nd = 0;
+    float nw[U];
+    if (nitem < count) head(nitem, nv, no, nd, nj, nw);
+    __syncthreads();
+    unsigned long long best = 0;
+    for (uint32_t s = tid; s < p1; s += BT) {
+      const uint32_t kk = keys[s];
+      if (kk != kEmpty) {
+        best = umax64(best, pack_key(vals[s], kk));
+        keys[s] = kEmpty;
+        vals[s] = 0.0f;
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) red[tid >> 6] = best;
+    __syncthreads();
+    best = red[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) best = umax64(best, red[q]);
+    uint32_t cstar = 0;
+    const bool moved = decide(best, cur, pl, &cstar);
+    if (tid == 0) {
+      if (a.async_mode) {
+        if (moved) a.C[v] = (int32_t)cstar;
+      } else {
+        a.Cn[v] = moved ? (int32_t)cstar : cur;
+      }
+      if (moved) a.chg[v] = 1;
+      my_edges += (unsigned long long)d;
+      my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d : 0ull;
+    }
+    __syncthreads();  // red[] is rewritten by the next vertex
+    item = nitem;
+    v = nv; o = no; d = nd;
+#pragma unroll
+    for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
 // ---- hubs: slices reduced in LDS, partitioned by label bucket, buckets
 // reduced in LDS ----------------------------------------------------------------
 // A hub row is cut into slices of chunk entries.  k_hub_part reduces a slice
@@ -1209,10 +1320,21 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
       else
         hipLaunchKernelGGL((k_sweep_wave_pipe<OffT, 1023, kWaveWaves, 4>), dim3(grid), dim3(256), 0, s, a);
       break;
-    case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4, FEAT>), dim3(grid), dim3(kBlockMid), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_sweep_block<OffT, 16383, kBlockBig, 4, FEAT>), dim3(grid), dim3(kBlockBig), 0, s, a); break;
+    case 5:  // rows of one step: the head prefetch measured slower here
+      hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a);
+      break;
+    case 6:
+      if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4, true>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 4095, 256, 4>), dim3(grid), dim3(256), 0, s, a);
+      break;
+    case 7:
+      if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4, true>), dim3(grid), dim3(kBlockMid), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 8191, kBlockMid, 4>), dim3(grid), dim3(kBlockMid), 0, s, a);
+      break;
+    case 8:
+      if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 16383, kBlockBig, 4, true>), dim3(grid), dim3(kBlockBig), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 16383, kBlockBig, 4>), dim3(grid), dim3(kBlockBig), 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

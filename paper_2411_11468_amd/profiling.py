@@ -36,10 +36,10 @@ _NAME_RULES = [
     (r"k_sweep_group<[^,]+, 127,", "sweep_wave127"),
     (r"k_sweep_wave_pipe<[^,]+, 1023,", "sweep_wave1023"),
     (r"k_sweep_wave<[^,]+, 1023,", "sweep_wave1023"),
-    (r"k_sweep_block<[^,]+, 2047,", "sweep_block2047"),
-    (r"k_sweep_block<[^,]+, 4095,", "sweep_block4095"),
-    (r"k_sweep_block<[^,]+, 8191,", "sweep_block8191"),
-    (r"k_sweep_block<[^,]+, 16383,", "sweep_block16383"),
+    (r"k_sweep_block(_pipe)?<[^,]+, 2047,", "sweep_block2047"),
+    (r"k_sweep_block(_pipe)?<[^,]+, 4095,", "sweep_block4095"),
+    (r"k_sweep_block(_pipe)?<[^,]+, 8191,", "sweep_block8191"),
+    (r"k_sweep_block(_pipe)?<[^,]+, 16383,", "sweep_block16383"),
     # the table-free first sweep: one instantiation per lane-group width, so
     # lpa_profile's direct_wave127 + direct_wave1023 make "direct_wave" and
     # its four direct_block classes "direct_block"
