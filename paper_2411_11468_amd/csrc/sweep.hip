@@ -858,30 +858,61 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   __syncthreads();
   const uint32_t nitems = a.st->hub_items;
   unsigned long long my_edges = 0;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int32_t h = (int32_t)a.items[2 * (uint64_t)it];
-    const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
-    const int32_t v = a.hub_vid[h];
-    int64_t o, d;
-    row_of<OffT>(a.off, v, &o, &d);
-    const int64_t e0 = (int64_t)c * a.chunk;
-    const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
+  // U entries per thread in flight: targets, then their labels, then the
+  // table inserts.  The first BT*U targets of the next slice (its head) are
+  // loaded before the barrier that ends the current slice's accumulation, so
+  // that they are in flight during its partition phase.
+  constexpr int U = 4;
+  struct Head {
+    int32_t h, c, v;
+    int64_t o, e0, n;
+    int32_t j[U];
+    float wt[U];
+  };
+  auto head = [&](uint32_t it, Head& H) {
+    H.h = (int32_t)a.items[2 * (uint64_t)it];
+    H.c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    H.v = a.hub_vid[H.h];
+    int64_t d;
+    row_of<OffT>(a.off, H.v, &H.o, &d);
+    H.e0 = (int64_t)H.c * a.chunk;
+    H.n = (d - H.e0 < a.chunk) ? d - H.e0 : a.chunk;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = (int64_t)u * BT + tid;
+      const bool has = e < H.n;
+      H.j[u] = has ? __builtin_nontemporal_load(&a.tgt[H.o + H.e0 + e]) : H.v;
+      H.wt[u] = has ? edge_weight(a.w, H.o + H.e0 + e) : 0.0f;
+    }
+  };
+  Head cur{};
+  uint32_t it = blockIdx.x;
+  if (it < nitems) head(it, cur);
+  while (it < nitems) {
+    const int32_t h = cur.h, c = cur.c, v = cur.v;
+    const int64_t o = cur.o, e0 = cur.e0, n = cur.n;
     const int lgb = a.hub_lgb[h];
+    // read here, before the next head's loads are issued, so that waiting
+    // for them later does not wait for that prefetch
+    const int32_t bq = a.hub_bq[h];
+    const int64_t boff0 = a.hub_boff0[h], slice0 = a.hub_slice0[h];
     const uint32_t nb = 1u << lgb;
     for (uint32_t b = tid; b < nb; b += BT) hist[b] = 0u;
     const uint32_t p1c = table_p1((uint32_t)n);
-    // U entries per thread in flight: targets, then their labels, then the
-    // table inserts
-    constexpr int U = 4;
     for (int64_t base = 0; base < n; base += (int64_t)BT * U) {
       int32_t j[U];
       float wt[U];
+      if (base == 0) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t e = base + u * BT + tid;
-        const bool has = e < n;
-        j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e0 + e]) : v;
-        wt[u] = has ? edge_weight(a.w, o + e0 + e) : 0.0f;
+        for (int u = 0; u < U; ++u) { j[u] = cur.j[u]; wt[u] = cur.wt[u]; }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = base + u * BT + tid;
+          const bool has = e < n;
+          j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e0 + e]) : v;
+          wt[u] = has ? edge_weight(a.w, o + e0 + e) : 0.0f;
+        }
       }
       uint32_t lab[U];
 #pragma unroll
@@ -891,6 +922,9 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.max_retries);
     }
+    const uint32_t nit = it + gridDim.x;
+    Head nxt{};
+    if (nit < nitems) head(nit, nxt);
     __syncthreads();
     for (uint32_t s = tid; s < p1c; s += BT) {
       const uint32_t kk = keys[s];
@@ -898,15 +932,14 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     }
     __syncthreads();
     // the bucket totals over all slices, which size the reduction's tables
-    const int32_t bq = a.hub_bq[h];
     for (uint32_t b = tid; b < nb; b += BT)
       if (hist[b]) atomicAdd(&a.bsize[bq + b], hist[b]);
     __syncthreads();
     const uint32_t total = block_exclusive_scan<BT, kMaxB / BT>(hist, nb, wsum);
-    uint32_t* bo = a.boff + a.hub_boff0[h] + (int64_t)c * (nb + 1);
+    uint32_t* bo = a.boff + boff0 + (int64_t)c * (nb + 1);
     for (uint32_t b = tid; b < nb; b += BT) bo[b] = hist[b];
     if (tid == 0) bo[nb] = total;
-    const int64_t base = (a.hub_slice0[h] + c) * (int64_t)a.chunk;
+    const int64_t base = (slice0 + c) * (int64_t)a.chunk;
     for (uint32_t s = tid; s < p1c; s += BT) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
@@ -919,6 +952,8 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     }
     if (tid == 0) my_edges += (unsigned long long)n;
     __syncthreads();
+    it = nit;
+    cur = nxt;
   }
   const unsigned long long e = wave_sum_u64(my_edges);
   if ((tid & 63) == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
