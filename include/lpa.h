@@ -69,7 +69,10 @@ typedef enum lpa_mode {
  *   offsets       N+1 entries, offsets[0] = 0, non-decreasing, offsets[N] = M
  *   targets       M entries in [0, N); a target equal to its row is a
  *                 self-loop, skipped by the label scan
- *   weights       M finite fp32 values >= 0 (no -0.0), or NULL for all 1.0f
+ *   weights       M finite fp32 values >= 0 (no -0.0), or NULL for all 1.0f;
+ *                 an array whose values are all exactly 1.0f is recognised
+ *                 by lpa_create and treated as NULL (not read again; the
+ *                 same results)
  *   on_device     0: host arrays, copied into library-owned device memory;
  *                 1: device arrays, borrowed: the caller keeps them alive and
  *                 unchanged until lpa_destroy

@@ -429,6 +429,27 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
       return fail(LPA_ERR_INVALID, "malformed CSR:" + why);
     }
   }
+  // weights that are all 1.0f are the unit weights of a NULL array: the
+  // kernels then read none (the sums, hence every result, are the same)
+  if (G->w && m > 0) {
+    unsigned int* other = nullptr;
+    if (hipMalloc(&other, sizeof(unsigned)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LPA_ERR_OOM, "hipMalloc failed for the weight check");
+    }
+    unsigned int h = 1u;
+    hipError_t e = launch_unit_weights(G->w, m, other, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, other, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(other);
+    if (e != hipSuccess)
+      return fail(LPA_ERR_HIP, std::string("weight check: ") + hipGetErrorString(e));
+    if (h == 0u) {
+      G->w = nullptr;
+      G->uw = nullptr;
+    }
+  }
+
   // rows with strictly increasing targets: in the first sweep from identity
   // labels every neighbour then carries its own label once, so the row's
   // Eq. 3 maximum is the largest (weight, smallest id) entry -- no table

@@ -269,6 +269,23 @@ hipError_t launch_validate(bool off64, const void* off, const int32_t* tgt,
   return hipGetLastError();
 }
 
+// Any weight other than 1.0f: *other receives 1 (else the weights are unit
+// weights, and the kernels need not read them).
+__global__ void k_unit_weights(const float* w, int64_t m, unsigned int* other) {
+  bool any = false;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    any |= __float_as_uint(__builtin_nontemporal_load(&w[e])) != 0x3F800000u;
+  if (__any(any) && (threadIdx.x & 63) == 0) *other = 1u;
+}
+
+hipError_t launch_unit_weights(const float* w, int64_t m, unsigned int* other, hipStream_t s) {
+  hipError_t e = launch_fill_u32(other, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unit_weights, dim3(grid_for(m, kBT, 8192)), dim3(kBT), 0, s, w, m, other);
+  return hipGetLastError();
+}
+
 // Rows with strictly increasing targets (sorted, no repeated neighbour):
 // mark the first entry of every non-empty row, then flag any entry whose
 // successor in the same row is not larger.  bad receives 1 on a violation.

@@ -283,6 +283,9 @@ int sweep_max_resident(int cls);
 int hub_block_threads();
 int hub_max_resident();
 
+// *other = 1 if any of the m weights differs from 1.0f, else 0.
+hipError_t launch_unit_weights(const float* w, int64_t m, unsigned int* other, hipStream_t s);
+
 // One pass reading every entry's target and neighbour label (sink: grid*256).
 hipError_t launch_label_read_probe(const int32_t* tgt, int64_t m, const int32_t* C,
                                    uint32_t* sink, int grid, hipStream_t s);

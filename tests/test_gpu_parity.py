@@ -369,3 +369,32 @@ def test_final_flags_are_the_neighbours_of_the_last_changes(relabel):
     np.logical_or.at(want, rows, changed[g.targets])
     np.testing.assert_array_equal(flags, want)
     G.close()
+
+
+def test_all_ones_weights_read_as_unit_weights():
+    # an explicit array of 1.0f gives the NULL-weight run (same labels and
+    # counters, no weight bytes in the profile); one other weight does not
+    g = graphgen.rmat_graph(13, 8, "unit")
+    assert g.weights is not None and np.all(g.weights == 1.0)
+    ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+    A = _graph_on_gpu(g)
+    B = _graph_on_gpu(g, weights=False)
+    for G in (A, B):
+        G.profile_reset()
+        res = G.run("det", profile=True)
+        assert res.iterations == ref.iterations
+        np.testing.assert_array_equal(res.labels.cpu().numpy(), ref.labels)
+    pa = {p["name"]: p["bytes"] for p in A.profile()}
+    pb = {p["name"]: p["bytes"] for p in B.profile()}
+    assert pa == pb
+    A.close()
+    B.close()
+    # one undirected edge of weight 2 (both directions)
+    w = g.weights.copy()
+    rows = np.repeat(np.arange(g.num_vertices), np.diff(g.offsets))
+    e = int(np.nonzero(rows != g.targets)[0][0])
+    u, v = int(rows[e]), int(g.targets[e])
+    back = int(g.offsets[v] + np.nonzero(g.targets[g.offsets[v]:g.offsets[v + 1]] == u)[0][0])
+    w[e] = w[back] = 2.0
+    g2 = graphgen.Graph(g.offsets, g.targets, w, "one-heavy-edge")
+    assert_det_parity(g2)
