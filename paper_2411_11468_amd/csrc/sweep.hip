@@ -1183,29 +1183,36 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     unsigned long long best = 0, b2 = 0;  // this lane's two largest entries
     float K = 0.0f;
     uint32_t nd = 0;
-    for (int64_t e = k; e < d; e += G) {
-      int32_t j;
-      bool other;
-      if constexpr (INT) {
-        const int32_t ji = __builtin_nontemporal_load(&a.tgt[o + e]);
-        other = ji != vi;
-        j = a.inv ? a.inv[ji] : ji;
+    const int32_t* rt = INT ? a.tgt : a.utgt;
+    const float* rw = INT ? a.w : a.uw;
+    const int32_t self = INT ? vi : v;
+    auto take = [&](int32_t jr, float wj) {
+      if (jr == self) return;
+      const int32_t j = (INT && a.inv) ? a.inv[jr] : jr;
+      const unsigned long long pk = pack_key(wj, (uint32_t)j);
+      if constexpr (FEAT) {
+        if (pk > best) { b2 = best; best = pk; } else if (pk > b2) { b2 = pk; }
+        K += wj;
+        ++nd;
       } else {
-        j = __builtin_nontemporal_load(&a.utgt[o + e]);
-        other = j != v;
+        best = umax64(best, pk);
       }
-      if (other) {
-        const float wj = edge_weight(INT ? a.w : a.uw, o + e);
-        const unsigned long long pk = pack_key(wj, (uint32_t)j);
-        if constexpr (FEAT) {
-          if (pk > best) { b2 = best; best = pk; } else if (pk > b2) { b2 = pk; }
-          K += wj;
-          ++nd;
-        } else {
-          best = umax64(best, pk);
-        }
+    };
+    // four entries per lane in flight, then the remainder
+    constexpr int UD = 4;
+    int64_t e = k;
+    for (; e + (UD - 1) * G < d; e += UD * G) {
+      int32_t jr[UD];
+      float wj[UD];
+#pragma unroll
+      for (int u = 0; u < UD; ++u) {
+        jr[u] = __builtin_nontemporal_load(&rt[o + e + u * G]);
+        wj[u] = edge_weight(rw, o + e + u * G);
       }
+#pragma unroll
+      for (int u = 0; u < UD; ++u) take(jr[u], wj[u]);
     }
+    for (; e < d; e += G) take(__builtin_nontemporal_load(&rt[o + e]), edge_weight(rw, o + e));
     const unsigned long long mine = best;
     if constexpr (G == 4) best = quad_max_u64(best);
     else if constexpr (G == 16) best = row16_max_u64(best);
@@ -1275,7 +1282,21 @@ __global__ __launch_bounds__(BT) void k_hub_direct(HubArgs a) {
     const int64_t e0 = (int64_t)c * a.chunk;
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
     unsigned long long best = 0;
-    for (int64_t e = tid; e < n; e += BT) {
+    constexpr int UD = 4;  // entries per thread in flight
+    int64_t e = tid;
+    for (; e + (UD - 1) * BT < n; e += UD * BT) {
+      int32_t j[UD];
+      float wj[UD];
+#pragma unroll
+      for (int u = 0; u < UD; ++u) {
+        j[u] = __builtin_nontemporal_load(&a.utgt[o + e0 + e + u * BT]);
+        wj[u] = edge_weight(a.uw, o + e0 + e + u * BT);
+      }
+#pragma unroll
+      for (int u = 0; u < UD; ++u)
+        if (j[u] != v) best = umax64(best, pack_key(wj[u], (uint32_t)j[u]));
+    }
+    for (; e < n; e += BT) {
       const int32_t j = __builtin_nontemporal_load(&a.utgt[o + e0 + e]);
       if (j != v) best = umax64(best, pack_key(edge_weight(a.uw, o + e0 + e), (uint32_t)j));
     }
