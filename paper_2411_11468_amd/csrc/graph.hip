@@ -549,26 +549,48 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
   __shared__ uint32_t base[kNumClasses];
   if (st->stop) return;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t proc = 0;
   for (int64_t chunk = (int64_t)blockIdx.x * kBT * 4; chunk < n;
        chunk += (int64_t)gridDim.x * kBT * 4) {
     if (tid < kNumClasses) cnt[tid] = 0;
     __syncthreads();
+    // four consecutive vertices per thread, read and written as words
+    const int64_t v0 = chunk + (int64_t)tid * 4;
+    uint32_t f4 = 0, c4 = 0;
+    if (v0 + 3 < n) {
+      f4 = *reinterpret_cast<const uint32_t*>(F + v0);
+      c4 = *reinterpret_cast<const uint32_t*>(cls + v0);
+      *reinterpret_cast<uint32_t*>(chg_clear + v0) = 0u;
+      if (f4) *reinterpret_cast<uint32_t*>(F + v0) = 0u;
+    } else {
+      for (int q = 0; q < 4 && v0 + q < n; ++q) {
+        f4 |= (uint32_t)F[v0 + q] << (8 * q);
+        c4 |= (uint32_t)cls[v0 + q] << (8 * q);
+        chg_clear[v0 + q] = 0;
+        F[v0 + q] = 0;
+      }
+    }
     int32_t cq[4];
     uint32_t pos[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t v = chunk + (int64_t)tid * 4 + q;
-      cq[q] = -1;
-      if (v < n) chg_clear[v] = 0;
-      if (v < n && F[v]) {
-        F[v] = 0;
-        ++proc;
-        const int c = cls[v];
-        if (c != 0 && c != kClassHub) {
-          cq[q] = c;
-          pos[q] = atomicAdd(&cnt[c], 1u);
-        }
+      const bool f = ((f4 >> (8 * q)) & 0xFFu) != 0u;
+      const int c = (int)((c4 >> (8 * q)) & 0xFFu);
+      proc += f ? 1u : 0u;
+      cq[q] = (f && c != 0 && c != kClassHub) ? c : -1;
+      // one LDS atomic per class present in the wave
+      unsigned long long left = __ballot(cq[q] >= 0);
+      while (left) {
+        const int src = __ffsll((long long)left) - 1;
+        const int cc = __shfl(cq[q], src);
+        const unsigned long long m = __ballot(cq[q] == cc);
+        uint32_t b = 0;
+        if (lane == src) b = atomicAdd(&cnt[cc], (uint32_t)__popcll(m));
+        b = __shfl(b, src);
+        if (cq[q] == cc) pos[q] = b + (uint32_t)__popcll(m & lt);
+        left &= ~m;
       }
     }
     __syncthreads();
@@ -576,7 +598,7 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (cq[q] >= 0) lists.p[cq[q]][base[cq[q]] + pos[q]] = (int32_t)(chunk + (int64_t)tid * 4 + q);
+      if (cq[q] >= 0) lists.p[cq[q]][base[cq[q]] + pos[q]] = (int32_t)(v0 + q);
     __syncthreads();
   }
   // one atomic per wave for the processed count
