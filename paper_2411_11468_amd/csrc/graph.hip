@@ -952,30 +952,59 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   unsigned long long scanned = 0;
-  for (int64_t base = wave * 8; base < n; base += nwaves * 8) {
-    const int64_t v = base + (lane >> 3);
+  constexpr int kFirst = 4;  // entries a lane checks for its own vertex
+  // one vertex per lane for its first kFirst entries (most rows find a
+  // changed neighbour there); the rows left unresolved are then scanned
+  // eight lanes per row, up to eight rows at a time
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t v = base + lane;
     const bool valid = v < n && cls[v] != kClassHub;
     int64_t o = 0, d = 0;
     if (valid) {
       o = (int64_t)off[v];
       d = (int64_t)off[v + 1] - o;
     }
-    bool done = d == 0;   // the same for the 8 lanes of a vertex
+    int32_t j[kFirst];
+#pragma unroll
+    for (int u = 0; u < kFirst; ++u) j[u] = (u < d) ? tgt[o + u] : -1;
     bool found = false;
-    for (int64_t t = 0; __any(!done); t += 8) {
-      uint32_t hit = 0;
-      const int64_t e = t + k;
-      if (!done && e < d) {
-        hit = chg[tgt[o + e]];
+#pragma unroll
+    for (int u = 0; u < kFirst; ++u) {
+      if (j[u] >= 0 && !found) {
         ++scanned;
-      }
-      hit = or8(hit);
-      if (!done) {
-        if (hit) { found = true; done = true; }
-        else if (t + 8 >= d) done = true;
+        found = chg[j[u]] != 0;
       }
     }
-    if (found && k == 0) F[v] = 1;
+    if (found) F[v] = 1;
+    unsigned long long pend = __ballot(!found && d > kFirst);
+    while (pend) {
+      // the g-th pending row of this round goes to lane group g
+      const int g = lane >> 3;
+      unsigned long long m = pend;
+      for (int q = 0; q < g && m; ++q) m &= m - 1;
+      const int src = m ? __ffsll((long long)m) - 1 : -1;
+      const int sl = src < 0 ? 0 : src;
+      const int64_t pv = base + sl;
+      const int64_t po = __shfl(o, sl), pd = __shfl(d, sl);
+      bool done = src < 0;  // the same for the 8 lanes of a group
+      bool hitany = false;
+      for (int64_t t = kFirst; __any(!done); t += 8) {
+        uint32_t hit = 0;
+        const int64_t e = t + k;
+        if (!done && e < pd) {
+          hit = chg[tgt[po + e]];
+          ++scanned;
+        }
+        hit = or8(hit);
+        if (!done) {
+          if (hit) { hitany = true; done = true; }
+          else if (t + 8 >= pd) done = true;
+        }
+      }
+      if (hitany && k == 0) F[pv] = 1;
+      // drop the (up to eight) rows taken this round
+      for (int q = 0; q < 8 && pend; ++q) pend &= pend - 1;
+    }
   }
   for (int ofs = 32; ofs > 0; ofs >>= 1) scanned += __shfl_xor(scanned, ofs);
   if (lane == 0 && scanned) atomicAdd(&st->pull_scanned, scanned);
