@@ -232,6 +232,60 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
+// ---- rows of at most 4 entries: one lane per vertex -------------------------
+// Plain variant for the smallest class: each lane loads its row's (up to 4)
+// targets, weights and labels at once and sums equal labels among them in
+// registers, so a wave has 64 rows' reads in flight.
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_sweep_lane4(SweepArgs a) {
+  if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
+  const uint32_t count = a.st->active[a.cls];
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  for (uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x; idx < count;
+       idx += (uint64_t)gridDim.x * 256) {
+    const int32_t v = a.active[idx];
+    int64_t o, d;
+    row_of<OffT>(a.off, v, &o, &d);
+    int32_t j[4];
+    float wt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool has = u < d;
+      j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + u]) : v;
+      wt[u] = has ? edge_weight(a.w, o + u) : 0.0f;
+    }
+    uint32_t lab[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+    const int32_t cur = a.C[v];
+    unsigned long long best = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (lab[u] == kEmpty) continue;
+      float sum = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sum += (lab[q] == lab[u]) ? wt[q] : 0.0f;
+      best = umax64(best, pack_key(sum, lab[u]));
+    }
+    uint32_t cstar = 0;
+    const bool moved = decide(best, cur, pl, &cstar);
+    if (a.async_mode) {
+      if (moved) a.C[v] = (int32_t)cstar;
+    } else {
+      a.Cn[v] = moved ? (int32_t)cstar : cur;
+    }
+    if (moved) a.chg[v] = 1;
+    my_edges += (unsigned long long)d;
+    my_changed += moved ? 1u : 0u;
+    my_flagw += moved ? (unsigned long long)d : 0ull;
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
 // Learned variant, table kernels: per-lane partials of the record quantities
 // gathered while the table is read back (each slot holds one label).
 struct RecPartial {
@@ -1214,9 +1268,15 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     }
     for (; e < d; e += G) take(__builtin_nontemporal_load(&rt[o + e]), edge_weight(rw, o + e));
     const unsigned long long mine = best;
-    if constexpr (G == 4) best = quad_max_u64(best);
-    else if constexpr (G == 16) best = row16_max_u64(best);
-    else best = wave_max_u64(best);
+    if constexpr (G == 1) {
+      // one lane per vertex: nothing to combine
+    } else if constexpr (G == 4) {
+      best = quad_max_u64(best);
+    } else if constexpr (G == 16) {
+      best = row16_max_u64(best);
+    } else {
+      best = wave_max_u64(best);
+    }
     if constexpr (G > 64) {
       if (lane == 0) red[tid >> 6] = best;
       __syncthreads();
@@ -1231,7 +1291,9 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     const bool leader = valid && k == 0;
     if constexpr (FEAT) {
       unsigned long long sc = (mine == best) ? b2 : mine;
-      if constexpr (G == 4) {
+      if constexpr (G == 1) {
+        // the lane's own top two and sums are the row's
+      } else if constexpr (G == 4) {
         sc = quad_max_u64(sc); K = group_sum_f32<4>(K); nd = group_sum_u32<4>(nd);
       } else if constexpr (G == 16) {
         sc = row16_max_u64(sc); K = group_sum_f32<16>(K); nd = group_sum_u32<16>(nd);
@@ -1336,7 +1398,7 @@ int sweep_items_per_block(int cls) {
 }
 int sweep_direct_items_per_block(int cls) {
   switch (cls) {
-    case 1: return 256 / 4;
+    case 1: return 256;
     case 2: case 3: return 256 / 16;
     case 4: return 256 / 64;
     default: return 1;
@@ -1362,7 +1424,10 @@ int hub_max_resident() { return 256; }
 template <typename OffT, bool FEAT>
 static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
-    case 1: hipLaunchKernelGGL((k_sweep_small<OffT, 4, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 1:
+      if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_small<OffT, 4, true>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_lane4<OffT>), dim3(grid), dim3(256), 0, s, a);
+      break;
     case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     case 3:
       if constexpr (FEAT)
@@ -1399,7 +1464,7 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
 template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
-    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 1, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
     case 2: case 3:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
