@@ -1399,8 +1399,8 @@ int sweep_items_per_block(int cls) {
 int sweep_direct_items_per_block(int cls) {
   switch (cls) {
     case 1: return 256;
-    case 2: case 3: return 256 / 16;
-    case 4: return 256 / 64;
+    case 2: case 3: case 4: return 256 / 16;
+    case 5: case 6: return 256 / 64;
     default: return 1;
   }
 }
@@ -1465,10 +1465,11 @@ template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
     case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 1, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
-    case 2: case 3:
+    case 2: case 3: case 4:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
-    case 5: case 6: case 7: case 8:
+    case 5: case 6:
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
+    case 7: case 8:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 256, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
