@@ -66,6 +66,10 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+PROBE_NAMES = ("quadratic-double", "linear", "quadratic", "double")
+PROBE_SUFFIX = ("", "-probe-linear", "-probe-quadratic", "-probe-double")
+
+
 def label_ceiling(prof: list, reads_per_s: float) -> dict:
     """The table sweeps' scan rate (CSR entries per second of their summed
     kernel time) against the rate of a pass that only reads every entry's
@@ -243,6 +247,9 @@ def main() -> int:
     ap.add_argument("--mode", default=None, choices=["async", "det"])
     ap.add_argument("--cpu-budget-edges", type=int, default=300_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="hashtable probe sequence (lpa_tuning.probe): 0 quadratic-double "
+                         "(the method's), 1 linear, 2 quadratic, 3 double hashing")
     ap.add_argument("--graph-launch", action="store_true",
                     help="also time the runs replayed as captured iterations (context "
                          "field graph_launch; off by default so that a kernel trace of "
@@ -280,7 +287,9 @@ def main() -> int:
     torch.cuda.synchronize()
     upload_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    G = LpaGraph(d_off, d_tgt, d_w)
+    tun = lpa.default_tuning()
+    tun.probe = args.probe
+    G = LpaGraph(d_off, d_tgt, d_w, tuning=tun)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     log(f"uploaded in {upload_s:.1f}s; handle created in {create_s:.2f}s; classes {G.classes()}")
@@ -330,8 +339,9 @@ def main() -> int:
 
     traffic, traffic_note = None, "no counter summary for these kernel sources"
     tj = None
+    # the committed counters were taken with the default probe sequence
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}-{mode}.json")
-    if os.path.exists(tpath):
+    if args.probe == 0 and os.path.exists(tpath):
         from paper_2411_11468_amd import profiling
         with open(tpath) as f:
             tj = json.load(f)
@@ -380,8 +390,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}-{mode}", "graph": wl["desc"],
-                   "vertices": n, "edges": m, "mode": mode,
+        "config": {"workload": f"{args.workload}-{mode}" + PROBE_SUFFIX[args.probe],
+                   "graph": wl["desc"], "vertices": n, "edges": m, "mode": mode,
+                   "probe": PROBE_NAMES[args.probe],
                    "offsets": np.dtype(wl["offsets"]).name,
                    "weights": "fp32 " + ("unit" if wl["weights"] == "unit" else "integers 1..8"),
                    "tolerance": 0.05, "max_iterations": 20, "pl_period": 4,

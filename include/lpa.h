@@ -129,6 +129,11 @@ typedef struct lpa_graph_s* lpa_graph;
  *   or out stay in the caller's numbering either way; a deterministic run
  *   returns the same labels.  lpa_create_batched keeps the caller's order
  *   (relabel = 1 there is LPA_ERR_UNSUPPORTED).
+ * probe: the hashtables' probe sequence (Sec. 4.2): 0 = quadratic-double
+ *   (default: step 1, then 2*step + (key mod p2)), 1 = linear, 2 = quadratic
+ *   (step doubled on each collision), 3 = double hashing (step key mod p2);
+ *   every mode continues linearly after max_retries probes.  The same
+ *   results; for measuring the probe sequences against each other.
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -140,6 +145,7 @@ typedef struct lpa_tuning {
   int32_t xcd_local;
   int32_t hub_table_cap;
   int32_t relabel;
+  int32_t probe;
 } lpa_tuning;
 
 /*

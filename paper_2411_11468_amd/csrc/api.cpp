@@ -280,7 +280,7 @@ struct lpa_graph_s {
     a.part_keys = part_keys; a.part_vals = part_vals; a.boff = boff;
     a.bsize = bsize; a.hub_bq = hub_bq;
     a.H = H; a.chunk = tun.hub_chunk; a.async_mode = async_mode;
-    a.max_retries = tun.max_retries;
+    a.probe = ProbeCfg{tun.max_retries, tun.probe};
     a.xcd_map = tun.xcd_local;
     uint32_t cap = 16383u;
     if (tun.hub_table_cap > 0) {
@@ -365,7 +365,8 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   if (!(0 <= t.small4 && t.small4 <= 4 && t.small4 <= t.small16 && t.small16 <= 16 &&
         t.small16 <= t.wave && t.wave <= 512 && t.wave <= t.block && t.block <= 8192 &&
         t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0 &&
-        t.hub_table_cap >= 0 && t.relabel >= -1 && t.relabel <= 1))
+        t.hub_table_cap >= 0 && t.relabel >= -1 && t.relabel <= 1 && t.probe >= 0 &&
+        t.probe <= 3))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   hipStream_t s = G->stream;
   const int64_t n = G->n, m = G->m;
@@ -746,7 +747,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   a.chg = g->chg; a.st = g->st;
   a.uoff = g->uoff; a.utgt = g->utgt; a.uw = g->uw; a.inv = g->inv;
   a.async_mode = async_mode;
-  a.max_retries = g->tun.max_retries;
+  a.probe = ProbeCfg{g->tun.max_retries, g->tun.probe};
   a.rec = g->lrec;
   for (int c = kClassHub - 1; c >= 1; --c) {
     if (g->cls_count[c] == 0) continue;

@@ -108,14 +108,28 @@ __device__ __forceinline__ unsigned long long quad_max_u64(unsigned long long x)
 }
 
 // ---- hashtable probing -------------------------------------------------------
+// Probe sequences of Sec. 4.2: mode 0 quadratic-double (step 1, then
+// 2*step + (k mod p2), the method's), 1 linear (step 1), 2 quadratic (step
+// 1, doubled on each collision), 3 double hashing (step (k mod p2) mod p1, 1
+// when that is 0).  After max_retries probes every mode continues linearly,
+// which visits every slot, so an insert into a table with a free slot ends.
 // Next probe slot.  t counts probes already made.  s, step < p1; r = (k mod p2)
 // mod p1.
 __device__ __forceinline__ void probe_next(uint32_t& s, uint32_t& step, uint32_t r,
-                                           uint32_t p1, int t, int max_retries) {
-  if (t < max_retries) {
+                                           uint32_t p1, int t, ProbeCfg pc) {
+  if (t < pc.max_retries) {
+    if (pc.mode == 1) {
+      s = (s + 1u == p1) ? 0u : s + 1u;
+      return;
+    }
+    if (pc.mode == 3) {
+      s += (r == 0u) ? 1u : r;
+      if (s >= p1) s -= p1;
+      return;
+    }
     s += step;
     if (s >= p1) s -= p1;
-    step = 2u * step + r;
+    step = 2u * step + (pc.mode == 0 ? r : 0u);
     if (step >= p1) step -= p1;
     if (step >= p1) step -= p1;
   } else {
@@ -127,7 +141,7 @@ __device__ __forceinline__ void probe_next(uint32_t& s, uint32_t& step, uint32_t
 // wave or workgroup: atomic compare-and-swap claims an empty key slot, atomic
 // add accumulates the weight (Algorithm 2, shared branch).
 __device__ __forceinline__ void lds_accumulate(uint32_t* keys, float* vals, uint32_t p1,
-                                               uint32_t k, float v, int max_retries) {
+                                               uint32_t k, float v, ProbeCfg pc) {
   const uint32_t p2 = 2u * p1 + 1u;
   uint32_t s = k % p1;
   uint32_t step = 1u % p1;
@@ -144,7 +158,7 @@ __device__ __forceinline__ void lds_accumulate(uint32_t* keys, float* vals, uint
       __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       return;
     }
-    probe_next(s, step, r, p1, t, max_retries);
+    probe_next(s, step, r, p1, t, pc);
   }
 }
 
@@ -156,7 +170,7 @@ __device__ __forceinline__ void lds_accumulate(uint32_t* keys, float* vals, uint
 template <int SCOPE>
 __device__ __forceinline__ uint32_t global_accumulate(uint32_t* keys, float* vals,
                                                       uint32_t p1, uint32_t k, float v,
-                                                      int max_retries, float* after) {
+                                                      ProbeCfg pc, float* after) {
   const uint32_t p2 = 2u * p1 + 1u;
   uint32_t s = k % p1;
   uint32_t step = 1u % p1;
@@ -174,7 +188,7 @@ __device__ __forceinline__ uint32_t global_accumulate(uint32_t* keys, float* val
       *after = old + v;
       return s;
     }
-    probe_next(s, step, r, p1, t, max_retries);
+    probe_next(s, step, r, p1, t, pc);
   }
 }
 

@@ -98,6 +98,13 @@ struct TraceArgs {
   const int32_t* perm;    // caller id -> internal id
 };
 
+// Hashtable probe sequence (probe_next in lpa_device.h): mode 0..3 and the
+// probes made before the linear continuation.
+struct ProbeCfg {
+  int max_retries;
+  int mode;
+};
+
 // Everything a sweep kernel needs, passed by value.
 struct SweepArgs {
   const void* off;        // int32_t* or int64_t* (kernel template picks)
@@ -112,7 +119,7 @@ struct SweepArgs {
   DevStats* st;
   int cls;                // class index (selects st->active[cls])
   int async_mode;         // 1: write labels in place, 0: queue them
-  int max_retries;        // hybrid probes before the linear continuation
+  ProbeCfg probe;         // probe sequence and probes before the linear continuation
   unsigned long long* rec;  // learned variant: per-vertex state records
   // the caller's CSR and inv (internal id -> caller id; NULL when the two
   // orders agree), read by the table-free first sweep
@@ -164,7 +171,7 @@ struct HubArgs {
   int32_t H;
   int32_t chunk;                   // edges per slice
   int async_mode;
-  int max_retries;
+  ProbeCfg probe;
   int xcd_map;                     // 1: consecutive buckets on one XCD
   uint32_t table_cap;              // largest bucket table (2^m - 1 slots)
 };

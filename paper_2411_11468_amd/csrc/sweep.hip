@@ -344,7 +344,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
-          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
           if constexpr (FEAT) rp.K += wt[u];
         }
     }
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
       lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
     for (int64_t base = 64 * U; base < d; base += 64 * U) {
       int32_t jj[U];
       float ww[U];
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
         lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.max_retries);
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
     }
     // next vertex's head, in flight during the scan below
     const uint32_t nitem = item + stride;
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     unsigned long long best = 0;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
-          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
           if constexpr (FEAT) rp.K += wt[u];
         }
     }
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
       lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.max_retries);
+      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
     for (int64_t base = (int64_t)BT * U; base < d; base += (int64_t)BT * U) {
       int32_t jj[U];
       float ww[U];
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
         lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.max_retries);
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
     }
     const uint32_t nitem = item + gridDim.x;
     int32_t nv = 0, nj[U];
@@ -870,15 +870,15 @@ __device__ uint32_t block_exclusive_scan(uint32_t* a, uint32_t n, uint32_t* wsum
 }
 
 // lds_accumulate that gives up (returns false) when the table holds neither
-// the key nor an empty slot: after max_retries hybrid probes the linear
+// the key nor an empty slot: after max_retries probes the linear
 // continuation has visited every slot once.
 __device__ __forceinline__ bool lds_accumulate_bounded(uint32_t* keys, float* vals, uint32_t p1,
-                                                       uint32_t k, float v, int max_retries) {
+                                                       uint32_t k, float v, ProbeCfg pc) {
   const uint32_t p2 = 2u * p1 + 1u;
   uint32_t s = k % p1;
   uint32_t step = 1u % p1;
   const uint32_t r = (k % p2) % p1;
-  const int limit = max_retries + (int)p1;
+  const int limit = pc.max_retries + (int)p1;
   for (int t = 0; t < limit; ++t) {
     uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (cur == kEmpty) {
@@ -891,7 +891,7 @@ __device__ __forceinline__ bool lds_accumulate_bounded(uint32_t* keys, float* va
       __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       return true;
     }
-    probe_next(s, step, r, p1, t, max_retries);
+    probe_next(s, step, r, p1, t, pc);
   }
   return false;
 }
@@ -974,7 +974,7 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.max_retries);
+        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.probe);
     }
     const uint32_t nit = it + gridDim.x;
     Head nxt{};
@@ -1083,9 +1083,9 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
         const int64_t idx = (slice0 + c) * (int64_t)a.chunk + e;
         const uint32_t kk = a.part_keys[idx];
         const float vv = a.part_vals[idx];
-        if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.max_retries)) {
+        if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.probe)) {
           float after;
-          (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, p1g, kk, vv, a.max_retries,
+          (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, p1g, kk, vv, a.probe,
                                                             &after);
           my_spill = true;
         }

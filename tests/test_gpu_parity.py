@@ -398,3 +398,15 @@ def test_all_ones_weights_read_as_unit_weights():
     w[e] = w[back] = 2.0
     g2 = graphgen.Graph(g.offsets, g.targets, w, "one-heavy-edge")
     assert_det_parity(g2)
+
+
+@pytest.mark.parametrize("probe", [0, 1, 2, 3])
+def test_det_probe_sequences(probe):
+    # every probe sequence of Sec. 4.2 gives the same tables, hence the
+    # oracle's labels and counters, through every class and the hub paths
+    t = _tuning(**SMALL_TUNING, probe=probe)
+    assert_det_parity(graphgen.random_graph(1500, 0.25, seed=5, wmax=8), tuning=t)
+    assert_det_parity(graphgen.rmat_graph(13, 8, "int8"), tuning=t)
+    t2 = _tuning(block=1024, hub_chunk=256, hub_table_cap=63, probe=probe, max_retries=4)
+    assert_det_parity(graphgen.rmat_graph(14, 16, "int8"), tuning=t2)
+    assert_det_parity(graphgen.planted_partition_10k(1), tuning=_tuning(probe=probe))
