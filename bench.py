@@ -55,6 +55,10 @@ WORKLOADS = {
                     desc="8,192 planted-partition graphs, vertex counts log-uniform in "
                          "[256, 65536], mean degree U[8, 32], mixing U[0.1, 0.4], blocks "
                          "U[32, 256], unit weights, packed in one CSR"),
+    "lowdeg26": dict(scale=None, lattice=8192, seed=7, weights="unit", offsets=np.int32,
+                     mode="async",
+                     desc="road-like lattice 8192 x 8192 (67,108,864 vertices), each lattice "
+                          "edge kept with probability 0.525 (mean degree 2.1), row-major ids"),
     "lfr1m": dict(scale=None, seed=2000, weights="unit", offsets=np.int32, mode="det",
                   desc="LFR-like planted partitions, 10^6 vertices, power-law degrees "
                        "(exponent 2.5, mean 20, max 1000), power-law communities "
@@ -86,6 +90,8 @@ def label_ceiling(prof: list, reads_per_s: float) -> dict:
 
 def make_graph(wl: dict):
     import graphgen
+    if wl.get("lattice"):
+        return graphgen.lowdeg_graph(wl["lattice"], wl["seed"])
     if wl["scale"] is None:
         return graphgen.planted_partition_10k(wl["seed"])
     return graphgen.rmat_graph(wl["scale"], wl["seed"], wl["weights"], wl["offsets"])

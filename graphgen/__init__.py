@@ -62,6 +62,8 @@ def _load():
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_int32, vp, ctypes.POINTER(_GG)]
+        lib.gg_lattice.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_uint64, ctypes.POINTER(_GG)]
         lib.gg_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -254,6 +256,26 @@ def planted_partition_batch(num_graphs: int, seed: int, n_range=(256, 65536),
         raise RuntimeError(f"gg_sbm_batch failed ({rc})")
     off, tgt = _take(gg, np.int64)
     return Graph(off, tgt, unit_weights(tgt.shape[0]), f"batch{num_graphs}"), v_off
+
+
+def lattice(rows: int, cols: int, keep: float, seed: int, offset_dtype=np.int32):
+    """Road-like lattice: grid vertices r*cols + c, each right and down lattice
+    edge kept with probability keep (mean degree 4*keep)."""
+    gg = _GG()
+    rc = _load().gg_lattice(int(rows), int(cols), float(keep), int(seed), ctypes.byref(gg))
+    if rc != 0:
+        raise RuntimeError(f"gg_lattice failed ({rc})")
+    return _take(gg, offset_dtype)
+
+
+def lowdeg_graph(side: int, seed: int, keep: float = 0.525, offset_dtype=None) -> Graph:
+    """Low-degree road-like workload: a side x side lattice with each edge kept
+    with probability 0.525 (mean degree 2.1, as the road and k-mer graphs of
+    the paper's Table 1), row-major ids, unit weights."""
+    if offset_dtype is None:
+        offset_dtype = np.int32 if 4 * side * side < 2 ** 31 else np.int64
+    off, tgt = lattice(side, side, keep, seed, offset_dtype)
+    return Graph(off, tgt, unit_weights(tgt.shape[0]), f"lattice{side}")
 
 
 def lfr_graph(n: int, seed: int, mu: float | None = None, tau1: float = 2.5,

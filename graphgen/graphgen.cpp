@@ -577,6 +577,58 @@ int gg_lfr(int64_t n, uint64_t seed, double tau1, double mean_deg, double kmax, 
 
 // Symmetric integer weights: w(u,v) = 1 + (h(min(u,v), max(u,v)) mod wmax)
 // where h is the first Philox word of counter (min, max) under the seed.
+// Road-like lattice: vertex (r, c) of a rows x cols grid has id r*cols + c;
+// each lattice edge -- right (r, c)-(r, c+1) and down (r, c)-(r+1, c) --
+// exists with probability keep, drawn from the edge's own counter.  Rows
+// come out sorted (up, left, right, down neighbours in id order).
+static inline bool gg_lattice_edge(uint64_t u, uint32_t dir, double keep, uint32_t k0,
+                                   uint32_t k1) {
+  const P4 x = philox((uint32_t)u, (uint32_t)(u >> 32), dir, 0x524F4144u, k0, k1);
+  return u01(x.v[0], x.v[1]) < keep;
+}
+
+int gg_lattice(int64_t rows, int64_t cols, double keep, uint64_t seed, gg_graph* out) {
+  if (rows <= 0 || cols <= 0 || !(keep >= 0.0 && keep <= 1.0)) return -1;
+  const int64_t n = rows * cols;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x4C415454u;
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!off) return -2;
+  // right(u) and down(u) decide the two edges owned by u
+  auto right = [&](int64_t u) {
+    return (u % cols) + 1 < cols && gg_lattice_edge((uint64_t)u, 0u, keep, k0, k1);
+  };
+  auto down = [&](int64_t u) {
+    return u / cols + 1 < rows && gg_lattice_edge((uint64_t)u, 1u, keep, k0, k1);
+  };
+#pragma omp parallel for schedule(static)
+  for (int64_t u = 0; u < n; ++u) {
+    int64_t d = 0;
+    if (u >= cols && down(u - cols)) ++d;
+    if (u % cols > 0 && right(u - 1)) ++d;
+    if (right(u)) ++d;
+    if (down(u)) ++d;
+    off[u + 1] = d;
+  }
+  off[0] = 0;
+  for (int64_t u = 0; u < n; ++u) off[u + 1] += off[u];
+  const int64_t m = off[n];
+  int32_t* tgt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+  if (!tgt) { free(off); return -2; }
+#pragma omp parallel for schedule(static)
+  for (int64_t u = 0; u < n; ++u) {
+    int64_t p = off[u];
+    if (u >= cols && down(u - cols)) tgt[p++] = (int32_t)(u - cols);
+    if (u % cols > 0 && right(u - 1)) tgt[p++] = (int32_t)(u - 1);
+    if (right(u)) tgt[p++] = (int32_t)(u + 1);
+    if (down(u)) tgt[p++] = (int32_t)(u + cols);
+  }
+  out->n = n;
+  out->m = m;
+  out->off = off;
+  out->tgt = tgt;
+  return 0;
+}
+
 void gg_pair_weights(int64_t n, const int64_t* off, const int32_t* tgt,
                      uint64_t seed, int32_t wmax, float* w) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32) ^ 0x57454947u;

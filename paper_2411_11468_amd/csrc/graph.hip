@@ -545,6 +545,10 @@ struct ListPtrs { int32_t* p[kNumClasses]; };
 __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
                                                   ListPtrs lists, uint8_t* chg_clear,
                                                   DevStats* st) {
+  // kWords words of four vertices per thread and block step: the block's
+  // appends cost one global atomic per class and step
+  constexpr int kWords = 4;
+  constexpr int64_t kStep = (int64_t)kBT * kWords * 4;
   __shared__ uint32_t cnt[kNumClasses];
   __shared__ uint32_t base[kNumClasses];
   if (st->stop) return;
@@ -552,53 +556,66 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
   const int lane = tid & 63;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t proc = 0;
-  for (int64_t chunk = (int64_t)blockIdx.x * kBT * 4; chunk < n;
-       chunk += (int64_t)gridDim.x * kBT * 4) {
+  for (int64_t chunk = (int64_t)blockIdx.x * kStep; chunk < n; chunk += (int64_t)gridDim.x * kStep) {
     if (tid < kNumClasses) cnt[tid] = 0;
     __syncthreads();
-    // four consecutive vertices per thread, read and written as words
-    const int64_t v0 = chunk + (int64_t)tid * 4;
-    uint32_t f4 = 0, c4 = 0;
-    if (v0 + 3 < n) {
-      f4 = *reinterpret_cast<const uint32_t*>(F + v0);
-      c4 = *reinterpret_cast<const uint32_t*>(cls + v0);
-      *reinterpret_cast<uint32_t*>(chg_clear + v0) = 0u;
-      if (f4) *reinterpret_cast<uint32_t*>(F + v0) = 0u;
-    } else {
-      for (int q = 0; q < 4 && v0 + q < n; ++q) {
-        f4 |= (uint32_t)F[v0 + q] << (8 * q);
-        c4 |= (uint32_t)cls[v0 + q] << (8 * q);
-        chg_clear[v0 + q] = 0;
-        F[v0 + q] = 0;
+    // word k of this thread holds vertices v0[k] .. v0[k] + 3 (coalesced)
+    int64_t v0[kWords];
+    uint32_t f4[kWords], c4[kWords];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) {
+      v0[k] = chunk + ((int64_t)k * kBT + tid) * 4;
+      f4[k] = 0u;
+      c4[k] = 0u;
+      if (v0[k] + 3 < n) {
+        f4[k] = *reinterpret_cast<const uint32_t*>(F + v0[k]);
+        c4[k] = *reinterpret_cast<const uint32_t*>(cls + v0[k]);
+        *reinterpret_cast<uint32_t*>(chg_clear + v0[k]) = 0u;
+        if (f4[k]) *reinterpret_cast<uint32_t*>(F + v0[k]) = 0u;
+      } else {
+        for (int q = 0; q < 4 && v0[k] + q < n; ++q) {
+          f4[k] |= (uint32_t)F[v0[k] + q] << (8 * q);
+          c4[k] |= (uint32_t)cls[v0[k] + q] << (8 * q);
+          chg_clear[v0[k] + q] = 0;
+          F[v0[k] + q] = 0;
+        }
       }
     }
-    int32_t cq[4];
-    uint32_t pos[4];
+    int8_t cq[kWords][4];
+    uint32_t pos[kWords][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool f = ((f4 >> (8 * q)) & 0xFFu) != 0u;
-      const int c = (int)((c4 >> (8 * q)) & 0xFFu);
-      proc += f ? 1u : 0u;
-      cq[q] = (f && c != 0 && c != kClassHub) ? c : -1;
-      // one LDS atomic per class present in the wave
-      unsigned long long left = __ballot(cq[q] >= 0);
-      while (left) {
-        const int src = __ffsll((long long)left) - 1;
-        const int cc = __shfl(cq[q], src);
-        const unsigned long long m = __ballot(cq[q] == cc);
-        uint32_t b = 0;
-        if (lane == src) b = atomicAdd(&cnt[cc], (uint32_t)__popcll(m));
-        b = __shfl(b, src);
-        if (cq[q] == cc) pos[q] = b + (uint32_t)__popcll(m & lt);
-        left &= ~m;
+    for (int k = 0; k < kWords; ++k) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool f = ((f4[k] >> (8 * q)) & 0xFFu) != 0u;
+        const int c = (int)((c4[k] >> (8 * q)) & 0xFFu);
+        proc += f ? 1u : 0u;
+        const int8_t cc0 = (f && c != 0 && c != kClassHub) ? (int8_t)c : (int8_t)-1;
+        cq[k][q] = cc0;
+        pos[k][q] = 0u;
+        // one LDS atomic per class present in the wave
+        unsigned long long left = __ballot(cc0 >= 0);
+        while (left) {
+          const int src = __ffsll((long long)left) - 1;
+          const int cc = __shfl((int)cc0, src);
+          const unsigned long long m = __ballot(cc0 == cc);
+          uint32_t b = 0;
+          if (lane == src) b = atomicAdd(&cnt[cc], (uint32_t)__popcll(m));
+          b = __shfl(b, src);
+          if (cc0 == cc) pos[k][q] = b + (uint32_t)__popcll(m & lt);
+          left &= ~m;
+        }
       }
     }
     __syncthreads();
     if (tid < kNumClasses) base[tid] = cnt[tid] ? atomicAdd(&st->active[tid], cnt[tid]) : 0u;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (cq[q] >= 0) lists.p[cq[q]][base[cq[q]] + pos[q]] = (int32_t)(v0 + q);
+    for (int k = 0; k < kWords; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (cq[k][q] >= 0)
+          lists.p[cq[k][q]][base[cq[k][q]] + pos[k][q]] = (int32_t)(v0[k] + q);
     __syncthreads();
   }
   // one atomic per wave for the processed count

@@ -410,3 +410,13 @@ def test_det_probe_sequences(probe):
     t2 = _tuning(block=1024, hub_chunk=256, hub_table_cap=63, probe=probe, max_retries=4)
     assert_det_parity(graphgen.rmat_graph(14, 16, "int8"), tuning=t2)
     assert_det_parity(graphgen.planted_partition_10k(1), tuning=_tuning(probe=probe))
+
+
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_det_low_degree_lattice(relabel):
+    # road-like lattice, mean degree 2.1: mostly the one-lane-per-row class,
+    # many tiny communities, degree-0 vertices
+    g = graphgen.lowdeg_graph(300, seed=7)
+    ref = assert_det_parity(g, tuning=_tuning(relabel=relabel))
+    assert ref.iterations >= 5
+    _async_invariant(g, _tuning(relabel=relabel))
