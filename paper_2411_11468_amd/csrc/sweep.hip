@@ -233,55 +233,73 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
 }
 
 // ---- rows of at most 4 entries: one lane per vertex -------------------------
-// Plain variant for the smallest class: each lane loads its row's (up to 4)
+// Plain variant for the smallest class: each lane loads its rows' (up to 4)
 // targets, weights and labels at once and sums equal labels among them in
-// registers, so a wave has 64 rows' reads in flight.
+// registers.  A lane takes two rows per step (the second one grid-stride
+// further), so that a wave has 128 rows' reads in flight.
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_sweep_lane4(SweepArgs a) {
+  constexpr int R = 2;  // rows per lane and step
   if (a.st->stop) return;
   const int pl = a.st->pl;  // fixed for the whole sweep
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0;
-  for (uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x; idx < count;
-       idx += (uint64_t)gridDim.x * 256) {
-    const int32_t v = a.active[idx];
-    int64_t o, d;
-    row_of<OffT>(a.off, v, &o, &d);
-    int32_t j[4];
-    float wt[4];
+  const uint64_t T = (uint64_t)gridDim.x * 256;
+  for (uint64_t idx0 = (uint64_t)blockIdx.x * 256 + threadIdx.x; idx0 < count; idx0 += R * T) {
+    int32_t v[R], j[R][4], cur[R];
+    int64_t o[R], d[R];
+    float wt[R][4];
+    uint32_t lab[R][4];
+    bool valid[R];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool has = u < d;
-      j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + u]) : v;
-      wt[u] = has ? edge_weight(a.w, o + u) : 0.0f;
+    for (int r = 0; r < R; ++r) {
+      valid[r] = idx0 + r * T < count;
+      v[r] = valid[r] ? a.active[idx0 + r * T] : 0;
+      o[r] = 0;
+      d[r] = 0;
+      if (valid[r]) row_of<OffT>(a.off, v[r], &o[r], &d[r]);
     }
-    uint32_t lab[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
-    const int32_t cur = a.C[v];
-    unsigned long long best = 0;
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (lab[u] == kEmpty) continue;
-      float sum = 0.0f;
+      for (int u = 0; u < 4; ++u) {
+        const bool has = u < d[r];
+        j[r][u] = has ? __builtin_nontemporal_load(&a.tgt[o[r] + u]) : v[r];
+        wt[r][u] = has ? edge_weight(a.w, o[r] + u) : 0.0f;
+      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sum += (lab[q] == lab[u]) ? wt[q] : 0.0f;
-      best = umax64(best, pack_key(sum, lab[u]));
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        lab[r][u] = (j[r][u] != v[r]) ? (id0 ? (uint32_t)j[r][u] : (uint32_t)a.C[j[r][u]]) : kEmpty;
+      cur[r] = valid[r] ? a.C[v[r]] : 0;
     }
-    uint32_t cstar = 0;
-    const bool moved = decide(best, cur, pl, &cstar);
-    if (a.async_mode) {
-      if (moved) a.C[v] = (int32_t)cstar;
-    } else {
-      a.Cn[v] = moved ? (int32_t)cstar : cur;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!valid[r]) continue;
+      unsigned long long best = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (lab[r][u] == kEmpty) continue;
+        float sum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum += (lab[r][q] == lab[r][u]) ? wt[r][q] : 0.0f;
+        best = umax64(best, pack_key(sum, lab[r][u]));
+      }
+      uint32_t cstar = 0;
+      const bool moved = decide(best, cur[r], pl, &cstar);
+      if (a.async_mode) {
+        if (moved) a.C[v[r]] = (int32_t)cstar;
+      } else {
+        a.Cn[v[r]] = moved ? (int32_t)cstar : cur[r];
+      }
+      if (moved) a.chg[v[r]] = 1;
+      my_edges += (unsigned long long)d[r];
+      my_changed += moved ? 1u : 0u;
+      my_flagw += moved ? (unsigned long long)d[r] : 0ull;
     }
-    if (moved) a.chg[v] = 1;
-    my_edges += (unsigned long long)d;
-    my_changed += moved ? 1u : 0u;
-    my_flagw += moved ? (unsigned long long)d : 0ull;
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
 }
