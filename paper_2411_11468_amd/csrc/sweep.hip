@@ -1273,6 +1273,20 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     // four entries per lane in flight, then the remainder
     constexpr int UD = 4;
     int64_t e = k;
+    if constexpr (G == 1) {
+      // rows of at most 4 entries (the smallest class): one predicated load
+      // per slot, all in flight at once
+      int32_t jr[4];
+      float wj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        jr[u] = (u < d) ? __builtin_nontemporal_load(&rt[o + u]) : self;
+        wj[u] = (u < d) ? edge_weight(rw, o + u) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) take(jr[u], wj[u]);
+      e = d;
+    }
     for (; e + (UD - 1) * G < d; e += UD * G) {
       int32_t jr[UD];
       float wj[UD];
