@@ -59,6 +59,10 @@ def _load():
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         vp, vp, vp, ctypes.c_int32, vp]
         lib.oracle_lpa_sync.restype = ctypes.c_int
+        lib.oracle_lpa_sync_cc.argtypes = [ctypes.c_int64, vp, vp, vp, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, vp, vp, vp, ctypes.c_int32, vp]
+        lib.oracle_lpa_sync_cc.restype = ctypes.c_int
         for f in (lib.oracle_modularity, lib.oracle_modularity_pairs):
             f.argtypes = [ctypes.c_int64, vp, vp, vp, vp]
             f.restype = ctypes.c_double
@@ -102,7 +106,9 @@ class SyncResult:
 
 def lpa_sync(offsets, targets, weights=None, tolerance: float = 0.05,
              max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
-             initial_labels=None) -> SyncResult:
+             initial_labels=None, cc_period: int = 0) -> SyncResult:
+    """Algorithm 1, deterministic synchronous order (lpa_oracle.c); cc_period
+    > 0 adds the Cross-Check of Sec. 4.1 in iterations l % cc_period == 0."""
     off, tgt, w = _csr(offsets, targets, weights)
     n = off.shape[0] - 1
     labels = np.empty(max(n, 0), dtype=np.int32)
@@ -110,10 +116,16 @@ def lpa_sync(offsets, targets, weights=None, tolerance: float = 0.05,
     cap = max(int(max_iterations), 0)
     stats = (IterStats * max(cap, 1))()
     iters = ctypes.c_int32(0)
-    rc = _load().oracle_lpa_sync(n, _p(off), _p(tgt), _p(w), float(tolerance), cap,
-                                 int(pl_period), int(bool(prune)), _p(init), _p(labels),
-                                 ctypes.cast(stats, ctypes.c_void_p), cap,
-                                 ctypes.cast(ctypes.byref(iters), ctypes.c_void_p))
+    if cc_period:
+        rc = _load().oracle_lpa_sync_cc(n, _p(off), _p(tgt), _p(w), float(tolerance), cap,
+                                        int(pl_period), int(cc_period), int(bool(prune)),
+                                        _p(init), _p(labels), ctypes.cast(stats, ctypes.c_void_p),
+                                        cap, ctypes.cast(ctypes.byref(iters), ctypes.c_void_p))
+    else:
+        rc = _load().oracle_lpa_sync(n, _p(off), _p(tgt), _p(w), float(tolerance), cap,
+                                     int(pl_period), int(bool(prune)), _p(init), _p(labels),
+                                     ctypes.cast(stats, ctypes.c_void_p), cap,
+                                     ctypes.cast(ctypes.byref(iters), ctypes.c_void_p))
     if rc != 0:
         raise ValueError("oracle_lpa_sync rejected its arguments")
     k = int(iters.value)

@@ -25,6 +25,14 @@
  *                        pairs (O(N^2); tiny graphs only).
  *   oracle_local_optimal per-vertex check that the current label attains the
  *                        maximum of Eq. 3 (used to judge asynchronous runs).
+ *   oracle_lpa_sync_cc   oracle_lpa_sync with the Cross-Check swap mitigation
+ *                        of Sec. 4.1 in every cc-th iteration (counting from
+ *                        0): after the sweep, the vertices that changed are
+ *                        visited in increasing id order; a change of vertex i
+ *                        to label c is kept when vertex c holds label c at
+ *                        that moment (the reverts made so far included), else
+ *                        i returns to its previous label.  A reverted vertex
+ *                        does not count as changed and flags no neighbour.
  *
  * Readings of the paper taken here (each also listed in the design notes):
  *   - ties go to the smallest label;
@@ -70,12 +78,12 @@ static double edge_w(const float* w, int64_t e) { return w ? (double)w[e] : 1.0;
  * stats: one record per performed iteration (up to stats_cap).
  * Returns 0 on success, -1 on an allocation failure or bad argument.
  */
-int oracle_lpa_sync(int64_t n, const int64_t* off, const int32_t* tgt,
-                    const float* w, double tol, int32_t cap, int32_t rho,
-                    int32_t prune, const int32_t* init, int32_t* labels,
-                    oracle_iter_stats* stats, int32_t stats_cap,
-                    int32_t* iters_done) {
-  if (n < 0 || cap < 0 || rho < 0) return -1;
+int oracle_lpa_sync_cc(int64_t n, const int64_t* off, const int32_t* tgt,
+                       const float* w, double tol, int32_t cap, int32_t rho,
+                       int32_t cc, int32_t prune, const int32_t* init, int32_t* labels,
+                       oracle_iter_stats* stats, int32_t stats_cap,
+                       int32_t* iters_done) {
+  if (n < 0 || cap < 0 || rho < 0 || cc < 0) return -1;
   *iters_done = 0;
   if (n == 0) return 0;
   int32_t* C = labels;
@@ -127,9 +135,24 @@ int oracle_lpa_sync(int64_t n, const int64_t* off, const int32_t* tgt,
       if (best != C[i] && (!pl || best < C[i])) {
         Cn[i] = best;
         ++changed;
-        for (int64_t e = off[i]; e < off[i + 1]; ++e) Fn[tgt[e]] = 1;
       }
     }
+    /* Cross-Check (Sec. 4.1): visit the changes in id order; Cn holds the
+     * labels with the reverts made so far. */
+    if (cc > 0 && l % cc == 0) {
+      for (int64_t i = 0; i < n; ++i) {
+        if (Cn[i] == C[i]) continue;
+        const int32_t c = Cn[i];
+        if (Cn[c] != c) {
+          Cn[i] = C[i];
+          --changed;
+        }
+      }
+    }
+    /* a vertex whose label changed flags every CSR neighbour */
+    for (int64_t i = 0; i < n; ++i)
+      if (Cn[i] != C[i])
+        for (int64_t e = off[i]; e < off[i + 1]; ++e) Fn[tgt[e]] = 1;
     memcpy(C, Cn, sizeof(int32_t) * (size_t)n);
     if (prune) memcpy(F, Fn, (size_t)n);
     else memset(F, 1, (size_t)n);
@@ -145,6 +168,15 @@ int oracle_lpa_sync(int64_t n, const int64_t* off, const int32_t* tgt,
   }
   free(Cn); free(F); free(Fn); free(acc); free(seen); free(touched);
   return 0;
+}
+
+int oracle_lpa_sync(int64_t n, const int64_t* off, const int32_t* tgt,
+                    const float* w, double tol, int32_t cap, int32_t rho,
+                    int32_t prune, const int32_t* init, int32_t* labels,
+                    oracle_iter_stats* stats, int32_t stats_cap,
+                    int32_t* iters_done) {
+  return oracle_lpa_sync_cc(n, off, tgt, w, tol, cap, rho, 0, prune, init, labels, stats,
+                            stats_cap, iters_done);
 }
 
 /*

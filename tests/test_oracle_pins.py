@@ -45,7 +45,7 @@ def test_hand_derived_lpa_runs(case):
     g = _graph(case["graph"])
     r = oracle.lpa_sync(g.offsets, g.targets, g.weights,
                         tolerance=case.get("tolerance", 0.05),
-                        pl_period=case["pl_period"])
+                        pl_period=case["pl_period"], cc_period=case.get("cc_period", 0))
     assert r.iterations == case["iterations"]
     assert r.labels.tolist() == case["labels"]
     for key in ("changed", "processed", "edges_scanned"):
@@ -328,3 +328,37 @@ def test_generators_shapes():
     assert r.weights.min() >= 1 and r.weights.max() <= 8
     r2 = graphgen.rmat_graph(12, 1, "int8")
     assert np.array_equal(r.targets, r2.targets) and np.array_equal(r.weights, r2.weights)
+
+
+def test_cross_check_properties():
+    # Sec. 4.1 Cross-Check: with the period 0 it is the plain run; a run with
+    # it never changes more vertices in an iteration than the changes it
+    # starts from; on the swap-prone inputs (single edge, path, K3,3) it
+    # converges where the plain run swaps until the cap
+    rng = np.random.default_rng(41)
+    for trial in range(60):
+        n = int(rng.integers(2, 40))
+        g = graphgen.random_graph(n, float(rng.uniform(0.05, 0.5)), seed=trial, wmax=3)
+        a = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=4)
+        b = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=4, cc_period=0)
+        assert np.array_equal(a.labels, b.labels) and a.stats == b.stats
+        # one Cross-Check iteration from the same labels: its kept changes are
+        # a subset of the plain iteration's changes
+        start = rng.integers(0, n, n).astype(np.int32)
+        p1 = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0, max_iterations=1,
+                             initial_labels=start, tolerance=-1.0)
+        c1 = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0, max_iterations=1,
+                             initial_labels=start, tolerance=-1.0, cc_period=1)
+        kept = c1.labels != start
+        assert np.all(c1.labels[kept] == p1.labels[kept])
+        assert c1.stats[0]["changed"] == int(kept.sum()) <= p1.stats[0]["changed"]
+        # the first kept change (lowest id) saw a leader holding its label,
+        # and every revert restored the starting label
+        moved = p1.labels != start
+        assert np.all(c1.labels[moved & ~kept] == start[moved & ~kept])
+        if kept.any():
+            i = int(np.nonzero(kept)[0][0])
+            c = int(c1.labels[i])
+            # vertex c is either below i (final) or above (its plain move)
+            lab_c = c1.labels[c] if c < i else p1.labels[c]
+            assert lab_c == c
