@@ -177,6 +177,17 @@ typedef struct lpa_tuning {
  *   learned         1: skip the vertices that the predictor attached with
  *                   lpa_set_predictor marks unchanged (see there; a project
  *                   addition, not in the paper); 0: plain run (default)
+ *   cc_period       Cross-Check (Sec. 4.1) in iterations l with
+ *                   l % cc_period == 0, counting from 0; 0 = off (default).
+ *                   After such an iteration's moves, the changed vertices are
+ *                   checked in increasing id order: a change to label c is
+ *                   kept when vertex c holds label c at that point (earlier
+ *                   reverts included), else the vertex returns to its previous
+ *                   label and counts as unchanged.  May be combined with
+ *                   pl_period (the paper's hybrid).  Single-graph runs with
+ *                   launch = LPA_LAUNCH_EAGER and learned = 0 only (else
+ *                   LPA_ERR_UNSUPPORTED): the id-order check is resolved by
+ *                   rounds the host repeats until nothing changes.
  */
 typedef enum lpa_flag_mode {
   LPA_FLAGS_AUTO = 0,
@@ -205,6 +216,7 @@ typedef struct lpa_options {
   int32_t flag_mode;
   int32_t launch;
   int32_t learned;
+  int32_t cc_period;
 } lpa_options;
 
 /* Statistics of one iteration. */

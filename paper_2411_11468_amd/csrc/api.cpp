@@ -77,6 +77,8 @@ struct lpa_graph_s {
   unsigned long long* stage64 = nullptr;  // n records in the caller's order
   uint32_t* probe_sink = nullptr;         // lpa_label_read_rate
   bool flags_pending = false;  // the last run left its final flags to chg
+  int32_t* cc_prev = nullptr;  // Cross-Check: labels before the iteration
+  uint8_t* cc_rev = nullptr;   // Cross-Check: revert decisions (zero between uses)
   lpa_tuning tun{};
   uint8_t* cls = nullptr;
   int32_t* C = nullptr;
@@ -714,12 +716,16 @@ struct RunCtx {
 };
 
 // direct: the first sweep of a run from identity labels over rows with
-// strictly increasing targets, which takes the table-free kernels.
+// strictly increasing targets, which takes the table-free kernels.  cc: a
+// Cross-Check iteration (eager launches only: its revert rounds are repeated
+// from the host until they settle).
 template <typename Mark>
 static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const RunCtx& rc,
-                                    hipStream_t s, Mark&& mark, bool direct = false) {
+                                    hipStream_t s, Mark&& mark, bool direct = false,
+                                    bool cc = false) {
   const int64_t n = g->n;
   const int async_mode = o.mode == LPA_MODE_ASYNC;
+  if (cc) LPA_HIP(launch_cc_save(g->C, g->cc_prev, n, s));
   // without pruning every vertex is processed in every iteration
   if (!o.prune) LPA_HIP(launch_arm_flags(g->F, n, g->st, s));
   const HubArgs ha = g->hub_args(async_mode);
@@ -766,6 +772,21 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   if (!async_mode) {
     if (lpa_status e = mark(kKidApply)) return e;
     LPA_HIP(launch_apply(g->st, g->lists, g->Cn, g->pend_v, g->pend_c, g->C, g->apply_grid, s));
+  }
+  if (cc) {
+    // Cross-Check: rounds until no revert decision changes (the decisions
+    // depend only on smaller ids, so at most one round per chain step)
+    if (lpa_status e = mark(-1)) return e;
+    for (int64_t round = 0;; ++round) {
+      if (round > n + 1) return fail(LPA_ERR_HIP, "Cross-Check rounds did not settle");
+      LPA_HIP(launch_cc_round(g->C, g->cc_prev, g->chg, g->cc_rev, g->perm, g->inv, n, g->st,
+                              s));
+      LPA_HIP(hipMemcpyAsync(&g->st_host->cc_moved, &g->st->cc_moved, sizeof(unsigned int),
+                             hipMemcpyDeviceToHost, s));
+      LPA_HIP(hipStreamSynchronize(s));
+      if (!g->st_host->cc_moved) break;
+    }
+    LPA_HIP(launch_cc_apply(g->C, g->cc_prev, g->chg, g->cc_rev, n, g->st, s));
   }
   // flag the neighbours of the changed vertices: the decide kernel picks
   // push or pull from this iteration's counters, the other kernels return
@@ -862,12 +883,21 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   if (o.learned != 0 && o.learned != 1) return fail(LPA_ERR_INVALID, "learned must be 0 or 1");
   if (o.learned && !g->pred)
     return fail(LPA_ERR_STATE, "learned run without a predictor (lpa_set_predictor)");
+  if (o.cc_period < 0) return fail(LPA_ERR_INVALID, "cc_period < 0");
+  if (o.cc_period > 0 && (o.launch != LPA_LAUNCH_EAGER || o.learned || trace || g->G > 0))
+    return fail(LPA_ERR_UNSUPPORTED,
+                "Cross-Check needs a single-graph, eager, plain run (cc_period > 0)");
   if ((o.learned || trace) && g->G > 0)
     return fail(LPA_ERR_UNSUPPORTED, "learned skipping and traces need a single graph");
   if (iters_done) *iters_done = 0;
   const int64_t n = g->n;
   if (n == 0) return LPA_OK;
   g->flags_pending = false;
+  if (o.cc_period > 0 && !g->cc_prev) {
+    if (lpa_status e = g->dalloc(&g->cc_prev, n)) return e;
+    if (lpa_status e = g->dalloc(&g->cc_rev, n)) return e;
+    LPA_HIP(launch_fill_u8(g->cc_rev, 0, n, g->stream));
+  }
   hipStream_t s = g->stream;
   if (lpa_status e = g->ensure_history(o.max_iterations)) return e;
 
@@ -967,7 +997,9 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         return LPA_OK;
       };
       LPA_HIP(hipEventRecord(g->ev0, s));
-      if (lpa_status e = enqueue_iteration(g, o, rc, s, mark, first_direct && l == 0)) return e;
+      const bool cc_it = o.cc_period > 0 && l % o.cc_period == 0;
+      if (lpa_status e = enqueue_iteration(g, o, rc, s, mark, first_direct && l == 0, cc_it))
+        return e;
       LPA_HIP(hipEventRecord(g->ev1, s));
       LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
       LPA_HIP(hipStreamSynchronize(s));
@@ -979,6 +1011,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
         changed += h.changed[c];
         edges += h.edges[c];
       }
+      changed -= h.reverted;  // Cross-Check reverts
       if (prof) {
         for (int q = 0; q + 1 < nev; ++q) {
           float kms = 0.0f;

@@ -112,6 +112,7 @@ __global__ void k_iter_end(DevStats* st, DevIterStats* hist, int64_t n) {
     changed += st->changed[c];
     edges += st->edges[c];
   }
+  changed -= st->reverted;  // Cross-Check reverts do not count as changes
   const int l = st->iter;
   // learned skipping: a plain iteration with predictions checks the vertices
   // predicted unchanged; too many of them changing turns skipping off
@@ -454,6 +455,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
   if (tid == 0) {
     st->processed = 0; st->pending = 0;
     st->pull_scanned = 0; st->pull_mode = 0;
+    st->reverted = 0;
     st->graphs_left = 0;
     // Pick-Less in iterations l with l mod rho == 0, counting from 0
     st->pl = (st->rho > 0 && st->iter % st->rho == 0) ? 1 : 0;
@@ -832,6 +834,7 @@ __global__ void k_flag_decide(DevStats* st, int64_t m, int64_t n, int force) {
     fw += st->flagw[c];
     changed += st->changed[c];
   }
+  changed -= st->reverted;
   // the run stops after this iteration (k_iter_end's test, same operands):
   // its flags matter only to a later lpa_get_flags, which sets them then
   if (!st->batched) {
@@ -848,6 +851,77 @@ __global__ void k_flag_decide(DevStats* st, int64_t m, int64_t n, int force) {
 
 hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, hipStream_t s) {
   hipLaunchKernelGGL(k_flag_decide, dim3(1), dim3(64), 0, s, st, m, n, force);
+  return hipGetLastError();
+}
+
+// ---- Cross-Check (Sec. 4.1) ---------------------------------------------------
+__global__ void k_cc_save(const int32_t* C, int32_t* Cp, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    Cp[i] = C[i];
+}
+
+// One round of revert decisions.  A changed vertex (caller id u, new label c)
+// reverts when vertex c, at its place in id order, does not hold label c:
+// for c < u that is c's final label (its previous label if it reverts), for
+// c > u its new label.  The decisions depend only on those of smaller ids, so
+// repeating rounds until none changes reaches the id-order result.
+__global__ void k_cc_round(const int32_t* C, const int32_t* Cp, const uint8_t* chg, uint8_t* R,
+                           const int32_t* perm, const int32_t* inv, int64_t n, DevStats* st) {
+  bool moved = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (!chg[i]) continue;
+    const int32_t c = C[i];                       // new label = a caller id
+    const int64_t u = inv ? (int64_t)inv[i] : i;  // this vertex's caller id
+    const int64_t ci = perm ? (int64_t)perm[c] : (int64_t)c;  // vertex c, internal
+    int32_t lab = C[ci];
+    if ((int64_t)c < u && chg[ci] && R[ci]) lab = Cp[ci];
+    const uint8_t r = lab != c ? 1 : 0;
+    if (r != R[i]) {
+      R[i] = r;
+      moved = true;
+    }
+  }
+  if (__any(moved) && (threadIdx.x & 63) == 0) st->cc_moved = 1u;
+}
+
+__global__ void k_cc_apply(int32_t* C, const int32_t* Cp, uint8_t* chg, uint8_t* R, int64_t n,
+                           DevStats* st) {
+  uint32_t rev = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (chg[i] && R[i]) {
+      C[i] = Cp[i];
+      chg[i] = 0;
+      R[i] = 0;
+      ++rev;
+    }
+  }
+  for (int ofs = 32; ofs > 0; ofs >>= 1) rev += __shfl_xor(rev, ofs);
+  if ((threadIdx.x & 63) == 0 && rev) atomicAdd(&st->reverted, (unsigned long long)rev);
+}
+
+__global__ void k_cc_clear_moved(DevStats* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->cc_moved = 0u;
+}
+
+hipError_t launch_cc_save(const int32_t* C, int32_t* Cp, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cc_save, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, C, Cp, n);
+  return hipGetLastError();
+}
+hipError_t launch_cc_round(const int32_t* C, const int32_t* Cp, const uint8_t* chg, uint8_t* R,
+                           const int32_t* perm, const int32_t* inv, int64_t n, DevStats* st,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_cc_clear_moved, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL(k_cc_round, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, C, Cp, chg, R,
+                     perm, inv, n, st);
+  return hipGetLastError();
+}
+hipError_t launch_cc_apply(int32_t* C, const int32_t* Cp, uint8_t* chg, uint8_t* R, int64_t n,
+                           DevStats* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_cc_apply, dim3(grid_for(n, kBT, 8192)), dim3(kBT), 0, s, C, Cp, chg, R,
+                     n, st);
   return hipGetLastError();
 }
 

@@ -32,6 +32,10 @@ struct DevStats {
                                                 // stops after this iteration)
   unsigned int flags_deferred;                  // the last iteration's flags are
                                                 // still to be set from chg
+  unsigned int cc_moved;                        // Cross-Check: a round changed a
+                                                // revert decision
+  unsigned long long reverted;                  // Cross-Check: changes reverted
+                                                // in this iteration
   unsigned int active[kNumClasses];             // vertices appended per class
   unsigned int hub_items;                       // hub slices queued this iteration
   unsigned int hub_bitems;                      // hub label buckets queued this iteration
@@ -246,6 +250,18 @@ hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
 hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const TraceArgs& tr,
                               hipStream_t s);
 hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, hipStream_t s);
+// Cross-Check (Sec. 4.1): save the labels before an iteration; one round of
+// the id-order revert decisions (st->cc_moved set when one changes; the host
+// repeats rounds until none does); apply the reverts.  perm/inv map caller
+// ids to internal ids (NULL: one order); R: one byte per vertex, zero
+// between iterations.
+hipError_t launch_cc_save(const int32_t* C, int32_t* Cp, int64_t n, hipStream_t s);
+hipError_t launch_cc_round(const int32_t* C, const int32_t* Cp, const uint8_t* chg, uint8_t* R,
+                           const int32_t* perm, const int32_t* inv, int64_t n, DevStats* st,
+                           hipStream_t s);
+hipError_t launch_cc_apply(int32_t* C, const int32_t* Cp, uint8_t* chg, uint8_t* R, int64_t n,
+                           DevStats* st, hipStream_t s);
+
 // Deferred flags of a finished run: re-open the run control for one pull
 // pass (resume), close it again (done).
 hipError_t launch_flags_resume(DevStats* st, hipStream_t s);

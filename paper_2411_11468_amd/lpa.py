@@ -60,7 +60,8 @@ class lpa_options(ctypes.Structure):
                 ("tolerance", ctypes.c_double), ("pl_period", ctypes.c_int32),
                 ("prune", ctypes.c_int32), ("initial_labels", ctypes.c_void_p),
                 ("profile", ctypes.c_int32), ("flag_mode", ctypes.c_int32),
-                ("launch", ctypes.c_int32), ("learned", ctypes.c_int32)]
+                ("launch", ctypes.c_int32), ("learned", ctypes.c_int32),
+                ("cc_period", ctypes.c_int32)]
 
 
 class lpa_learned_options(ctypes.Structure):
@@ -306,9 +307,10 @@ def lpa_create_batched(v_off, offsets, targets, weights=None, *, validate: bool 
 
 
 def _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, profile,
-             flag_mode, launch, learned=False):
+             flag_mode, launch, learned=False, cc_period=0):
     o = default_options()
     o.learned = int(bool(learned))
+    o.cc_period = int(cc_period)
     o.mode = int(mode)
     o.tolerance = float(tolerance)
     o.max_iterations = int(max_iterations)
@@ -341,12 +343,12 @@ def lpa_run_batched(handle, labels, num_graphs: int, *, mode: int = MODE_ASYNC,
 def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
             max_iterations: int = 20, pl_period: int = 4, prune: bool = True,
             initial_labels=None, profile: bool = False, flag_mode: int = FLAGS_AUTO,
-            launch: int = LAUNCH_EAGER, learned: bool = False):
+            launch: int = LAUNCH_EAGER, learned: bool = False, cc_period: int = 0):
     """Run to termination; labels is a preallocated int32 torch tensor or numpy
     array of N entries.  Returns (iterations, list of stats dicts)."""
     lib = load_library()
     o = _options(mode, tolerance, max_iterations, pl_period, prune, initial_labels, profile,
-                 flag_mode, launch, learned)
+                 flag_mode, launch, learned, cc_period)
     cap = max(int(max_iterations), 1)
     st = (lpa_iter_stats * cap)()
     it = ctypes.c_int32(0)

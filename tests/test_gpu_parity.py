@@ -82,7 +82,8 @@ def _golden_graph(spec):
 def test_det_hand_derived_cases(case):
     g = _golden_graph(case["graph"])
     G = _graph_on_gpu(g)
-    res = G.run("det", pl_period=case["pl_period"], tolerance=case.get("tolerance", 0.05))
+    res = G.run("det", pl_period=case["pl_period"], tolerance=case.get("tolerance", 0.05),
+                cc_period=case.get("cc_period", 0))
     assert res.iterations == case["iterations"]
     assert res.labels.cpu().tolist() == case["labels"]
     for key in ("changed", "processed", "edges_scanned"):
@@ -420,3 +421,34 @@ def test_det_low_degree_lattice(relabel):
     ref = assert_det_parity(g, tuning=_tuning(relabel=relabel))
     assert ref.iterations >= 5
     _async_invariant(g, _tuning(relabel=relabel))
+
+
+
+@pytest.mark.parametrize("relabel", [0, 1])
+@pytest.mark.parametrize("pl,cc", [(0, 1), (0, 2), (4, 2), (4, 3), (2, 1)])
+def test_det_cross_check(pl, cc, relabel):
+    # Cross-Check (Sec. 4.1) alone and in the hybrids with Pick-Less: labels
+    # and counters equal the oracle's id-order reading, in both vertex orders
+    t = _tuning(relabel=relabel, **SMALL_TUNING)
+    for g in (graphgen.random_graph(1500, 0.25, seed=5, wmax=8),
+              graphgen.rmat_graph(13, 8, "int8"),
+              graphgen.planted_partition_10k(1),
+              graphgen.complete_bipartite(40)):
+        assert_det_parity(g, tuning=t, pl_period=pl, cc_period=cc)
+
+
+def test_cross_check_breaks_swaps_and_rejects_unsupported_runs():
+    g = graphgen.complete_bipartite(50)
+    G = _graph_on_gpu(g)
+    plain = G.run("det", pl_period=0)
+    assert plain.iterations == 20          # swaps until the cap
+    cc = G.run("det", pl_period=0, cc_period=1)
+    assert cc.iterations < 20
+    ref = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0, cc_period=1)
+    np.testing.assert_array_equal(cc.labels.cpu().numpy(), ref.labels)
+    a = G.run("async", pl_period=0, cc_period=2)
+    assert 1 <= a.iterations <= 20
+    for kw in (dict(cc_period=-1), dict(cc_period=1, launch=lpa.LAUNCH_GRAPH)):
+        with pytest.raises(lpa.LpaError):
+            G.run("det", **kw)
+    G.close()
