@@ -45,3 +45,10 @@ def test_cache_round_trip(tmp_path):
     autotune.tuned(g.offsets, g.targets, g.weights, mode=lpa.MODE_DETERMINISTIC,
                    cache_path=path, tuner=fake)
     assert len(calls) == 2 and len(json.load(open(path))) == 2
+
+
+def test_swapstudy_variants():
+    from paper_2411_11468_amd import swapstudy
+    v = swapstudy.variants()
+    assert len(v) == 24 and len({name for name, _, _ in v}) == 24
+    assert ("PL4", 4, 0) in v and ("CC2", 0, 2) in v and ("H3,1", 3, 1) in v
