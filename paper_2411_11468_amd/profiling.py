@@ -40,13 +40,16 @@ _NAME_RULES = [
     (r"k_sweep_block(_pipe)?<[^,]+, 4095,", "sweep_block4095"),
     (r"k_sweep_block(_pipe)?<[^,]+, 8191,", "sweep_block8191"),
     (r"k_sweep_block(_pipe)?<[^,]+, 16383,", "sweep_block16383"),
-    # the table-free first sweep: one instantiation per lane-group width, so
-    # lpa_profile's direct_wave127 + direct_wave1023 make "direct_wave" and
-    # its four direct_block classes "direct_block"
-    (r"k_sweep_direct<[^,]+, 4,", "direct_small4"),
-    (r"k_sweep_direct<[^,]+, 16,", "direct_small16"),
-    (r"k_sweep_direct<[^,]+, 64,", "direct_wave"),
-    (r"k_sweep_direct<[^,]+, 256,", "direct_block"),
+    # the table-free first sweep: one instantiation per lane-group width
+    # (1 for degrees up to 4; 16 for 5..512; 64 for 513..4096; 256 above),
+    # so lpa_profile's direct_small16 + direct_wave127 + direct_wave1023 make
+    # "direct_g16", its block2047 + block4095 "direct_g64" and its
+    # block8191 + block16383 "direct_g256"
+    (r"k_sweep_direct<[^,]+, 1,", "direct_small4"),
+    (r"k_sweep_direct<[^,]+, 16,", "direct_g16"),
+    (r"k_sweep_direct<[^,]+, 64,", "direct_g64"),
+    (r"k_sweep_direct<[^,]+, 256,", "direct_g256"),
+    (r"k_sweep_lane4<", "sweep_small4"),
     (r"k_hub_direct<", "hub_direct"),
     (r"k_rl_|k_scan_chunks|k_scan_add", "relabel_build"),
     (r"k_unpermute<", "unpermute"),
@@ -78,7 +81,10 @@ def short_name(kernel: str) -> str:
     for pat, name in _NAME_RULES:
         if re.search(pat, kernel):
             return name
-    return kernel.split("(")[0][:60]
+    # anything else: the bare function name without its namespace,
+    # template arguments or the k_ prefix
+    base = re.sub(r"<.*", "", kernel.replace("(anonymous namespace)::", "").split("(")[0])
+    return re.sub(r"^(void )?(lpa::)?(k_)?", "", base)[:60]
 
 
 def source_hash() -> str:
