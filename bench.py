@@ -256,6 +256,10 @@ def main() -> int:
     ap.add_argument("--probe", type=int, default=0, choices=[0, 1, 2, 3],
                     help="hashtable probe sequence (lpa_tuning.probe): 0 quadratic-double "
                          "(the method's), 1 linear, 2 quadratic, 3 double hashing")
+    ap.add_argument("--table-values", type=int, default=0, choices=[0, 32, 64],
+                    help="hashtable values (lpa_tuning.table_values): 0 fp32 in the class "
+                         "kernels (the method's), 32 / 64 fp32 / fp64 in the ablation "
+                         "kernel set shared by both widths")
     ap.add_argument("--graph-launch", action="store_true",
                     help="also time the runs replayed as captured iterations (context "
                          "field graph_launch; off by default so that a kernel trace of "
@@ -295,6 +299,7 @@ def main() -> int:
     t0 = time.perf_counter()
     tun = lpa.default_tuning()
     tun.probe = args.probe
+    tun.table_values = args.table_values
     G = LpaGraph(d_off, d_tgt, d_w, tuning=tun)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
@@ -347,7 +352,7 @@ def main() -> int:
     tj = None
     # the committed counters were taken with the default probe sequence
     tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}-{mode}.json")
-    if args.probe == 0 and os.path.exists(tpath):
+    if args.probe == 0 and args.table_values == 0 and os.path.exists(tpath):
         from paper_2411_11468_amd import profiling
         with open(tpath) as f:
             tj = json.load(f)
@@ -394,11 +399,14 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.table_values == 64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}-{mode}" + PROBE_SUFFIX[args.probe],
+        "config": {"workload": f"{args.workload}-{mode}" + PROBE_SUFFIX[args.probe] +
+                   (f"-tv{args.table_values}" if args.table_values else ""),
                    "graph": wl["desc"], "vertices": n, "edges": m, "mode": mode,
                    "probe": PROBE_NAMES[args.probe],
+                   "table_values": (f"fp{args.table_values} (ablation kernels)"
+                                    if args.table_values else "fp32"),
                    "offsets": np.dtype(wl["offsets"]).name,
                    "weights": "fp32 " + ("unit" if wl["weights"] == "unit" else "integers 1..8"),
                    "tolerance": 0.05, "max_iterations": 20, "pl_period": 4,

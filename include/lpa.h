@@ -134,6 +134,15 @@ typedef struct lpa_graph_s* lpa_graph;
  *   (step doubled on each collision), 3 = double hashing (step key mod p2);
  *   every mode continues linearly after max_retries probes.  The same
  *   results; for measuring the probe sequences against each other.
+ * table_values: the precision of the hashtable values (Sec. 4.4 compares
+ *   32- and 64-bit).  0 (default) = 32-bit, in every class kernel above.
+ *   32 or 64 = 32- or 64-bit values in one simpler kernel set used for
+ *   both widths, so that only the width differs between the two: a wave per
+ *   row of up to `wave` entries, a workgroup per row of up to 4096 entries
+ *   (LDS tables of up to 8191 slots; `block` is capped at 4096), and for
+ *   longer rows every slice adding into the row's global-memory table; no
+ *   register-only classes and no table-free first sweep.  Not with learned
+ *   runs, traces or lpa_create_batched (LPA_ERR_UNSUPPORTED).
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -146,6 +155,7 @@ typedef struct lpa_tuning {
   int32_t hub_table_cap;
   int32_t relabel;
   int32_t probe;
+  int32_t table_values;
 } lpa_tuning;
 
 /*

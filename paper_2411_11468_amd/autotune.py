@@ -16,7 +16,7 @@ import numpy as np
 from . import lpa
 
 TUNING_FIELDS = ("small4", "small16", "wave", "block", "hub_chunk", "max_retries", "xcd_local",
-                 "hub_table_cap", "relabel", "probe")
+                 "hub_table_cap", "relabel", "probe", "table_values")
 
 
 def _round2(x: int) -> int:

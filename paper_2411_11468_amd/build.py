@@ -11,8 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblpa.so")
-SOURCES = ["api.cpp", "graph.hip", "sweep.hip", "relabel.hip", "mlp.hip", "predictor.cpp",
-           "autotune.cpp"]
+SOURCES = ["api.cpp", "graph.hip", "sweep.hip", "sweep_tv.hip", "relabel.hip", "mlp.hip",
+           "predictor.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -87,6 +87,10 @@ struct lpa_graph_s {
   int64_t cls_count[kNumClasses] = {};
   int grid[kNumClasses] = {};
   int direct_grid[kNumClasses] = {};  // table-free first sweep
+  int tv_grid[kNumClasses] = {};      // table_values 32 / 64: sweep_tv.hip
+  void* tv_gvals = nullptr;           // hubs' table values of that width
+  unsigned long long* tv_vmax = nullptr;
+  uint32_t* tv_nl = nullptr;
   int frontier_grid = 1, apply_grid = 1, hub_acc_grid = 1, hub_fin_grid = 1, pull_grid = 1,
       push_grid = 1, hub_direct_grid = 1;
   int32_t* pend_v = nullptr;
@@ -368,8 +372,11 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
         t.small16 <= t.wave && t.wave <= 512 && t.wave <= t.block && t.block <= 8192 &&
         t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0 &&
         t.hub_table_cap >= 0 && t.relabel >= -1 && t.relabel <= 1 && t.probe >= 0 &&
-        t.probe <= 3))
+        t.probe <= 3 &&
+        (t.table_values == 0 || t.table_values == 32 || t.table_values == 64)))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
+  // the ablation kernels' largest LDS table has 8191 slots (rows of <= 4096)
+  if (t.table_values != 0) G->tun.block = std::min(G->tun.block, 4096);
   hipStream_t s = G->stream;
   const int64_t n = G->n, m = G->m;
 
@@ -569,6 +576,12 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     const int64_t dper = sweep_direct_items_per_block(c);
     G->direct_grid[c] =
         (int)std::max<int64_t>(1, std::min<int64_t>((G->cls_count[c] + dper - 1) / dper, 256 * 8));
+    if (t.table_values != 0 && c <= 7) {
+      const int64_t tper = tv_items_per_block(c);
+      G->tv_grid[c] = (int)std::max<int64_t>(
+          1, std::min<int64_t>((G->cls_count[c] + tper - 1) / tper,
+                               tv_max_resident(c, t.table_values)));
+    }
   }
   G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256 * 8));
   G->learn_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 2048));
@@ -629,6 +642,20 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     if (lpa_status e = G->dalloc(&G->gvals, slots)) return e;
     LPA_HIP(launch_fill_u32(G->gkeys, kEmpty, slots, s));
     LPA_HIP(launch_fill_f32(G->gvals, 0.0f, slots, s));
+    if (t.table_values == 64) {
+      double* gv = nullptr;
+      if (lpa_status e = G->dalloc(&gv, slots)) return e;
+      LPA_HIP(launch_fill_f64(gv, 0.0, slots, s));
+      G->tv_gvals = gv;
+    } else if (t.table_values == 32) {
+      G->tv_gvals = G->gvals;
+    }
+    if (t.table_values != 0) {
+      if (lpa_status e = G->dalloc(&G->tv_vmax, G->H)) return e;
+      if (lpa_status e = G->dalloc(&G->tv_nl, G->H)) return e;
+      LPA_HIP(launch_fill_u64(G->tv_vmax, 0ull, G->H, s));
+      LPA_HIP(launch_fill_u32(G->tv_nl, 0u, G->H, s));
+    }
     if (lpa_status e = G->dalloc(&G->items, 2 * items)) return e;
     if (lpa_status e = G->dalloc(&G->bitems, 2 * bitems)) return e;
     if (lpa_status e = G->dalloc(&G->part_keys, items * (int64_t)t.hub_chunk)) return e;
@@ -725,6 +752,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
                                     bool cc = false) {
   const int64_t n = g->n;
   const int async_mode = o.mode == LPA_MODE_ASYNC;
+  const int tv = g->tun.table_values;  // 0, or the ablation kernels' value bits
   if (cc) LPA_HIP(launch_cc_save(g->C, g->cc_prev, n, s));
   // without pruning every vertex is processed in every iteration
   if (!o.prune) LPA_HIP(launch_arm_flags(g->F, n, g->st, s));
@@ -740,6 +768,12 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   if (g->H > 0 && direct) {
     if (lpa_status e = mark(kKidHubDirect)) return e;
     LPA_HIP(launch_hub_direct(g->off64, ha, g->hub_direct_grid, s));
+  } else if (g->H > 0 && tv) {
+    if (lpa_status e = mark(kKidHubPart)) return e;
+    LPA_HIP(launch_tv_hub_acc(g->off64, tv, ha, g->tv_gvals, g->hub_fin_grid, s));
+    if (lpa_status e = mark(kKidHubReduce)) return e;
+    LPA_HIP(launch_tv_hub_select(g->off64, tv, ha, g->tv_gvals, g->tv_vmax, g->tv_nl,
+                                 g->hub_fin_grid, s));
   } else if (g->H > 0) {
     if (lpa_status e = mark(kKidHubPart)) return e;
     LPA_HIP(launch_hub_part(g->off64, ha, g->hub_acc_grid, s));
@@ -762,6 +796,8 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     if (lpa_status e = mark((direct ? kKidDirect0 : kKidSweep0) + c)) return e;
     if (direct)
       LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c], rc.feat, s));
+    else if (tv)
+      LPA_HIP(launch_sweep_tv(g->off64, c, tv, a, g->tv_grid[c], s));
     else
       LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], rc.feat, s));
   }
@@ -889,6 +925,9 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
                 "Cross-Check needs a single-graph, eager, plain run (cc_period > 0)");
   if ((o.learned || trace) && g->G > 0)
     return fail(LPA_ERR_UNSUPPORTED, "learned skipping and traces need a single graph");
+  if ((o.learned || trace) && g->tun.table_values != 0)
+    return fail(LPA_ERR_UNSUPPORTED,
+                "learned skipping and traces use the fp32 class kernels (table_values 0)");
   if (iters_done) *iters_done = 0;
   const int64_t n = g->n;
   if (n == 0) return LPA_OK;
@@ -949,7 +988,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   }
 
   // a run from identity labels over strict rows: table-free first sweep
-  const bool first_direct = !init && g->strict_rows;
+  const bool first_direct = !init && g->strict_rows && g->tun.table_values == 0;
   int32_t done = 0;
   const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {
@@ -1092,6 +1131,8 @@ lpa_status lpa_create_batched(int32_t num_graphs, const int64_t* v_off, const lp
   if (tuning) tb = *tuning; else lpa_tuning_default(&tb);
   if (tb.relabel == 1)
     return fail(LPA_ERR_UNSUPPORTED, "relabel = 1 needs a single graph (lpa_create)");
+  if (tb.table_values != 0)
+    return fail(LPA_ERR_UNSUPPORTED, "table_values 32 / 64 need a single graph (lpa_create)");
   tb.relabel = 0;
   lpa_graph g = nullptr;
   if (lpa_status e = lpa_create(csr, stream, &tb, &g)) return e;

@@ -290,6 +290,19 @@ hipError_t launch_hub_part(bool off64, const HubArgs& a, int grid, hipStream_t s
 hipError_t launch_hub_reduce(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_spill(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_hub_fin(bool off64, const HubArgs& a, int grid, hipStream_t s);
+// Table-value precision ablation (sweep_tv.hip; lpa_tuning.table_values):
+// the class sweeps and the hub tables with bits = 32 or 64 bit values.
+// gvals holds the hubs' table values (float or double, at a.hub_tab[h]);
+// vmax (u64) and hub_nl (u32) hold H zeros between iterations.
+hipError_t launch_sweep_tv(bool off64, int cls, int bits, const SweepArgs& a, int grid,
+                           hipStream_t s);
+hipError_t launch_tv_hub_acc(bool off64, int bits, const HubArgs& a, void* gvals, int grid,
+                             hipStream_t s);
+hipError_t launch_tv_hub_select(bool off64, int bits, const HubArgs& a, void* gvals,
+                                unsigned long long* vmax, uint32_t* hub_nl, int grid,
+                                hipStream_t s);
+int tv_items_per_block(int cls);
+int tv_max_resident(int cls, int bits);
 // Bucket count of a hub of degree d: 2^lgb buckets of about chunk entries.
 int hub_bucket_log2(int64_t d, int chunk);
 constexpr int kHubMaxBucketLog2 = 12;   // 4096 buckets (LDS histogram of k_hub_part)

@@ -52,7 +52,8 @@ class lpa_tuning(ctypes.Structure):
                 ("wave", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("hub_chunk", ctypes.c_int32), ("max_retries", ctypes.c_int32),
                 ("xcd_local", ctypes.c_int32), ("hub_table_cap", ctypes.c_int32),
-                ("relabel", ctypes.c_int32), ("probe", ctypes.c_int32)]
+                ("relabel", ctypes.c_int32), ("probe", ctypes.c_int32),
+                ("table_values", ctypes.c_int32)]
 
 
 class lpa_options(ctypes.Structure):

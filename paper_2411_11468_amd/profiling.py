@@ -50,6 +50,10 @@ _NAME_RULES = [
     (r"k_sweep_direct<[^,]+, 64,", "direct_g64"),
     (r"k_sweep_direct<[^,]+, 256,", "direct_g256"),
     (r"k_sweep_lane4<", "sweep_small4"),
+    # the table-value ablation kernels (sweep_tv.hip)
+    (r"k_tv_wave<|k_tv_block<", "tv_sweep"),
+    (r"k_tv_hub_acc<", "tv_hub_acc"),
+    (r"k_tv_hub_(max|arg|pack)", "tv_hub_select"),
     (r"k_hub_direct<", "hub_direct"),
     (r"k_rl_|k_scan_chunks|k_scan_add", "relabel_build"),
     (r"k_unpermute<", "unpermute"),

@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     from paper_2411_11468_amd import lpa
     # sizes implied by the header's field lists on LP64
     assert ctypes.sizeof(lpa.lpa_csr) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(lpa.lpa_tuning) == 10 * 4
+    assert ctypes.sizeof(lpa.lpa_tuning) == 11 * 4
     assert ctypes.sizeof(lpa.lpa_options) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(lpa.lpa_kernel_profile) == 24 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lpa.lpa_iter_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4
@@ -57,7 +57,8 @@ def test_defaults(lib):
         (lpa.MODE_ASYNC, 20, 0.05, 4, 1)
     t = lpa.default_tuning()
     assert (t.small4, t.small16, t.wave, t.block, t.hub_chunk, t.max_retries, t.xcd_local,
-            t.hub_table_cap, t.relabel, t.probe) == (4, 16, 512, 8192, 8192, 32, 1, 0, -1, 0)
+            t.hub_table_cap, t.relabel, t.probe, t.table_values) == \
+        (4, 16, 512, 8192, 8192, 32, 1, 0, -1, 0, 0)
 
 
 def test_status_strings(lib):
