@@ -698,17 +698,28 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
     __syncthreads();
     int8_t cq[kLearnChunks];
     uint32_t pos[kLearnChunks];
+    // flags, classes and records of the wave's chunks, loaded together (the
+    // records of listed vertices reach their tile lanes by shuffles)
+    uint8_t fq[kLearnChunks], cl[kLearnChunks];
+    unsigned long long rq[kLearnChunks];
+#pragma unroll
+    for (int q = 0; q < kLearnChunks; ++q) {
+      const int64_t v = step0 + ((int64_t)wv * kLearnChunks + q) * 64 + lane;
+      fq[q] = 0;
+      cl[q] = 0;
+      rq[q] = kRecordInit;
+      if (v < n) {
+        fq[q] = F[v];
+        cl[q] = cls[v];
+        if (predict || tracing) rq[q] = rec[v];
+        chg_clear[v] = 0;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < kLearnChunks; ++q) {
       const int64_t base = step0 + ((int64_t)wv * kLearnChunks + q) * 64;
       const int64_t v = base + lane;
-      const bool valid = v < n;
-      uint8_t f = 0, c = 0;
-      if (valid) {
-        chg_clear[v] = 0;
-        f = F[v];
-        c = cls[v];
-      }
+      const uint8_t f = fq[q], c = cl[q];
       const bool cand = f && c >= 1 && c < kClassHub && (predict || tracing);
       const unsigned long long cm = __ballot(cand);
       const uint32_t ncand = __popcll(cm);
@@ -720,7 +731,10 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
         const bool has = si < ncand;
         const int src = has ? lst[si] : 0;
         const int64_t u = base + src;
-        const unsigned long long rr = has ? rec[u] : kRecordInit;
+        const uint32_t rlo = (uint32_t)__shfl((int)(uint32_t)rq[q], src);
+        const uint32_t rhi = (uint32_t)__shfl((int)(uint32_t)(rq[q] >> 32), src);
+        const unsigned long long rr =
+            has ? (((unsigned long long)rhi << 32) | rlo) : kRecordInit;
         float x[4];
         rec_features(rr, l, cap, rho, g, x);
         bool pred = false;
@@ -754,7 +768,7 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
       if (dd & 1) {
         ++npred;
         // plain iteration: mark for the false-negative count of the sweep
-        if (!skip) rec[v] |= 0x80ull << 48;
+        if (!skip) rec[v] = rq[q] | (0x80ull << 48);
       }
       if (skip) ++skipped;
       cq[q] = -1;

@@ -519,9 +519,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
 // Rows of up to 4G entries: a wave takes 64/G vertices at once, each group of
 // G lanes with a table of its own, so that four rows' label reads are in
 // flight per wave where the one-wave-per-vertex kernel has one.  G = 16 is
-// one DPP row, whose reductions stay inside the group.  Plain variant only
-// (the learned variant keeps k_sweep_wave for this class).
-template <typename OffT, int SLOTS, int G>
+// one DPP row, whose reductions stay inside the group.  FEAT: the learned
+// variant, which also reduces the record quantities over the group.
+template <typename OffT, int SLOTS, int G, bool FEAT>
 __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
   static_assert(G == 16, "group reductions are DPP-row wide");
   constexpr int NG = 256 / G;
@@ -533,13 +533,14 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int tid = threadIdx.x;
   const int gi = tid / G, k = tid & (G - 1);
+  [[maybe_unused]] const int l = a.st->iter;
   uint32_t* keys = keys_all[gi];
   float* vals = vals_all[gi];
   for (int s = k; s < SLOTS; s += G) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
-  uint32_t my_changed = 0;
+  uint32_t my_changed = 0, my_fneg = 0;
   // the 16 lanes of a group are active or inactive together
   for (uint64_t item = (uint64_t)blockIdx.x * NG + gi; item < count;
        item += (uint64_t)gridDim.x * NG) {
@@ -548,6 +549,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
     row_of<OffT>(a.off, v, &o, &d);
     const int32_t cur = a.C[v];
     const uint32_t p1 = table_p1((uint32_t)d);
+    RecPartial rp;
     for (int64_t base = 0; base < d; base += G * U) {
       int32_t j[U];
       float wt[U];
@@ -564,14 +566,19 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
+        if (lab[u] != kEmpty) {
+          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
+          if constexpr (FEAT) rp.K += wt[u];
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     unsigned long long best = 0;
     for (uint32_t s = k; s < p1; s += G) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
-        best = umax64(best, pack_key(vals[s], kk));
+        const unsigned long long pk = pack_key(vals[s], kk);
+        if constexpr (FEAT) rp.slot(pk, kk, vals[s], cur);
+        best = umax64(best, pk);
         keys[s] = kEmpty;
         vals[s] = 0.0f;
       }
@@ -579,6 +586,16 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
     best = row16_max_u64(best);
     uint32_t cstar = 0;
     const bool moved = decide(best, cur, pl, &cstar);
+    if constexpr (FEAT) {
+      const float second =
+          __uint_as_float((uint32_t)(row16_max_u64(rp.b1 == best ? rp.b2 : rp.b1) >> 32));
+      const float own = __uint_as_float((uint32_t)row16_max_u64(__float_as_uint(rp.own)));
+      const uint32_t distinct = group_sum_u32<G>(rp.distinct);
+      const float K = group_sum_f32<G>(rp.K);
+      if (k == 0)
+        my_fneg += rec_write(a.rec, v, l, K, own, __uint_as_float((uint32_t)(best >> 32)),
+                             second, distinct, (uint32_t)d, moved);
+    }
     if (k == 0) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -593,6 +610,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
 // ---- one workgroup per vertex, LDS table per workgroup ---------------------
@@ -1462,10 +1480,7 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
       break;
     case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
     case 3:
-      if constexpr (FEAT)
-        hipLaunchKernelGGL((k_sweep_wave<OffT, 127, kWaveWaves, 1, true>), dim3(grid), dim3(256), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_sweep_group<OffT, 127, 16>), dim3(grid), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_sweep_group<OffT, 127, 16, FEAT>), dim3(grid), dim3(256), 0, s, a);
       break;
     case 4:
       if constexpr (FEAT)
