@@ -583,7 +583,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
                                tv_max_resident(c, t.table_values)));
     }
   }
-  G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4095) / 4096, 256 * 8));
+  G->frontier_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 8191) / 8192, 256 * 8));
   G->learn_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 2048));
   G->apply_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256 * 8));
   G->pull_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 31) / 32, 256 * 8));

@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
                                                   DevStats* st) {
   // kWords words of four vertices per thread and block step: the block's
   // appends cost one global atomic per class and step
-  constexpr int kWords = 4;
+  constexpr int kWords = 8;
   constexpr int64_t kStep = (int64_t)kBT * kWords * 4;
   __shared__ uint32_t cnt[kNumClasses];
   __shared__ uint32_t base[kNumClasses];
@@ -620,10 +620,17 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
           lists.p[cq[k][q]][base[cq[k][q]] + pos[k][q]] = (int32_t)(v0[k] + q);
     __syncthreads();
   }
-  // one atomic per wave for the processed count
+  // one atomic per workgroup for the processed count (cnt is free after the
+  // last step's barrier; every thread of the workgroup gets here)
   uint32_t x = proc;
   for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
-  if ((tid & 63) == 0 && x) atomicAdd(&st->processed, (unsigned long long)x);
+  if ((tid & 63) == 0) cnt[tid >> 6] = x;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t = 0;
+    for (int q = 0; q < kBT / 64; ++q) t += cnt[q];
+    if (t) atomicAdd(&st->processed, (unsigned long long)t);
+  }
 }
 
 hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
@@ -1111,8 +1118,16 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
       for (int q = 0; q < 8 && pend; ++q) pend &= pend - 1;
     }
   }
+  // one atomic per workgroup
+  __shared__ unsigned long long ws[kBT / 64];
   for (int ofs = 32; ofs > 0; ofs >>= 1) scanned += __shfl_xor(scanned, ofs);
-  if (lane == 0 && scanned) atomicAdd(&st->pull_scanned, scanned);
+  if (lane == 0) ws[threadIdx.x >> 6] = scanned;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < kBT / 64; ++q) t += ws[q];
+    if (t) atomicAdd(&st->pull_scanned, t);
+  }
 }
 
 template <typename OffT>

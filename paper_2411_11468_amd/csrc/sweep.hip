@@ -55,16 +55,37 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 }
 
 
+// Adds a workgroup's counters to the iteration's: sums over each wave, then
+// over the waves in LDS, then one device atomic per counter and workgroup
+// (atomics on one address from every wave of a full grid serialise at the
+// memory side: tens of microseconds per kernel).  Every thread of the
+// workgroup calls it, at the end of the kernel.
 __device__ __forceinline__ void flush_stats(unsigned long long edges, uint32_t changed,
                                             unsigned long long flagw, DevStats* st,
                                             int cls) {
+  __shared__ unsigned long long fs_e[16], fs_f[16];
+  __shared__ uint32_t fs_c[16];
   const unsigned long long e = wave_sum_u64(edges);
   const uint32_t c = wave_sum_u32(changed);
   const unsigned long long f = wave_sum_u64(flagw);
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    if (e) atomicAdd(&st->edges[cls], e);
-    if (c) atomicAdd(&st->changed[cls], (unsigned long long)c);
-    if (f) atomicAdd(&st->flagw[cls], f);
+    fs_e[w] = e;
+    fs_c[w] = c;
+    fs_f[w] = f;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long te = 0, tf = 0;
+    uint32_t tc = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      te += fs_e[q];
+      tc += fs_c[q];
+      tf += fs_f[q];
+    }
+    if (te) atomicAdd(&st->edges[cls], te);
+    if (tc) atomicAdd(&st->changed[cls], (unsigned long long)tc);
+    if (tf) atomicAdd(&st->flagw[cls], tf);
   }
 }
 
@@ -1045,8 +1066,16 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     it = nit;
     cur = nxt;
   }
+  // one atomic per workgroup
+  __shared__ unsigned long long we[BT / 64];
   const unsigned long long e = wave_sum_u64(my_edges);
-  if ((tid & 63) == 0 && e) atomicAdd(&a.st->edges[kClassHub], e);
+  if ((tid & 63) == 0) we[tid >> 6] = e;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < BT / 64; ++q) t += we[q];
+    if (t) atomicAdd(&a.st->edges[kClassHub], t);
+  }
 }
 
 // Two instantiations share the queued buckets: the small one (SLOTS 4095,
