@@ -799,11 +799,25 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
             (int32_t)(step0 + ((int64_t)wv * kLearnChunks + q) * 64 + lane);
     __syncthreads();
   }
+  // one atomic per counter and workgroup (cnt and cbase are free after the
+  // last step's barrier; every thread of the workgroup gets here)
   const uint32_t tp = wave_sum_u32(proc), ts = wave_sum_u32(skipped), tn = wave_sum_u32(npred);
   if (lane == 0) {
-    if (tp) atomicAdd(&st->processed, (unsigned long long)tp);
-    if (ts) atomicAdd(&st->skipped, (unsigned long long)ts);
-    if (tn) atomicAdd(&st->npred, (unsigned long long)tn);
+    cnt[wv] = tp;
+    cnt[kLearnWaves + wv] = ts;
+    cbase[wv] = tn;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t sp = 0, ss = 0, sn = 0;
+    for (int q = 0; q < kLearnWaves; ++q) {
+      sp += cnt[q];
+      ss += cnt[kLearnWaves + q];
+      sn += cbase[q];
+    }
+    if (sp) atomicAdd(&st->processed, (unsigned long long)sp);
+    if (ss) atomicAdd(&st->skipped, (unsigned long long)ss);
+    if (sn) atomicAdd(&st->npred, (unsigned long long)sn);
   }
 }
 

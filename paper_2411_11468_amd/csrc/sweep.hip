@@ -159,9 +159,18 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
   return x;
 }
 
+// The learned variant's false-negative count, one atomic per workgroup as in
+// flush_stats (every thread calls it, at the end of the kernel).
 __device__ __forceinline__ void flush_fneg(uint32_t fneg, DevStats* st) {
+  __shared__ uint32_t fn_w[16];
   const uint32_t f = wave_sum_u32(fneg);
-  if ((threadIdx.x & 63) == 0 && f) atomicAdd(&st->fneg, (unsigned long long)f);
+  if ((threadIdx.x & 63) == 0) fn_w[threadIdx.x >> 6] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += fn_w[q];
+    if (t) atomicAdd(&st->fneg, (unsigned long long)t);
+  }
 }
 
 }  // namespace
