@@ -1149,28 +1149,42 @@ __global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_
                                                    const int32_t* hub_vid, int32_t H,
                                                    const uint8_t* chg, uint8_t* F,
                                                    DevStats* st) {
-  __shared__ int any;
+  constexpr int U = 8;  // entries per thread and step, all in flight at once
+  __shared__ unsigned long long ws[kBT / 64];
   if (st->stop || st->pull_mode != 1u) return;
   unsigned long long scanned = 0;
   for (int32_t h = blockIdx.x; h < H; h += gridDim.x) {
     const int32_t v = hub_vid[h];
     const int64_t o = (int64_t)off[v];
     const int64_t d = (int64_t)off[v + 1] - o;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    for (int64_t t = 0; t < d; t += kBT) {
-      const int64_t e = t + threadIdx.x;
-      if (e < d) {
-        ++scanned;
-        if (chg[tgt[o + e]]) any = 1;
+    bool found = false;
+    for (int64_t t = 0; t < d && !found; t += (int64_t)kBT * U) {
+      int32_t j[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = t + (int64_t)u * kBT + threadIdx.x;
+        j[u] = e < d ? tgt[o + e] : -1;
       }
-      if (__syncthreads_or(any)) break;
+      int hit = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j[u] >= 0) {
+          ++scanned;
+          hit |= chg[j[u]] ? 1 : 0;
+        }
+      found = __syncthreads_or(hit) != 0;  // uniform over the workgroup
     }
-    if (threadIdx.x == 0 && any) F[v] = 1;
-    __syncthreads();
+    if (threadIdx.x == 0 && found) F[v] = 1;
   }
+  // one atomic per workgroup
   for (int ofs = 32; ofs > 0; ofs >>= 1) scanned += __shfl_xor(scanned, ofs);
-  if ((threadIdx.x & 63) == 0 && scanned) atomicAdd(&st->pull_scanned, scanned);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = scanned;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < kBT / 64; ++q) t += ws[q];
+    if (t) atomicAdd(&st->pull_scanned, t);
+  }
 }
 
 hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
