@@ -89,6 +89,35 @@ __device__ __forceinline__ void flush_stats(unsigned long long edges, uint32_t c
   }
 }
 
+// Wave-level merge before the LDS inserts of one unrolled step: the lanes
+// holding the same label as the wave's first lane with an entry hand their
+// weights to that lane (a popcount for unit weights, else a wave sum) and
+// drop their own entries.  Atomic adds to one LDS slot from one wave
+// instruction are serialised; after the first iteration a row's labels
+// concentrate on a few values, and the first lane's label is most often the
+// step's most frequent one.  The table then receives the same per-label sums
+// (exactly so for integer weights).  All 64 lanes must be active.
+__device__ __forceinline__ void merge_lead(uint32_t& lab, float& wt, bool unit) {
+  const unsigned long long act = __ballot(lab != kEmpty);
+  if (act == 0ull) return;
+  const int first = __ffsll((long long)act) - 1;
+  const uint32_t lead = (uint32_t)__builtin_amdgcn_readlane((int)lab, first);
+  const bool mine = lab == lead;
+  const unsigned long long m = __ballot(mine);
+  float sum;
+  if (unit) {
+    sum = (float)__popcll(m);
+  } else {
+    float x = mine ? wt : 0.0f;
+    for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
+    sum = x;
+  }
+  if (mine) {
+    if ((int)(threadIdx.x & 63) == first) wt = sum;
+    else lab = kEmpty;
+  }
+}
+
 __device__ __forceinline__ bool decide(unsigned long long best, int32_t cur, int pl,
                                        uint32_t* cstar) {
   if (best == 0ull) return false;  // no neighbour other than itself
@@ -486,6 +515,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+    #pragma unroll
+    for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
@@ -502,6 +533,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
+      #pragma unroll
+      for (int u = 0; u < U; ++u) merge_lead(lab[u], ww[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
@@ -809,6 +842,8 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+    #pragma unroll
+    for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
@@ -825,6 +860,8 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
+      #pragma unroll
+      for (int u = 0; u < U; ++u) merge_lead(lab[u], ww[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
@@ -1038,6 +1075,8 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+      #pragma unroll
+      for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.probe);
