@@ -118,6 +118,34 @@ __device__ __forceinline__ void merge_lead(uint32_t& lab, float& wt, bool unit) 
   }
 }
 
+// merge_lead within each 16-lane row, for k_sweep_group (one row per vertex;
+// the lanes of a row are active or inactive together).
+__device__ __forceinline__ void merge_lead16(uint32_t& lab, float& wt, bool unit) {
+  const unsigned long long act = __ballot(lab != kEmpty);
+  const int lane = (int)(threadIdx.x & 63);
+  const int row0 = lane & ~15;
+  const uint32_t ract = (uint32_t)(act >> row0) & 0xFFFFu;
+  const int first = row0 + (ract ? __ffs((int)ract) - 1 : 0);
+  const uint32_t lead = (uint32_t)__shfl((int)lab, first);
+  const bool mine = ract != 0u && lab == lead;
+  const unsigned long long m = __ballot(mine);
+  float sum;
+  if (unit) {
+    sum = (float)__popc((uint32_t)(m >> row0) & 0xFFFFu);
+  } else {
+    float x = mine ? wt : 0.0f;
+    x += dppf<0x128>(x);  // row_ror:8
+    x += dppf<0x124>(x);
+    x += dppf<0x122>(x);
+    x += dppf<0x121>(x);
+    sum = x;
+  }
+  if (mine) {
+    if (lane == first) wt = sum;
+    else lab = kEmpty;
+  }
+}
+
 __device__ __forceinline__ bool decide(unsigned long long best, int32_t cur, int pl,
                                        uint32_t* cstar) {
   if (best == 0ull) return false;  // no neighbour other than itself
@@ -627,6 +655,9 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if constexpr (!FEAT) merge_lead16(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
