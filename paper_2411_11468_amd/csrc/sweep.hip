@@ -447,6 +447,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
       for (int u = 0; u < U; ++u)
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
+      for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
+#pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
           lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
@@ -656,8 +658,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
       for (int u = 0; u < U; ++u)
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if constexpr (!FEAT) merge_lead16(lab[u], wt[u], a.w == nullptr);
+      for (int u = 0; u < U; ++u) merge_lead16(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
@@ -752,6 +753,11 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+      // the merge slowed the 513-1024-entry class (2047 slots); the learned
+      // variant of the larger classes runs here and takes it
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if constexpr (FEAT && SLOTS > 2047) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
