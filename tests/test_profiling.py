@@ -1,0 +1,68 @@
+"""CPU: the rocprofv3 summary helpers (kernel short names, traffic scaling)."""
+import csv
+import json
+
+from paper_2411_11468_amd import profiling
+
+
+def test_short_names():
+    cases = {
+        "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)": "hub_part",
+        "void lpa::k_sweep_block_pipe<long, 16383, 1024, 4>(lpa::SweepArgs)": "sweep_block16383",
+        "void lpa::k_sweep_block<long, 2047, 256, 4, false>(lpa::SweepArgs)": "sweep_block2047",
+        "void lpa::k_sweep_group<long, 127, 16, false>(lpa::SweepArgs)": "sweep_wave127",
+        "void lpa::k_sweep_wave_pipe<long, 1023, 4, 4>(lpa::SweepArgs)": "sweep_wave1023",
+        "void lpa::k_sweep_lane4<long>(lpa::SweepArgs)": "sweep_small4",
+        "void lpa::k_sweep_direct<long, 1, 256, false, true>(lpa::SweepArgs)": "direct_small4",
+        "void lpa::k_sweep_direct<long, 16, 256, false, false>(lpa::SweepArgs)": "direct_g16",
+        "void lpa::k_sweep_direct<long, 256, 256, false, false>(lpa::SweepArgs)": "direct_g256",
+        "void lpa::(anonymous namespace)::k_tv_wave<long, double, 1023>(lpa::SweepArgs)":
+            "tv_sweep",
+        "lpa::k_frontier(long, unsigned char*, unsigned char const*, lpa::ListPtrs)": "frontier",
+        "void lpa::(anonymous namespace)::k_fill<float>(float*, float, long)": "fill",
+        "lpa::k_init(long, int const*, int const*, int*, unsigned char*, lpa::DevStats*)": "init",
+        "__amd_rocclr_copyBuffer": "__amd_rocclr_copyBuffer",
+    }
+    for kernel, name in cases.items():
+        assert profiling.short_name(kernel) == name, kernel
+
+
+def _counter_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_scaling(tmp_path):
+    # a 1 GiB copy reads half its bytes per the counter (scale 2) and writes
+    # all of them (scale 1); a sweep kernel's two dispatches are averaged
+    gib = float(1 << 30)
+    kib = gib / 1024
+    fetch = [
+        {"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "FETCH_SIZE",
+         "Counter_Value": kib / 2},
+        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
+         "Counter_Name": "FETCH_SIZE", "Counter_Value": 100.0},
+        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
+         "Counter_Name": "FETCH_SIZE", "Counter_Value": 300.0},
+    ]
+    write = [
+        {"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "WRITE_SIZE",
+         "Counter_Value": kib},
+        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
+         "Counter_Name": "WRITE_SIZE", "Counter_Value": 10.0},
+        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
+         "Counter_Name": "WRITE_SIZE", "Counter_Value": 30.0},
+    ]
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    _counter_csv(fp, fetch)
+    _counter_csv(wp, write)
+    t = profiling.traffic_json(str(fp), str(wp), gib, "cmd")
+    json.dumps(t)
+    assert abs(t["fetch_scale"] - 2.0) < 1e-9 and abs(t["write_scale"] - 1.0) < 1e-9
+    hp = t["kernels"]["hub_part"]
+    assert hp["dispatches"] == 2
+    assert abs(hp["bytes_per_dispatch"] - 1024.0 * (200.0 * 2.0 + 20.0)) < 1e-6
+    assert t["sources"] == profiling.source_hash()
