@@ -26,15 +26,23 @@
 // also write back the XCD's L2 on every move.)
 //
 // Classes:
+//   k_sweep_lane4     rows of up to 4 entries, one lane per row, sums in
+//                     registers (learned variant: k_sweep_small<4>).
 //   k_sweep_small<G>  G lanes per vertex (G = 4 or 16), one edge per lane,
 //                     per-label sums by DPP rotations inside the group; no
 //                     hashtable is needed for rows this short.
-//   k_sweep_wave      one wave per vertex, LDS hashtable per wave.
-//   k_sweep_block     one workgroup per vertex, LDS hashtable per workgroup.
-//   k_hub_acc/fin     rows longer than the largest LDS table: each slice of
-//                     the row is reduced in an LDS table, then merged into a
-//                     global-memory table with atomics; the merge also
-//                     maintains the packed maximum, since sums only grow.
+//   k_sweep_group     rows of up to 64 entries, 16 lanes and an LDS table per
+//                     vertex, four vertices per wave.
+//   k_sweep_wave(_pipe)   one wave per vertex, LDS hashtable per wave.
+//   k_sweep_block(_pipe)  one workgroup per vertex, LDS hashtable per
+//                     workgroup; the _pipe forms load the next row's head
+//                     during the table scan.
+//   k_hub_part/reduce/spill/fin   rows longer than the largest LDS table:
+//                     each slice of the row is reduced in an LDS table and
+//                     its (label, sum) pairs written grouped by label bucket;
+//                     each bucket is summed in an LDS table (a full table
+//                     spills into the hub's global table) and its maximum
+//                     folded into the hub's packed best; k_hub_fin moves.
 #include "lpa_device.h"
 #include "lpa_record.h"
 
