@@ -12,6 +12,7 @@ Functions and the passages they follow (paper arXiv 2411.11468):
   modularity        Eq. 1, community form.
   modularity_pairs  Eq. 1, pair form over all vertex pairs (tiny graphs).
   local_optimal     Eq. 3 attained by the current label, per vertex.
+  pl_refusable      Eq. 3's maxima all above the current label (Pick-Less).
   lpa_learned       Algorithm 1 with the learned change predictor: per-vertex
                     state records, features, skipping schedule, guard and
                     fallback, traces (learned_oracle.c; a project addition).
@@ -155,6 +156,30 @@ def local_optimal(offsets, targets, weights, labels) -> np.ndarray:
     if bad < 0:
         raise MemoryError("oracle_local_optimal")
     return out.astype(bool)
+
+
+def pl_refusable(offsets, targets, weights, labels, verts) -> np.ndarray:
+    """Per vertex of verts: True when every label of maximum Eq. 3 weight is
+    larger than the vertex's own, i.e. a move that Pick-Less (Sec. 4.1)
+    refuses.  With Pick-Less on, an asynchronous run may end with such a
+    vertex unflagged and off the maximum (it was refused at its last
+    evaluation and no neighbour changed since); any other unflagged vertex
+    must attain the maximum.  Plain numpy over the given rows."""
+    off, tgt, w = _csr(offsets, targets, weights)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.zeros(len(verts), dtype=bool)
+    for q, i in enumerate(np.asarray(verts, dtype=np.int64)):
+        a, b = int(off[i]), int(off[i + 1])
+        nb = tgt[a:b]
+        keep = nb != i
+        if not keep.any():
+            continue
+        ls, inv = np.unique(lab[nb[keep]], return_inverse=True)
+        sums = np.zeros(ls.shape[0])
+        ww = np.ones(b - a) if w is None else w[a:b].astype(np.float64)
+        np.add.at(sums, inv, ww[keep])
+        out[q] = bool(np.all(ls[sums == sums.max()] > lab[i]))
+    return out
 
 
 class LearnedStats(ctypes.Structure):

@@ -92,6 +92,7 @@ def test_graph_launch_replays_match_eager(mode):
     G = lpa.LpaGraph(_dev(g.offsets), _dev(g.targets), _dev(g.weights))
     eager = G.run(mode, launch=lpa.LAUNCH_EAGER)
     ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+    q_ref = oracle.modularity(g.offsets, g.targets, g.weights, ref.labels)
     if mode == "det":
         assert np.array_equal(eager.labels.cpu().numpy(), ref.labels)
     for rep in range(3):
@@ -103,10 +104,58 @@ def test_graph_launch_replays_match_eager(mode):
                 for k in ("iteration", "pick_less", "changed", "processed", "edges_scanned"):
                     assert a[k] == b[k], (rep, k)
         else:
+            # each replay: Pick-Less refusals aside (labels above the
+            # vertex's own), every unflagged vertex holds a label of maximum
+            # weight, and modularity lies within 0.01 of the oracle's
             flags = G.flags().astype(bool)
             lab = res.labels.cpu().numpy()
             assert 1 <= res.iterations <= 20
+            ok = oracle.local_optimal(g.offsets, g.targets, g.weights, lab)
+            bad = np.nonzero(~ok & ~flags)[0]
+            assert oracle.pl_refusable(g.offsets, g.targets, g.weights, lab, bad).all(), (rep, bad[:5])
+            q = oracle.modularity(g.offsets, g.targets, g.weights, lab)
+            assert abs(q - q_ref) <= 0.01, (rep, q, q_ref)
+            assert G.modularity(res.labels) == pytest.approx(q, rel=1e-9, abs=1e-12)
         # eager work between replays
         e2 = G.run(mode, launch=lpa.LAUNCH_EAGER, pl_period=0, max_iterations=3)
         assert e2.iterations <= 3
     G.close()
+
+
+@pytest.fixture(scope="module")
+def batch8k():
+    # the batched configuration at its full size: 8,192 planted partitions
+    # (vertex counts log-uniform in [256, 65536], seed 5), the benchmark's
+    # batch and handle
+    g, v_off = graphgen.planted_partition_batch(8192, 5)
+    B = lpa.LpaBatch(v_off, _dev(g.offsets), _dev(g.targets), _dev(g.weights))
+    sizes = np.diff(v_off)
+    rng = np.random.default_rng(5)
+    pick = np.unique(np.concatenate([rng.choice(len(sizes), 256, replace=False),
+                                     np.argsort(sizes, kind="stable")[-8:]]))
+    refs = {}
+    for q in pick:
+        a, b = int(v_off[q]), int(v_off[q + 1])
+        ea, eb = int(g.offsets[a]), int(g.offsets[b])
+        refs[int(q)] = oracle.lpa_sync(g.offsets[a:b + 1] - ea, g.targets[ea:eb] - a,
+                                       g.weights[ea:eb])
+    yield g, v_off, B, refs
+    B.close()
+
+
+@pytest.mark.parametrize("launch", [lpa.LAUNCH_EAGER, lpa.LAUNCH_GRAPH])
+def test_batched_full_size_sampled_graphs_equal_oracle(batch8k, launch):
+    # one deterministic batched run over all 8,192 graphs; 256 graphs drawn
+    # at random and the 8 largest equal their solo oracle runs (labels,
+    # iteration count, last iteration's changed count)
+    g, v_off, B, refs = batch8k
+    res = B.run_batched("det", launch=launch)
+    lab = res.labels.cpu().numpy()
+    assert int(np.diff(v_off).max()) > 60000
+    for q, ref in refs.items():
+        got = lab[v_off[q]:v_off[q + 1]] - v_off[q]
+        mism = np.nonzero(got != ref.labels)[0]
+        assert mism.size == 0, (q, mism.size, mism[:5])
+        assert res.iters_per_graph[q] == ref.iterations, (q, res.iters_per_graph[q], ref.iterations)
+        assert res.changed_last[q] == ref.stats[-1]["changed"], q
+    assert res.iterations == int(res.iters_per_graph.max())

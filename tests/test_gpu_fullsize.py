@@ -4,13 +4,15 @@ vertices, 2,103,831,556 CSR entries, int64 offsets, an fp32 weight array of
 
 The oracle cannot run Algorithm 1 over the whole graph in test time, so it
 decides sampled vertices one by one:
-  - deterministic mode: the labels before the last iteration (a run capped
-    one iteration short) and the flags that select the last iteration's
-    vertices go into one oracle iteration over the sampled rows (the other
-    rows empty, so they keep their labels); every sampled vertex's final
-    label must equal the oracle's, and the last iteration's processed and
-    changed counts must equal the flag and label differences over all
-    vertices;
+  - deterministic mode, every iteration k of the run: the labels after k - 1
+    iterations (a run capped there; the vertex ids for k = 1) and the flags
+    that select iteration k's vertices go into one oracle iteration over the
+    sampled rows (the other rows empty, so they keep their labels); every
+    sampled vertex's label after k iterations must equal the oracle's, and
+    iteration k's processed and changed counts must equal the flag and label
+    differences over all vertices.  Iteration 1 is the table-free first
+    sweep; the later ones run the table kernels, hub slices and bucket
+    reductions;
   - asynchronous mode: every sampled vertex that is not flagged at exit
     holds a label of maximum weight (the oracle's local-optimality check on
     the sampled rows).
@@ -63,26 +65,33 @@ def _sampled_rows(g, sample):
     return off, np.ascontiguousarray(g.targets[idx])
 
 
-def test_det_last_iteration_sampled(big):
+def test_det_every_iteration_sampled(big):
     g, G, sample = big
     n = g.num_vertices
     full = G.run("det", profile=True)
-    k = full.iterations
-    assert k >= 2
-    final = full.labels.cpu().numpy()
-    prev = G.run("det", max_iterations=k - 1).labels.cpu().numpy()
-    flags = G.flags().astype(bool)        # the vertices iteration k-1 processes
-    last = full.stats[-1]
-    assert last["processed"] == int(flags.sum())
-    assert last["changed"] == int((final != prev).sum())
+    K = full.iterations
+    assert K >= 2
     off, tgt = _sampled_rows(g, sample)
-    pl = 1 if (k - 1) % 4 == 0 else 0     # Pick-Less period 4, from iteration 0
-    one = oracle.lpa_sync(off, tgt, None, tolerance=0.0, max_iterations=1, pl_period=pl,
-                          initial_labels=prev).labels
-    want = np.where(flags[sample], one[sample], prev[sample])
-    mism = np.nonzero(final[sample] != want)[0]
-    assert mism.size == 0, f"{mism.size} sampled labels differ, first at {sample[mism[:5]]}"
-    assert final.shape == (n,)
+    prev = np.arange(n, dtype=np.int32)
+    flags = np.ones(n, dtype=bool)
+    for k in range(1, K + 1):
+        nxt = None
+        if k == K:
+            cur = full.labels.cpu().numpy()
+        else:
+            cur = G.run("det", max_iterations=k).labels.cpu().numpy()
+            nxt = G.flags().astype(bool)      # the vertices iteration k + 1 processes
+        st = full.stats[k - 1]
+        assert st["processed"] == int(flags.sum()), k
+        assert st["changed"] == int((cur != prev).sum()), k
+        pl = 1 if (k - 1) % 4 == 0 else 0     # Pick-Less period 4, from iteration 0
+        one = oracle.lpa_sync(off, tgt, None, tolerance=0.0, max_iterations=1, pl_period=pl,
+                              initial_labels=prev).labels
+        want = np.where(flags[sample], one[sample], prev[sample])
+        mism = np.nonzero(cur[sample] != want)[0]
+        assert mism.size == 0, \
+            f"iteration {k}: {mism.size} sampled labels differ, first at {sample[mism[:5]]}"
+        prev, flags = cur, nxt
 
 
 def test_async_invariant_sampled(big):

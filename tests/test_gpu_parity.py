@@ -309,6 +309,39 @@ def test_det_rmat_scale22_full_size():
     assert_det_parity(g)
 
 
+def test_async_rmat_scale22_full_size():
+    # the second configuration in asynchronous mode at its full size, both
+    # launch modes: with Pick-Less off every vertex left unflagged holds a
+    # label of maximum weight; with Pick-Less every 4th iteration (the
+    # configuration's) an unflagged vertex off the maximum must be one whose
+    # maximum-weight labels are all larger than its own (a Pick-Less refusal
+    # since its last evaluation), and modularity lies within 0.01 of the
+    # oracle's deterministic run
+    g = graphgen.rmat_graph(22, 22, "int8")
+    ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+    q_ref = oracle.modularity(g.offsets, g.targets, g.weights, ref.labels)
+    G = _graph_on_gpu(g)
+    for launch in (lpa.LAUNCH_EAGER, lpa.LAUNCH_GRAPH):
+        for pl in (0, 4):
+            res = G.run("async", pl_period=pl, launch=launch)
+            lab = res.labels.cpu().numpy()
+            flags = G.flags().astype(bool)
+            ok = oracle.local_optimal(g.offsets, g.targets, g.weights, lab)
+            bad = np.nonzero(~ok & ~flags)[0]
+            if pl == 0:
+                assert bad.size == 0, f"{bad.size} unflagged vertices off the maximum"
+            else:
+                refused = oracle.pl_refusable(g.offsets, g.targets, g.weights, lab, bad)
+                assert refused.all(), f"{int((~refused).sum())} unflagged vertices off the maximum"
+                q = oracle.modularity(g.offsets, g.targets, g.weights, lab)
+                assert abs(q - q_ref) <= 0.01, (q, q_ref)
+                assert G.modularity(res.labels) == pytest.approx(q, rel=1e-9, abs=1e-12)
+            assert 1 <= res.iterations <= 20
+            for st in res.stats:
+                assert 0 <= st["changed"] <= st["processed"] <= g.num_vertices
+    G.close()
+
+
 def test_profile_books_each_kernel():
     # every class kernel once per iteration; the table-free first sweep
     # under its own names, once per run

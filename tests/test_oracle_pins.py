@@ -362,3 +362,30 @@ def test_cross_check_properties():
             # vertex c is either below i (final) or above (its plain move)
             lab_c = c1.labels[c] if c < i else p1.labels[c]
             assert lab_c == c
+
+
+def test_pl_refusable_hand_cases_and_pick_less_sweeps():
+    # a star 0 - {1, 2, 3}: the centre's neighbour labels 5, 5, 7 sum to
+    # {5: 2, 7: 1}; its maximum (5) lies above 0 and below 6
+    g = graphgen.from_edges(4, [(0, 1), (0, 2), (0, 3)])
+    assert oracle.pl_refusable(g.offsets, g.targets, g.weights,
+                               np.array([0, 5, 5, 7], np.int32), [0]).tolist() == [True]
+    assert oracle.pl_refusable(g.offsets, g.targets, g.weights,
+                               np.array([6, 5, 5, 7], np.int32), [0]).tolist() == [False]
+    # tied maxima {3, 9}: refusable only when both lie above the own label
+    g = graphgen.from_edges(3, [(0, 1), (0, 2)])
+    for own, want in ((2, True), (5, False), (10, False)):
+        lab = np.array([own, 3, 9], np.int32)
+        assert oracle.pl_refusable(g.offsets, g.targets, g.weights, lab, [0]).tolist() == [want]
+    # against Algorithm 1: in one Pick-Less sweep a vertex off the maximum
+    # keeps its label exactly when it is refusable
+    rng = np.random.default_rng(7)
+    for t in range(40):
+        g = graphgen.random_graph(30, 0.2, 100 + t, wmax=4)
+        lab = rng.integers(0, 30, 30).astype(np.int32)
+        one = oracle.lpa_sync(g.offsets, g.targets, g.weights, tolerance=0.0, max_iterations=1,
+                              pl_period=1, initial_labels=lab).labels
+        ok = oracle.local_optimal(g.offsets, g.targets, g.weights, lab)
+        off_max = np.nonzero(~ok)[0]
+        ref = oracle.pl_refusable(g.offsets, g.targets, g.weights, lab, off_max)
+        assert np.array_equal(ref, one[off_max] == lab[off_max]), t
