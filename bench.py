@@ -144,20 +144,37 @@ def run_batched(args, wl) -> int:
     d_off = torch.from_numpy(g.offsets).to(dev)
     d_tgt = torch.from_numpy(g.targets).to(dev)
     d_w = torch.from_numpy(g.weights).to(dev)
-    B = lpa.LpaBatch(v_off, d_off, d_tgt, d_w)
-    labels = torch.empty(n, dtype=torch.int32, device=dev)
-    for _ in range(args.warmup):
-        B.run_batched(mode, out=labels)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        br = B.run_batched(mode, out=labels)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
     e_per = np.diff(g.offsets[v_off])           # CSR entries per graph
+
+    def timed(tuning, launch):
+        B = lpa.LpaBatch(v_off, d_off, d_tgt, d_w, tuning=tuning)
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+        for _ in range(args.warmup):
+            B.run_batched(mode, out=out, launch=launch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = B.run_batched(mode, out=out, launch=launch)
+        torch.cuda.synchronize()
+        return B, out, r, (time.perf_counter() - t0) / args.steps
+
+    # the batched schedules: the persistent work queue (the default for rows
+    # of at most 512 entries) and the class kernels over the packed CSR,
+    # both with captured iterations
+    tq = lpa.default_tuning()
+    tq.batch_queue = 1
+    B, labels, br, t_batch = timed(tq, lpa.LAUNCH_GRAPH)
     edge_iters = float(np.sum(e_per * br.iters_per_graph))
-    log(f"batched: {t_batch * 1e3:.1f} ms per run, {br.iterations} iterations, "
+    log(f"batched (work queue): {t_batch * 1e3:.1f} ms per run, {br.iterations} iterations, "
         f"{edge_iters / t_batch / 1e9:.2f} G edge-iterations/s")
+    tc = lpa.default_tuning()
+    tc.batch_queue = 0
+    Bc, labels_c, brc, t_classes = timed(tc, lpa.LAUNCH_GRAPH)
+    same_packed = bool(torch.equal(labels, labels_c)) if mode == "det" else None
+    log(f"batched (class kernels): {t_classes * 1e3:.1f} ms per run; "
+        f"labels equal to the work queue's: {same_packed}")
+    Bc.close()
+    del labels_c
     # per-graph runs of the same graphs (pre-uploaded, one handle each)
     t0 = time.perf_counter()
     handles = []
@@ -203,6 +220,9 @@ def run_batched(args, wl) -> int:
         "per_graph": {"value": float(np.sum(e_per * iters_solo)) / t_solo,
                       "ms": 1e3 * t_solo, "launch": lname},
         "speedup": t_solo / t_batch,
+        "class_kernels": {"value": float(np.sum(e_per * brc.iters_per_graph)) / t_classes,
+                          "ms": 1e3 * t_classes, "labels_equal": same_packed},
+        "queue_vs_class_kernels": t_classes / t_batch,
         "iterations_equal_to_solo": same_iters,
         "labels_equal_to_solo": same_labels,
         "batch_iterations": br.iterations,

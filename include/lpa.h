@@ -143,6 +143,27 @@ typedef struct lpa_graph_s* lpa_graph;
  *   longer rows every slice adding into the row's global-memory table; no
  *   register-only classes and no table-free first sweep.  Not with learned
  *   runs, traces or lpa_create_batched (LPA_ERR_UNSUPPORTED).
+ * batch_queue (lpa_create_batched only): how a batched run is scheduled.
+ *   1 = a persistent work queue: per iteration one resident grid pops
+ *   (graph, vertex chunk) items from atomic queues, one part per XCD holding
+ *   all chunks of the graphs assigned to it, and processes each chunk's
+ *   flagged vertices; a per-graph kernel then applies the stop test and
+ *   queues the chunks that hold flagged vertices or changed labels.  Rows
+ *   of up to 512 entries only (a longer row makes it LPA_ERR_UNSUPPORTED).
+ *   0 = the degree-class kernels of a single graph over the packed CSR.
+ *   -1 (default) = the work queue when every row has at most 512 entries.
+ *   Both give the same results.  Runs without pruning (prune = 0) always
+ *   take the class kernels.
+ * queue_chunk: vertices per queue item, a power of two in 64 .. 1024
+ *   (0 = default 512).
+ * queue_group: rows of up to this many entries (16 .. 64, 0 = default 64)
+ *   are processed by 16 lanes each with a 127-slot LDS table; longer rows
+ *   by a wavefront each with a 1023-slot table.
+ * sort_rows: with the internal order (relabel), sort each row of the
+ *   internal CSR by target id at create, so that the label reads of a row
+ *   walk upwards through the label array and the entries in its dense
+ *   low-id part share cache lines.  1 = sort, 0 = keep
+ *   the caller's entry order, -1 (default) = sort.  The same results.
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -156,6 +177,10 @@ typedef struct lpa_tuning {
   int32_t relabel;
   int32_t probe;
   int32_t table_values;
+  int32_t batch_queue;
+  int32_t queue_chunk;
+  int32_t queue_group;
+  int32_t sort_rows;
 } lpa_tuning;
 
 /*

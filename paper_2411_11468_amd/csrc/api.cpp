@@ -47,14 +47,15 @@ constexpr int kKidPlan = 0, kKidFrontier = 1, kKidHubPart = 2, kKidSweep0 = 2,
               kKidHubFin = 11, kKidApply = 12, kKidPull = 13, kKidPullHubs = 14,
               kKidPush = 15, kKidPushHubs = 16, kKidDecide = 17, kKidHubReduce = 18,
               kKidBatch = 19, kKidHubSpill = 20, kKidDirect0 = 20, kKidHubDirect = 29,
-              kNumKids = 30;
+              kKidQueueSweep = 30, kKidQueueStep = 31, kNumKids = 32;
 const char* const kKidNames[kNumKids] = {
     "hub_plan", "frontier", "hub_part", "sweep_small4", "sweep_small16", "sweep_wave127",
     "sweep_wave1023", "sweep_block2047", "sweep_block4095", "sweep_block8191",
     "sweep_block16383", "hub_fin", "apply", "pull_flags", "pull_hubs", "push_flags",
     "push_hubs", "flag_decide", "hub_reduce", "batch_step", "hub_spill", "direct_small4",
     "direct_small16", "direct_wave127", "direct_wave1023", "direct_block2047",
-    "direct_block4095", "direct_block8191", "direct_block16383", "hub_direct"};
+    "direct_block4095", "direct_block8191", "direct_block16383", "hub_direct", "queue_sweep",
+    "queue_step"};
 
 }  // namespace
 
@@ -204,6 +205,14 @@ struct lpa_graph_s {
         edges = (int64_t)fw;
         bytes = 5.0 * (double)listed + (off64 ? 16.0 : 8.0) * (double)ch + 5.0 * (double)fw;
       }
+    } else if (kid == kKidQueueSweep) {
+      // per scanned entry as the class sweeps; per processed vertex its flag,
+      // offsets and own label (and the next label in deterministic mode);
+      // per change the new label (asynchronous mode)
+      edges = (int64_t)h.edges[0];
+      verts = (int64_t)h.processed;
+      bytes = eb * edges + (1.0 + ob + 4.0 + (async_mode ? 0.0 : 4.0)) * verts +
+              (async_mode ? 4.0 * h.changed[0] : 0.0);
     } else if (kid == kKidBatch) {
       bytes = 2.0 * n;  // change byte read, flag cleared at most once
     } else if (kid == kKidApply) {
@@ -244,6 +253,36 @@ struct lpa_graph_s {
   uint8_t* b_done = nullptr;
   int32_t* b_iters = nullptr;
   long long* b_changed = nullptr;
+  // batched runs as a work queue (queue.hip)
+  bool wq = false;             // queue structures built at create
+  int wq_grid = 1;
+  int32_t wq_chunk_log2 = 9;
+  int32_t wq_group = 64;
+  int64_t wq_nchunks = 0;
+  int64_t* wq_cbase = nullptr;
+  int32_t* wq_cgraph = nullptr;
+  uint32_t* wq_items = nullptr;
+  uint32_t* wq_items0 = nullptr;     // the initial queue
+  int64_t* wq_qbase = nullptr;
+  unsigned int* wq_qctr = nullptr;
+  unsigned int* wq_qctr0 = nullptr;  // the initial queue's counters
+  uint8_t* wq_cmark = nullptr;
+  uint8_t* wq_F1 = nullptr;
+  unsigned int* wq_gchanged = nullptr;
+  QueueArgs queue_args(int async_mode) const {
+    QueueArgs q;
+    q.off = off; q.tgt = tgt; q.w = w;
+    q.C0 = C; q.C1 = async_mode ? C : Cn;
+    q.F0 = F; q.F1 = wq_F1;
+    q.cmark = wq_cmark; q.cbase = wq_cbase; q.cgraph = wq_cgraph;
+    q.items = wq_items; q.qbase = wq_qbase; q.qctr = wq_qctr; q.gchanged = wq_gchanged;
+    q.b = batch_args(); q.st = st;
+    q.nchunks = wq_nchunks; q.chunk_log2 = wq_chunk_log2; q.group_max = wq_group;
+    q.async_mode = async_mode;
+    q.strict_rows = strict_rows ? 1 : 0;
+    q.probe = ProbeCfg{tun.max_retries, tun.probe};
+    return q;
+  }
   // captured iterations, one executable graph per launch configuration
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec[24] = {};
@@ -336,6 +375,10 @@ void lpa_tuning_default(lpa_tuning* t) {
   t->max_retries = 32;
   t->xcd_local = 1;
   t->relabel = -1;
+  t->batch_queue = -1;
+  t->queue_chunk = 512;
+  t->queue_group = 64;
+  t->sort_rows = -1;
 }
 
 void lpa_learned_options_default(lpa_learned_options* o) {
@@ -373,7 +416,13 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
         t.hub_chunk >= 64 && t.hub_chunk <= 8192 && t.max_retries >= 0 &&
         t.hub_table_cap >= 0 && t.relabel >= -1 && t.relabel <= 1 && t.probe >= 0 &&
         t.probe <= 3 &&
-        (t.table_values == 0 || t.table_values == 32 || t.table_values == 64)))
+        (t.table_values == 0 || t.table_values == 32 || t.table_values == 64) &&
+        t.batch_queue >= -1 && t.batch_queue <= 1 &&
+        (t.queue_chunk == 0 ||
+         (t.queue_chunk >= 64 && t.queue_chunk <= (1 << kQueueMaxChunkLog2) &&
+          (t.queue_chunk & (t.queue_chunk - 1)) == 0)) &&
+        (t.queue_group == 0 || (t.queue_group >= 16 && t.queue_group <= 64)) &&
+        t.sort_rows >= -1 && t.sort_rows <= 1))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   // the ablation kernels' largest LDS table has 8191 slots (rows of <= 4096)
   if (t.table_values != 0) G->tun.block = std::min(G->tun.block, 4096);
@@ -526,6 +575,15 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     }
     if (e != hipSuccess)
       return fail(LPA_ERR_HIP, std::string("internal order: ") + hipGetErrorString(e));
+    if (t.sort_rows != 0 && m <= (int64_t)INT32_MAX) {
+      const hipError_t se = sort_rows(G->off64, noff, ntgt, nw, n, m, s);
+      if (se == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return fail(LPA_ERR_OOM, "hipMalloc failed while sorting the internal rows");
+      }
+      if (se != hipSuccess)
+        return fail(LPA_ERR_HIP, std::string("row sort: ") + hipGetErrorString(se));
+    }
     G->off = noff;
     G->tgt = ntgt;
     G->w = nw;
@@ -752,6 +810,19 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
                                     bool cc = false) {
   const int64_t n = g->n;
   const int async_mode = o.mode == LPA_MODE_ASYNC;
+  if (g->wq && o.prune) {
+    // batched run as a work queue: counters, sweep, per-graph step
+    const QueueArgs q = g->queue_args(async_mode);
+    if (lpa_status e = mark(-1)) return e;
+    LPA_HIP(launch_queue_iter_begin(q, s));
+    if (lpa_status e = mark(kKidQueueSweep)) return e;
+    LPA_HIP(launch_queue_sweep(g->off64, q, g->wq_grid, s));
+    if (lpa_status e = mark(kKidQueueStep)) return e;
+    LPA_HIP(launch_queue_step(q, s));
+    if (lpa_status e = mark(-1)) return e;
+    LPA_HIP(launch_iter_end(g->st, g->hist, n, s));
+    return LPA_OK;
+  }
   const int tv = g->tun.table_values;  // 0, or the ablation kernels' value bits
   if (cc) LPA_HIP(launch_cc_save(g->C, g->cc_prev, n, s));
   // without pruning every vertex is processed in every iteration
@@ -987,8 +1058,20 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
       return fail(LPA_ERR_INVALID, "initial_labels must lie in [0, N)");
   }
 
+  const bool use_queue = g->wq && o.prune;
+  if (use_queue) {
+    const QueueArgs q = g->queue_args(o.mode == LPA_MODE_ASYNC);
+    LPA_HIP(launch_queue_begin(q, n, s));
+    if (g->wq_nchunks > 0)
+      LPA_HIP(hipMemcpyAsync(g->wq_items, g->wq_items0, sizeof(uint32_t) * g->wq_nchunks,
+                             hipMemcpyDeviceToDevice, s));
+    LPA_HIP(hipMemcpyAsync(g->wq_qctr, g->wq_qctr0,
+                           sizeof(unsigned int) * 2 * kXcds * 2 * kQueueCtrStride,
+                           hipMemcpyDeviceToDevice, s));
+  }
   // a run from identity labels over strict rows: table-free first sweep
-  const bool first_direct = !init && g->strict_rows && g->tun.table_values == 0;
+  const bool first_direct =
+      !use_queue && !init && g->strict_rows && g->tun.table_values == 0;
   int32_t done = 0;
   const bool graph_mode = o.launch == LPA_LAUNCH_GRAPH && !o.profile && !trace;
   if (graph_mode) {
@@ -1073,6 +1156,12 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
       if (h.stop) break;
     }
   }
+  if (use_queue) {
+    LPA_HIP(launch_queue_finish(g->queue_args(o.mode == LPA_MODE_ASYNC), s));
+    if (g->st_host->error & 32u)
+      return fail(LPA_ERR_INVALID,
+                  "a row is longer than the work queue takes (the CSR changed after create)");
+  }
   if (iters_done) *iters_done = done;
   g->flags_pending = g->st_host->flags_deferred != 0;
   g->learned_iters = o.learned ? done : 0;
@@ -1112,6 +1201,83 @@ lpa_status lpa_run_batched(lpa_graph g, const lpa_options* opt, int32_t* labels,
     LPA_HIP(hipMemcpyAsync(changed_last_per_graph, g->b_changed, sizeof(int64_t) * g->G,
                            hipMemcpyDeviceToHost, g->stream));
   LPA_HIP(hipStreamSynchronize(g->stream));
+  return LPA_OK;
+}
+
+// Work-queue structures of a batched handle (queue.hip): chunks of
+// 2^chunk_log2 vertices per graph, the graphs' first chunks, each chunk's
+// graph, and the initial queue -- every chunk of every non-empty graph in
+// one part per XCD (graph g in part g mod 8) -- with its counters.  With
+// batch_queue = -1 a row longer than the queue kernel takes leaves the
+// handle on the class kernels.
+static lpa_status build_queue(lpa_graph g, const int64_t* v_off, const lpa_tuning& t) {
+  hipStream_t s = g->stream;
+  unsigned long long* dmax = nullptr;
+  if (lpa_status e = g->dalloc(&dmax, 1)) return e;
+  unsigned long long hmax = 0;
+  LPA_HIP(launch_fill_u64(dmax, 0ull, 1, s));
+  LPA_HIP(launch_max_degree(g->off64, g->off, g->n, dmax, s));
+  LPA_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(hmax), hipMemcpyDeviceToHost, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  if (hmax > (unsigned long long)kQueueMaxDegree) {
+    if (t.batch_queue == 1)
+      return fail(LPA_ERR_UNSUPPORTED, "batch_queue = 1 takes rows of at most 512 entries; "
+                                       "the longest has " + std::to_string(hmax));
+    return LPA_OK;
+  }
+  const int chunk = t.queue_chunk ? t.queue_chunk : 512;
+  int lg = 0;
+  while ((1 << lg) < chunk) ++lg;
+  g->wq_chunk_log2 = lg;
+  g->wq_group = t.queue_group ? t.queue_group : 64;
+  const int32_t G = g->G;
+  std::vector<int64_t> cbase(G + 1, 0);
+  for (int32_t q = 0; q < G; ++q)
+    cbase[q + 1] = cbase[q] + (((v_off[q + 1] - v_off[q]) + (1 << lg) - 1) >> lg);
+  const int64_t nch = cbase[G];
+  if (nch >= (int64_t)UINT32_MAX) return fail(LPA_ERR_INVALID, "too many queue items");
+  std::vector<int32_t> cgraph((size_t)std::max<int64_t>(nch, 1));
+  std::vector<int64_t> qbase(kXcds + 1, 0);
+  for (int32_t q = 0; q < G; ++q) {
+    for (int64_t c = cbase[q]; c < cbase[q + 1]; ++c) cgraph[(size_t)c] = q;
+    qbase[(q & (kXcds - 1)) + 1] += cbase[q + 1] - cbase[q];
+  }
+  for (int x = 0; x < kXcds; ++x) qbase[x + 1] += qbase[x];
+  std::vector<uint32_t> items0((size_t)std::max<int64_t>(nch, 1));
+  std::vector<int64_t> fill(qbase.begin(), qbase.end() - 1);
+  for (int32_t q = 0; q < G; ++q)
+    for (int64_t c = cbase[q]; c < cbase[q + 1]; ++c)
+      items0[(size_t)fill[q & (kXcds - 1)]++] = (uint32_t)c;
+  const int nctr = 2 * kXcds * 2 * kQueueCtrStride;
+  std::vector<unsigned int> ctr0(nctr, 0u);
+  for (int x = 0; x < kXcds; ++x)  // iteration 0: head 0, tail = the part's size
+    ctr0[(size_t)(x * 2 + 1) * kQueueCtrStride] = (unsigned int)(qbase[x + 1] - qbase[x]);
+  g->wq_nchunks = nch;
+  if (lpa_status e = g->dalloc(&g->wq_cbase, G + 1)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_cgraph, nch)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_items, 2 * nch)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_items0, nch)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_qbase, kXcds + 1)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_qctr, nctr)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_qctr0, nctr)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_cmark, nch)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_F1, g->n)) return e;
+  if (lpa_status e = g->dalloc(&g->wq_gchanged, G)) return e;
+  LPA_HIP(hipMemcpyAsync(g->wq_cbase, cbase.data(), sizeof(int64_t) * (G + 1),
+                         hipMemcpyHostToDevice, s));
+  if (nch > 0) {
+    LPA_HIP(hipMemcpyAsync(g->wq_cgraph, cgraph.data(), sizeof(int32_t) * nch,
+                           hipMemcpyHostToDevice, s));
+    LPA_HIP(hipMemcpyAsync(g->wq_items0, items0.data(), sizeof(uint32_t) * nch,
+                           hipMemcpyHostToDevice, s));
+  }
+  LPA_HIP(hipMemcpyAsync(g->wq_qbase, qbase.data(), sizeof(int64_t) * (kXcds + 1),
+                         hipMemcpyHostToDevice, s));
+  LPA_HIP(hipMemcpyAsync(g->wq_qctr0, ctr0.data(), sizeof(unsigned int) * nctr,
+                         hipMemcpyHostToDevice, s));
+  LPA_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  g->wq_grid = queue_sweep_resident();
+  g->wq = true;
   return LPA_OK;
 }
 
@@ -1159,6 +1325,9 @@ lpa_status lpa_create_batched(int32_t num_graphs, const int64_t* v_off, const lp
       return cleanup(fail(LPA_ERR_HIP, "batched validation failed to run"));
     if (g->st_host->error & 16u)
       return cleanup(fail(LPA_ERR_INVALID, "a CSR entry points outside its own graph"));
+  }
+  if (tb.batch_queue != 0) {
+    if (lpa_status e = build_queue(g, v_off, tb)) return cleanup(e);
   }
   if (hipStreamSynchronize(s) != hipSuccess) return cleanup(fail(LPA_ERR_HIP, "sync failed"));
   *out = g;

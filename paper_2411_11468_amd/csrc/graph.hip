@@ -1079,9 +1079,13 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   unsigned long long scanned = 0;
   constexpr int kFirst = 4;  // entries a lane checks for its own vertex
-  // one vertex per lane for its first kFirst entries (most rows find a
+  // one vertex per lane for its last kFirst entries (most rows find a
   // changed neighbour there); the rows left unresolved are then scanned
-  // eight lanes per row, up to eight rows at a time
+  // eight lanes per row, up to eight rows at a time.  Rows are read from
+  // their end: with the internal order's rows sorted by target, the last
+  // entries are the lowest-degree neighbours, which are the ones that still
+  // change late in a run (from the start: 0.58 -> 0.89 ms per launch on
+  // R-MAT 26)
   for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
     const int64_t v = base + lane;
     const bool valid = v < n && cls[v] != kClassHub;
@@ -1092,7 +1096,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
     }
     int32_t j[kFirst];
 #pragma unroll
-    for (int u = 0; u < kFirst; ++u) j[u] = (u < d) ? tgt[o + u] : -1;
+    for (int u = 0; u < kFirst; ++u) j[u] = (u < d) ? tgt[o + d - 1 - u] : -1;
     bool found = false;
 #pragma unroll
     for (int u = 0; u < kFirst; ++u) {
@@ -1118,7 +1122,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
         uint32_t hit = 0;
         const int64_t e = t + k;
         if (!done && e < pd) {
-          hit = chg[tgt[po + e]];
+          hit = chg[tgt[po + pd - 1 - e]];
           ++scanned;
         }
         hit = or8(hit);

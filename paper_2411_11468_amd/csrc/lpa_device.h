@@ -192,6 +192,119 @@ __device__ __forceinline__ uint32_t global_accumulate(uint32_t* keys, float* val
   }
 }
 
+// ---- shared by the sweep kernels (sweep.hip, queue.hip) ----------------------
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+  x += dpp64<0x111>(x);
+  x += dpp64<0x112>(x);
+  x += dpp64<0x114>(x);
+  x += dpp64<0x118>(x);
+  x += dpp64<0x142, 0xA>(x);
+  x += dpp64<0x143, 0xC>(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+
+// Adds a workgroup's counters to the iteration's: sums over each wave, then
+// over the waves in LDS, then one device atomic per counter and workgroup
+// (atomics on one address from every wave of a full grid serialise at the
+// memory side: tens of microseconds per kernel).  Every thread of the
+// workgroup calls it, at the end of the kernel.
+__device__ __forceinline__ void flush_stats(unsigned long long edges, uint32_t changed,
+                                            unsigned long long flagw, DevStats* st,
+                                            int cls) {
+  __shared__ unsigned long long fs_e[16], fs_f[16];
+  __shared__ uint32_t fs_c[16];
+  const unsigned long long e = wave_sum_u64(edges);
+  const uint32_t c = wave_sum_u32(changed);
+  const unsigned long long f = wave_sum_u64(flagw);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    fs_e[w] = e;
+    fs_c[w] = c;
+    fs_f[w] = f;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long te = 0, tf = 0;
+    uint32_t tc = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      te += fs_e[q];
+      tc += fs_c[q];
+      tf += fs_f[q];
+    }
+    if (te) atomicAdd(&st->edges[cls], te);
+    if (tc) atomicAdd(&st->changed[cls], (unsigned long long)tc);
+    if (tf) atomicAdd(&st->flagw[cls], tf);
+  }
+}
+
+// Wave-level merge before the LDS inserts of one unrolled step: the lanes
+// holding the same label as the wave's first lane with an entry hand their
+// weights to that lane (a popcount for unit weights, else a wave sum) and
+// drop their own entries.  Atomic adds to one LDS slot from one wave
+// instruction are serialised; after the first iteration a row's labels
+// concentrate on a few values, and the first lane's label is most often the
+// step's most frequent one.  The table then receives the same per-label sums
+// (exactly so for integer weights).  All 64 lanes must be active.
+__device__ __forceinline__ void merge_lead(uint32_t& lab, float& wt, bool unit) {
+  const unsigned long long act = __ballot(lab != kEmpty);
+  if (act == 0ull) return;
+  const int first = __ffsll((long long)act) - 1;
+  const uint32_t lead = (uint32_t)__builtin_amdgcn_readlane((int)lab, first);
+  const bool mine = lab == lead;
+  const unsigned long long m = __ballot(mine);
+  float sum;
+  if (unit) {
+    sum = (float)__popcll(m);
+  } else {
+    float x = mine ? wt : 0.0f;
+    for (int ofs = 32; ofs > 0; ofs >>= 1) x += __shfl_xor(x, ofs);
+    sum = x;
+  }
+  if (mine) {
+    if ((int)(threadIdx.x & 63) == first) wt = sum;
+    else lab = kEmpty;
+  }
+}
+
+// merge_lead within each 16-lane row, for k_sweep_group (one row per vertex;
+// the lanes of a row are active or inactive together).
+__device__ __forceinline__ void merge_lead16(uint32_t& lab, float& wt, bool unit) {
+  const unsigned long long act = __ballot(lab != kEmpty);
+  const int lane = (int)(threadIdx.x & 63);
+  const int row0 = lane & ~15;
+  const uint32_t ract = (uint32_t)(act >> row0) & 0xFFFFu;
+  const int first = row0 + (ract ? __ffs((int)ract) - 1 : 0);
+  const uint32_t lead = (uint32_t)__shfl((int)lab, first);
+  const bool mine = ract != 0u && lab == lead;
+  const unsigned long long m = __ballot(mine);
+  float sum;
+  if (unit) {
+    sum = (float)__popc((uint32_t)(m >> row0) & 0xFFFFu);
+  } else {
+    float x = mine ? wt : 0.0f;
+    x += dppf<0x128>(x);  // row_ror:8
+    x += dppf<0x124>(x);
+    x += dppf<0x122>(x);
+    x += dppf<0x121>(x);
+    sum = x;
+  }
+  if (mine) {
+    if (lane == first) wt = sum;
+    else lab = kEmpty;
+  }
+}
+
+__device__ __forceinline__ bool decide(unsigned long long best, int32_t cur, int pl,
+                                       uint32_t* cstar) {
+  if (best == 0ull) return false;  // no neighbour other than itself
+  const uint32_t c = unpack_label(best);
+  *cstar = c;
+  return (int32_t)c != cur && (!pl || (int32_t)c < cur);
+}
+
 // Index of the accelerator complex die (XCD) this wave runs on.
 __device__ __forceinline__ uint32_t xcc_id() {
   uint32_t x;

@@ -204,6 +204,43 @@ struct BatchArgs {
   long long* changed_last;         // changed vertices in its last iteration
 };
 
+// Batched runs as a persistent work queue (queue.hip).  Each graph's vertex
+// range is cut into chunks of 2^chunk_log2 vertices (the last one shorter);
+// an item is a chunk's global index.  Two queues alternate by iteration
+// parity; each is split into 8 parts, one per XCD, and all chunks of graph g
+// go to part g mod 8 (its labels then stay in one XCD's L2).  The sweep
+// kernel's resident workgroups pop items from their own XCD's part, then
+// from the others; the step kernel applies each graph's stop test and queues
+// the chunks marked for the next iteration.
+constexpr int kQueueMaxChunkLog2 = 10;   // chunks of at most 1024 vertices
+constexpr int kQueueMaxDegree = 512;     // longest row the queue kernel takes
+constexpr int kQueueCtrStride = 16;      // words between two queue counters
+struct QueueArgs {
+  const void* off;
+  const int32_t* tgt;
+  const float* w;                  // NULL: unit weights
+  int32_t* C0;                     // labels read in even iterations ...
+  int32_t* C1;                     // ... and odd ones (the same array in
+                                   // asynchronous mode)
+  uint8_t* F0;                     // flags of even / odd iterations
+  uint8_t* F1;
+  uint8_t* cmark;                  // per chunk: visit in the next iteration
+  const int64_t* cbase;            // G + 1: each graph's first chunk
+  const int32_t* cgraph;           // per chunk: its graph
+  uint32_t* items;                 // two queues of nchunks items each
+  const int64_t* qbase;            // 9: start of each XCD's part of a queue
+  unsigned int* qctr;              // [parity][xcd] head, tail (kQueueCtrStride apart)
+  unsigned int* gchanged;          // per graph: labels changed in this iteration
+  BatchArgs b;
+  DevStats* st;
+  int64_t nchunks;
+  int32_t chunk_log2;
+  int32_t group_max;               // rows of up to this many entries: 16 lanes
+  int async_mode;
+  int strict_rows;                 // every row's targets strictly increase
+  ProbeCfg probe;
+};
+
 // ---- launch wrappers (defined in the .hip files) ----------------------------
 // C[v'] = initial label of the caller's vertex inv[v'] (its id when init is
 // NULL; inv NULL: one order).
@@ -311,6 +348,22 @@ hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt,
                              const int32_t* C, double* sig, double* acc,
                              hipStream_t s);
 
+// Work-queue form of a batched run (queue.hip): queue every chunk of every
+// non-empty graph for iteration 0 (counters, marks and the odd flags
+// cleared, the odd labels copied in deterministic mode); per iteration the
+// counters reset, the sweep, the per-graph stop test and next queue; at the
+// end the flags (and deterministic labels) of graphs that stopped after an
+// odd number of iterations moved to F0 (C0).
+hipError_t launch_queue_begin(const QueueArgs& q, int64_t n, hipStream_t s);
+hipError_t launch_queue_iter_begin(const QueueArgs& q, hipStream_t s);
+hipError_t launch_queue_sweep(bool off64, const QueueArgs& q, int grid, hipStream_t s);
+hipError_t launch_queue_step(const QueueArgs& q, hipStream_t s);
+hipError_t launch_queue_finish(const QueueArgs& q, hipStream_t s);
+int queue_sweep_resident();
+// *dmax = the largest row length (atomic max; *dmax zeroed by the caller).
+hipError_t launch_max_degree(bool off64, const void* off, int64_t n, unsigned long long* dmax,
+                             hipStream_t s);
+
 // Threads per workgroup of each sweep class and resident-workgroup estimate.
 int sweep_block_threads(int cls);
 int sweep_items_per_block(int cls);
@@ -330,6 +383,10 @@ hipError_t launch_label_read_probe(const int32_t* tgt, int64_t m, const int32_t*
 hipError_t relabel_build(bool off64, const void* uoff, const int32_t* utgt, const float* uw,
                          int64_t n, int32_t* perm, int32_t* inv, void* noff, int32_t* ntgt,
                          float* nw, hipStream_t s);
+// Sort every row of a CSR by target id, weights (may be NULL) alongside
+// (rowsort.hip; n, m < 2^31).
+hipError_t sort_rows(bool off64, const void* off, int32_t* tgt, float* w, int64_t n, int64_t m,
+                     hipStream_t s);
 hipError_t relabel_locality(bool off64, const void* off, const int32_t* tgt, int64_t n,
                             unsigned long long* acc, hipStream_t s);
 hipError_t launch_unpermute_i32(const int32_t* in, const int32_t* perm, int64_t n, int32_t* out,

@@ -53,7 +53,9 @@ class lpa_tuning(ctypes.Structure):
                 ("hub_chunk", ctypes.c_int32), ("max_retries", ctypes.c_int32),
                 ("xcd_local", ctypes.c_int32), ("hub_table_cap", ctypes.c_int32),
                 ("relabel", ctypes.c_int32), ("probe", ctypes.c_int32),
-                ("table_values", ctypes.c_int32)]
+                ("table_values", ctypes.c_int32), ("batch_queue", ctypes.c_int32),
+                ("queue_chunk", ctypes.c_int32), ("queue_group", ctypes.c_int32),
+                ("sort_rows", ctypes.c_int32)]
 
 
 class lpa_options(ctypes.Structure):

@@ -66,11 +66,13 @@ def _cases():
     ]
 
 
+@pytest.mark.parametrize("sort_rows", [1, 0])
 @pytest.mark.parametrize("launch", [lpa.LAUNCH_EAGER, lpa.LAUNCH_GRAPH])
 @pytest.mark.parametrize("name,g,tun", _cases(), ids=[c[0] for c in _cases()])
-def test_det_parity_internal_order(name, g, tun, launch):
+def test_det_parity_internal_order(name, g, tun, launch, sort_rows):
+    # internal rows sorted by target (the default) or in the caller's order
     ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
-    G = _graph(g, 1, **tun)
+    G = _graph(g, 1, sort_rows=sort_rows, **tun)
     _assert_matches(ref, G.run("det", launch=launch))
     # a second run on the same handle (the captured iteration is replayed)
     _assert_matches(ref, G.run("det", launch=launch))
