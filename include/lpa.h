@@ -492,6 +492,22 @@ lpa_status lpa_autotune(const lpa_csr* csr, int32_t num_graphs, const int64_t* v
 lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q);
 
 /*
+ * lpa_modularity that allocates no device memory, for callers that cannot
+ * allocate: code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result and errors as lpa_modularity,
+ * for graphs of at most LPA_MODULARITY_NOALLOC_MAX_VERTICES vertices
+ * (larger: LPA_ERR_INVALID, nothing launched).  Its scratch (per-community
+ * sums and accumulators, 32 MiB) is a fixed array in the library's device
+ * code: each GPU the library runs on holds one copy until the process ends,
+ * and every call on that GPU uses it, so calls that overlap on one GPU (from
+ * several threads or streams) race and must not be made; each call clears
+ * what it uses.  Host labels are staged through the handle's own buffer
+ * (allocated by lpa_create).
+ */
+#define LPA_MODULARITY_NOALLOC_MAX_VERTICES 4194304
+lpa_status lpa_modularity_noalloc(lpa_graph g, const int32_t* labels, double* q);
+
+/*
  * Ceiling of the sweep kernels' memory side: the rate (CSR entries per
  * second, into *reads_per_s) of a pass that does nothing but read every
  * entry's target and then its neighbour's label, in the order and vertex

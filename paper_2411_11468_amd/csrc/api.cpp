@@ -1570,4 +1570,41 @@ lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q) {
   return LPA_OK;
 }
 
+// The same result as lpa_modularity with no device allocation: Sigma_c and
+// the accumulators in the GPU's file-scope scratch (graph.hip), host labels
+// staged through the handle's own buffer, the accumulators read back with
+// the handle's pinned counters.
+lpa_status lpa_modularity_noalloc(lpa_graph g, const int32_t* labels, double* q) {
+  if (!g || !q) return fail(LPA_ERR_INVALID, "NULL argument");
+  *q = 0.0;
+  if (g->n > kModScratchVertices)
+    return fail(LPA_ERR_INVALID, "lpa_modularity_noalloc takes at most " +
+                                     std::to_string(kModScratchVertices) +
+                                     " vertices (its fixed scratch); use lpa_modularity");
+  if (g->n == 0) return LPA_OK;
+  if (!labels) return fail(LPA_ERR_INVALID, "labels is NULL");
+  hipStream_t s = g->stream;
+  double* sig = nullptr;
+  double* acc = nullptr;
+  LPA_HIP(modularity_scratch(&sig, &acc));
+  const int32_t* lab = labels;
+  if (!is_device_ptr(labels)) {
+    if (lpa_status e = stage_labels(g, labels, g->pend_v)) return e;
+    lab = g->pend_v;
+  }
+  LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(g->st), 0u,
+                          sizeof(DevStats) / sizeof(uint32_t), s));
+  LPA_HIP(launch_check_labels(g->n, lab, g->st, s));
+  LPA_HIP(launch_modularity(g->off64, g->uoff, g->utgt, g->uw, g->n, g->m, lab, sig, acc, s));
+  LPA_HIP(hipMemcpyAsync(g->st->mod_acc, acc, sizeof(double) * 4, hipMemcpyDeviceToDevice, s));
+  LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  if (g->st_host->error & 4u) return fail(LPA_ERR_INVALID, "labels must lie in [0, N)");
+  const double two_m = g->st_host->mod_acc[1];
+  *q = two_m > 0.0 ? g->st_host->mod_acc[0] / two_m -
+                         g->st_host->mod_acc[2] / (two_m * two_m)
+                   : 0.0;
+  return LPA_OK;
+}
+
 }  // extern "C"

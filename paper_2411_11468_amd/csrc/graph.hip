@@ -3,6 +3,8 @@
 // vertex in its own community and unprocessed), the frontier of flagged
 // vertices ("for all unprocessed i ... mark i processed"), the hub slice plan,
 // the deterministic-mode label apply, and fp64 modularity (Eq. 1).
+#include <mutex>
+
 #include "lpa_device.h"
 #include "lpa_mlp.h"
 #include "lpa_record.h"
@@ -1385,6 +1387,34 @@ __global__ __launch_bounds__(kBT) void k_mod_sq(const double* sig, int64_t n, do
     s += sig[c] * sig[c];
   const double t = block_sum_f64(s, sh);
   if (threadIdx.x == 0) atomicAdd(&acc[2], t);
+}
+
+// ---- modularity scratch for callers that cannot allocate ----------------------
+// Sigma_c (one double per vertex) and the four accumulators of
+// lpa_modularity_noalloc live in this file-scope array: one copy per GPU,
+// 32 MiB, held until the process ends.  Host code never takes the array's
+// name as an address (it is a host-side stand-in); the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) double scratch[kModScratchVertices + 4];
+
+hipError_t modularity_scratch(double** sig, double** acc) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *sig = addr[dev];
+  *acc = addr[dev] + kModScratchVertices;
+  return hipSuccess;
 }
 
 hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt, const float* w,

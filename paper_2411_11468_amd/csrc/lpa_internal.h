@@ -70,6 +70,9 @@ struct DevStats {
   unsigned long long fneg;                      // of those, processed and changed
   unsigned long long trace_n;                   // samples drawn so far
   unsigned long long trace_first;               // trace_n when the iteration began
+  double mod_acc[4];                            // lpa_modularity_noalloc: the
+                                                // accumulators, read back with
+                                                // the counters
 };
 
 // Learned-skipping parameters of a run (zero: plain run).
@@ -343,6 +346,11 @@ int tv_max_resident(int cls, int bits);
 // Bucket count of a hub of degree d: 2^lgb buckets of about chunk entries.
 int hub_bucket_log2(int64_t d, int chunk);
 constexpr int kHubMaxBucketLog2 = 12;   // 4096 buckets (LDS histogram of k_hub_part)
+// lpa_modularity_noalloc: the device addresses of the current GPU's
+// file-scope scratch (kModScratchVertices doubles for Sigma_c, then 4
+// accumulators), looked up once per device.
+constexpr int64_t kModScratchVertices = (int64_t)1 << 22;
+hipError_t modularity_scratch(double** sig, double** acc);
 hipError_t launch_modularity(bool off64, const void* off, const int32_t* tgt,
                              const float* w, int64_t n, int64_t m,
                              const int32_t* C, double* sig, double* acc,

@@ -112,7 +112,7 @@ EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run"
             "lpa_predictor_gradient", "lpa_predictor_adam", "lpa_predictor_train",
             "lpa_predictor_predict", "lpa_learned_options_default", "lpa_set_predictor",
             "lpa_learned_history", "lpa_get_records", "lpa_trace", "lpa_autotune",
-            "lpa_label_read_rate")
+            "lpa_label_read_rate", "lpa_modularity_noalloc")
 
 _lib = None
 
@@ -151,6 +151,8 @@ def load_library(path: str | None = None):
     lib.lpa_run.restype = ctypes.c_int
     lib.lpa_modularity.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     lib.lpa_modularity.restype = ctypes.c_int
+    lib.lpa_modularity_noalloc.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.lpa_modularity_noalloc.restype = ctypes.c_int
     lib.lpa_label_read_rate.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     lib.lpa_label_read_rate.restype = ctypes.c_int
     lib.lpa_graph_classes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -436,6 +438,15 @@ def lpa_autotune(offsets, targets, weights=None, *, v_off=None, mode: int = MODE
     _check(lib.lpa_autotune(ctypes.byref(g), ng, _addr(vo), s, ctypes.byref(o),
                             float(budget_ms), ctypes.byref(best), ctypes.byref(rep)))
     return best, {f: getattr(rep, f) for f, _ in lpa_tune_report._fields_ if f != "reserved"}
+
+
+MODULARITY_NOALLOC_MAX_VERTICES = 4194304
+
+
+def lpa_modularity_noalloc(handle, labels) -> float:
+    q = ctypes.c_double(0.0)
+    _check(load_library().lpa_modularity_noalloc(handle, _addr(labels), ctypes.byref(q)))
+    return q.value
 
 
 def lpa_modularity(handle, labels) -> float:
