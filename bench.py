@@ -128,6 +128,25 @@ def cpu_baseline(g, budget_edges: int) -> dict:
                        f"{dt:.1f} s on one host core")}
 
 
+def oracle_full_run() -> dict:
+    """The oracle (one thread, as written) run to termination on the whole
+    R-MAT scale 22 graph (4,194,304 vertices, integer weights 1..8, the
+    second configuration): |E| * iterations / its wall time."""
+    import graphgen
+    import oracle
+    wl = WORKLOADS["rmat22"]
+    g = make_graph(wl)
+    t0 = time.perf_counter()
+    r = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+    dt = time.perf_counter() - t0
+    return {"value": g.num_edges * r.iterations / dt, "unit": "edges/s", "cores": 1,
+            "kind": "oracle", "ms": 1e3 * dt, "iterations": r.iterations,
+            "sample": f"the whole R-MAT scale 22 graph ({g.num_vertices} vertices, "
+                      f"{g.num_edges} CSR entries, integer weights), deterministic "
+                      f"synchronous run to termination ({r.iterations} iterations) on one "
+                      f"host core"}
+
+
 def run_batched(args, wl) -> int:
     """Batched LPA over 8,192 packed graphs against per-graph runs."""
     import torch
@@ -352,7 +371,13 @@ def main() -> int:
         wall_graph = time.perf_counter() - t1
         graph_launch = {"ms_per_step": 1e3 * wall_graph / args.steps,
                         "edges_per_s": m * sum(iters) / wall_graph}
+    # Eq. 1 on the final labels (after the timed region): its time and rate,
+    # at 8 B per entry (target + neighbour label) plus 4 B with weights
+    torch.cuda.synchronize()
+    tq = time.perf_counter()
     q = G.modularity(labels)
+    mod_s = time.perf_counter() - tq
+    mod_bytes = (8.0 + (0.0 if g.weights is None or wl["weights"] == "unit" else 4.0)) * m
     prof = G.profile()
     # memory-side ceiling of the sweeps: a pass that only reads each entry's
     # target and neighbour label (after the timed region; resets the labels)
@@ -394,19 +419,32 @@ def main() -> int:
         scan_total["traffic_GBps"] = tb / (scan_ms * 1e-3) / 1e9
         scan_total["traffic_frac"] = scan_total["traffic_GBps"] / HBM_PEAK_GBPS
 
-    if args.calibrate_copy:
-        src = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # measured copy peak: a 2 GiB device-to-device copy (torch's copy
+    # kernel), read + write bytes over its event time, best of five; the
+    # same kernel calibrates the HBM counters (--calibrate-copy)
+    src = torch.empty(2 ** 29, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_gbps = 0.0
+    for _ in range(5 if not args.calibrate_copy else 3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        copy_gbps = max(copy_gbps, 2.0 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    torch.cuda.synchronize()
+    del src, dst
+    log(f"copy peak {copy_gbps:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         cpu = cpu_baseline(g, args.cpu_budget_edges)
         log(f"cpu baseline {cpu['value'] / 1e6:.1f} M edges/s ({time.perf_counter() - t0:.1f}s)")
+        if args.workload == "rmat26":
+            cpu["full_run"] = oracle_full_run()
+            log(f"oracle full run: {cpu['full_run']}")
 
     out = {
         "metric": METRIC,
@@ -438,13 +476,17 @@ def main() -> int:
                      "avg_launch_us": 1e3 * dom["total_ms"] / dom["launches"],
                      "traffic_GBps": (None if traffic is None else
                                       traffic / (dom["total_ms"] / dom["launches"] * 1e-3) / 1e9),
-                     "traffic_note": traffic_note},
+                     "traffic_note": traffic_note,
+                     "copy_peak_GBps": copy_gbps,
+                     "frac_of_copy_peak": achieved / copy_gbps if copy_gbps > 0 else None},
         "scan_total": scan_total,
         "cpu_baseline": cpu,
         "iterations": iters,
         "time_to_termination_ms": float(np.median([1e3 * wall / args.steps])),
         "scanned_edges_per_s": scanned / wall,
         "modularity": q,
+        "modularity_call": {"ms": 1e3 * mod_s, "entries_per_s": m / mod_s,
+                            "alg_GBps": mod_bytes / mod_s / 1e9},
         "kernels": kernels,
         "label_read_ceiling": label_ceiling(prof, reads_per_s),
         "graph_launch": graph_launch,

@@ -162,8 +162,21 @@ typedef struct lpa_graph_s* lpa_graph;
  * sort_rows: with the internal order (relabel), sort each row of the
  *   internal CSR by target id at create, so that the label reads of a row
  *   walk upwards through the label array and the entries in its dense
- *   low-id part share cache lines.  1 = sort, 0 = keep
- *   the caller's entry order, -1 (default) = sort.  The same results.
+ *   low-id part share cache lines.  1 = sort, 0 = keep the caller's entry
+ *   order, -1 (default) = sort.  The same results.
+ * block_threads: threads per workgroup of the four workgroup classes (rows
+ *   of wave+1 .. block entries): 0 (default) = 256, 256, 512 and 1024 for
+ *   the 2047-, 4095-, 8191- and 16383-slot tables; 256, 512 or 1024 = that
+ *   many for all four.  Learned runs keep the defaults.
+ * table_load: the hashtable capacity of a row of D entries, as a bound on
+ *   its load: 1 = nextPow2(D) - 1 (the smallest 2^m > D, minus one: the
+ *   paper's, up to full load), 2 (default) = the smallest 2^m >= 2D, minus
+ *   one (load <= 1/2), 4 = the smallest 2^m >= 4D, minus one (load <= 1/4),
+ *   capped by the class's LDS table.  Same results.
+ * pull_divisor: the neighbour flags of an iteration are pulled (every vertex
+ *   checks its row) when the changed rows hold at least 1/pull_divisor of
+ *   the CSR entries, else pushed (each changed row flags its neighbours);
+ *   default 16.  Same flags.
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -181,6 +194,9 @@ typedef struct lpa_tuning {
   int32_t queue_chunk;
   int32_t queue_group;
   int32_t sort_rows;
+  int32_t block_threads;
+  int32_t table_load;
+  int32_t pull_divisor;
 } lpa_tuning;
 
 /*
@@ -455,19 +471,25 @@ lpa_status lpa_trace(lpa_graph g, const lpa_options* opt, double sample_rate, ui
 
 /*
  * Autotuner: pick lpa_tuning for a graph (num_graphs = 0) or a packed batch
- * (num_graphs, v_off as for lpa_create_batched) by successive halving over a
- * grid of class thresholds (small4 2/4, small16 8/16, wave 128/256/512,
- * block 2048/4096/8192) and slice sizes (4096/8192), the defaults included.
- * Each candidate is a fresh handle timed on complete runs with opt (NULL:
- * defaults; profile and learned are turned off); each round keeps the
- * fastest third and doubles the timed runs.  The search stops early when
- * budget_ms of wall time is spent (the best measured so far is returned).
+ * (num_graphs, v_off as for lpa_create_batched) by successive halving in
+ * stages, each over a grid around the best tuning so far (the defaults
+ * first): for a batch, the schedule (batch_queue 0, or 1 with queue_chunk
+ * 128/256/512/1024 and queue_group 16/32/64); unless the work queue won,
+ * the class thresholds (small4 2/4, small16 8/16, wave 128/256/512, block
+ * 2048/4096/8192) with slice sizes (4096/8192), then the workgroup sizes
+ * (block_threads 0/256/512/1024), table capacities (table_load 1/2/4) and
+ * flag policy (pull_divisor 8/16/32).  Each candidate is a fresh handle
+ * timed on complete runs with opt (NULL: defaults; profile and learned are
+ * turned off); each round keeps the fastest third and doubles the timed
+ * runs; a tuning the handle refuses (LPA_ERR_UNSUPPORTED) drops out.  The
+ * stages share budget_ms of wall time (the best measured so far is
+ * returned when it runs out).
  * The graph is validated once, on the first handle.  Device-resident arrays
  * avoid a copy per candidate.
  * Errors: as lpa_create / lpa_run; LPA_ERR_INVALID for budget_ms <= 0.
  */
 typedef struct lpa_tune_report {
-  int32_t candidates;   /* grid size */
+  int32_t candidates;   /* grid sizes, summed over the stages */
   int32_t runs;         /* lpa_run calls made */
   int32_t rounds;
   int32_t reserved;

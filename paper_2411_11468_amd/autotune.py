@@ -1,7 +1,9 @@
 """Autotuned lpa_tuning with a cache keyed by the graph's degree histogram.
 
-The search itself is lpa_autotune in liblpa.so (successive halving over class
-thresholds and slice sizes, each candidate timed on complete runs).  Graphs
+The search itself is lpa_autotune in liblpa.so (successive halving in stages:
+the batched schedule, class thresholds and slice sizes, workgroup sizes,
+table capacities and the flag policy; each candidate timed on complete
+runs).  Graphs
 whose degree distributions agree to two significant digits per power-of-two
 bin (and in vertex / entry counts) share a cache entry.
 """
@@ -16,7 +18,9 @@ import numpy as np
 from . import lpa
 
 TUNING_FIELDS = ("small4", "small16", "wave", "block", "hub_chunk", "max_retries", "xcd_local",
-                 "hub_table_cap", "relabel", "probe", "table_values")
+                 "hub_table_cap", "relabel", "probe", "table_values", "batch_queue",
+                 "queue_chunk", "queue_group", "sort_rows", "block_threads", "table_load",
+                 "pull_divisor")
 
 
 def _round2(x: int) -> int:

@@ -179,6 +179,11 @@ struct lpa_graph_s {
     } else if (kid == kKidHubPart || kid == kKidHubDirect) {
       edges = (int64_t)h.edges[kClassHub];
       bytes = eb * edges;
+    } else if (kid == kKidHubReduce) {
+      // not the method's bytes: the (label, sum) pairs the slices wrote,
+      // 8 B each, read back and reduced per bucket (their entries)
+      edges = (int64_t)h.hub_pairs;
+      bytes = 8.0 * (double)h.hub_pairs;
     } else if (kid == kKidHubFin) {
       bytes = chb * h.changed[kClassHub] + (double)h.changed[kClassHub];
     } else if (kid == kKidFrontier) {
@@ -379,6 +384,9 @@ void lpa_tuning_default(lpa_tuning* t) {
   t->queue_chunk = 512;
   t->queue_group = 64;
   t->sort_rows = -1;
+  t->block_threads = 0;
+  t->table_load = 2;
+  t->pull_divisor = 16;
 }
 
 void lpa_learned_options_default(lpa_learned_options* o) {
@@ -422,7 +430,11 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
          (t.queue_chunk >= 64 && t.queue_chunk <= (1 << kQueueMaxChunkLog2) &&
           (t.queue_chunk & (t.queue_chunk - 1)) == 0)) &&
         (t.queue_group == 0 || (t.queue_group >= 16 && t.queue_group <= 64)) &&
-        t.sort_rows >= -1 && t.sort_rows <= 1))
+        t.sort_rows >= -1 && t.sort_rows <= 1 &&
+        (t.block_threads == 0 || t.block_threads == 256 || t.block_threads == 512 ||
+         t.block_threads == 1024) &&
+        (t.table_load == 1 || t.table_load == 2 || t.table_load == 4) &&
+        t.pull_divisor >= 1 && t.pull_divisor <= 4096))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   // the ablation kernels' largest LDS table has 8191 slots (rows of <= 4096)
   if (t.table_values != 0) G->tun.block = std::min(G->tun.block, 4096);
@@ -860,6 +872,8 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   a.async_mode = async_mode;
   a.probe = ProbeCfg{g->tun.max_retries, g->tun.probe};
   a.rec = g->lrec;
+  a.tload = g->tun.table_load;
+  a.block_threads = g->tun.block_threads;
   for (int c = kClassHub - 1; c >= 1; --c) {
     if (g->cls_count[c] == 0) continue;
     a.cls = c;
@@ -898,7 +912,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   // flag the neighbours of the changed vertices: the decide kernel picks
   // push or pull from this iteration's counters, the other kernels return
   if (lpa_status e = mark(kKidDecide)) return e;
-  LPA_HIP(launch_flag_decide(g->st, g->m, g->n, o.flag_mode, s));
+  LPA_HIP(launch_flag_decide(g->st, g->m, g->n, o.flag_mode, g->tun.pull_divisor, s));
   if (lpa_status e = mark(kKidPush)) return e;
   LPA_HIP(launch_push_lists(g->off64, g->off, g->tgt, g->lists, g->chg, g->F, g->st,
                             g->push_grid, s));
@@ -1539,6 +1553,26 @@ lpa_status lpa_label_read_rate(lpa_graph g, int32_t reps, double* reads_per_s) {
   return LPA_OK;
 }
 
+// The CSR and labels Eq. 1's edge pass reads.  With an internal order the
+// pass goes through the internal CSR (degree order, rows sorted by target,
+// where a neighbour-label read costs half as much as in an unordered
+// caller's order), with the labels first moved to the internal positions
+// (into the deterministic next-label array, free between runs).  The sums
+// are the same up to fp64 rounding order.  lab NULL in the result: the move
+// failed to launch.
+struct ModCsr {
+  const void* off;
+  const int32_t* tgt;
+  const float* w;
+  const int32_t* lab;
+};
+static ModCsr modularity_csr(lpa_graph g, const int32_t* lab) {
+  if (!g->perm) return ModCsr{g->uoff, g->utgt, g->uw, lab};
+  if (launch_unpermute_i32(lab, g->inv, g->n, g->Cn, g->stream) != hipSuccess)
+    return ModCsr{nullptr, nullptr, nullptr, nullptr};
+  return ModCsr{g->off, g->tgt, g->w, g->Cn};
+}
+
 lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q) {
   if (!g || !q) return fail(LPA_ERR_INVALID, "NULL argument");
   *q = 0.0;
@@ -1560,7 +1594,9 @@ lpa_status lpa_modularity(lpa_graph g, const int32_t* labels, double* q) {
   LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
   LPA_HIP(hipStreamSynchronize(s));
   if (g->st_host->error & 4u) return fail(LPA_ERR_INVALID, "labels must lie in [0, N)");
-  LPA_HIP(launch_modularity(g->off64, g->uoff, g->utgt, g->uw, g->n, g->m, lab, g->mod_sig,
+  const ModCsr mc = modularity_csr(g, lab);
+  if (!mc.lab) return fail(LPA_ERR_HIP, "moving the labels to the internal order failed");
+  LPA_HIP(launch_modularity(g->off64, mc.off, mc.tgt, mc.w, g->n, g->m, mc.lab, g->mod_sig,
                             g->mod_acc, s));
   double acc[4];
   LPA_HIP(hipMemcpyAsync(acc, g->mod_acc, sizeof(acc), hipMemcpyDeviceToHost, s));
@@ -1595,7 +1631,9 @@ lpa_status lpa_modularity_noalloc(lpa_graph g, const int32_t* labels, double* q)
   LPA_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(g->st), 0u,
                           sizeof(DevStats) / sizeof(uint32_t), s));
   LPA_HIP(launch_check_labels(g->n, lab, g->st, s));
-  LPA_HIP(launch_modularity(g->off64, g->uoff, g->utgt, g->uw, g->n, g->m, lab, sig, acc, s));
+  const ModCsr mc = modularity_csr(g, lab);
+  if (!mc.lab) return fail(LPA_ERR_HIP, "moving the labels to the internal order failed");
+  LPA_HIP(launch_modularity(g->off64, mc.off, mc.tgt, mc.w, g->n, g->m, mc.lab, sig, acc, s));
   LPA_HIP(hipMemcpyAsync(g->st->mod_acc, acc, sizeof(double) * 4, hipMemcpyDeviceToDevice, s));
   LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
   LPA_HIP(hipStreamSynchronize(s));

@@ -457,6 +457,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
   if (tid == 0) {
     st->processed = 0; st->pending = 0;
     st->pull_scanned = 0; st->pull_mode = 0;
+    st->hub_pairs = 0;
     st->reverted = 0;
     st->graphs_left = 0;
     // Pick-Less in iterations l with l mod rho == 0, counting from 0
@@ -862,9 +863,10 @@ hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const Trac
 // neighbour, about 1/p entries per vertex when the changed rows hold a share
 // p of the entries.  On R-MAT scale 26 the two cost the same near p = 1/16
 // (push of a quarter of the entries: 18.6 ms; pull at p near 1/2: 2.7 ms), so
-// k_flag_decide picks pull when the changed rows hold at least 1/16 of the CSR
-// entries, push otherwise; the kernels of the other way return at once.
-__global__ void k_flag_decide(DevStats* st, int64_t m, int64_t n, int force) {
+// k_flag_decide picks pull when the changed rows hold at least 1/pdiv of the
+// CSR entries (lpa_tuning.pull_divisor, default 16), push otherwise; the
+// kernels of the other way return at once.
+__global__ void k_flag_decide(DevStats* st, int64_t m, int64_t n, int force, int pdiv) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop) return;
   unsigned long long fw = 0, changed = 0;
   for (int c = 0; c < kNumClasses; ++c) {
@@ -883,11 +885,14 @@ __global__ void k_flag_decide(DevStats* st, int64_t m, int64_t n, int force) {
       return;
     }
   }
-  st->pull_mode = force == 2 ? 1u : force == 1 ? 0u : (16ull * fw >= (unsigned long long)m ? 1u : 0u);
+  st->pull_mode = force == 2   ? 1u
+                  : force == 1 ? 0u
+                               : ((unsigned long long)pdiv * fw >= (unsigned long long)m ? 1u : 0u);
 }
 
-hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, hipStream_t s) {
-  hipLaunchKernelGGL(k_flag_decide, dim3(1), dim3(64), 0, s, st, m, n, force);
+hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, int pdiv,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_decide, dim3(1), dim3(64), 0, s, st, m, n, force, pdiv);
   return hipGetLastError();
 }
 

@@ -43,6 +43,19 @@ __device__ __forceinline__ uint32_t table_p1(uint32_t d) {
   return (d <= 1u) ? 1u : ((1u << (32 - __clz(2u * d - 1u))) - 1u);
 }
 
+// Capacity under a load bound of 1/load for a row of d >= 1 entries in a
+// table of `slots` slots (2^m - 1): load 1 = smallest 2^m > d, minus one
+// (the paper's nextPow2(d) - 1: up to full load), 2 = table_p1 (the
+// default: load <= 1/2), 4 = smallest 2^m >= 4d, minus one (load <= 1/4);
+// never above `slots`, which every class sizes for load <= 1/2.
+__device__ __forceinline__ uint32_t table_p1_load(uint32_t d, int load, uint32_t slots) {
+  uint32_t p;
+  if (load == 1) p = (d <= 1u) ? 1u : ((1u << (32 - __clz(d))) - 1u);
+  else if (load == 4) p = table_p1(2u * d);
+  else p = table_p1(d);
+  return p < slots ? p : slots;
+}
+
 // ---- DPP -------------------------------------------------------------------
 // dpp_ctrl encodings (GCN/CDNA): quad_perm 0x00-0xFF, row_shr:n 0x110+n,
 // row_ror:n 0x120+n, row_bcast:15 0x142, row_bcast:31 0x143.

@@ -37,6 +37,8 @@ struct DevStats {
   unsigned long long reverted;                  // Cross-Check: changes reverted
                                                 // in this iteration
   unsigned int active[kNumClasses];             // vertices appended per class
+  unsigned long long hub_pairs;                 // (label, sum) pairs the hub slices
+                                                // wrote this iteration
   unsigned int hub_items;                       // hub slices queued this iteration
   unsigned int hub_bitems;                      // hub label buckets queued this iteration
   // run control, resident on the device so that iterations can be launched
@@ -128,6 +130,8 @@ struct SweepArgs {
   int async_mode;         // 1: write labels in place, 0: queue them
   ProbeCfg probe;         // probe sequence and probes before the linear continuation
   unsigned long long* rec;  // learned variant: per-vertex state records
+  int tload;              // table capacity rule (lpa_tuning.table_load: 1, 2, 4)
+  int block_threads;      // workgroup classes: threads (0: per-class defaults)
   // the caller's CSR and inv (internal id -> caller id; NULL when the two
   // orders agree), read by the table-free first sweep
   const void* uoff;
@@ -289,7 +293,8 @@ hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
                                    const TraceArgs& tr, int grid, hipStream_t s);
 hipError_t launch_trace_label(const DevStats* st, const uint8_t* chg, const TraceArgs& tr,
                               hipStream_t s);
-hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, hipStream_t s);
+hipError_t launch_flag_decide(DevStats* st, int64_t m, int64_t n, int force, int pdiv,
+                              hipStream_t s);
 // Cross-Check (Sec. 4.1): save the labels before an iteration; one round of
 // the id-order revert decisions (st->cc_moved set when one changes; the host
 // repeats rounds until none does); apply the reverts.  perm/inv map caller

@@ -325,7 +325,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
     int64_t o, d;
     row_of<OffT>(a.off, v, &o, &d);
     const int32_t cur = a.C[v];
-    const uint32_t p1 = table_p1((uint32_t)d);
+    const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
     unsigned long long best = 0;
     for (int64_t base = 0; base < d; base += 64 * U) {
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   if (item < count) head(item, v, o, d, j, wt);
   while (item < count) {
     const int32_t cur = a.C[v];
-    const uint32_t p1 = table_p1((uint32_t)d);
+    const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     uint32_t lab[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
     int64_t o, d;
     row_of<OffT>(a.off, v, &o, &d);
     const int32_t cur = a.C[v];
-    const uint32_t p1 = table_p1((uint32_t)d);
+    const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
     for (int64_t base = 0; base < d; base += G * U) {
       int32_t j[U];
@@ -632,7 +632,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     // Own label, read before the barriers below: in asynchronous mode thread 0
     // overwrites it, and every thread must reach the same move decision.
     const int32_t cur = a.C[v];
-    const uint32_t p1 = table_p1((uint32_t)d);
+    const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
     unsigned long long best = 0;
     for (int64_t base = 0; base < d; base += (int64_t)BT * U) {
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     // own label, read before the barriers below: in asynchronous mode thread
     // 0 overwrites it, and every thread must reach the same move decision
     const int32_t cur = a.C[v];
-    const uint32_t p1 = table_p1((uint32_t)d);
+    const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     uint32_t lab[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __syncthreads();
   const uint32_t nitems = a.st->hub_items;
-  unsigned long long my_edges = 0;
+  unsigned long long my_edges = 0, my_pairs = 0;
   // U entries per thread in flight: targets, then their labels, then the
   // table inserts.  The first BT*U targets of the next slice (its head) are
   // loaded before the barrier that ends the current slice's accumulation, so
@@ -1030,7 +1030,10 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     const uint32_t total = block_exclusive_scan<BT, kMaxB / BT>(hist, nb, wsum);
     uint32_t* bo = a.boff + boff0 + (int64_t)c * (nb + 1);
     for (uint32_t b = tid; b < nb; b += BT) bo[b] = hist[b];
-    if (tid == 0) bo[nb] = total;
+    if (tid == 0) {
+      bo[nb] = total;
+      my_pairs += total;
+    }
     const int64_t base = (slice0 + c) * (int64_t)a.chunk;
     for (uint32_t s = tid; s < p1c; s += BT) {
       const uint32_t kk = keys[s];
@@ -1047,7 +1050,8 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     it = nit;
     cur = nxt;
   }
-  // one atomic per workgroup
+  // one atomic per workgroup (my_pairs lives in thread 0: the (label, sum)
+  // pairs its slices wrote, read back by k_hub_reduce)
   __shared__ unsigned long long we[BT / 64];
   const unsigned long long e = wave_sum_u64(my_edges);
   if ((tid & 63) == 0) we[tid >> 6] = e;
@@ -1056,6 +1060,7 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     unsigned long long t = 0;
     for (int q = 0; q < BT / 64; ++q) t += we[q];
     if (t) atomicAdd(&a.st->edges[kClassHub], t);
+    if (my_pairs) atomicAdd(&a.st->hub_pairs, my_pairs);
   }
 }
 
@@ -1118,17 +1123,27 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
       }
       __syncthreads();
       const uint32_t total = block_exclusive_scan<BT, kRuns / BT>(start, cn, wsum);
-      for (uint32_t g = tid; g < total; g += BT) {
-        uint32_t lo = 0, hi = cn - 1;  // largest i with start[i] <= g
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi + 1) >> 1;
-          if (start[mid] <= g) lo = mid; else hi = mid - 1;
+      // whole-wave steps (the last one partial), so that the lanes holding
+      // the label of the wave's first pair can merge before the inserts:
+      // the runs of different slices repeat the same labels
+      for (uint32_t g0 = 0; g0 < total; g0 += BT) {
+        const uint32_t g = g0 + tid;
+        uint32_t kk = kEmpty;
+        float vv = 0.0f;
+        if (g < total) {
+          uint32_t lo = 0, hi = cn - 1;  // largest i with start[i] <= g
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= g) lo = mid; else hi = mid - 1;
+          }
+          const uint32_t c = c0 + lo;
+          const uint32_t e = bo[c * nb1 + b] + (g - start[lo]);
+          const int64_t idx = (slice0 + c) * (int64_t)a.chunk + e;
+          kk = a.part_keys[idx];
+          vv = a.part_vals[idx];
         }
-        const uint32_t c = c0 + lo;
-        const uint32_t e = bo[c * nb1 + b] + (g - start[lo]);
-        const int64_t idx = (slice0 + c) * (int64_t)a.chunk + e;
-        const uint32_t kk = a.part_keys[idx];
-        const float vv = a.part_vals[idx];
+        merge_lead(kk, vv, false);
+        if (kk == kEmpty) continue;
         if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.probe)) {
           float after;
           (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, p1g, kk, vv, a.probe,
@@ -1481,8 +1496,29 @@ int sweep_max_resident(int cls) {
 int hub_block_threads() { return kHubThreads; }
 int hub_max_resident() { return 256; }
 
+// Workgroup classes with another thread count (lpa_tuning.block_threads).
+template <typename OffT, int BT>
+static hipError_t sweep_block_bt(int cls, const SweepArgs& a, int grid, hipStream_t s) {
+  switch (cls) {
+    case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, BT, 4, false>), dim3(grid), dim3(BT), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 4095, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 8191, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 16383, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename OffT, bool FEAT>
 static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
+  if (!FEAT && cls >= 5 && cls <= 8 && a.block_threads != 0) {
+    switch (a.block_threads) {
+      case 256: return sweep_block_bt<OffT, 256>(cls, a, grid, s);
+      case 512: return sweep_block_bt<OffT, 512>(cls, a, grid, s);
+      case 1024: return sweep_block_bt<OffT, 1024>(cls, a, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (cls) {
     case 1:
       if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_small<OffT, 4, true>), dim3(grid), dim3(256), 0, s, a);

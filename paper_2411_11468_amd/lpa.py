@@ -55,7 +55,8 @@ class lpa_tuning(ctypes.Structure):
                 ("relabel", ctypes.c_int32), ("probe", ctypes.c_int32),
                 ("table_values", ctypes.c_int32), ("batch_queue", ctypes.c_int32),
                 ("queue_chunk", ctypes.c_int32), ("queue_group", ctypes.c_int32),
-                ("sort_rows", ctypes.c_int32)]
+                ("sort_rows", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("table_load", ctypes.c_int32), ("pull_divisor", ctypes.c_int32)]
 
 
 class lpa_options(ctypes.Structure):

@@ -19,6 +19,8 @@ def _dev(a):
 def _valid(t):
     assert 0 <= t.small4 <= 4 and t.small4 <= t.small16 <= 16 and t.small16 <= t.wave
     assert t.wave <= 512 and t.wave <= t.block <= 8192 and 64 <= t.hub_chunk <= 8192
+    assert t.block_threads in (0, 256, 512, 1024) and t.table_load in (1, 2, 4)
+    assert 1 <= t.pull_divisor <= 4096 and t.batch_queue in (-1, 0, 1)
 
 
 def test_autotune_single_graph():
@@ -44,3 +46,24 @@ def test_autotune_batch_and_budget():
     assert rep["runs"] >= 2
     with pytest.raises(lpa.LpaError):
         lpa.lpa_autotune(_dev(g.offsets), _dev(g.targets), budget_ms=0.0)
+
+
+def test_autotune_batch_schedule_and_labels():
+    # a batch: the search covers the schedule (work queue chunk and group
+    # sizes, or the class kernels); the tuned deterministic run equals the
+    # oracle graph by graph
+    g, v_off = graphgen.planted_partition_batch(48, 4, n_range=(256, 6000))
+    t, rep = lpa.lpa_autotune(_dev(g.offsets), _dev(g.targets), _dev(g.weights), v_off=v_off,
+                              mode=lpa.MODE_DETERMINISTIC, budget_ms=15_000)
+    _valid(t)
+    assert t.batch_queue in (0, 1)
+    assert rep["candidates"] >= 14 and rep["best_ms"] > 0
+    B = lpa.LpaBatch(v_off, _dev(g.offsets), _dev(g.targets), _dev(g.weights), tuning=t)
+    res = B.run_batched("det")
+    lab = res.labels.cpu().numpy()
+    for q in range(48):
+        a, b = int(v_off[q]), int(v_off[q + 1])
+        ea, eb = int(g.offsets[a]), int(g.offsets[b])
+        ref = oracle.lpa_sync(g.offsets[a:b + 1] - ea, g.targets[ea:eb] - a, g.weights[ea:eb])
+        np.testing.assert_array_equal(lab[a:b] - a, ref.labels)
+    B.close()

@@ -180,6 +180,18 @@ def test_det_unit_weights_null_pointer():
     assert_det_parity(g, weights=False)
 
 
+@pytest.mark.parametrize("bt,load,pdiv", [(256, 2, 16), (512, 1, 16), (1024, 4, 16),
+                                           (0, 1, 1), (0, 4, 4096)])
+def test_det_block_shapes_table_loads_and_flag_policy(bt, load, pdiv):
+    # the autotuner's axes: threads of the workgroup classes, the table
+    # capacity rule (load up to 1, 1/2, 1/4) and the push/pull crossover
+    # leave every label and counter unchanged
+    for g, tun in ((graphgen.rmat_graph(16, 16, "int8"), {}),
+                   (graphgen.random_graph(1500, 0.25, 5, wmax=8), SMALL_TUNING)):
+        assert_det_parity(g, _tuning(block_threads=bt, table_load=load, pull_divisor=pdiv,
+                                     **tun))
+
+
 def test_det_options():
     g = graphgen.rmat_graph(12, 9, "int8")
     t = _tuning(**SMALL_TUNING)
