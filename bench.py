@@ -254,13 +254,17 @@ def run_batched(args, wl) -> int:
 
 
 def run_learned(args, wl) -> int:
-    """Learned skipping against the plain run on held-out LFR-like graphs."""
+    """Learned skipping against the plain run on held-out LFR-like graphs
+    (seeds from 2000, one per step) and R-MAT scale 24."""
     from paper_2411_11468_amd import learned
     path = os.path.join(ROOT, "paper_2411_11468_amd", "predictor_lfr.npz")
     pred, info = learned.load(path)
     mode = args.mode or info["mode"]
+    import graphgen
     graphs = [(f"lfr1m-s{s}", learned.lfr(1_000_000, s))
               for s in range(wl["seed"], wl["seed"] + max(1, args.steps))]
+    # and R-MAT scale 24 (unit weights), the other evaluation graph
+    graphs.append(("rmat24", graphgen.rmat_graph(24, 24, "unit")))
     res = learned.evaluate(pred, info["threshold"], graphs, mode, reps=3)
     sp = float(np.exp(np.mean([np.log(r["speedup"]) for r in res])))
     m = sum(r["edges"] * r["plain_iters"] for r in res)

@@ -427,7 +427,19 @@ typedef struct lpa_learned_options {
   float threshold;        /* skip when P(change) < threshold (default 0.1) */
   float fn_bound;         /* fallback bound on false negatives (default 0.02) */
   int32_t guard_period;   /* plain guard sweep every guard_period (default 4) */
-  int32_t reserved;
+  int32_t predict_small;  /* 1: rows of at most small16 entries are predicted
+                             (and keep records, and are traced) too; 0
+                             (default): they are always processed, by the
+                             plain register kernels */
+  int32_t predict_large;  /* 1: rows of wave+1 .. block entries (the
+                             workgroup classes) are predicted too; 0
+                             (default): they are always processed, by the
+                             plain pipelined kernels.  Longer rows are never
+                             predicted */
+  int32_t first_predicted;  /* first iteration with predictions (>= 1,
+                               default 2); the records are kept from the
+                               iteration before, and traces sample from this
+                               iteration on */
 } lpa_learned_options;
 
 typedef struct lpa_learned_iter {

@@ -71,7 +71,8 @@ def _load():
         lib.oracle_local_optimal.restype = ctypes.c_int64
         lib.oracle_lpa_learned.argtypes = [
             ctypes.c_int64, vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-            ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_double,
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, vp,
+            ctypes.c_double,
             ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int64,
             vp, vp, vp, vp, ctypes.c_int32, vp, vp]
         lib.oracle_lpa_learned.restype = ctypes.c_int
@@ -204,10 +205,14 @@ class LearnedResult:
 def lpa_learned(offsets, targets, weights=None, *, params=None, z_theta: float = 0.0,
                 tolerance: float = 0.05, max_iterations: int = 20, pl_period: int = 4,
                 prune: bool = True, guard: int = 4, max_pred_degree: int = 8192,
+                min_pred_degree: int = 1, pred_start: int = 1,
                 fn_bound: float = 0.02, sample_rate: float = 0.0, seed: int = 0,
                 trace_cap: int = 0) -> LearnedResult:
     """Synchronous LPA with the learned change predictor (learned_oracle.c).
-    params: 5,057 fp32 network parameters or None (plain schedule)."""
+    params: 5,057 fp32 network parameters or None (plain schedule).  Rows of
+    min_pred_degree .. max_pred_degree entries are predicted (and keep
+    records); the others are always processed.  Predictions (and traces)
+    start at iteration pred_start, records one iteration earlier."""
     off, tgt, w = _csr(offsets, targets, weights)
     n = off.shape[0] - 1
     labels = np.empty(max(n, 0), dtype=np.int32)
@@ -227,7 +232,9 @@ def lpa_learned(offsets, targets, weights=None, *, params=None, z_theta: float =
     tcount = ctypes.c_int64(0)
     rc = _load().oracle_lpa_learned(
         n, _p(off), _p(tgt), _p(w), float(tolerance), cap, int(pl_period), int(bool(prune)),
-        int(guard), int(max_pred_degree), _p(P), float(z_theta), float(fn_bound),
+        int(guard), int(min_pred_degree), int(max_pred_degree), int(pred_start), _p(P),
+        float(z_theta),
+        float(fn_bound),
         float(sample_rate), int(seed) & 0xFFFFFFFFFFFFFFFF, _p(tX), _p(ty), _p(tv), _p(tl),
         tc, ctypes.cast(ctypes.byref(tcount), ctypes.c_void_p), _p(labels), _p(rec),
         ctypes.cast(stats, ctypes.c_void_p), cap,

@@ -13,8 +13,10 @@
  * with three additions:
  *
  *  1. A per-vertex state record of 8 bytes, rewritten whenever the vertex is
- *     processed (every vertex with 1 <= D_i <= max_pred_degree, D_i = row
- *     length).  From the label sums of that evaluation (fp32 values of the
+ *     processed (every vertex with min_pred_degree <= D_i <= max_pred_degree,
+ *     D_i = row length, min_pred_degree >= 1: the rows that are predicted)
+ *     in an iteration l >= pred_start - 1 (the evaluation before the first
+ *     prediction on).  From the label sums of that evaluation (fp32 values of the
  *     sums; all sums skip self-loops, labels as at the iteration start):
  *        K     = total neighbour weight,  own = weight of the current label,
  *        best  = maximum label weight,    second = largest weight among the
@@ -45,14 +47,16 @@
  *     bf16 (through fp32), the second not; biases fp32.  The vertex is
  *     predicted unchanged when the logit z is below z_theta.
  *
- *  3. The schedule.  Iteration l "skips" when a predictor is given, l >= 1,
+ *  3. The schedule.  Iteration l "skips" when a predictor is given,
+ *     l >= pred_start (>= 1),
  *     l is not a multiple of the guard period (0: no periodic guard), the
  *     previous iteration changed at least 2 * tolerance * N labels (below
  *     that the run is near its stop and the plain sweep is taken, so that
  *     the stop comes where the plain run's would), and the fallback is off.  In a skipping iteration a flagged vertex with
- *     1 <= D_i <= max_pred_degree that is predicted unchanged is not
- *     processed and stays flagged.  Every other iteration is plain; in a
- *     plain iteration with l >= 1 and the fallback off the predictions are
+ *     min_pred_degree <= D_i <= max_pred_degree that is predicted unchanged
+ *     is not processed and stays flagged; shorter and longer rows are never
+ *     predicted.  Every other iteration is plain; in a
+ *     plain iteration with l >= pred_start and the fallback off the predictions are
  *     still made, and if more than fn_bound of the vertices predicted
  *     unchanged do change, the fallback turns on for the rest of the run.
  *     The run stops after an iteration that is not Pick-Less and in which
@@ -62,8 +66,8 @@
  *     labels either way), so the test is Algorithm 1's, applied to an upper
  *     bound of the plain count; with nothing skipped it is Algorithm 1's.
  *
- * Traces: in every iteration l >= 1, each processed vertex with
- * 1 <= D_i <= max_pred_degree whose sample draw falls below sample_rate
+ * Traces: in every iteration l >= pred_start, each processed vertex with
+ * min_pred_degree <= D_i <= max_pred_degree whose sample draw falls below sample_rate
  * contributes its features (at the iteration start) and whether it changed
  * label.  The draw is SplitMix64 (Steele, Lea and Flood 2014): state =
  * seed + 0x9E3779B97F4A7C15 * (1 + (l << 32 | v)), then the SplitMix64 output
@@ -182,8 +186,9 @@ static void features(const uint8_t* r, int32_t l, int32_t cap, int32_t rho, floa
 
 /*
  * n, off, tgt, w (NULL = unit weights): symmetric CSR.  tol, cap, rho, prune
- * as in oracle_lpa_sync.  guard: guard period.  max_pred_degree: largest row
- * length that is predicted (and recorded).  params: 5,057 fp32 values, or
+ * as in oracle_lpa_sync.  guard: guard period.  min_pred_degree (>= 1),
+ * max_pred_degree: shortest and longest row length that is predicted (and
+ * recorded).  pred_start (>= 1): first iteration with predictions.  params: 5,057 fp32 values, or
  * NULL for no predictor (plain schedule, records and traces still kept).
  * z_theta: logit threshold.  fn_bound: fallback bound.  sample_rate, seed,
  * tX (cap x 12), ty, tv, tl, tcap, tcount: trace output (tX NULL = none).
@@ -193,12 +198,14 @@ static void features(const uint8_t* r, int32_t l, int32_t cap, int32_t rho, floa
  */
 int oracle_lpa_learned(int64_t n, const int64_t* off, const int32_t* tgt, const float* w,
                        double tol, int32_t cap, int32_t rho, int32_t prune, int32_t guard,
-                       int64_t max_pred_degree, const float* params, double z_theta,
+                       int64_t min_pred_degree, int64_t max_pred_degree, int32_t pred_start,
+                       const float* params, double z_theta,
                        double fn_bound, double sample_rate, uint64_t seed, float* tX,
                        float* ty, int32_t* tv, int32_t* tl, int64_t tcap, int64_t* tcount,
                        int32_t* labels, uint8_t* rec, oracle_learned_stats* stats,
                        int32_t stats_cap, int32_t* iters_done, double* min_margin) {
-  if (n < 0 || cap < 0 || rho < 0 || guard < 0) return -1;
+  if (n < 0 || cap < 0 || rho < 0 || guard < 0 || min_pred_degree < 1 || pred_start < 1)
+    return -1;
   *iters_done = 0;
   *min_margin = INFINITY;
   if (tcount) *tcount = 0;
@@ -227,7 +234,7 @@ int oracle_lpa_learned(int64_t n, const int64_t* off, const int32_t* tgt, const 
   int64_t nt_out = 0;
   for (int32_t l = 0; l < cap; ++l) {
     const int pl = (rho > 0) && (l % rho == 0);
-    const int predict = params && !fallback && l >= 1;
+    const int predict = params && !fallback && l >= pred_start;
     const int skipping = predict && (guard == 0 || l % guard != 0) &&
                          !((double)changed_prev < 2.0 * tol * (double)n);
     int64_t changed = 0, processed = 0, scanned = 0, skipped = 0, npred = 0, fneg = 0;
@@ -236,7 +243,7 @@ int oracle_lpa_learned(int64_t n, const int64_t* off, const int32_t* tgt, const 
       const int64_t d = off[i + 1] - off[i];
       skip[i] = 0;
       pred[i] = 0;
-      if ((prune && !F[i]) || d < 1 || d > max_pred_degree || !predict) continue;
+      if ((prune && !F[i]) || d < min_pred_degree || d > max_pred_degree || !predict) continue;
       float f[N_IN];
       features(rec + 8 * i, l, cap, rho, f);
       const double z = mlp_logit(params, f);
@@ -291,9 +298,9 @@ int oracle_lpa_learned(int64_t n, const int64_t* off, const int32_t* tgt, const 
         }
       }
       if (pred[i] && moved) ++fneg;
-      if (d < 1 || d > max_pred_degree) continue;
+      if (d < min_pred_degree || d > max_pred_degree || l < pred_start - 1) continue;
       /* trace sample (features as of the iteration start) */
-      if (tX && l >= 1 && sample_rate > 0.0 && draw(seed, l, i) < sample_rate) {
+      if (tX && l >= pred_start && sample_rate > 0.0 && draw(seed, l, i) < sample_rate) {
         if (nt_out < tcap) {
           features(rec + 8 * i, l, cap, rho, tX + N_IN * nt_out);
           ty[nt_out] = (float)moved;

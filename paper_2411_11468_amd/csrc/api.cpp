@@ -175,7 +175,8 @@ struct lpa_graph_s {
       const double ebc = eb + ((direct && c == 1 && perm) ? 4.0 : 0.0);
       bytes = ebc * edges + (4.0 + ob + own) * verts + (double)h.changed[c] +
               (async_mode ? 4.0 * h.changed[c] : 4.0 * verts);
-      if (acct_feat) bytes += 16.0 * verts;  // state record read and written
+      if (acct_feat && c >= acct_feat_cmin && c <= acct_feat_cmax)
+        bytes += 16.0 * verts;  // state record read and written
     } else if (kid == kKidHubPart || kid == kKidHubDirect) {
       edges = (int64_t)h.edges[kClassHub];
       bytes = eb * edges;
@@ -299,7 +300,9 @@ struct lpa_graph_s {
   bool lrec_valid = false;
   int learn_grid = 1;
   int32_t learned_iters = 0;   // iterations of the last learned run
-  bool acct_feat = false;      // profile: the run keeps records
+  bool acct_feat = false;      // profile: the run keeps records ...
+  int acct_feat_cmin = 1;      // ... for the classes acct_feat_cmin ..
+  int acct_feat_cmax = 8;      // acct_feat_cmax
 
   BatchArgs batch_args() const {
     BatchArgs b;
@@ -395,6 +398,7 @@ void lpa_learned_options_default(lpa_learned_options* o) {
   o->threshold = 0.1f;
   o->fn_bound = 0.02f;
   o->guard_period = 4;
+  o->first_predicted = 2;
 }
 
 const char* lpa_status_string(lpa_status s) {
@@ -808,6 +812,8 @@ static lpa_status stage_labels(lpa_graph g, const int32_t* src, int32_t* dst) {
 // (NULL: no predictions) and trace buffers (X NULL: no trace).
 struct RunCtx {
   bool feat = false;
+  int feat_cmin = 1;  // classes outside feat_cmin .. feat_cmax run the plain
+  int feat_cmax = 8;  // kernels (no records)
   const MlpTiles* tiles = nullptr;
   TraceArgs tr{};
 };
@@ -880,11 +886,13 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     a.active = g->lists[c];
     if (lpa_status e = mark((direct ? kKidDirect0 : kKidSweep0) + c)) return e;
     if (direct)
-      LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c], rc.feat, s));
+      LPA_HIP(launch_sweep_direct(g->off64, c, a, g->direct_grid[c],
+                                  rc.feat && c >= rc.feat_cmin && c <= rc.feat_cmax, s));
     else if (tv)
       LPA_HIP(launch_sweep_tv(g->off64, c, tv, a, g->tv_grid[c], s));
     else
-      LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c], rc.feat, s));
+      LPA_HIP(launch_sweep(g->off64, c, a, g->grid[c],
+                           rc.feat && c >= rc.feat_cmin && c <= rc.feat_cmax, s));
   }
   if (g->H > 0) {
     if (lpa_status e = mark(kKidHubFin)) return e;
@@ -1055,7 +1063,24 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     lp.trace_seed = trace->seed;
     lp.trace_cap = (unsigned long long)trace->cap;
   }
+  // rows of the register classes (at most small16 entries) are predicted,
+  // recorded and traced only with predict_small, those of the workgroup
+  // classes (wave+1 .. block entries) only with predict_large
+  rc.feat_cmin = g->lopt.predict_small ? 1 : 3;
+  rc.feat_cmax = g->lopt.predict_large ? kClassHub - 1 : 4;
+  lp.cmin = rc.feat_cmin;
+  lp.cmax = rc.feat_cmax;
+  // the iterations before the one ahead of the first prediction keep no
+  // records: plain kernels (a handle without a predictor: the defaults)
+  lp.pstart = g->lopt.first_predicted >= 1 ? g->lopt.first_predicted : 2;
+  const int32_t feat_from = rc.feat ? lp.pstart - 1 : 0;
+  RunCtx rc_plain = rc;
+  rc_plain.feat = false;
+  rc_plain.tiles = nullptr;
+  rc_plain.tr.X = nullptr;
   g->acct_feat = rc.feat;
+  g->acct_feat_cmin = rc.feat_cmin;
+  g->acct_feat_cmax = rc.feat_cmax;
   LPA_HIP(launch_run_begin(g->st, o.tolerance, o.max_iterations, o.pl_period, g->G > 0,
                            g->G, lp, s));
   if (g->G > 0) LPA_HIP(launch_batch_reset(g->batch_args(), s));
@@ -1094,11 +1119,14 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     // return at once
     hipGraphExec_t exec = nullptr;
     if (lpa_status e = g->iteration_graph(o, rc, &exec)) return e;
-    int32_t l0 = 0;
-    if (first_direct && o.max_iterations > 0) {
+    // iterations enqueued one by one: the table-free first sweep, and the
+    // iterations that keep no records yet
+    int32_t l0 = std::min(o.max_iterations, std::max<int32_t>(first_direct ? 1 : 0, feat_from));
+    for (int32_t l = 0; l < l0; ++l) {
       auto nomark = [](int) -> lpa_status { return LPA_OK; };
-      if (lpa_status e = enqueue_iteration(g, o, rc, s, nomark, true)) return e;
-      l0 = 1;
+      if (lpa_status e = enqueue_iteration(g, o, l < feat_from ? rc_plain : rc, s, nomark,
+                                           first_direct && l == 0))
+        return e;
     }
     for (int32_t l = l0; l < o.max_iterations; ++l) LPA_HIP(hipGraphLaunch(exec, s));
     LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
@@ -1134,7 +1162,8 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
       };
       LPA_HIP(hipEventRecord(g->ev0, s));
       const bool cc_it = o.cc_period > 0 && l % o.cc_period == 0;
-      if (lpa_status e = enqueue_iteration(g, o, rc, s, mark, first_direct && l == 0, cc_it))
+      if (lpa_status e = enqueue_iteration(g, o, l < feat_from ? rc_plain : rc, s, mark,
+                                           first_direct && l == 0, cc_it))
         return e;
       LPA_HIP(hipEventRecord(g->ev1, s));
       LPA_HIP(hipMemcpyAsync(g->st_host, g->st, sizeof(DevStats), hipMemcpyDeviceToHost, s));
@@ -1378,6 +1407,10 @@ lpa_status lpa_set_predictor(lpa_graph g, lpa_predictor p, const lpa_learned_opt
     return fail(LPA_ERR_INVALID, "threshold must lie in (0, 1)");
   if (!(o.fn_bound >= 0.0f)) return fail(LPA_ERR_INVALID, "fn_bound must be >= 0");
   if (o.guard_period < 0) return fail(LPA_ERR_INVALID, "guard_period must be >= 0");
+  if ((o.predict_small != 0 && o.predict_small != 1) ||
+      (o.predict_large != 0 && o.predict_large != 1))
+    return fail(LPA_ERR_INVALID, "predict_small and predict_large must be 0 or 1");
+  if (o.first_predicted < 1) return fail(LPA_ERR_INVALID, "first_predicted must be >= 1");
   g->pred = p;
   g->lopt = o;
   return LPA_OK;

@@ -77,6 +77,9 @@ __global__ void k_run_begin(DevStats* st, double tol, int cap, int rho, int batc
     st->batched = batched;
     st->graphs_left = (unsigned int)graphs;
     st->learn = lp.learn;
+    st->pred_cmin = lp.cmin < 1 ? 1 : lp.cmin;
+    st->pred_cmax = lp.cmax < 1 || lp.cmax >= kClassHub ? kClassHub - 1 : lp.cmax;
+    st->pred_start = lp.pstart < 1 ? 1 : lp.pstart;
     st->guard = lp.guard;
     st->trace = lp.trace;
     st->z_theta = lp.z_theta;
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     // learned skipping: predictions from iteration 1 on until a fallback;
     // skip unless this is a guard iteration or the last one changed few
     const int l = st->iter;
-    st->predict = (st->learn && !st->fallback && l >= 1) ? 1 : 0;
+    st->predict = (st->learn && !st->fallback && l >= st->pred_start) ? 1 : 0;
     st->skipping = (st->predict && (st->guard == 0 || l % st->guard != 0) && !st->cand) ? 1 : 0;
     st->skipped = 0; st->npred = 0; st->fneg = 0;
     st->trace_first = st->trace_n;
@@ -691,7 +694,9 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   const int cap = st->cap, rho = st->rho;
   const bool predict = st->predict != 0;
   const bool skipping = st->skipping != 0;
-  const bool tracing = st->trace != 0 && l >= 1 && tr.X != nullptr;
+  // rows of other classes are never predicted or traced
+  const int cmin = st->pred_cmin, cmax = st->pred_cmax;
+  const bool tracing = st->trace != 0 && l >= st->pred_start && tr.X != nullptr;
   const float z_theta = st->z_theta;
   const double rate = st->trace_rate;
   const unsigned long long seed = st->trace_seed, tcap = st->trace_cap;
@@ -730,7 +735,7 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
       const int64_t base = step0 + ((int64_t)wv * kLearnChunks + q) * 64;
       const int64_t v = base + lane;
       const uint8_t f = fq[q], c = cl[q];
-      const bool cand = f && c >= 1 && c < kClassHub && (predict || tracing);
+      const bool cand = f && c >= cmin && c <= cmax && (predict || tracing);
       const unsigned long long cm = __ballot(cand);
       const uint32_t ncand = __popcll(cm);
       if (cand) lst[lane_rank(cm)] = (uint8_t)lane;

@@ -55,6 +55,9 @@ struct DevStats {
   unsigned int error;                           // sticky error bits (validation, labels)
   // learned skipping (a project addition): run parameters ...
   int learn;                                    // 1: predictions are made
+  int pred_cmin;                                // predicted classes: pred_cmin ..
+  int pred_cmax;                                // pred_cmax
+  int pred_start;                               // first predicted iteration
   int guard;                                    // guard period (0: none)
   int trace;                                    // 1: record trace samples
   float z_theta;                                // predicted unchanged: logit < z_theta
@@ -82,6 +85,9 @@ struct LearnParams {
   int learn;
   int guard;
   int trace;
+  int cmin;               // classes cmin .. cmax are predicted, recorded, traced
+  int cmax;
+  int pstart;             // first iteration with predictions and traces
   float z_theta;
   double fn_bound;
   double trace_rate;

@@ -70,7 +70,8 @@ class lpa_options(ctypes.Structure):
 
 class lpa_learned_options(ctypes.Structure):
     _fields_ = [("threshold", ctypes.c_float), ("fn_bound", ctypes.c_float),
-                ("guard_period", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("guard_period", ctypes.c_int32), ("predict_small", ctypes.c_int32),
+                ("predict_large", ctypes.c_int32), ("first_predicted", ctypes.c_int32)]
 
 
 class lpa_learned_iter(ctypes.Structure):
@@ -367,16 +368,23 @@ def lpa_run(handle, labels, *, mode: int = MODE_ASYNC, tolerance: float = 0.05,
 
 
 def learned_options(threshold: float = 0.1, fn_bound: float = 0.02,
-                    guard_period: int = 4) -> lpa_learned_options:
+                    guard_period: int = 4, predict_small: bool = False,
+                    predict_large: bool = False,
+                    first_predicted: int = 2) -> lpa_learned_options:
     o = lpa_learned_options()
     load_library().lpa_learned_options_default(ctypes.byref(o))
     o.threshold, o.fn_bound, o.guard_period = threshold, fn_bound, guard_period
+    o.predict_small = int(bool(predict_small))
+    o.predict_large = int(bool(predict_large))
+    o.first_predicted = int(first_predicted)
     return o
 
 
 def lpa_set_predictor(handle, predictor, *, threshold: float = 0.1, fn_bound: float = 0.02,
-                      guard_period: int = 4) -> None:
-    o = learned_options(threshold, fn_bound, guard_period)
+                      guard_period: int = 4, predict_small: bool = False,
+                      predict_large: bool = False, first_predicted: int = 2) -> None:
+    o = learned_options(threshold, fn_bound, guard_period, predict_small, predict_large,
+                        first_predicted)
     ph = None if predictor is None else predictor.handle
     _check(load_library().lpa_set_predictor(handle, ph, ctypes.byref(o)))
 

@@ -71,19 +71,33 @@ def _graphs():
     ]
 
 
-def _max_pred_degree(tuning):
-    return (tuning or {}).get("block", 8192)
+def _max_pred_degree(tuning, predict_large=False):
+    # rows of the workgroup classes (wave+1 .. block entries) are predicted
+    # only with predict_large; longer rows never
+    t = tuning or {}
+    return t.get("block", 8192) if predict_large else t.get("wave", 512)
+
+
+def _min_pred_degree(tuning, predict_small=False):
+    # rows of the register classes (at most small16 entries) are predicted
+    # only with predict_small
+    return 1 if predict_small else (tuning or {}).get("small16", 16) + 1
 
 
 def _learned_pair(g, tuning, params, *, threshold=0.5, fn_bound=0.02, guard=4, pl_period=4,
-                  launch=lpa.LAUNCH_EAGER, mode="det"):
+                  launch=lpa.LAUNCH_EAGER, mode="det", predict_small=False,
+                  predict_large=False, first=2):
     zt = float(np.float32(np.log(threshold / (1 - threshold))))
     ref = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=params, z_theta=zt,
                              pl_period=pl_period, guard=guard, fn_bound=fn_bound,
-                             max_pred_degree=_max_pred_degree(tuning))
+                             max_pred_degree=_max_pred_degree(tuning, predict_large),
+                             min_pred_degree=_min_pred_degree(tuning, predict_small),
+                             pred_start=first)
     G = _gpu_graph(g, None if tuning is None else _tuning(**tuning))
     pr = lpa.Predictor(params=params)
-    G.set_predictor(pr, threshold=threshold, fn_bound=fn_bound, guard_period=guard)
+    G.set_predictor(pr, threshold=threshold, fn_bound=fn_bound, guard_period=guard,
+                    predict_small=predict_small, predict_large=predict_large,
+                    first_predicted=first)
     res = G.run(mode, learned=True, pl_period=pl_period, launch=launch)
     return ref, G, pr, res
 
@@ -105,11 +119,17 @@ def _assert_same(ref, G, res):
 
 @pytest.mark.parametrize("name,g,tuning", _graphs(), ids=[x[0] for x in _graphs()])
 @pytest.mark.parametrize("pname", ["history", "gain"])
-def test_learned_det_matches_oracle(name, g, tuning, pname):
+@pytest.mark.parametrize("small,large,first", [(False, False, 2), (True, True, 1),
+                                               (False, True, 3)])
+def test_learned_det_matches_oracle(name, g, tuning, pname, small, large, first):
     params = P_HISTORY if pname == "history" else P_GAIN
-    ref, G, pr, res = _learned_pair(g, tuning, params, fn_bound=1.0)
-    assert ref.min_margin > 0.1
-    assert any(s["skipped"] > 0 for s in ref.stats)
+    ref, G, pr, res = _learned_pair(g, tuning, params, fn_bound=1.0, predict_small=small,
+                                    predict_large=large, first=first)
+    deg = np.diff(g.offsets)
+    eligible = (deg >= _min_pred_degree(tuning, small)) & (deg <= _max_pred_degree(tuning, large))
+    if eligible.sum() > 100:
+        assert ref.min_margin > 0.1
+        assert any(s["skipped"] > 0 for s in ref.stats)
     _assert_same(ref, G, res)
     G.close()
     pr.close()
@@ -131,8 +151,10 @@ def test_always_unchanged_falls_back():
     ref, G, pr, res = _learned_pair(g, None, P_ALWAYS, fn_bound=0.02, pl_period=0)
     assert any(s["fallback"] for s in ref.stats)
     _assert_same(ref, G, res)
-    # and without a fallback bound the skipping alternates to the plain result
-    ref2, G2, pr2, res2 = _learned_pair(g, None, P_ALWAYS, fn_bound=1.0, pl_period=0)
+    # and without a fallback bound the skipping alternates to the plain
+    # result (every row predicted, so that a skipping iteration does nothing)
+    ref2, G2, pr2, res2 = _learned_pair(g, None, P_ALWAYS, fn_bound=1.0, pl_period=0,
+                                        predict_small=True, predict_large=True)
     _assert_same(ref2, G2, res2)
     plain = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0)
     np.testing.assert_array_equal(res2.labels.cpu().numpy(), plain.labels)
@@ -168,7 +190,8 @@ def test_learned_graph_launch_matches_eager():
 @pytest.mark.parametrize("name,g,tuning", _graphs()[:3], ids=[x[0] for x in _graphs()[:3]])
 def test_trace_matches_oracle(name, g, tuning):
     ref = oracle.lpa_learned(g.offsets, g.targets, g.weights, sample_rate=1.0,
-                             trace_cap=4_000_000, max_pred_degree=_max_pred_degree(tuning))
+                             trace_cap=4_000_000, max_pred_degree=_max_pred_degree(tuning),
+                             min_pred_degree=_min_pred_degree(tuning), pred_start=2)
     G = _gpu_graph(g, None if tuning is None else _tuning(**tuning))
     X, y, v, it, drawn = G.trace(sample_rate=1.0, cap=4_000_000)
     assert drawn == ref.trace_total == X.shape[0]
@@ -185,7 +208,8 @@ def test_trace_matches_oracle(name, g, tuning):
 def test_trace_sampling_cap_and_device_buffers():
     g = graphgen.planted_partition_10k(1)
     ref = oracle.lpa_learned(g.offsets, g.targets, g.weights, sample_rate=0.3, seed=77,
-                             trace_cap=1_000_000)
+                             trace_cap=1_000_000, min_pred_degree=_min_pred_degree(None),
+                             max_pred_degree=_max_pred_degree(None), pred_start=2)
     G = _gpu_graph(g)
     X, y, v, it, drawn = G.trace(sample_rate=0.3, seed=77, cap=1_000_000,
                                  device=torch.device("cuda"))
@@ -272,7 +296,7 @@ def test_stop_after_a_skip_iteration_matches_oracle():
     K, L = 30, 20
     edges = [(c, K + c * L + i) for c in range(K) for i in range(L)]
     g = graphgen.from_edges(K + K * L, edges)
-    ref, G, pr, res = _learned_pair(g, None, P_ALWAYS, fn_bound=1.0)
+    ref, G, pr, res = _learned_pair(g, None, P_ALWAYS, fn_bound=1.0, first=1)
     assert ref.iterations == 2 and ref.stats[1]["skipping"] == 1
     _assert_same(ref, G, res)
     G.close()

@@ -1,11 +1,13 @@
 """What the trained change predictor gains over the run without it (GPU).
 
 The predictor shipped in paper_2411_11468_amd/predictor_lfr.npz was trained
-by the library's own kernels on traces of 32 LFR-like graphs (seeds
-1000-1031, 10^6 vertices).  On a held-out graph it must cut the label-scan
+by the library's own kernels on traces of 64 LFR-like graphs (seeds
+1000-1063, 10^6 vertices).  On a held-out graph it must cut the label-scan
 work (CSR entries scanned) of a deterministic run while keeping modularity
-within 0.5% and the iteration count of the plain run.  A tiny end-to-end
-pipeline (traces -> training -> threshold) checks the training path.
+within 0.5% and the iteration count of the plain run, and its time to
+termination (median of graph-launched runs) is reported beside the plain
+run's and may not be more than 10% longer.  A tiny end-to-end pipeline
+(traces -> training -> threshold) checks the training path.
 """
 import os
 
@@ -43,6 +45,16 @@ def test_trained_predictor_cuts_scan_work_on_heldout_graph():
     assert learn.iterations <= plain.iterations + 1
     assert sl <= 0.95 * sp
     assert (qp - ql) / qp <= 0.005
+    # time to termination on a held-out graph of the training size
+    g1 = learned.lfr(1_000_000, 2003)
+    G1 = learned.gpu_graph(g1)
+    G1.set_predictor(pred, threshold=info["threshold"])
+    _, tp = learned.timed_run(G1, "det", False, 5, lpa.LAUNCH_GRAPH)
+    _, tl = learned.timed_run(G1, "det", True, 5, lpa.LAUNCH_GRAPH)
+    print(f"10^6 vertices: plain {1e3 * tp:.3f} ms, learned {1e3 * tl:.3f} ms, "
+          f"speedup {tp / tl:.3f}")
+    assert tl <= 1.10 * tp
+    G1.close()
     # an untrained network at the same threshold: the guard sweeps catch
     # its mistakes (fallback) or it skips far less usefully
     rnd = lpa.Predictor(seed=3)

@@ -172,7 +172,8 @@ def test_learned_records_and_traces_in_caller_order():
     params = _params_history()
     zt = float(np.float32(np.log(0.5 / 0.5)))
     ref = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=params, z_theta=zt,
-                             fn_bound=1.0, max_pred_degree=SMALL_TUNING["block"])
+                             fn_bound=1.0, max_pred_degree=SMALL_TUNING["wave"],
+                             min_pred_degree=SMALL_TUNING["small16"] + 1, pred_start=2)
     G = _graph(g, 1, **SMALL_TUNING)
     pr = lpa.Predictor(params=params)
     G.set_predictor(pr, threshold=0.5, fn_bound=1.0)
@@ -185,7 +186,8 @@ def test_learned_records_and_traces_in_caller_order():
     np.testing.assert_array_equal(G.records(), ref.records)
     # traces: sampled by caller id, reported in caller ids
     tref = oracle.lpa_learned(g.offsets, g.targets, g.weights, sample_rate=0.4, seed=11,
-                              trace_cap=1_000_000, max_pred_degree=SMALL_TUNING["block"])
+                              trace_cap=1_000_000, max_pred_degree=SMALL_TUNING["wave"],
+                              min_pred_degree=SMALL_TUNING["small16"] + 1, pred_start=2)
     X, y, v, it, drawn = G.trace(sample_rate=0.4, seed=11, cap=1_000_000)
     assert drawn == tref.trace_total == X.shape[0]
     order = np.lexsort((v, it))

@@ -290,3 +290,61 @@ def test_stop_after_a_skip_iteration():
     s = got.stats[1]
     assert (s["skipping"], s["skipped"], s["processed"], s["changed"]) == (1, K, 0, 0)
     assert np.array_equal(got.labels, want.labels)
+
+
+@pytest.mark.parametrize("name,g", _graphs(), ids=[n for n, _ in _graphs()])
+def test_rows_below_the_predicted_length_are_always_processed(name, g):
+    # min_pred_degree k: rows shorter than k are never predicted, skipped or
+    # recorded; with an always-"unchanged" predictor and no fallback a
+    # skipping iteration skips exactly the flagged rows of >= k entries, and
+    # with k above every row length the run is the plain run
+    deg = np.diff(g.offsets)
+    k = int(np.median(deg[deg > 0])) + 1
+    got = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=_const_params(-50.0),
+                             pl_period=0, guard=4, fn_bound=1.0, max_iterations=40,
+                             min_pred_degree=k)
+    short = deg < k
+    assert (got.records[short, 7] == 255).all()
+    assert (got.records[short, :7] == 0).all()
+    for s in got.stats:
+        if s["iteration"] >= 1 and s["skipping"]:
+            assert s["skipped"] == s["predicted"]
+        assert s["predicted"] + s["processed"] >= s["skipped"]
+    plain = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=4)
+    none = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=_const_params(-50.0),
+                              pl_period=4, guard=4, fn_bound=1.0,
+                              min_pred_degree=int(deg.max()) + 1)
+    assert none.iterations == plain.iterations
+    assert np.array_equal(none.labels, plain.labels)
+    for a, b in zip(none.stats, plain.stats):
+        for key in ("changed", "processed", "edges_scanned"):
+            assert a[key] == b[key]
+        assert a["skipped"] == 0 and a["predicted"] == 0
+    with pytest.raises(ValueError):
+        oracle.lpa_learned(g.offsets, g.targets, g.weights, min_pred_degree=0)
+
+
+def test_predictions_records_and_traces_start_at_pred_start():
+    # pred_start k: no prediction (or skip) before iteration k, no record
+    # written before iteration k - 1, no trace sample before iteration k
+    g = graphgen.planted_partition_10k(1)
+    P = _const_params(-50.0)
+    k = 3
+    r = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=P, pl_period=0, guard=4,
+                           fn_bound=1.0, pred_start=k, sample_rate=1.0, trace_cap=4_000_000)
+    for s in r.stats[:k]:
+        assert s["predicted"] == 0 and s["skipped"] == 0 and not s["skipping"]
+    assert any(s["predicted"] > 0 for s in r.stats[k:])
+    assert (r.trace["l"] >= k).all() and r.trace["l"].size > 0
+    early = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=P, pl_period=0,
+                               guard=4, fn_bound=1.0, pred_start=k, max_iterations=k - 1)
+    assert (early.records[:, 7] == 255).all()
+    at = oracle.lpa_learned(g.offsets, g.targets, g.weights, params=P, pl_period=0,
+                            guard=4, fn_bound=1.0, pred_start=k, max_iterations=k)
+    ev = at.records[:, 7] != 255
+    assert ev.any() and (at.records[ev, 7] == k - 1).all()
+    # the first k iterations are those of the plain run
+    plain = oracle.lpa_sync(g.offsets, g.targets, g.weights, pl_period=0, max_iterations=k)
+    assert np.array_equal(at.labels, plain.labels)
+    with pytest.raises(ValueError):
+        oracle.lpa_learned(g.offsets, g.targets, g.weights, pred_start=0)
