@@ -128,6 +128,48 @@ def cpu_baseline(g, budget_edges: int) -> dict:
                        f"{dt:.1f} s on one host core")}
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_all_cores(g, wl) -> dict:
+    """The CPU throughput baseline (oracle.cpu_lpa_async: asynchronous
+    Algorithm 1 on every OpenMP thread of this host; not the oracle) on the
+    whole benchmark graph, to termination: |E| * iterations / its wall time."""
+    import oracle
+    w = None if wl["weights"] == "unit" else g.weights
+    t0 = time.perf_counter()
+    r = oracle.cpu_lpa_async(g.offsets, g.targets, w)
+    dt = time.perf_counter() - t0
+    return {"value": g.num_edges * r.iterations / dt, "unit": "edges/s", "cores": r.threads,
+            "affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model(),
+            "kind": "cpu_async_omp", "ms": 1e3 * dt, "iterations": r.iterations,
+            "sample": "the whole graph, asynchronous order, run to termination on all "
+                      "OpenMP threads"}
+
+
+def oracle_run(g, wl) -> dict:
+    """The oracle (one thread, as written) run to termination on the whole
+    benchmark graph: |E| * iterations / its wall time."""
+    import oracle
+    w = None if wl["weights"] == "unit" else g.weights
+    t0 = time.perf_counter()
+    r = oracle.lpa_sync(g.offsets, g.targets, w)
+    dt = time.perf_counter() - t0
+    return {"value": g.num_edges * r.iterations / dt, "unit": "edges/s", "cores": 1,
+            "kind": "oracle", "ms": 1e3 * dt, "iterations": r.iterations,
+            "sample": f"the whole benchmark graph ({g.num_vertices} vertices, {g.num_edges} "
+                      f"CSR entries), deterministic synchronous run to termination "
+                      f"({r.iterations} iterations) on one host core"}
+
+
 def oracle_full_run() -> dict:
     """The oracle (one thread, as written) run to termination on the whole
     R-MAT scale 22 graph (4,194,304 vertices, integer weights 1..8, the
@@ -296,6 +338,9 @@ def main() -> int:
     ap.add_argument("--mode", default=None, choices=["async", "det"])
     ap.add_argument("--cpu-budget-edges", type=int, default=300_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="also run the oracle to termination on the whole workload graph "
+                         "(one core; minutes at R-MAT scale 26)")
     ap.add_argument("--probe", type=int, default=0, choices=[0, 1, 2, 3],
                     help="hashtable probe sequence (lpa_tuning.probe): 0 quadratic-double "
                          "(the method's), 1 linear, 2 quadratic, 3 double hashing")
@@ -449,6 +494,11 @@ def main() -> int:
         if args.workload == "rmat26":
             cpu["full_run"] = oracle_full_run()
             log(f"oracle full run: {cpu['full_run']}")
+        if args.oracle_full:
+            cpu["full_run_workload"] = oracle_run(g, wl)
+            log(f"oracle full run on the workload: {cpu['full_run_workload']}")
+        cpu["all_cores"] = cpu_all_cores(g, wl)
+        log(f"CPU on all cores: {cpu['all_cores']}")
 
     out = {
         "metric": METRIC,

@@ -177,6 +177,13 @@ typedef struct lpa_graph_s* lpa_graph;
  *   checks its row) when the changed rows hold at least 1/pull_divisor of
  *   the CSR entries, else pushed (each changed row flags its neighbours);
  *   default 16.  Same flags.
+ * memory_limit_kib: a cap on the device memory the handle keeps (its copies
+ *   of the graph, labels, flags, lists, tables and run buffers, allocated by
+ *   lpa_create and on first use by lpa_run / lpa_modularity), in KiB; 0
+ *   (default) = none.  An allocation that would pass it fails with
+ *   LPA_ERR_OOM like a failed hipMalloc; a failed lpa_create frees
+ *   everything it allocated.  Buffers used only during lpa_create (checks,
+ *   sort scratch) are freed before it returns and are not counted.
  */
 typedef struct lpa_tuning {
   int32_t small4;
@@ -197,6 +204,7 @@ typedef struct lpa_tuning {
   int32_t block_threads;
   int32_t table_load;
   int32_t pull_divisor;
+  int32_t memory_limit_kib;
 } lpa_tuning;
 
 /*
@@ -387,6 +395,22 @@ void lpa_predictor_destroy(lpa_predictor p);
 /* Replace / read the fp32 parameters (host arrays); set also resets Adam. */
 lpa_status lpa_predictor_set_params(lpa_predictor p, const float* params);
 lpa_status lpa_predictor_get_params(lpa_predictor p, float* params);
+/* Checkpoint and resume (host memory): lpa_predictor_save writes the
+ * network's shape, its fp32 parameters and Adam's state (moments and step
+ * count) into blob (cap bytes) and the blob's size into *size; blob NULL
+ * only reports the size (LPA_PREDICTOR_BLOB_BYTES).  lpa_predictor_load
+ * restores them into p: it then holds exactly the saved state (the same
+ * predictions; training continues from the same parameters and moments,
+ * and follows the saved predictor up to the order of the gradient's float
+ * atomic sums).  Layout: a 32-byte header
+ * (magic "LPAPRED1", uint32 version 1, uint16 layer sizes 12, 64, 64, 1,
+ * uint32 parameter count 5057, int32 Adam steps, uint32 0), then 3 x 5057
+ * fp32 (parameters, first moments, second moments), little-endian.
+ * Errors: LPA_ERR_INVALID (cap too small; load: wrong magic, version or
+ * shape, truncated, non-finite parameters; p unchanged then), LPA_ERR_HIP. */
+#define LPA_PREDICTOR_BLOB_BYTES (32 + 3 * 4 * LPA_PREDICTOR_PARAMS)
+lpa_status lpa_predictor_save(lpa_predictor p, void* blob, int64_t cap, int64_t* size);
+lpa_status lpa_predictor_load(lpa_predictor p, const void* blob, int64_t size);
 /* Gradient of the loss over the n samples (grad: host, may be NULL; loss:
  * host mean loss, may be NULL). */
 lpa_status lpa_predictor_gradient(lpa_predictor p, const float* X, const float* y, int64_t n,

@@ -13,6 +13,8 @@ Functions and the passages they follow (paper arXiv 2411.11468):
   modularity_pairs  Eq. 1, pair form over all vertex pairs (tiny graphs).
   local_optimal     Eq. 3 attained by the current label, per vertex.
   pl_refusable      Eq. 3's maxima all above the current label (Pick-Less).
+  cpu_lpa_async     not the oracle: the multi-core CPU throughput baseline of
+                    the benchmark (asynchronous order, OpenMP; cpu_async.c).
   lpa_learned       Algorithm 1 with the learned change predictor: per-vertex
                     state records, features, skipping schedule, guard and
                     fallback, traces (learned_oracle.c; a project addition).
@@ -28,7 +30,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "lpa_oracle.c"), os.path.join(_HERE, "learned_oracle.c")]
+_SRCS = [os.path.join(_HERE, "lpa_oracle.c"), os.path.join(_HERE, "learned_oracle.c"),
+         os.path.join(_HERE, "cpu_async.c")]
 _LIB = os.path.join(_HERE, "liblpa_oracle.so")
 _lib = None
 
@@ -43,7 +46,7 @@ def build(force: bool = True) -> str:
     """Compile liblpa_oracle.so with gcc (plain C, -O2, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                                *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -76,6 +79,9 @@ def _load():
             ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int64,
             vp, vp, vp, vp, ctypes.c_int32, vp, vp]
         lib.oracle_lpa_learned.restype = ctypes.c_int
+        lib.cpu_lpa_async_omp.argtypes = [ctypes.c_int64, vp, vp, vp, ctypes.c_double,
+                                          ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        lib.cpu_lpa_async_omp.restype = ctypes.c_int32
         lib.oracle_mlp_logit.argtypes = [vp, vp]
         lib.oracle_mlp_logit.restype = ctypes.c_double
         lib.oracle_features.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
@@ -134,6 +140,32 @@ def lpa_sync(offsets, targets, weights=None, tolerance: float = 0.05,
     st = [dict(iteration=s.iteration, pick_less=s.pick_less, changed=s.changed,
                processed=s.processed, edges_scanned=s.edges_scanned) for s in stats[:k]]
     return SyncResult(labels, st, k)
+
+
+@dataclass
+class AsyncCpuResult:
+    labels: np.ndarray
+    iterations: int
+    changed_last: int
+    threads: int
+
+
+def cpu_lpa_async(offsets, targets, weights=None, tolerance: float = 0.05,
+                  max_iterations: int = 20, pl_period: int = 4) -> AsyncCpuResult:
+    """The CPU throughput baseline (cpu_async.c; not the oracle): Algorithm 1
+    in asynchronous order on all OpenMP threads."""
+    off, tgt, w = _csr(offsets, targets, weights)
+    n = off.shape[0] - 1
+    labels = np.empty(max(n, 0), dtype=np.int32)
+    last = ctypes.c_int64(0)
+    thr = ctypes.c_int32(0)
+    it = _load().cpu_lpa_async_omp(n, _p(off), _p(tgt), _p(w), float(tolerance),
+                                   int(max_iterations), int(pl_period), _p(labels),
+                                   ctypes.cast(ctypes.byref(last), ctypes.c_void_p),
+                                   ctypes.cast(ctypes.byref(thr), ctypes.c_void_p))
+    if it < 0:
+        raise MemoryError("cpu_lpa_async_omp")
+    return AsyncCpuResult(labels, int(it), int(last.value), int(thr.value))
 
 
 def modularity(offsets, targets, weights, labels) -> float:

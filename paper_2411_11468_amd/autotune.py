@@ -20,7 +20,7 @@ from . import lpa
 TUNING_FIELDS = ("small4", "small16", "wave", "block", "hub_chunk", "max_retries", "xcd_local",
                  "hub_table_cap", "relabel", "probe", "table_values", "batch_queue",
                  "queue_chunk", "queue_group", "sort_rows", "block_threads", "table_load",
-                 "pull_divisor")
+                 "pull_divisor", "memory_limit_kib")
 
 
 def _round2(x: int) -> int:

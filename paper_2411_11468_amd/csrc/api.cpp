@@ -125,6 +125,7 @@ struct lpa_graph_s {
   double* mod_acc = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<void*> dev_allocs;
+  size_t dev_bytes = 0;          // bytes held in dev_allocs
   // optional per-kernel profile: events bracketing each launch, and the
   // accumulated launches, time and algorithmic bytes per kernel
   std::vector<hipEvent_t> ev_pool;
@@ -238,6 +239,14 @@ struct lpa_graph_s {
   lpa_status dalloc(T** p, int64_t count) {
     void* q = nullptr;
     const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    if (tun.memory_limit_kib > 0 &&
+        dev_bytes + bytes > (size_t)tun.memory_limit_kib * 1024u) {
+      *p = nullptr;
+      return fail(LPA_ERR_OOM, "the handle's device memory limit (" +
+                                   std::to_string(tun.memory_limit_kib) +
+                                   " KiB) would be exceeded by " + std::to_string(bytes) +
+                                   " more bytes");
+    }
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -246,6 +255,7 @@ struct lpa_graph_s {
                                    hipGetErrorString(e));
     }
     dev_allocs.push_back(q);
+    dev_bytes += bytes;
     *p = static_cast<T*>(q);
     return LPA_OK;
   }
@@ -438,6 +448,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
         (t.block_threads == 0 || t.block_threads == 256 || t.block_threads == 512 ||
          t.block_threads == 1024) &&
         (t.table_load == 1 || t.table_load == 2 || t.table_load == 4) &&
+        t.memory_limit_kib >= 0 &&
         t.pull_divisor >= 1 && t.pull_divisor <= 4096))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   // the ablation kernels' largest LDS table has 8191 slots (rows of <= 4096)
@@ -812,6 +823,8 @@ static lpa_status stage_labels(lpa_graph g, const int32_t* src, int32_t* dst) {
 // (NULL: no predictions) and trace buffers (X NULL: no trace).
 struct RunCtx {
   bool feat = false;
+  bool infer = true;  // feat: the frontier may run the network (else the
+                      // plain frontier, which lists the same vertices)
   int feat_cmin = 1;  // classes outside feat_cmin .. feat_cmax run the plain
   int feat_cmax = 8;  // kernels (no records)
   const MlpTiles* tiles = nullptr;
@@ -849,7 +862,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   if (lpa_status e = mark(kKidPlan)) return e;
   LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
   if (lpa_status e = mark(kKidFrontier)) return e;
-  if (rc.feat)
+  if (rc.feat && rc.infer)
     LPA_HIP(launch_frontier_learned(n, g->F, g->cls, g->lists, g->chg, g->st, g->lrec, rc.tiles,
                                     rc.tr, g->learn_grid, s));
   else
@@ -1078,6 +1091,14 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
   rc_plain.feat = false;
   rc_plain.tiles = nullptr;
   rc_plain.tr.X = nullptr;
+  // the iteration ahead of the first prediction writes records but neither
+  // predicts nor traces (both start at pstart): the plain frontier
+  RunCtx rc_rec = rc;
+  rc_rec.infer = false;
+  const int32_t infer_from = rc.feat ? lp.pstart : 0;
+  auto ctx_of = [&](int32_t l) -> const RunCtx& {
+    return l < feat_from ? rc_plain : (l < infer_from ? rc_rec : rc);
+  };
   g->acct_feat = rc.feat;
   g->acct_feat_cmin = rc.feat_cmin;
   g->acct_feat_cmax = rc.feat_cmax;
@@ -1120,11 +1141,12 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
     hipGraphExec_t exec = nullptr;
     if (lpa_status e = g->iteration_graph(o, rc, &exec)) return e;
     // iterations enqueued one by one: the table-free first sweep, and the
-    // iterations that keep no records yet
-    int32_t l0 = std::min(o.max_iterations, std::max<int32_t>(first_direct ? 1 : 0, feat_from));
+    // iterations before the first prediction (no records, or records
+    // without the network)
+    int32_t l0 = std::min(o.max_iterations, std::max<int32_t>(first_direct ? 1 : 0, infer_from));
     for (int32_t l = 0; l < l0; ++l) {
       auto nomark = [](int) -> lpa_status { return LPA_OK; };
-      if (lpa_status e = enqueue_iteration(g, o, l < feat_from ? rc_plain : rc, s, nomark,
+      if (lpa_status e = enqueue_iteration(g, o, ctx_of(l), s, nomark,
                                            first_direct && l == 0))
         return e;
     }
@@ -1162,7 +1184,7 @@ static lpa_status run_impl(lpa_graph g, const lpa_options* opt, int32_t* labels,
       };
       LPA_HIP(hipEventRecord(g->ev0, s));
       const bool cc_it = o.cc_period > 0 && l % o.cc_period == 0;
-      if (lpa_status e = enqueue_iteration(g, o, l < feat_from ? rc_plain : rc, s, mark,
+      if (lpa_status e = enqueue_iteration(g, o, ctx_of(l), s, mark,
                                            first_direct && l == 0, cc_it))
         return e;
       LPA_HIP(hipEventRecord(g->ev1, s));

@@ -682,6 +682,9 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   __shared__ unsigned long long slot_all[kLearnWaves][16];
   __shared__ uint32_t cnt[kNumClasses];
   __shared__ uint32_t cbase[kNumClasses];
+  // the network's operand tiles, read from LDS at each use: held in
+  // registers they would leave room for two waves per SIMD
+  __shared__ MlpTiles wl;
   if (st->stop) return;
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
@@ -700,8 +703,14 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   const float z_theta = st->z_theta;
   const double rate = st->trace_rate;
   const unsigned long long seed = st->trace_seed, tcap = st->trace_cap;
-  MlpLane W;
-  if (predict) mlp_load(*tiles, W);
+  if (predict) {
+    static_assert(sizeof(MlpTiles) % 4 == 0, "tiles are copied as words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(tiles);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&wl);
+    for (int q = tid; q < (int)(sizeof(MlpTiles) / 4); q += kLearnWaves * 64) dst[q] = src[q];
+  }
+  __syncthreads();
+  const MlpFromTiles W{wl, lane, g};
   uint32_t proc = 0, skipped = 0, npred = 0;
   constexpr int64_t kStep = (int64_t)kLearnWaves * kLearnChunks * 64;
   // the whole workgroup walks the same steps of kStep vertices (barriers
@@ -754,7 +763,7 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
         rec_features(rr, l, cap, rho, g, x);
         bool pred = false;
         if (predict) {
-          const float z = mlp_logit16(W, x);
+          const float z = mlp_logit16_src(W, x);
           pred = has && z < z_theta;
         }
         const bool skip = pred && skipping;

@@ -71,23 +71,51 @@ __device__ inline void mlp_load(const MlpTiles& t, MlpLane& r) {
   r.b3 = t.b3;
 }
 
+// Operand sources for mlp_logit16: the registers of an MlpLane, or the
+// tiles themselves (e.g. a copy in LDS), read at each use so that they hold
+// no registers between calls.
+struct MlpFromRegs {
+  const MlpLane& r;
+  __device__ bf16x4_t w1(int m) const { return r.w1[m]; }
+  __device__ bf16x4_t w2(int m, int kb) const { return r.w2[m][kb]; }
+  __device__ float b1(int m, int i) const { return r.b1[4 * m + i]; }
+  __device__ float b2(int m, int i) const { return r.b2[4 * m + i]; }
+  __device__ float w3(int m, int i) const { return r.w3[4 * m + i]; }
+  __device__ float b3() const { return r.b3; }
+};
+struct MlpFromTiles {
+  const MlpTiles& t;
+  int lane, g;
+  __device__ bf16x4_t w1(int m) const {
+    return *reinterpret_cast<const bf16x4_t*>(t.w1t[m][lane]);
+  }
+  __device__ bf16x4_t w2(int m, int kb) const {
+    return *reinterpret_cast<const bf16x4_t*>(t.w2t[m][kb][lane]);
+  }
+  __device__ float b1(int m, int i) const { return t.b1[16 * m + 4 * g + i]; }
+  __device__ float b2(int m, int i) const { return t.b2[16 * m + 4 * g + i]; }
+  __device__ float w3(int m, int i) const { return t.w3[16 * m + 4 * g + i]; }
+  __device__ float b3() const { return t.b3; }
+};
+
 // Logit for 16 samples, one wave: lane l holds features 4 (l/16) .. 4 (l/16)+3
 // of sample l % 16 in f (zero beyond feature 11); every lane returns the logit
 // of its sample.  Layer 1 and 2 run on v_mfma_f32_16x16x16_bf16 with the
 // weights as the A operand and the 16 samples as the columns, so the output
 // tile of layer 1 (after bias, ReLU and bf16 rounding) is the B operand of
 // layer 2 as it stands.  Layer 3 is a fp32 dot product.  All 64 lanes must be
-// active.
-__device__ inline float mlp_logit16(const MlpLane& r, const float f[4]) {
+// active.  The same operations in the same order whatever the source.
+template <typename Src>
+__device__ inline float mlp_logit16_src(const Src& r, const float f[4]) {
   bf16x4_t xb;
   for (int j = 0; j < 4; ++j) xb[j] = (short)bf16_bits(f[j]);
   bf16x4_t h1[4];
   const f32x4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w1[m], xb, zero, 0, 0, 0);
+    const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w1(m), xb, zero, 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) h1[m][i] = (short)bf16_bits(fmaxf(acc[i] + r.b1[4 * m + i], 0.0f));
+    for (int i = 0; i < 4; ++i) h1[m][i] = (short)bf16_bits(fmaxf(acc[i] + r.b1(m, i), 0.0f));
   }
   float part = 0.0f;
 #pragma unroll
@@ -95,13 +123,17 @@ __device__ inline float mlp_logit16(const MlpLane& r, const float f[4]) {
     f32x4_t acc = zero;
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w2[mo][kb], h1[kb], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w2(mo, kb), h1[kb], acc, 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) part += fmaxf(acc[i] + r.b2[4 * mo + i], 0.0f) * r.w3[4 * mo + i];
+    for (int i = 0; i < 4; ++i) part += fmaxf(acc[i] + r.b2(mo, i), 0.0f) * r.w3(mo, i);
   }
   part += __shfl_xor(part, 16);
   part += __shfl_xor(part, 32);
-  return part + r.b3;
+  return part + r.b3();
+}
+
+__device__ inline float mlp_logit16(const MlpLane& r, const float f[4]) {
+  return mlp_logit16_src(MlpFromRegs{r}, f);
 }
 
 hipError_t launch_mlp_grad(const float* p, const float* X, const float* y, int64_t B,

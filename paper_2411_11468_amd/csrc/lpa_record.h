@@ -39,12 +39,15 @@ __device__ __forceinline__ uint32_t rec_lq_float(float x) {  // x >= 1
   return q > 255 ? 255u : (q < 0 ? 0u : (uint32_t)q);
 }
 
-// Rewrite the record of v after its evaluation in iteration l; returns 1 when
-// the vertex had been predicted unchanged in this plain iteration and moved.
-__device__ __forceinline__ uint32_t rec_write(unsigned long long* rec, int32_t v, int l,
-                                              float K, float own, float bw, float second,
+// Rewrite the record of v after its evaluation in iteration l, given its
+// previous value `old` (loaded by the caller when the vertex's evaluation
+// starts, so that the read's latency hides behind the row scan); returns 1
+// when the vertex had been predicted unchanged in this plain iteration and
+// moved.
+__device__ __forceinline__ uint32_t rec_write(unsigned long long* rec, int32_t v,
+                                              unsigned long long old, int l, float K,
+                                              float own, float bw, float second,
                                               uint32_t distinct, uint32_t d, bool moved) {
-  const unsigned long long old = rec[v];
   const uint32_t hist = (uint32_t)(old >> 48) & 0xFFu;
   const uint32_t lu = (uint32_t)(old >> 56);
   const int shift = lu == 255u ? 8 : l - (int)lu;

@@ -153,6 +153,79 @@ lpa_status lpa_predictor_get_params(lpa_predictor p, float* params) {
   return LPA_OK;
 }
 
+// Checkpoint blob: a 32-byte header (magic "LPAPRED1", format version 1,
+// the layer sizes 12, 64, 64, 1, the parameter count and the Adam step
+// count), then the fp32 master parameters and Adam's first and second
+// moments, 5,057 values each, little-endian as in memory.
+namespace {
+struct BlobHeader {
+  char magic[8];
+  uint32_t version;
+  uint16_t n_in, n_h1, n_h2, n_out;
+  uint32_t n_params;
+  int32_t steps;
+  uint32_t reserved;
+};
+static_assert(sizeof(BlobHeader) == 32, "blob header layout");
+constexpr int64_t kBlobBytes = (int64_t)sizeof(BlobHeader) + 3 * (int64_t)kMlpParams * 4;
+}  // namespace
+
+lpa_status lpa_predictor_save(lpa_predictor p, void* blob, int64_t cap, int64_t* size) {
+  if (!p || !size) return fail(LPA_ERR_INVALID, "NULL argument");
+  *size = kBlobBytes;
+  if (!blob) return LPA_OK;
+  if (cap < kBlobBytes)
+    return fail(LPA_ERR_INVALID, "blob capacity below " + std::to_string(kBlobBytes) + " bytes");
+  BlobHeader h{};
+  std::memcpy(h.magic, "LPAPRED1", 8);
+  h.version = 1;
+  h.n_in = (uint16_t)kMlpIn;
+  h.n_h1 = (uint16_t)kMlpHidden;
+  h.n_h2 = (uint16_t)kMlpHidden;
+  h.n_out = 1;
+  h.n_params = (uint32_t)kMlpParams;
+  h.steps = p->steps;
+  uint8_t* out = static_cast<uint8_t*>(blob);
+  std::memcpy(out, &h, sizeof(h));
+  float* body = reinterpret_cast<float*>(out + sizeof(h));
+  LPA_HIP(hipMemcpyAsync(body, p->p, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost,
+                         p->stream));
+  LPA_HIP(hipMemcpyAsync(body + kMlpParams, p->m, sizeof(float) * kMlpParams,
+                         hipMemcpyDeviceToHost, p->stream));
+  LPA_HIP(hipMemcpyAsync(body + 2 * kMlpParams, p->v, sizeof(float) * kMlpParams,
+                         hipMemcpyDeviceToHost, p->stream));
+  LPA_HIP(hipStreamSynchronize(p->stream));
+  return LPA_OK;
+}
+
+lpa_status lpa_predictor_load(lpa_predictor p, const void* blob, int64_t size) {
+  if (!p || !blob) return fail(LPA_ERR_INVALID, "NULL argument");
+  if (size < (int64_t)sizeof(BlobHeader)) return fail(LPA_ERR_INVALID, "blob too short");
+  BlobHeader h;
+  std::memcpy(&h, blob, sizeof(h));
+  if (std::memcmp(h.magic, "LPAPRED1", 8) != 0) return fail(LPA_ERR_INVALID, "not a predictor blob");
+  if (h.version != 1) return fail(LPA_ERR_INVALID, "unknown predictor blob version");
+  if (h.n_in != kMlpIn || h.n_h1 != kMlpHidden || h.n_h2 != kMlpHidden || h.n_out != 1 ||
+      h.n_params != (uint32_t)kMlpParams)
+    return fail(LPA_ERR_INVALID, "predictor blob of another network shape");
+  if (size < kBlobBytes) return fail(LPA_ERR_INVALID, "blob truncated");
+  if (h.steps < 0) return fail(LPA_ERR_INVALID, "negative Adam step count in the blob");
+  const float* body =
+      reinterpret_cast<const float*>(static_cast<const uint8_t*>(blob) + sizeof(h));
+  for (int64_t i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(body[i])) return fail(LPA_ERR_INVALID, "non-finite parameter in the blob");
+  LPA_HIP(hipMemcpyAsync(p->p, body, sizeof(float) * kMlpParams, hipMemcpyHostToDevice,
+                         p->stream));
+  LPA_HIP(hipMemcpyAsync(p->m, body + kMlpParams, sizeof(float) * kMlpParams,
+                         hipMemcpyHostToDevice, p->stream));
+  LPA_HIP(hipMemcpyAsync(p->v, body + 2 * kMlpParams, sizeof(float) * kMlpParams,
+                         hipMemcpyHostToDevice, p->stream));
+  LPA_HIP(hipStreamSynchronize(p->stream));
+  p->steps = h.steps;
+  p->tiles_ok = false;
+  return LPA_OK;
+}
+
 lpa_status lpa_predictor_gradient(lpa_predictor p, const float* X, const float* y, int64_t n,
                                   float pos_weight, float* grad, double* loss) {
   if (!p || n < 0 || (n > 0 && (!X || !y))) return fail(LPA_ERR_INVALID, "bad argument");

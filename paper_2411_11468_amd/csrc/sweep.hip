@@ -33,7 +33,8 @@
 //                     hashtable is needed for rows this short.
 //   k_sweep_group     rows of up to 64 entries, 16 lanes and an LDS table per
 //                     vertex, four vertices per wave.
-//   k_sweep_wave(_pipe)   one wave per vertex, LDS hashtable per wave.
+//   k_sweep_wave_pipe  one wave per vertex, LDS hashtable per wave, the next
+//                     row's head loaded during the table scan.
 //   k_sweep_block(_pipe)  one workgroup per vertex, LDS hashtable per
 //                     workgroup; the _pipe forms load the next row's head
 //                     during the table scan.
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
     int32_t v = valid ? a.active[idx] : 0;
     int64_t o = 0, d = 0;
     if (valid) row_of<OffT>(a.off, v, &o, &d);
+    [[maybe_unused]] const unsigned long long rold = (FEAT && valid && k == 0) ? a.rec[v] : 0ull;
     const bool has = valid && k < d;
     const int32_t j = has ? __builtin_nontemporal_load(&a.tgt[o + k]) : -1;
     const float wt = has ? edge_weight(a.w, o + k) : 0.0f;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
       const uint32_t distinct =
           (uint32_t)rintf(group_sum_f32<G>(lab != kEmpty ? 1.0f / mult : 0.0f));
       if (leader && d >= 1)
-        my_fneg += rec_write(a.rec, v, l, K, own, bw, second, distinct, (uint32_t)d, moved);
+        my_fneg += rec_write(a.rec, v, rold, l, K, own, bw, second, distinct, (uint32_t)d, moved);
     }
     if (leader) {
       if (a.async_mode) {
@@ -302,9 +304,15 @@ struct RecPartial {
   }
 };
 
-// ---- one wave per vertex, LDS table per wave -------------------------------
+// ---- one wave per vertex, next row's head loaded during the table scan ------
+// Rows of 65-512 entries, one wave per vertex; the wave issues the
+// loads of its next vertex (list entry, row offsets, first 64U targets and
+// weights) before it scans and clears the current vertex's table, so that
+// those loads are in flight while the scan runs.  Labels are not
+// prefetched: they are read when the row is accumulated, as before.
+// FEAT: the learned variant, which also rewrites the state record.
 template <typename OffT, int SLOTS, int WAVES, int U, bool FEAT>
-__global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
+__global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   __shared__ uint32_t keys_all[WAVES][SLOTS];
   __shared__ float vals_all[WAVES][SLOTS];
   if (a.st->stop) return;
@@ -318,40 +326,73 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
   for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const uint32_t count = a.st->active[a.cls];
+  const uint32_t stride = gridDim.x * WAVES;
   unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0, my_fneg = 0;
-  for (uint32_t item = blockIdx.x * WAVES + wv; item < count; item += gridDim.x * WAVES) {
-    const int32_t v = a.active[item];
-    int64_t o, d;
-    row_of<OffT>(a.off, v, &o, &d);
+  int32_t v = 0, j[U];
+  int64_t o = 0, d = 0;
+  float wt[U];
+  auto head = [&](uint32_t it, int32_t& hv, int64_t& ho, int64_t& hd, int32_t* hj,
+                  float* hw) {
+    hv = a.active[it];
+    row_of<OffT>(a.off, hv, &ho, &hd);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = u * 64 + lane;
+      const bool has = e < hd;
+      hj[u] = has ? __builtin_nontemporal_load(&a.tgt[ho + e]) : hv;
+      hw[u] = has ? edge_weight(a.w, ho + e) : 0.0f;
+    }
+  };
+  uint32_t item = blockIdx.x * WAVES + wv;
+  if (item < count) head(item, v, o, d, j, wt);
+  while (item < count) {
     const int32_t cur = a.C[v];
+    [[maybe_unused]] const unsigned long long rold = (FEAT && lane == 0) ? a.rec[v] : 0ull;
     const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
-    unsigned long long best = 0;
-    for (int64_t base = 0; base < d; base += 64 * U) {
-      int32_t j[U];
-      float wt[U];
-      uint32_t lab[U];
+    uint32_t lab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+    #pragma unroll
+    for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (lab[u] != kEmpty) {
+        lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
+        if constexpr (FEAT) rp.K += wt[u];
+      }
+    for (int64_t base = 64 * U; base < d; base += 64 * U) {
+      int32_t jj[U];
+      float ww[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t e = base + u * 64 + lane;
         const bool has = e < d;
-        j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
-        wt[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+        jj[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
+        ww[u] = has ? edge_weight(a.w, o + e) : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
-#pragma unroll
-      for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
+        lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
+      #pragma unroll
+      for (int u = 0; u < U; ++u) merge_lead(lab[u], ww[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
-          lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
-          if constexpr (FEAT) rp.K += wt[u];
+          lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
+          if constexpr (FEAT) rp.K += ww[u];
         }
     }
+    // next vertex's head, in flight during the scan below
+    const uint32_t nitem = item + stride;
+    int32_t nv = 0, nj[U];
+    int64_t no = 0, nd = 0;
+    float nw[U];
+    if (nitem < count) head(nitem, nv, no, nd, nj, nw);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned long long best = 0;
     for (uint32_t s = lane; s < p1; s += 64) {
       const uint32_t kk = keys[s];
       if (kk != kEmpty) {
@@ -372,118 +413,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave(SweepArgs a) {
       const uint32_t distinct = wave_sum_u32(rp.distinct);
       const float K = wave_sum_f32(rp.K);
       if (lane == 0)
-        my_fneg += rec_write(a.rec, v, l, K, own, __uint_as_float((uint32_t)(best >> 32)),
+        my_fneg += rec_write(a.rec, v, rold, l, K, own, __uint_as_float((uint32_t)(best >> 32)),
                              second, distinct, (uint32_t)d, moved);
     }
-    if (lane == 0) {
-      if (a.async_mode) {
-        if (moved) a.C[v] = (int32_t)cstar;
-      } else {
-        a.Cn[v] = moved ? (int32_t)cstar : cur;
-      }
-    }
-    if (moved && lane == 0) a.chg[v] = 1;
-    if (lane == 0) {
-      my_edges += (unsigned long long)d;
-      my_changed += moved ? 1u : 0u;
-      my_flagw += moved ? (unsigned long long)d : 0ull;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  }
-  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
-  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
-}
-
-// ---- one wave per vertex, next row's head loaded during the table scan ------
-// Plain variant of k_sweep_wave for the rows of 65-512 entries: the wave
-// issues the loads of its next vertex (list entry, row offsets, first 64U
-// targets and weights) before it scans and clears the current vertex's
-// table, so that those loads are in flight while the scan runs.  Labels are
-// not prefetched: they are read when the row is accumulated, as before.
-template <typename OffT, int SLOTS, int WAVES, int U>
-__global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
-  __shared__ uint32_t keys_all[WAVES][SLOTS];
-  __shared__ float vals_all[WAVES][SLOTS];
-  if (a.st->stop) return;
-  const int pl = a.st->pl;  // fixed for the whole sweep
-  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
-  const int wv = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  uint32_t* keys = keys_all[wv];
-  float* vals = vals_all[wv];
-  for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  const uint32_t count = a.st->active[a.cls];
-  const uint32_t stride = gridDim.x * WAVES;
-  unsigned long long my_edges = 0, my_flagw = 0;
-  uint32_t my_changed = 0;
-  int32_t v = 0, j[U];
-  int64_t o = 0, d = 0;
-  float wt[U];
-  auto head = [&](uint32_t it, int32_t& hv, int64_t& ho, int64_t& hd, int32_t* hj,
-                  float* hw) {
-    hv = a.active[it];
-    row_of<OffT>(a.off, hv, &ho, &hd);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t e = u * 64 + lane;
-      const bool has = e < hd;
-      hj[u] = has ? __builtin_nontemporal_load(&a.tgt[ho + e]) : hv;
-      hw[u] = has ? edge_weight(a.w, ho + e) : 0.0f;
-    }
-  };
-  uint32_t item = blockIdx.x * WAVES + wv;
-  if (item < count) head(item, v, o, d, j, wt);
-  while (item < count) {
-    const int32_t cur = a.C[v];
-    const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
-    uint32_t lab[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
-    #pragma unroll
-    for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
-    for (int64_t base = 64 * U; base < d; base += 64 * U) {
-      int32_t jj[U];
-      float ww[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t e = base + u * 64 + lane;
-        const bool has = e < d;
-        jj[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
-        ww[u] = has ? edge_weight(a.w, o + e) : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
-      #pragma unroll
-      for (int u = 0; u < U; ++u) merge_lead(lab[u], ww[u], a.w == nullptr);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
-    }
-    // next vertex's head, in flight during the scan below
-    const uint32_t nitem = item + stride;
-    int32_t nv = 0, nj[U];
-    int64_t no = 0, nd = 0;
-    float nw[U];
-    if (nitem < count) head(nitem, nv, no, nd, nj, nw);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    unsigned long long best = 0;
-    for (uint32_t s = lane; s < p1; s += 64) {
-      const uint32_t kk = keys[s];
-      if (kk != kEmpty) {
-        best = umax64(best, pack_key(vals[s], kk));
-        keys[s] = kEmpty;
-        vals[s] = 0.0f;
-      }
-    }
-    best = wave_max_u64(best);
-    uint32_t cstar = 0;
-    const bool moved = decide(best, cur, pl, &cstar);
     if (lane == 0) {
       if (a.async_mode) {
         if (moved) a.C[v] = (int32_t)cstar;
@@ -502,6 +434,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
     for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
   }
   flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+  if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
 // ---- G lanes per vertex, LDS table per lane group ----------------------------
@@ -537,6 +470,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
     int64_t o, d;
     row_of<OffT>(a.off, v, &o, &d);
     const int32_t cur = a.C[v];
+    [[maybe_unused]] const unsigned long long rold = (FEAT && k == 0) ? a.rec[v] : 0ull;
     const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
     for (int64_t base = 0; base < d; base += G * U) {
@@ -584,7 +518,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a) {
       const uint32_t distinct = group_sum_u32<G>(rp.distinct);
       const float K = group_sum_f32<G>(rp.K);
       if (k == 0)
-        my_fneg += rec_write(a.rec, v, l, K, own, __uint_as_float((uint32_t)(best >> 32)),
+        my_fneg += rec_write(a.rec, v, rold, l, K, own, __uint_as_float((uint32_t)(best >> 32)),
                              second, distinct, (uint32_t)d, moved);
     }
     if (k == 0) {
@@ -632,6 +566,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
     // Own label, read before the barriers below: in asynchronous mode thread 0
     // overwrites it, and every thread must reach the same move decision.
     const int32_t cur = a.C[v];
+    [[maybe_unused]] const unsigned long long rold = (FEAT && tid == 0) ? a.rec[v] : 0ull;
     const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
     unsigned long long best = 0;
@@ -649,11 +584,9 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
-      // the merge slowed the 513-1024-entry class (2047 slots); the learned
-      // variant of the larger classes runs here and takes it
+      // rows sorted by target put runs of equal labels into one wave's lanes
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if constexpr (FEAT && SLOTS > 2047) merge_lead(lab[u], wt[u], a.w == nullptr);
+      for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) {
@@ -702,7 +635,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block(SweepArgs a) {
           distinct += redc[q];
           K += redk[q];
         }
-        my_fneg += rec_write(a.rec, v, l, K, __uint_as_float((uint32_t)ow),
+        my_fneg += rec_write(a.rec, v, rold, l, K, __uint_as_float((uint32_t)ow),
                              __uint_as_float((uint32_t)(best >> 32)),
                              __uint_as_float((uint32_t)(sec >> 32)), distinct, (uint32_t)d,
                              moved);
@@ -1295,6 +1228,7 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     const int32_t v = a.inv ? a.inv[vi] : vi;            // caller's id = its label
     int64_t o = 0, d = 0;
     if (valid) row_of<OffT>(INT ? a.off : a.uoff, INT ? vi : v, &o, &d);
+    [[maybe_unused]] const unsigned long long rold = (FEAT && valid && k == 0) ? a.rec[vi] : 0ull;
     unsigned long long best = 0, b2 = 0;  // this lane's two largest entries
     float K = 0.0f;
     uint32_t nd = 0;
@@ -1384,7 +1318,7 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
         __syncthreads();
       }
       if (leader && d >= 1)
-        my_fneg += rec_write(a.rec, vi, l, K, 0.0f, __uint_as_float((uint32_t)(best >> 32)),
+        my_fneg += rec_write(a.rec, vi, rold, l, K, 0.0f, __uint_as_float((uint32_t)(best >> 32)),
                              __uint_as_float((uint32_t)(sc >> 32)), nd, (uint32_t)d, moved);
     }
     if (leader) {
@@ -1529,10 +1463,7 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
       hipLaunchKernelGGL((k_sweep_group<OffT, 127, 16, FEAT>), dim3(grid), dim3(256), 0, s, a);
       break;
     case 4:
-      if constexpr (FEAT)
-        hipLaunchKernelGGL((k_sweep_wave<OffT, 1023, kWaveWaves, 4, true>), dim3(grid), dim3(256), 0, s, a);
-      else
-        hipLaunchKernelGGL((k_sweep_wave_pipe<OffT, 1023, kWaveWaves, 4>), dim3(grid), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_sweep_wave_pipe<OffT, 1023, kWaveWaves, 4, FEAT>), dim3(grid), dim3(256), 0, s, a);
       break;
     case 5:  // rows of one step: the head prefetch measured slower here
       hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a);

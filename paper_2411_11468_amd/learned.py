@@ -187,6 +187,32 @@ def load(path: str):
     return lpa.Predictor(params=z["params"]), info
 
 
+def table_md(res: dict, command: str) -> str:
+    """Markdown table of a learned-vs-plain evaluation (the JSON line of
+    bench.py --workload lfr1m, or of the evaluate command)."""
+    runs = res["runs"]
+    th = res.get("config", {}).get("threshold", res.get("threshold"))
+    mode = runs[0]["mode"] if runs else "?"
+    sp = res.get("speedup_geomean", res.get("geomean_speedup"))
+    out = [f"# Learned skipping vs plain ({'deterministic' if mode == 'det' else 'asynchronous'}"
+           " mode)", "", f"Command: `{command}`", "",
+           f"Threshold {th}; times are medians of graph-launched runs to termination on one "
+           "MI355X.", "",
+           "| graph | vertices | CSR entries | iterations plain / learned | ms plain | "
+           "ms learned | speedup | Q plain | Q learned | scanned plain | scanned learned | "
+           "skipped | fallback |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in runs:
+        out.append(f"| {r['graph']} | {r['vertices']} | {r['edges']} | {r['plain_iters']} / "
+                   f"{r['learned_iters']} | {r['plain_ms']:.3f} | {r['learned_ms']:.3f} | "
+                   f"{r['speedup']:.3f} | {r['plain_q']:.4f} | {r['learned_q']:.4f} | "
+                   f"{r['plain_scanned']} | {r['learned_scanned']} | {r['skipped']} | "
+                   f"{r['fallback']} |")
+    out += ["", f"Geometric-mean speedup {sp:.3f}; worst relative modularity loss "
+                f"{res['worst_dq_rel']:.4f}."]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -209,7 +235,17 @@ def main(argv=None) -> int:
     e.add_argument("--mode", default=None, choices=["det", "async"])
     e.add_argument("--threshold", type=float, default=None)
     e.add_argument("--out", default=None)
+    tb = sub.add_parser("table")
+    tb.add_argument("json")
+    tb.add_argument("--command", required=True)
+    tb.add_argument("--out", required=True)
     args = ap.parse_args(argv)
+    if args.cmd == "table":
+        with open(args.json) as f:
+            res = json.loads(f.read().strip().splitlines()[-1])
+        with open(args.out, "w") as f:
+            f.write(table_md(res, args.command))
+        return 0
     if args.cmd == "train":
         pred, info = train(args.n, args.graphs, args.mode, args.rate, args.epochs, args.batch,
                            args.lr, args.seed, args.fn_target)

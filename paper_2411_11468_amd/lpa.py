@@ -21,6 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblpa.so")
 
 LPA_OK = 0
+# lpa_status
+OK, ERR_INVALID, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
+
 MODE_DETERMINISTIC = 0
 MODE_ASYNC = 1
 INDEX_I32 = 0
@@ -56,7 +59,8 @@ class lpa_tuning(ctypes.Structure):
                 ("table_values", ctypes.c_int32), ("batch_queue", ctypes.c_int32),
                 ("queue_chunk", ctypes.c_int32), ("queue_group", ctypes.c_int32),
                 ("sort_rows", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("table_load", ctypes.c_int32), ("pull_divisor", ctypes.c_int32)]
+                ("table_load", ctypes.c_int32), ("pull_divisor", ctypes.c_int32),
+                ("memory_limit_kib", ctypes.c_int32)]
 
 
 class lpa_options(ctypes.Structure):
@@ -114,7 +118,8 @@ EXPORTED = ("lpa_options_default", "lpa_tuning_default", "lpa_create", "lpa_run"
             "lpa_predictor_gradient", "lpa_predictor_adam", "lpa_predictor_train",
             "lpa_predictor_predict", "lpa_learned_options_default", "lpa_set_predictor",
             "lpa_learned_history", "lpa_get_records", "lpa_trace", "lpa_autotune",
-            "lpa_label_read_rate", "lpa_modularity_noalloc")
+            "lpa_label_read_rate", "lpa_modularity_noalloc", "lpa_predictor_save",
+            "lpa_predictor_load")
 
 _lib = None
 
@@ -183,6 +188,10 @@ def load_library(path: str | None = None):
     lib.lpa_predictor_set_params.restype = ctypes.c_int
     lib.lpa_predictor_get_params.argtypes = [vp, vp]
     lib.lpa_predictor_get_params.restype = ctypes.c_int
+    lib.lpa_predictor_save.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.lpa_predictor_save.restype = ctypes.c_int
+    lib.lpa_predictor_load.argtypes = [vp, vp, ctypes.c_int64]
+    lib.lpa_predictor_load.restype = ctypes.c_int
     lib.lpa_predictor_gradient.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, vp,
                                            ctypes.POINTER(ctypes.c_double)]
     lib.lpa_predictor_gradient.restype = ctypes.c_int
@@ -658,6 +667,20 @@ class Predictor:
         out = np.empty(PREDICTOR_PARAMS, dtype=np.float32)
         _check(load_library().lpa_predictor_get_params(self.handle, _addr(out)))
         return out
+
+    def save_blob(self) -> bytes:
+        """Checkpoint (lpa_predictor_save): shape, parameters, Adam state."""
+        lib = load_library()
+        size = ctypes.c_int64(0)
+        _check(lib.lpa_predictor_save(self.handle, None, 0, ctypes.byref(size)))
+        buf = (ctypes.c_uint8 * size.value)()
+        _check(lib.lpa_predictor_save(self.handle, buf, size.value, ctypes.byref(size)))
+        return bytes(buf)
+
+    def load_blob(self, blob: bytes) -> None:
+        """Resume from a checkpoint (lpa_predictor_load)."""
+        buf = (ctypes.c_uint8 * len(blob)).from_buffer_copy(blob)
+        _check(load_library().lpa_predictor_load(self.handle, buf, len(blob)))
 
     def gradient(self, X, y, pos_weight: float = 1.0):
         X, y = _f32(X), _f32(y)

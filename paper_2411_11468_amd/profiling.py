@@ -10,6 +10,11 @@
       same files), and the hash of the kernel sources the counters were
       taken with.
 
+  python -m paper_2411_11468_amd.profiling counters <counter_collection.csv>...
+      --command CMD --out F.md
+      per-kernel mean per dispatch of every counter in the given files (one
+      file per --pmc pass), e.g. the L2 hits, misses and HBM read requests
+
 The traffic summary is read by bench.py, which reports it only while the
 kernel sources still hash to the recorded value.
 """
@@ -161,6 +166,29 @@ def traffic_json(fetch_csv: str, write_csv: str, copy_bytes: float, command: str
             "kernels": kernels}
 
 
+def counters_md(paths: list, command: str) -> str:
+    vals = defaultdict(lambda: defaultdict(list))   # kernel -> counter -> values
+    names = []
+    for p in paths:
+        for r in csv.DictReader(open(p)):
+            c = r.get("Counter_Name")
+            if not c:
+                continue
+            if c not in names:
+                names.append(c)
+            vals[short_name(r["Kernel_Name"])][c].append(float(r["Counter_Value"]))
+    out = ["# rocprofv3 counters per dispatch", "", f"Command: `{command}`", "",
+           f"Kernel sources: {source_hash()}", "",
+           "Mean per dispatch over the kernel's dispatches.", "",
+           "| kernel | dispatches | " + " | ".join(names) + " |",
+           "|---|---|" + "---|" * len(names)]
+    for k in sorted(vals, key=lambda k: -max(sum(v) for v in vals[k].values())):
+        n = max(len(v) for v in vals[k].values())
+        cells = [f"{sum(vals[k][c]) / len(vals[k][c]):.4g}" if vals[k][c] else "" for c in names]
+        out.append(f"| {k} | {n} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -174,8 +202,15 @@ def main(argv=None) -> int:
     b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--command", required=True)
     b.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--command", required=True)
+    c.add_argument("--out", required=True)
     args = ap.parse_args(argv)
-    if args.cmd == "stats":
+    if args.cmd == "counters":
+        with open(args.out, "w") as f:
+            f.write(counters_md(args.csv, args.command))
+    elif args.cmd == "stats":
         with open(args.out, "w") as f:
             f.write(kernel_stats_md(args.csv, args.command))
     else:

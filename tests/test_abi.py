@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     from paper_2411_11468_amd import lpa
     # sizes implied by the header's field lists on LP64
     assert ctypes.sizeof(lpa.lpa_csr) == 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
-    assert ctypes.sizeof(lpa.lpa_tuning) == 18 * 4
+    assert ctypes.sizeof(lpa.lpa_tuning) == 19 * 4
     assert ctypes.sizeof(lpa.lpa_options) == 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(lpa.lpa_kernel_profile) == 24 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lpa.lpa_iter_stats) == 4 + 4 + 8 + 8 + 8 + 4 + 4

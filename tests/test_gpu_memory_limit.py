@@ -1,0 +1,128 @@
+"""GPU: the handle's device memory limit (lpa_tuning.memory_limit_kib).
+
+An allocation that would pass the limit fails like a failed hipMalloc:
+lpa_create / lpa_create_batched return LPA_ERR_OOM, hand back no handle and
+leave the device's free memory where it was, at every point where the
+limit can strike; with room enough the same graph runs and equals the
+oracle.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2411_11468_amd import lpa  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _free():
+    """Device memory held by neither torch's caching allocator nor anyone
+    else: what the library's own allocations take from."""
+    torch.cuda.synchronize()
+    return torch.cuda.mem_get_info()[0] + torch.cuda.memory_reserved()
+
+
+def _warm(d, v_off=None):
+    """Unlimited handles in both vertex orders (and batched), run and
+    modularity: each source file's code object is loaded onto the device on
+    its first launch, and the static device arrays with it, which must
+    happen before free memory is compared."""
+    for relabel in (0, 1):
+        t = lpa.default_tuning()
+        t.relabel = relabel
+        G = lpa.LpaGraph(*d, tuning=t)
+        G.modularity(G.run("det").labels)
+        G.close()
+    if v_off is not None:
+        B = lpa.LpaBatch(v_off, *d)
+        B.run_batched("det")
+        B.close()
+
+
+@pytest.mark.parametrize("relabel", [0, 1])
+def test_memory_limit_fails_cleanly_at_every_allocation(relabel):
+    g = graphgen.rmat_graph(14, 3, "int8")
+    d = (_dev(g.offsets), _dev(g.targets), _dev(g.weights))
+    _warm(d)
+    free0 = _free()
+    limits = [1, 16, 64, 256, 1024, 2048, 4096, 8192, 16384]
+    failed = 0
+    for kib in limits:
+        t = lpa.default_tuning()
+        t.memory_limit_kib, t.relabel = kib, relabel
+        try:
+            G = lpa.LpaGraph(*d, tuning=t)
+        except lpa.LpaError as e:
+            assert e.status == lpa.ERR_OOM, e
+            failed += 1
+            assert _free() == free0, kib
+            continue
+        res = G.run("det")
+        np.testing.assert_array_equal(res.labels.cpu().numpy(),
+                                      oracle.lpa_sync(g.offsets, g.targets, g.weights).labels)
+        G.close()
+        assert _free() == free0, kib
+    assert 3 <= failed < len(limits) - 1
+    t = lpa.default_tuning()
+    t.memory_limit_kib = -1
+    with pytest.raises(lpa.LpaError):
+        lpa.LpaGraph(*d, tuning=t)
+
+
+def test_memory_limit_batched_and_run_buffers():
+    g, v_off = graphgen.planted_partition_batch(16, 2, n_range=(256, 2000))
+    d = (_dev(g.offsets), _dev(g.targets), _dev(g.weights))
+    _warm(d, v_off)
+    free0 = _free()
+    t = lpa.default_tuning()
+    t.memory_limit_kib = 8
+    with pytest.raises(lpa.LpaError) as ei:
+        lpa.LpaBatch(v_off, *d, tuning=t)
+    assert ei.value.status == lpa.ERR_OOM
+    assert _free() == free0
+    # a handle within its limit for lpa_create and lpa_run (whose buffers are
+    # allocated on first use), whose modularity buffers (first use too) would
+    # pass it: lpa_modularity reports LPA_ERR_OOM, the handle stays usable
+    single = graphgen.planted_partition_10k(4)
+    ds = (_dev(single.offsets), _dev(single.targets), _dev(single.weights))
+
+    def fits(kib):
+        t.memory_limit_kib = kib
+        try:
+            G = lpa.LpaGraph(*ds, tuning=t)
+        except lpa.LpaError as e:
+            assert e.status == lpa.ERR_OOM, e
+            return False
+        try:
+            G.run("det")
+            return True
+        except lpa.LpaError as e:
+            assert e.status == lpa.ERR_OOM, e
+            return False
+        finally:
+            G.close()
+
+    lo, hi = 1, 1 << 16
+    assert fits(hi)
+    while lo < hi:  # the smallest limit that lets lpa_create and lpa_run succeed
+        mid = (lo + hi) // 2
+        if fits(mid):
+            hi = mid
+        else:
+            lo = mid + 1
+    assert _free() == free0
+    t.memory_limit_kib = lo
+    G = lpa.LpaGraph(*ds, tuning=t)
+    res = G.run("det")
+    with pytest.raises(lpa.LpaError) as ei:
+        G.modularity(res.labels)
+    assert ei.value.status == lpa.ERR_OOM
+    np.testing.assert_array_equal(G.run("det").labels.cpu().numpy(), res.labels.cpu().numpy())
+    G.close()

@@ -173,3 +173,51 @@ def test_predictor_invalid_arguments():
     with pytest.raises(lpa.LpaError):
         pr.train(X, y, epochs=1, batch=4, lr=0.0)
     pr.close()
+
+
+def test_save_load_checkpoint_resumes_training():
+    # lpa_predictor_save / lpa_predictor_load: shape header, parameters and
+    # Adam state.  A loaded predictor holds exactly the saved state (its own
+    # blob is the same bytes, its predictions the same values); trained on,
+    # it follows the saved one up to the order of the gradient kernel's
+    # float atomic sums, far closer than a predictor given only the
+    # parameters, whose Adam state starts at zero
+    X, y = _samples(4000, 7)
+    a = lpa.Predictor(seed=3)
+    a.train(X, y, epochs=1, batch=256, lr=2e-3, seed=1)
+    blob = a.save_blob()
+    assert len(blob) == 32 + 3 * 4 * lpa.PREDICTOR_PARAMS
+    assert blob[:8] == b"LPAPRED1"
+    b = lpa.Predictor(seed=99)
+    b.load_blob(blob)
+    assert b.save_blob() == blob
+    np.testing.assert_array_equal(a.params(), b.params())
+    pa, pb = a.predict(X), b.predict(X)
+    np.testing.assert_array_equal(np.asarray(pa.cpu() if hasattr(pa, "cpu") else pa),
+                                  np.asarray(pb.cpu() if hasattr(pb, "cpu") else pb))
+    c = lpa.Predictor(seed=99)
+    c.set_params(np.frombuffer(blob[32:32 + 4 * lpa.PREDICTOR_PARAMS], dtype=np.float32))
+    la = a.train(X, y, epochs=2, batch=256, lr=2e-3, seed=5)
+    lb = b.train(X, y, epochs=2, batch=256, lr=2e-3, seed=5)
+    c.train(X, y, epochs=2, batch=256, lr=2e-3, seed=5)
+    assert abs(la - lb) <= 1e-5 * abs(la)
+    # quantiles, not maxima: a parameter whose gradient is pure cancellation
+    # may take an Adam step of either sign in either run
+    d_ab = float(np.quantile(np.abs(a.params() - b.params()), 0.99))
+    d_ac = float(np.quantile(np.abs(a.params() - c.params()), 0.5))
+    print(f"99th percentile |a-b| {d_ab:.3g}, median |a-c| {d_ac:.3g}")
+    assert d_ac >= 1e-4
+    assert d_ab <= 0.02 * d_ac
+    # corrupted or foreign blobs are refused and leave the predictor as it was
+    before = b.params()
+    bad = [b"XXXXXXXX" + blob[8:], blob[:100], blob[:8] + b"\x02" + blob[9:],
+           blob[:12] + b"\x0d" + blob[13:]]
+    nan = bytearray(blob)
+    nan[32:36] = np.array([np.nan], np.float32).tobytes()
+    bad.append(bytes(nan))
+    for x in bad:
+        with pytest.raises(lpa.LpaError):
+            b.load_blob(x)
+    np.testing.assert_array_equal(b.params(), before)
+    for p in (a, b, c):
+        p.close()

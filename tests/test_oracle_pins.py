@@ -389,3 +389,24 @@ def test_pl_refusable_hand_cases_and_pick_less_sweeps():
         off_max = np.nonzero(~ok)[0]
         ref = oracle.pl_refusable(g.offsets, g.targets, g.weights, lab, off_max)
         assert np.array_equal(ref, one[off_max] == lab[off_max]), t
+
+
+def test_cpu_async_baseline_results():
+    # the multi-core CPU baseline (not the oracle): disjoint cliques end with
+    # one label per clique, Q = 1 - 1/r; on the planted partition every label
+    # names a vertex, the run stops within the cap and finds the planted
+    # structure (its in-place order, 1024 vertices per thread and step in id
+    # order, ends near Q 0.69 where the synchronous oracle reaches 0.75)
+    for r_, s_ in ((6, 5), (20, 4)):
+        g = graphgen.disjoint_cliques(r_, s_)
+        res = oracle.cpu_lpa_async(g.offsets, g.targets, g.weights)
+        q = oracle.modularity(g.offsets, g.targets, g.weights, res.labels)
+        assert q == pytest.approx(1 - 1 / r_, abs=1e-12)
+        assert res.iterations <= 20 and res.threads >= 1
+    g = _planted()
+    res = oracle.cpu_lpa_async(g.offsets, g.targets, g.weights)
+    assert ((res.labels >= 0) & (res.labels < g.num_vertices)).all()
+    ref = oracle.lpa_sync(g.offsets, g.targets, g.weights)
+    q = oracle.modularity(g.offsets, g.targets, g.weights, res.labels)
+    assert q >= 0.6 and q <= oracle.modularity(g.offsets, g.targets, g.weights, ref.labels) + 0.05
+    assert 1 <= res.iterations <= 20
