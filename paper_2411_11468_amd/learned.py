@@ -234,6 +234,8 @@ def main(argv=None) -> int:
     e.add_argument("--rmat", type=int, default=24, help="R-MAT scale (0: none)")
     e.add_argument("--mode", default=None, choices=["det", "async"])
     e.add_argument("--threshold", type=float, default=None)
+    e.add_argument("--seeds", default=None,
+                   help="comma-separated LFR seeds instead of the first --heldout held-out ones")
     e.add_argument("--out", default=None)
     tb = sub.add_parser("table")
     tb.add_argument("json")
@@ -256,7 +258,9 @@ def main(argv=None) -> int:
     pred, info = load(args.params)
     mode = args.mode or info["mode"]
     th = args.threshold if args.threshold is not None else info["threshold"]
-    graphs = [(f"lfr{args.n}-s{s}", lfr(args.n, s)) for s in list(HELDOUT_SEEDS)[:args.heldout]]
+    seeds = ([int(x) for x in args.seeds.split(",")] if args.seeds
+             else list(HELDOUT_SEEDS)[:args.heldout])
+    graphs = [(f"lfr{args.n}-s{s}", lfr(args.n, s)) for s in seeds]
     if args.rmat:
         graphs.append((f"rmat{args.rmat}", graphgen.rmat_graph(args.rmat, args.rmat, "unit")))
     res = evaluate(pred, th, graphs, mode)

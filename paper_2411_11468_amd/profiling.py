@@ -131,15 +131,30 @@ def _counter_rows(csv_path: str, counter: str) -> list:
             for r in csv.DictReader(open(csv_path)) if r.get("Counter_Name") == counter]
 
 
-def _calibration(rows: list, copy_kib: float) -> tuple:
-    """Scale that maps the counter of the largest device copies (the
-    reference copies of copy_kib KiB each) onto their true size."""
-    copies = [v for k, v in rows if "copy" in k.lower()]
+def _copy_rows(csv_path: str, counter: str) -> list:
+    """(dispatch id, grid size, value) of the copy kernels, in dispatch order."""
+    rows = [(int(r["Dispatch_Id"]), int(r.get("Grid_Size") or 0), float(r["Counter_Value"]))
+            for r in csv.DictReader(open(csv_path))
+            if r.get("Counter_Name") == counter and "copy" in r["Kernel_Name"].lower()]
+    return sorted(rows)
+
+
+def _calibration(copies: list, copy_kib: float) -> tuple:
+    """Scale that maps the counter of the reference copies (copy_kib KiB
+    each) onto their true size.  bench.py --calibrate-copy runs them last:
+    one untimed and three timed copies of the same size, so they are the
+    trailing copy dispatches of the run with the last one's grid size (an
+    upload earlier in the run may be a larger copy kernel)."""
     if not copies:
         raise SystemExit("no copy kernel in the counter run")
-    big = [v for v in copies if v >= 0.5 * max(copies)]
-    mean = sum(big) / len(big)
-    return copy_kib / mean, len(big)
+    grid = copies[-1][1]
+    tail = []
+    for d, gsz, v in reversed(copies):
+        if gsz != grid or len(tail) == 3:
+            break
+        tail.append(v)
+    mean = sum(tail) / len(tail)
+    return copy_kib / mean, len(tail)
 
 
 def _means_by_kernel(rows: list) -> dict:
@@ -153,8 +168,8 @@ def traffic_json(fetch_csv: str, write_csv: str, copy_bytes: float, command: str
     frows = _counter_rows(fetch_csv, "FETCH_SIZE")
     wrows = _counter_rows(write_csv, "WRITE_SIZE")
     kib = copy_bytes / 1024.0
-    f_scale, nf = _calibration(frows, kib)
-    w_scale, nw = _calibration(wrows, kib)
+    f_scale, nf = _calibration(_copy_rows(fetch_csv, "FETCH_SIZE"), kib)
+    w_scale, nw = _calibration(_copy_rows(write_csv, "WRITE_SIZE"), kib)
     fm, wm = _means_by_kernel(frows), _means_by_kernel(wrows)
     kernels = {}
     for s, (f, n) in fm.items():

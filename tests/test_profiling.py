@@ -29,39 +29,42 @@ def test_short_names():
 
 def _counter_csv(path, rows):
     with open(path, "w", newline="") as f:
-        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Grid_Size", "Kernel_Name",
+                                          "Counter_Name", "Counter_Value"])
         w.writeheader()
-        for r in rows:
-            w.writerow(r)
+        for i, r in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Grid_Size": r.pop("grid", 256), **r})
 
 
 def test_traffic_scaling(tmp_path):
-    # a 1 GiB copy reads half its bytes per the counter (scale 2) and writes
-    # all of them (scale 1); a sweep kernel's two dispatches are averaged
+    # the reference copies (1 GiB each, the trailing copy dispatches: one
+    # untimed, three timed) read half their bytes per the counter (scale 2)
+    # and write all of them (scale 1); a larger upload copy earlier in the
+    # run does not enter the scale; a sweep kernel's two dispatches are
+    # averaged
     gib = float(1 << 30)
     kib = gib / 1024
-    fetch = [
-        {"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "FETCH_SIZE",
-         "Counter_Value": kib / 2},
-        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
-         "Counter_Name": "FETCH_SIZE", "Counter_Value": 100.0},
-        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
-         "Counter_Name": "FETCH_SIZE", "Counter_Value": 300.0},
-    ]
-    write = [
-        {"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": "WRITE_SIZE",
-         "Counter_Value": kib},
-        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
-         "Counter_Name": "WRITE_SIZE", "Counter_Value": 10.0},
-        {"Kernel_Name": "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)",
-         "Counter_Name": "WRITE_SIZE", "Counter_Value": 30.0},
-    ]
+    copy = "__amd_rocclr_copyBuffer"
+    hub = "void lpa::k_hub_part<long, 16383, 1024>(lpa::HubArgs)"
+
+    def run(counter, upload, hub_vals, ref):
+        rows = [{"Kernel_Name": copy, "Counter_Name": counter, "Counter_Value": upload,
+                 "grid": 999}]
+        rows += [{"Kernel_Name": hub, "Counter_Name": counter, "Counter_Value": v}
+                 for v in hub_vals]
+        rows += [{"Kernel_Name": copy, "Counter_Name": counter, "Counter_Value": ref,
+                  "grid": 131072} for _ in range(4)]
+        return rows
+
+    fetch = run("FETCH_SIZE", 4 * kib, [100.0, 300.0], kib / 2)
+    write = run("WRITE_SIZE", 8 * kib, [10.0, 30.0], kib)
     fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
     _counter_csv(fp, fetch)
     _counter_csv(wp, write)
     t = profiling.traffic_json(str(fp), str(wp), gib, "cmd")
     json.dumps(t)
     assert abs(t["fetch_scale"] - 2.0) < 1e-9 and abs(t["write_scale"] - 1.0) < 1e-9
+    assert t["copy_dispatches"] == [3, 3]
     hp = t["kernels"]["hub_part"]
     assert hp["dispatches"] == 2
     assert abs(hp["bytes_per_dispatch"] - 1024.0 * (200.0 * 2.0 + 20.0)) < 1e-6
