@@ -113,8 +113,12 @@ typedef struct lpa_graph_s* lpa_graph;
  * Every hashtable holding D keys has 2^m - 1 >= 2D - 1 slots (load <= 1/2).
  * hub_chunk: edges per workgroup slice for the largest rows (default 8192).
  * max_retries: hybrid probes before the linear continuation (default 32).
- * xcd_local: 1 = the buckets of consecutive indices run on one XCD (their
- *   pair runs share cache lines); 0 = plain round-robin (default 1; same
+ * xcd_local: bit 0 (1): the hub buckets of consecutive indices run on one
+ *   XCD (their pair runs share cache lines); bit 1 (2): when every hub is
+ *   flagged and the rows hold strictly increasing targets, the hub slices
+ *   are taken in eight groups by target window, group x first by the
+ *   workgroups on XCD x (each XCD's L2 then holds the labels of one window
+ *   of ids); 0 = plain round-robin (default 3; every value gives the same
  *   results).
  * hub_table_cap: 0 (default) = bucket tables of up to 16383 slots; else at
  *   most this many slots (rounded down to 2^m - 1), to exercise the spill

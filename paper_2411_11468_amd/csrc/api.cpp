@@ -109,6 +109,9 @@ struct lpa_graph_s {
   float* gvals = nullptr;
   uint32_t* items = nullptr;
   uint32_t* bitems = nullptr;
+  uint32_t* witems = nullptr;     // hub slices grouped by target window (or NULL)
+  unsigned int* wctr = nullptr;   // their pop counters
+  uint32_t wbase[kXcds + 1] = {};
   uint32_t* part_keys = nullptr;
   float* part_vals = nullptr;
   uint32_t* boff = nullptr;
@@ -344,7 +347,10 @@ struct lpa_graph_s {
     a.bsize = bsize; a.hub_bq = hub_bq;
     a.H = H; a.chunk = tun.hub_chunk; a.async_mode = async_mode;
     a.probe = ProbeCfg{tun.max_retries, tun.probe};
-    a.xcd_map = tun.xcd_local;
+    a.xcd_map = tun.xcd_local & 1;
+    a.witems = witems;
+    a.wctr = wctr;
+    for (int x = 0; x <= kXcds; ++x) a.wbase[x] = wbase[x];
     uint32_t cap = 16383u;
     if (tun.hub_table_cap > 0) {
       cap = 1u;
@@ -391,7 +397,7 @@ void lpa_tuning_default(lpa_tuning* t) {
   t->block = 8192;
   t->hub_chunk = 8192;
   t->max_retries = 32;
-  t->xcd_local = 1;
+  t->xcd_local = 3;
   t->relabel = -1;
   t->batch_queue = -1;
   t->queue_chunk = 512;
@@ -425,6 +431,62 @@ const char* lpa_status_string(lpa_status s) {
 
 const char* lpa_last_error(void) { return g_err.c_str(); }
 
+// Hub slices grouped by target window, one group per XCD: a slice of a
+// row sorted by target covers a contiguous range of ids, placed here by its
+// middle entry's position in the id order weighted by entries (rows are
+// read as often as their vertex's degree, so equal-weight windows spread
+// the label reads evenly).  The slices are sorted by that position and cut
+// into kXcds runs of equal entry counts; k_hub_part takes run x on XCD x
+// first, so that each XCD's L2 holds the labels of its own window.
+static lpa_status group_hub_slices(lpa_graph G, const std::vector<int64_t>& hd, int64_t items,
+                                   hipStream_t s) {
+  const int chunk = G->tun.hub_chunk;
+  std::vector<uint32_t> sl(2 * (size_t)items);
+  std::vector<int64_t> len((size_t)items);
+  int64_t k = 0;
+  for (int32_t h = 0; h < G->H; ++h)
+    for (int64_t c = 0, nch = (hd[h] + chunk - 1) / chunk; c < nch; ++c, ++k) {
+      sl[2 * k] = (uint32_t)h;
+      sl[2 * k + 1] = (uint32_t)c;
+      len[k] = std::min<int64_t>(chunk, hd[h] - c * chunk);
+    }
+  uint32_t* dsl = nullptr;
+  int64_t* dkey = nullptr;
+  if (lpa_status e = G->dalloc(&dsl, 2 * items)) return e;
+  if (lpa_status e = G->dalloc(&dkey, items)) return e;
+  LPA_HIP(hipMemcpyAsync(dsl, sl.data(), sizeof(uint32_t) * sl.size(), hipMemcpyHostToDevice, s));
+  LPA_HIP(launch_slice_keys(G->off64, G->off, G->tgt, G->hub_vid, dsl, items, chunk, dkey, s));
+  std::vector<int64_t> key((size_t)items);
+  LPA_HIP(hipMemcpyAsync(key.data(), dkey, sizeof(int64_t) * items, hipMemcpyDeviceToHost, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> order((size_t)items);
+  for (int64_t i = 0; i < items; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+  int64_t total = 0;
+  for (int64_t i = 0; i < items; ++i) total += len[i];
+  std::vector<uint32_t> out(2 * (size_t)items);
+  int64_t acc = 0;
+  int x = 0;
+  G->wbase[0] = 0;
+  for (int64_t i = 0; i < items; ++i) {
+    // group x holds the slices whose entries start below (x + 1) / kXcds
+    // of the total
+    while (x + 1 < kXcds && acc >= total * (x + 1) / kXcds) G->wbase[++x] = (uint32_t)i;
+    out[2 * i] = sl[2 * order[i]];
+    out[2 * i + 1] = sl[2 * order[i] + 1];
+    acc += len[order[i]];
+  }
+  while (x + 1 <= kXcds) G->wbase[++x] = (uint32_t)items;
+  // the slice list is reused for the grouped order
+  LPA_HIP(hipMemcpyAsync(dsl, out.data(), sizeof(uint32_t) * out.size(), hipMemcpyHostToDevice, s));
+  if (lpa_status e = G->dalloc(&G->wctr, kXcds * kQueueCtrStride)) return e;
+  LPA_HIP(launch_fill_u32(G->wctr, 0u, kXcds * kQueueCtrStride, s));
+  LPA_HIP(hipStreamSynchronize(s));
+  G->witems = dsl;
+  return LPA_OK;
+}
+
 static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* tuning,
                               lpa_graph_s* G) {
   G->stream = (hipStream_t)stream;
@@ -448,7 +510,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
         (t.block_threads == 0 || t.block_threads == 256 || t.block_threads == 512 ||
          t.block_threads == 1024) &&
         (t.table_load == 1 || t.table_load == 2 || t.table_load == 4) &&
-        t.memory_limit_kib >= 0 &&
+        t.memory_limit_kib >= 0 && t.xcd_local >= 0 && t.xcd_local <= 3 &&
         t.pull_divisor >= 1 && t.pull_divisor <= 4096))
     return fail(LPA_ERR_INVALID, "tuning thresholds out of range");
   // the ablation kernels' largest LDS table has 8191 slots (rows of <= 4096)
@@ -755,6 +817,8 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->hub_fin_grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, 256 * 8));
     G->hub_direct_grid = G->hub_fin_grid;
     LPA_HIP(hipStreamSynchronize(s));
+    if ((t.xcd_local & 2) && G->strict_rows && items > 0)
+      if (lpa_status e = group_hub_slices(G, hd, items, s)) return e;
   }
   LPA_HIP(hipEventCreate(&G->ev0));
   LPA_HIP(hipEventCreate(&G->ev1));

@@ -424,6 +424,35 @@ hipError_t launch_gather_degrees(bool off64, const void* off, const int32_t* vid
   return hipGetLastError();
 }
 
+// Position of each hub slice's middle entry in the id order by entry mass:
+// the row offset of its target (the entries of all rows before it).  Slices
+// are listed as (hub index, slice index) pairs.
+template <typename OffT>
+__global__ void k_slice_keys(const OffT* off, const int32_t* tgt, const int32_t* hub_vid,
+                             const uint32_t* sl, int64_t ns, int chunk, int64_t* key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int32_t v = hub_vid[sl[2 * i]];
+  const int64_t c = sl[2 * i + 1];
+  const int64_t o = (int64_t)off[v], d = (int64_t)off[v + 1] - o;
+  const int64_t e0 = c * chunk;
+  const int64_t n = d - e0 < chunk ? d - e0 : chunk;
+  key[i] = (int64_t)off[tgt[o + e0 + n / 2]];
+}
+
+hipError_t launch_slice_keys(bool off64, const void* off, const int32_t* tgt,
+                             const int32_t* hub_vid, const uint32_t* sl, int64_t ns, int chunk,
+                             int64_t* key, hipStream_t s) {
+  const int g = grid_for(ns, kBT, 1 << 20);
+  if (off64)
+    hipLaunchKernelGGL(k_slice_keys<int64_t>, dim3(g), dim3(kBT), 0, s, (const int64_t*)off, tgt,
+                       hub_vid, sl, ns, chunk, key);
+  else
+    hipLaunchKernelGGL(k_slice_keys<int32_t>, dim3(g), dim3(kBT), 0, s, (const int32_t*)off, tgt,
+                       hub_vid, sl, ns, chunk, key);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(count, kBT, 8192)), dim3(kBT), 0, s, p, v, count);
   return hipGetLastError();
@@ -480,6 +509,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     st->changed[tid] = 0;
     st->flagw[tid] = 0;
   }
+  if (a.witems && tid < kXcds) a.wctr[tid * kQueueCtrStride] = 0u;
   __syncthreads();
   const OffT* off = reinterpret_cast<const OffT*>(a.off);
   // queue the flagged hubs' slices and buckets (inclusive Hillis-Steele scans
@@ -535,6 +565,7 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
     st->hub_items = run_s;
     st->hub_bitems = run_b;
     st->processed = nproc;
+    st->hub_all = (int32_t)nproc == a.H ? 1u : 0u;
   }
 }
 

@@ -40,6 +40,7 @@ struct DevStats {
   unsigned long long hub_pairs;                 // (label, sum) pairs the hub slices
                                                 // wrote this iteration
   unsigned int hub_items;                       // hub slices queued this iteration
+  unsigned int hub_all;                         // every hub is flagged this iteration
   unsigned int hub_bitems;                      // hub label buckets queued this iteration
   // run control, resident on the device so that iterations can be launched
   // back to back (or replayed from a captured graph) without the host
@@ -191,6 +192,13 @@ struct HubArgs {
   ProbeCfg probe;
   int xcd_map;                     // 1: consecutive buckets on one XCD
   uint32_t table_cap;              // largest bucket table (2^m - 1 slots)
+  // slices grouped by target window: when every hub is flagged, k_hub_part
+  // takes the slices of group x (witems[wbase[x] .. wbase[x+1]), (hub,
+  // slice) word pairs) on XCD x first, popped with the counters wctr (one
+  // per group, kQueueCtrStride words apart), then the other groups'
+  const uint32_t* witems;          // NULL: no grouping
+  unsigned int* wctr;
+  uint32_t wbase[kXcds + 1];
 };
 
 // Statistics of one iteration as recorded on the device (same layout as the
@@ -279,6 +287,9 @@ hipError_t launch_classify(bool off64, const void* off, int64_t n,
                            const int32_t* bounds, uint8_t* cls,
                            unsigned long long* counts, int32_t* hub_out,
                            unsigned int* hub_count, hipStream_t s);
+hipError_t launch_slice_keys(bool off64, const void* off, const int32_t* tgt,
+                             const int32_t* hub_vid, const uint32_t* sl, int64_t ns, int chunk,
+                             int64_t* key, hipStream_t s);
 hipError_t launch_gather_degrees(bool off64, const void* off, const int32_t* vids,
                                  int32_t h, int64_t* deg, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);

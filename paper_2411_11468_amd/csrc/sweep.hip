@@ -880,6 +880,30 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __syncthreads();
   const uint32_t nitems = a.st->hub_items;
+  // with every hub flagged, the slices grouped by target window: group x
+  // first on XCD x, then the others (the results do not depend on which
+  // workgroup takes a slice)
+  const bool grouped = a.witems != nullptr && a.st->hub_all != 0;
+  const uint32_t* isrc = grouped ? a.witems : a.items;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  __shared__ uint32_t s_next[2];
+  uint32_t home = grouped ? xcc_id() : 0u, done_groups = 0u, seq = 0u;
+  // the next slice for this workgroup (thread 0 only)
+  auto fetch = [&]() -> uint32_t {
+    if (!grouped) {
+      const uint32_t i = blockIdx.x + seq * gridDim.x;
+      ++seq;
+      return i < nitems ? i : kNone;
+    }
+    for (int k = 0; k < kXcds; ++k) {
+      const uint32_t x = (home + (uint32_t)k) & (uint32_t)(kXcds - 1);
+      if (done_groups & (1u << x)) continue;
+      const uint32_t i = atomicAdd(&a.wctr[x * kQueueCtrStride], 1u);
+      if (i < a.wbase[x + 1] - a.wbase[x]) return a.wbase[x] + i;
+      done_groups |= 1u << x;
+    }
+    return kNone;
+  };
   unsigned long long my_edges = 0, my_pairs = 0;
   // U entries per thread in flight: targets, then their labels, then the
   // table inserts.  The first BT*U targets of the next slice (its head) are
@@ -893,8 +917,8 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     float wt[U];
   };
   auto head = [&](uint32_t it, Head& H) {
-    H.h = (int32_t)a.items[2 * (uint64_t)it];
-    H.c = (int32_t)a.items[2 * (uint64_t)it + 1];
+    H.h = (int32_t)isrc[2 * (uint64_t)it];
+    H.c = (int32_t)isrc[2 * (uint64_t)it + 1];
     H.v = a.hub_vid[H.h];
     int64_t d;
     row_of<OffT>(a.off, H.v, &H.o, &d);
@@ -908,10 +932,17 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
       H.wt[u] = has ? edge_weight(a.w, H.o + H.e0 + e) : 0.0f;
     }
   };
+  if (tid == 0) {
+    s_next[0] = fetch();
+    s_next[1] = s_next[0] != kNone ? fetch() : kNone;
+  }
+  __syncthreads();
+  uint32_t it = s_next[0], nit = s_next[1];
+  int par = 0;
+  __syncthreads();
   Head cur{};
-  uint32_t it = blockIdx.x;
-  if (it < nitems) head(it, cur);
-  while (it < nitems) {
+  if (it != kNone) head(it, cur);
+  while (it != kNone) {
     const int32_t h = cur.h, c = cur.c, v = cur.v;
     const int64_t o = cur.o, e0 = cur.e0, n = cur.n;
     const int lgb = a.hub_lgb[h];
@@ -947,9 +978,12 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
       for (int u = 0; u < U; ++u)
         if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.probe);
     }
-    const uint32_t nit = it + gridDim.x;
     Head nxt{};
-    if (nit < nitems) head(nit, nxt);
+    if (nit != kNone) head(nit, nxt);
+    // the slice after the next one, read by every thread after the last
+    // barrier of this slice (two words: a slow thread may still read the
+    // previous one while thread 0 writes this one)
+    if (tid == 0) s_next[par] = nit != kNone ? fetch() : kNone;
     __syncthreads();
     for (uint32_t s = tid; s < p1c; s += BT) {
       const uint32_t kk = keys[s];
@@ -980,7 +1014,10 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     }
     if (tid == 0) my_edges += (unsigned long long)n;
     __syncthreads();
+    const uint32_t nn = s_next[par];
+    par ^= 1;
     it = nit;
+    nit = nn;
     cur = nxt;
   }
   // one atomic per workgroup (my_pairs lives in thread 0: the (label, sum)
@@ -1434,7 +1471,7 @@ int hub_max_resident() { return 256; }
 template <typename OffT, int BT>
 static hipError_t sweep_block_bt(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
-    case 5: hipLaunchKernelGGL((k_sweep_block<OffT, 2047, BT, 4, false>), dim3(grid), dim3(BT), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 2047, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 4095, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
     case 7: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 8191, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 16383, BT, 4>), dim3(grid), dim3(BT), 0, s, a); break;
@@ -1465,8 +1502,9 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
     case 4:
       hipLaunchKernelGGL((k_sweep_wave_pipe<OffT, 1023, kWaveWaves, 4, FEAT>), dim3(grid), dim3(256), 0, s, a);
       break;
-    case 5:  // rows of one step: the head prefetch measured slower here
-      hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, FEAT>), dim3(grid), dim3(256), 0, s, a);
+    case 5:
+      if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 2047, 256, 4, true>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 2047, 256, 4>), dim3(grid), dim3(256), 0, s, a);
       break;
     case 6:
       if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4, true>), dim3(grid), dim3(256), 0, s, a);

@@ -58,7 +58,7 @@ def test_defaults(lib):
     t = lpa.default_tuning()
     assert (t.small4, t.small16, t.wave, t.block, t.hub_chunk, t.max_retries, t.xcd_local,
             t.hub_table_cap, t.relabel, t.probe, t.table_values) == \
-        (4, 16, 512, 8192, 8192, 32, 1, 0, -1, 0, 0)
+        (4, 16, 512, 8192, 8192, 32, 3, 0, -1, 0, 0)
 
 
 def test_status_strings(lib):

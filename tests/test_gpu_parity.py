@@ -116,9 +116,10 @@ def test_det_every_class_small_thresholds():
     assert_det_parity(r, tuning=t)
 
 
-@pytest.mark.parametrize("xcd_local", [0, 1])
+@pytest.mark.parametrize("xcd_local", [0, 1, 2, 3])
 def test_det_hub_merge_paths(xcd_local):
-    # hub slices merged on one XCD with L2-local atomics, or device-wide only
+    # hub buckets merged on one XCD with L2-local atomics, or device-wide
+    # only; hub slices taken in target-window groups per XCD, or round-robin
     t = _tuning(**SMALL_TUNING, xcd_local=xcd_local)
     assert_det_parity(graphgen.random_graph(1500, 0.25, seed=5, wmax=8), tuning=t)
     assert_det_parity(graphgen.rmat_graph(13, 8, "int8"), tuning=t)
@@ -302,6 +303,11 @@ def test_invalid_inputs_rejected():
     bad_o[2] = 0
     with pytest.raises(lpa.LpaError):
         lpa.LpaGraph(_dev(bad_o), _dev(g.targets), _dev(g.weights))
+    for bad in (-1, 4):
+        t = lpa.default_tuning()
+        t.xcd_local = bad
+        with pytest.raises(lpa.LpaError):
+            lpa.LpaGraph(_dev(g.offsets), _dev(g.targets), _dev(g.weights), tuning=t)
     G = _graph_on_gpu(g)
     with pytest.raises(lpa.LpaError):
         G.run("det", initial_labels=_dev(np.array([0, 1, 2, 9], np.int32)))
