@@ -1063,6 +1063,11 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
   for (uint32_t j = lw; j < per; j += nlw) {
     const uint32_t it = x * per + j;
     if (it >= nitems) break;
+    // pairs of this bucket over all slices (counted by k_hub_part), read
+    // first: the buckets of the other size class are passed over with this
+    // one load
+    const uint32_t E = a.bsize[it];
+    if (E == 0 || (E > kHubSmallE) != LARGE) continue;  // uniform over the workgroup
     const int32_t h = (int32_t)a.bitems[2 * (uint64_t)it];
     const uint32_t b = a.bitems[2 * (uint64_t)it + 1];
     const int32_t v = a.hub_vid[h];
@@ -1072,9 +1077,6 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
     const int lgb = a.hub_lgb[h];
     const uint32_t nb1 = (1u << lgb) + 1u;
     const uint32_t* bo = a.boff + a.hub_boff0[h];
-    // pairs of this bucket over all slices (counted by k_hub_part)
-    const uint32_t E = a.bsize[it];
-    if (E == 0 || (E > kHubSmallE) != LARGE) continue;  // uniform over the workgroup
     uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
     if (p1 > a.table_cap) p1 = a.table_cap;
     const int64_t slice0 = a.hub_slice0[h];
