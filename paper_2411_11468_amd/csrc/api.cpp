@@ -71,6 +71,7 @@ struct lpa_graph_s {
   const float* w = nullptr;
   const void* uoff = nullptr;    // the caller's CSR (uploaded or borrowed)
   const int32_t* utgt = nullptr;
+  int32_t* ctgt = nullptr;       // internal rows with the caller's ids (or NULL)
   const float* uw = nullptr;
   int32_t* perm = nullptr;       // caller id -> internal id; NULL: one order
   int32_t* inv = nullptr;        // internal id -> caller id
@@ -337,7 +338,7 @@ struct lpa_graph_s {
   HubArgs hub_args(int async_mode) const {
     HubArgs a;
     a.off = off; a.tgt = tgt; a.w = w; a.C = C; a.F = F; a.chg = chg;
-    a.uoff = uoff; a.utgt = utgt; a.uw = uw; a.inv = inv;
+    a.uoff = uoff; a.utgt = utgt; a.uw = uw; a.inv = inv; a.ctgt = ctgt;
     a.pend_v = pend_v; a.pend_c = pend_c; a.st = st;
     a.hub_vid = hub_vid; a.hub_tab = hub_tab; a.hub_best = hub_best; a.hub_old = hub_old;
     a.hub_nch = hub_nch; a.hub_ovf = hub_ovf; a.hub_lgb = hub_lgb;
@@ -676,6 +677,11 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
     G->off = noff;
     G->tgt = ntgt;
     G->w = nw;
+    // the internal rows once more with the caller's ids as targets: the
+    // first sweep of a run, whose labels are the caller's ids, streams them
+    // instead of reading the caller's rows in a scattered order
+    if (lpa_status e = G->dalloc(&G->ctgt, m)) return e;
+    if (m > 0) LPA_HIP(launch_unpermute_i32(G->inv, ntgt, m, G->ctgt, s));
   }
 
   // labels, flags, deterministic-mode queue
@@ -951,7 +957,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   SweepArgs a;
   a.off = g->off; a.tgt = g->tgt; a.w = g->w; a.C = g->C; a.Cn = g->Cn; a.F = g->F;
   a.chg = g->chg; a.st = g->st;
-  a.uoff = g->uoff; a.utgt = g->utgt; a.uw = g->uw; a.inv = g->inv;
+  a.uoff = g->uoff; a.utgt = g->utgt; a.uw = g->uw; a.inv = g->inv; a.ctgt = g->ctgt;
   a.async_mode = async_mode;
   a.probe = ProbeCfg{g->tun.max_retries, g->tun.probe};
   a.rec = g->lrec;

@@ -143,6 +143,9 @@ struct SweepArgs {
   // orders agree), read by the table-free first sweep
   const void* uoff;
   const int32_t* utgt;
+  // internal rows with the caller's ids as targets (NULL: none); the first
+  // sweep streams these instead of the caller's rows
+  const int32_t* ctgt = nullptr;
   const float* uw;
   const int32_t* inv;
 };
@@ -160,6 +163,7 @@ struct HubArgs {
   const float* w;
   const void* uoff;                // the caller's CSR and inv, as in SweepArgs
   const int32_t* utgt;
+  const int32_t* ctgt = nullptr;   // as in SweepArgs
   const float* uw;
   const int32_t* inv;
   int32_t* C;

@@ -336,7 +336,9 @@ hipError_t relabel_locality(bool off64, const void* off, const int32_t* tgt, int
   return hipGetLastError();
 }
 
-// out[v] = in[perm[v]] for 4-, 1- and 8-byte per-vertex arrays.
+// out[i] = in[idx[i]] for 4-, 1- and 8-byte arrays: per-vertex arrays put
+// back into the caller's order (idx = perm), or the internal targets mapped
+// to the caller's ids (in = inv, idx = the internal targets).
 template <typename T>
 __global__ void k_unpermute(const T* in, const int32_t* perm, int64_t n, T* out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;

@@ -1266,17 +1266,22 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
     const int32_t vi = valid ? a.active[idx] : 0;       // internal id
     const int32_t v = a.inv ? a.inv[vi] : vi;            // caller's id = its label
     int64_t o = 0, d = 0;
-    if (valid) row_of<OffT>(INT ? a.off : a.uoff, INT ? vi : v, &o, &d);
+    // cint: the internal rows carry the caller's ids (no inv reads, rows of
+    // one class contiguous)
+    const bool cint = a.ctgt != nullptr;
+    const bool irow = INT || cint;
+    if (valid) row_of<OffT>(irow ? a.off : a.uoff, irow ? vi : v, &o, &d);
     [[maybe_unused]] const unsigned long long rold = (FEAT && valid && k == 0) ? a.rec[vi] : 0ull;
     unsigned long long best = 0, b2 = 0;  // this lane's two largest entries
     float K = 0.0f;
     uint32_t nd = 0;
-    const int32_t* rt = INT ? a.tgt : a.utgt;
-    const float* rw = INT ? a.w : a.uw;
-    const int32_t self = INT ? vi : v;
+    const int32_t* rt = cint ? a.ctgt : (INT ? a.tgt : a.utgt);
+    const float* rw = irow ? a.w : a.uw;
+    const bool remap = INT && !cint && a.inv != nullptr;
+    const int32_t self = (INT && !cint) ? vi : v;
     auto take = [&](int32_t jr, float wj) {
       if (jr == self) return;
-      const int32_t j = (INT && a.inv) ? a.inv[jr] : jr;
+      const int32_t j = remap ? a.inv[jr] : jr;
       const unsigned long long pk = pack_key(wj, (uint32_t)j);
       if constexpr (FEAT) {
         if (pk > best) { b2 = best; best = pk; } else if (pk > b2) { b2 = pk; }
@@ -1387,8 +1392,12 @@ __global__ __launch_bounds__(BT) void k_hub_direct(HubArgs a) {
     const int32_t c = (int32_t)a.items[2 * (uint64_t)it + 1];
     const int32_t vi = a.hub_vid[h];
     const int32_t v = a.inv ? a.inv[vi] : vi;  // the caller's row, same length
+    // the internal row with the caller's ids, when the handle keeps one
+    const bool cint = a.ctgt != nullptr;
+    const int32_t* rt = cint ? a.ctgt : a.utgt;
+    const float* rw = cint ? a.w : a.uw;
     int64_t o, d;
-    row_of<OffT>(a.uoff, v, &o, &d);
+    row_of<OffT>(cint ? a.off : a.uoff, cint ? vi : v, &o, &d);
     const int64_t e0 = (int64_t)c * a.chunk;
     const int64_t n = (d - e0 < a.chunk) ? d - e0 : a.chunk;
     unsigned long long best = 0;
@@ -1399,16 +1408,16 @@ __global__ __launch_bounds__(BT) void k_hub_direct(HubArgs a) {
       float wj[UD];
 #pragma unroll
       for (int u = 0; u < UD; ++u) {
-        j[u] = __builtin_nontemporal_load(&a.utgt[o + e0 + e + u * BT]);
-        wj[u] = edge_weight(a.uw, o + e0 + e + u * BT);
+        j[u] = __builtin_nontemporal_load(&rt[o + e0 + e + u * BT]);
+        wj[u] = edge_weight(rw, o + e0 + e + u * BT);
       }
 #pragma unroll
       for (int u = 0; u < UD; ++u)
         if (j[u] != v) best = umax64(best, pack_key(wj[u], (uint32_t)j[u]));
     }
     for (; e < n; e += BT) {
-      const int32_t j = __builtin_nontemporal_load(&a.utgt[o + e0 + e]);
-      if (j != v) best = umax64(best, pack_key(edge_weight(a.uw, o + e0 + e), (uint32_t)j));
+      const int32_t j = __builtin_nontemporal_load(&rt[o + e0 + e]);
+      if (j != v) best = umax64(best, pack_key(edge_weight(rw, o + e0 + e), (uint32_t)j));
     }
     best = wave_max_u64(best);
     if (lane == 0 && best) atomicMax(&a.hub_best[h], best);
