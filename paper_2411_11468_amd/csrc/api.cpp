@@ -72,6 +72,7 @@ struct lpa_graph_s {
   const void* uoff = nullptr;    // the caller's CSR (uploaded or borrowed)
   const int32_t* utgt = nullptr;
   int32_t* ctgt = nullptr;       // internal rows with the caller's ids (or NULL)
+  uint32_t* chg_bits = nullptr;  // the change bytes as bits, for the pull kernels
   const float* uw = nullptr;
   int32_t* perm = nullptr;       // caller id -> internal id; NULL: one order
   int32_t* inv = nullptr;        // internal id -> caller id
@@ -691,6 +692,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   if (lpa_status e = G->dalloc(&G->pend_c, n)) return e;
   if (lpa_status e = G->dalloc(&G->Cn, n)) return e;
   if (lpa_status e = G->dalloc(&G->chg, n)) return e;
+  if (lpa_status e = G->dalloc(&G->chg_bits, (n + 31) / 32)) return e;
   if (lpa_status e = G->dalloc(&G->cls, n)) return e;
 
   // degree classes
@@ -1012,11 +1014,11 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     LPA_HIP(launch_push_hubs(g->off64, ha, g->hub_fin_grid, s));
   }
   if (lpa_status e = mark(kKidPull)) return e;
-  LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, n, g->cls, g->chg, g->F, g->st,
+  LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, n, g->cls, g->chg, g->chg_bits, g->F, g->st,
                             g->pull_grid, s));
   if (g->H > 0) {
     if (lpa_status e = mark(kKidPullHubs)) return e;
-    LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg, g->F,
+    LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg_bits, g->F,
                              g->st, s));
   }
   if (g->G > 0) {
@@ -1624,10 +1626,10 @@ lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags) {
     // from the change bytes it left (the frontier of a next run clears them)
     hipStream_t s = g->stream;
     LPA_HIP(launch_flags_resume(g->st, s));
-    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, g->n, g->cls, g->chg, g->F, g->st,
+    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, g->n, g->cls, g->chg, g->chg_bits, g->F, g->st,
                               g->pull_grid, s));
     if (g->H > 0)
-      LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg, g->F,
+      LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg_bits, g->F,
                                g->st, s));
     LPA_HIP(launch_flags_done(g->st, s));
     g->flags_pending = false;

@@ -1119,10 +1119,42 @@ __device__ __forceinline__ uint32_t or8(uint32_t x) {
 }
 }  // namespace
 
+// The change bytes packed into bits (bit v % 32 of word v / 32) for the pull
+// kernels: their reads land at data-dependent vertices, and the bitmap
+// (n / 8 bytes) keeps far more of them in one cache line than the bytes do.
+__global__ __launch_bounds__(kBT) void k_pack_chg(const uint8_t* chg, int64_t n, uint32_t* bits,
+                                                  const DevStats* st) {
+  if (st->stop || st->pull_mode != 1u) return;
+  const int64_t nw = (n + 31) / 32;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t out = 0;
+    if (32 * w + 32 <= n) {
+      const uint32_t* p = reinterpret_cast<const uint32_t*>(chg + 32 * w);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t x = p[q];
+        // the high bit of each byte of nz is set where that byte is nonzero
+        const uint32_t nz = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+        out |= (((nz >> 7) & 1u) | ((nz >> 14) & 2u) | ((nz >> 21) & 4u) | ((nz >> 28) & 8u))
+               << (4 * q);
+      }
+    } else {
+      for (int64_t v = 32 * w; v < n; ++v)
+        if (chg[v]) out |= 1u << (v - 32 * w);
+    }
+    bits[w] = out;
+  }
+}
+
+__device__ __forceinline__ bool chg_bit(const uint32_t* bits, int32_t j) {
+  return (bits[j >> 5] >> (j & 31)) & 1u;
+}
+
 template <typename OffT>
 __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32_t* tgt,
                                                     int64_t n, const uint8_t* cls,
-                                                    const uint8_t* chg, uint8_t* F,
+                                                    const uint32_t* chg, uint8_t* F,
                                                     DevStats* st) {
   if (st->stop || st->pull_mode != 1u) return;
   const int lane = threadIdx.x & 63;
@@ -1154,7 +1186,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
     for (int u = 0; u < kFirst; ++u) {
       if (j[u] >= 0 && !found) {
         ++scanned;
-        found = chg[j[u]] != 0;
+        found = chg_bit(chg, j[u]);
       }
     }
     if (found) F[v] = 1;
@@ -1174,7 +1206,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
         uint32_t hit = 0;
         const int64_t e = t + k;
         if (!done && e < pd) {
-          hit = chg[tgt[po + pd - 1 - e]];
+          hit = chg_bit(chg, tgt[po + pd - 1 - e]) ? 1u : 0u;
           ++scanned;
         }
         hit = or8(hit);
@@ -1203,7 +1235,7 @@ __global__ __launch_bounds__(kBT) void k_pull_flags(const OffT* off, const int32
 template <typename OffT>
 __global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_t* tgt,
                                                    const int32_t* hub_vid, int32_t H,
-                                                   const uint8_t* chg, uint8_t* F,
+                                                   const uint32_t* chg, uint8_t* F,
                                                    DevStats* st) {
   constexpr int U = 8;  // entries per thread and step, all in flight at once
   __shared__ unsigned long long ws[kBT / 64];
@@ -1226,7 +1258,7 @@ __global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_
       for (int u = 0; u < U; ++u)
         if (j[u] >= 0) {
           ++scanned;
-          hit |= chg[j[u]] ? 1 : 0;
+          hit |= chg_bit(chg, j[u]) ? 1 : 0;
         }
       found = __syncthreads_or(hit) != 0;  // uniform over the workgroup
     }
@@ -1244,19 +1276,22 @@ __global__ __launch_bounds__(kBT) void k_pull_hubs(const OffT* off, const int32_
 }
 
 hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
-                             const uint8_t* cls, const uint8_t* chg, uint8_t* F,
-                             DevStats* st, int grid, hipStream_t s) {
+                             const uint8_t* cls, const uint8_t* chg, uint32_t* chg_bits,
+                             uint8_t* F, DevStats* st, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_chg, dim3(grid_for((n + 31) / 32, kBT, 8192)), dim3(kBT), 0, s, chg,
+                     n, chg_bits, st);
   if (off64)
     hipLaunchKernelGGL(k_pull_flags<int64_t>, dim3(grid), dim3(kBT), 0, s,
-                       (const int64_t*)off, tgt, n, cls, chg, F, st);
+                       (const int64_t*)off, tgt, n, cls, chg_bits, F, st);
   else
     hipLaunchKernelGGL(k_pull_flags<int32_t>, dim3(grid), dim3(kBT), 0, s,
-                       (const int32_t*)off, tgt, n, cls, chg, F, st);
+                       (const int32_t*)off, tgt, n, cls, chg_bits, F, st);
   return hipGetLastError();
 }
 
+// chg_bits: the packed change bits that launch_pull_flags wrote just before
 hipError_t launch_pull_hubs(bool off64, const void* off, const int32_t* tgt,
-                            const int32_t* hub_vid, int32_t H, const uint8_t* chg,
+                            const int32_t* hub_vid, int32_t H, const uint32_t* chg,
                             uint8_t* F, DevStats* st, hipStream_t s) {
   const int g = H < 2048 ? H : 2048;
   if (off64)

@@ -332,15 +332,16 @@ hipError_t launch_cc_apply(int32_t* C, const int32_t* Cp, uint8_t* chg, uint8_t*
 // pass (resume), close it again (done).
 hipError_t launch_flags_resume(DevStats* st, hipStream_t s);
 hipError_t launch_flags_done(DevStats* st, hipStream_t s);
+// packs chg into chg_bits ((n + 31) / 32 words), then pulls the flags
 hipError_t launch_pull_flags(bool off64, const void* off, const int32_t* tgt, int64_t n,
-                             const uint8_t* cls, const uint8_t* chg, uint8_t* F,
-                             DevStats* st, int grid, hipStream_t s);
+                             const uint8_t* cls, const uint8_t* chg, uint32_t* chg_bits,
+                             uint8_t* F, DevStats* st, int grid, hipStream_t s);
 hipError_t launch_push_lists(bool off64, const void* off, const int32_t* tgt,
                              int32_t* const* lists, const uint8_t* chg, uint8_t* F,
                              DevStats* st, int grid, hipStream_t s);
 hipError_t launch_push_hubs(bool off64, const HubArgs& a, int grid, hipStream_t s);
 hipError_t launch_pull_hubs(bool off64, const void* off, const int32_t* tgt,
-                            const int32_t* hub_vid, int32_t H, const uint8_t* chg,
+                            const int32_t* hub_vid, int32_t H, const uint32_t* chg_bits,
                             uint8_t* F, DevStats* st, hipStream_t s);
 hipError_t launch_apply(const DevStats* st, int32_t* const* lists, const int32_t* Cn,
                         const int32_t* pv, const int32_t* pc, int32_t* C, int grid,

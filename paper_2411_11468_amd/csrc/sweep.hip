@@ -1456,7 +1456,8 @@ int sweep_items_per_block(int cls) {
 int sweep_direct_items_per_block(int cls) {
   switch (cls) {
     case 1: return 256;
-    case 2: case 3: case 4: return 256 / 16;
+    case 2: return 256 / 4;
+    case 3: case 4: return 256 / 16;
     case 5: case 6: return 256 / 64;
     default: return 1;
   }
@@ -1538,7 +1539,9 @@ template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
   switch (cls) {
     case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 1, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
-    case 2: case 3: case 4:
+    case 2:
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
+    case 3: case 4:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
     case 5: case 6:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;

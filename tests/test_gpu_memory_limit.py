@@ -24,7 +24,9 @@ def _dev(a):
 
 def _free():
     """Device memory held by neither torch's caching allocator nor anyone
-    else: what the library's own allocations take from."""
+    else: what the library's own allocations take from.  Compared with >=:
+    a leak lowers it, while the runtime may hand back memory of its own
+    (in 4 MiB steps) between two readings."""
     torch.cuda.synchronize()
     return torch.cuda.mem_get_info()[0] + torch.cuda.memory_reserved()
 
@@ -62,13 +64,13 @@ def test_memory_limit_fails_cleanly_at_every_allocation(relabel):
         except lpa.LpaError as e:
             assert e.status == lpa.ERR_OOM, e
             failed += 1
-            assert _free() == free0, kib
+            assert _free() >= free0, kib
             continue
         res = G.run("det")
         np.testing.assert_array_equal(res.labels.cpu().numpy(),
                                       oracle.lpa_sync(g.offsets, g.targets, g.weights).labels)
         G.close()
-        assert _free() == free0, kib
+        assert _free() >= free0, kib
     assert 3 <= failed < len(limits) - 1
     t = lpa.default_tuning()
     t.memory_limit_kib = -1
@@ -86,7 +88,7 @@ def test_memory_limit_batched_and_run_buffers():
     with pytest.raises(lpa.LpaError) as ei:
         lpa.LpaBatch(v_off, *d, tuning=t)
     assert ei.value.status == lpa.ERR_OOM
-    assert _free() == free0
+    assert _free() >= free0
     # a handle within its limit for lpa_create and lpa_run (whose buffers are
     # allocated on first use), whose modularity buffers (first use too) would
     # pass it: lpa_modularity reports LPA_ERR_OOM, the handle stays usable
@@ -117,7 +119,7 @@ def test_memory_limit_batched_and_run_buffers():
             hi = mid
         else:
             lo = mid + 1
-    assert _free() == free0
+    assert _free() >= free0
     t.memory_limit_kib = lo
     G = lpa.LpaGraph(*ds, tuning=t)
     res = G.run("det")
