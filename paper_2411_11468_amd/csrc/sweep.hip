@@ -1325,6 +1325,10 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
       // one lane per vertex: nothing to combine
     } else if constexpr (G == 4) {
       best = quad_max_u64(best);
+    } else if constexpr (G == 8) {
+      // the two quads of each half row: quad maxima, then row_half_mirror
+      best = quad_max_u64(best);
+      best = umax64(best, dpp64<0x141>(best));
     } else if constexpr (G == 16) {
       best = row16_max_u64(best);
     } else {
@@ -1348,6 +1352,13 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
         // the lane's own top two and sums are the row's
       } else if constexpr (G == 4) {
         sc = quad_max_u64(sc); K = group_sum_f32<4>(K); nd = group_sum_u32<4>(nd);
+      } else if constexpr (G == 8) {
+        sc = quad_max_u64(sc);
+        sc = umax64(sc, dpp64<0x141>(sc));
+        K = group_sum_f32<4>(K);
+        K += dppf<0x141>(K);
+        nd = group_sum_u32<4>(nd);
+        nd += dpp32<0x141>(nd);
       } else if constexpr (G == 16) {
         sc = row16_max_u64(sc); K = group_sum_f32<16>(K); nd = group_sum_u32<16>(nd);
       } else {
@@ -1457,7 +1468,8 @@ int sweep_direct_items_per_block(int cls) {
   switch (cls) {
     case 1: return 256;
     case 2: return 256 / 4;
-    case 3: case 4: return 256 / 16;
+    case 3: return 256 / 8;
+    case 4: return 256 / 16;
     case 5: case 6: return 256 / 64;
     default: return 1;
   }
@@ -1541,7 +1553,9 @@ static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s)
     case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 1, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
     case 2:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 4, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
-    case 3: case 4:
+    case 3:
+      hipLaunchKernelGGL((k_sweep_direct<OffT, 8, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
+    case 4:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 16, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;
     case 5: case 6:
       hipLaunchKernelGGL((k_sweep_direct<OffT, 64, 256, FEAT, false>), dim3(grid), dim3(256), 0, s, a); break;

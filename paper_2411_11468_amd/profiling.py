@@ -46,12 +46,13 @@ _NAME_RULES = [
     (r"k_sweep_block(_pipe)?<[^,]+, 8191,", "sweep_block8191"),
     (r"k_sweep_block(_pipe)?<[^,]+, 16383,", "sweep_block16383"),
     # the table-free first sweep: one instantiation per lane-group width
-    # (1 for degrees up to 4; 4 for 5..16; 16 for 17..512; 64 for
-    # 513..2048; 256 above), so lpa_profile's direct_wave127 +
-    # direct_wave1023 make "direct_g16", its block2047 + block4095
-    # "direct_g64" and its block8191 + block16383 "direct_g256"
+    # (1 for degrees up to 4; 4 for 5..16; 8 for 17..64; 16 for 65..512;
+    # 64 for 513..2048; 256 above), so lpa_profile's direct_wave1023 is
+    # "direct_g16", its block2047 + block4095 "direct_g64" and its
+    # block8191 + block16383 "direct_g256"
     (r"k_sweep_direct<[^,]+, 1,", "direct_small4"),
     (r"k_sweep_direct<[^,]+, 4,", "direct_small16"),
+    (r"k_sweep_direct<[^,]+, 8,", "direct_wave127"),
     (r"k_sweep_direct<[^,]+, 16,", "direct_g16"),
     (r"k_sweep_direct<[^,]+, 64,", "direct_g64"),
     (r"k_sweep_direct<[^,]+, 256,", "direct_g256"),
