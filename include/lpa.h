@@ -125,8 +125,10 @@ typedef struct lpa_graph_s* lpa_graph;
  *   path in tests.
  * relabel: where the handle keeps each vertex's label and row.  1 = in an
  *   internal order by degree, largest first (8 steps per octave, ties by
- *   id), built once by lpa_create as a second copy of the CSR: the label
- *   reads of every sweep then concentrate on few cache lines.  0 = in the
+ *   id), built once by lpa_create as a second copy of the CSR (plus its
+ *   targets once more as the caller's ids, 4 bytes per entry, which the
+ *   first sweep of a run streams): the label reads of every sweep then
+ *   concentrate on few cache lines.  0 = in the
  *   caller's order.  -1 (default) = automatic: internal order when N > 2^20
  *   and fewer than half of the CSR entries of a row sample point within
  *   2^16 ids of their row.  Label values, results and every array passed in
