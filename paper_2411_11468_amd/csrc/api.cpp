@@ -88,6 +88,10 @@ struct lpa_graph_s {
   uint8_t* F = nullptr;
   int32_t* lists[kNumClasses] = {};
   int64_t cls_count[kNumClasses] = {};
+  // vertices that can be flagged after the first iteration: in the internal
+  // order (by degree, largest first) those of degree 0 come last and are
+  // left out; in the caller's order all n
+  int64_t n_active = 0;
   int grid[kNumClasses] = {};
   int direct_grid[kNumClasses] = {};  // table-free first sweep
   int tv_grid[kNumClasses] = {};      // table_values 32 / 64: sweep_tv.hip
@@ -721,6 +725,7 @@ static lpa_status create_impl(const lpa_csr* g, void* stream, const lpa_tuning* 
   LPA_HIP(hipMemcpyAsync(hcounts, counts, sizeof(hcounts), hipMemcpyDeviceToHost, s));
   LPA_HIP(hipStreamSynchronize(s));
   for (int c = 0; c < kNumClasses; ++c) G->cls_count[c] = (int64_t)hcounts[c];
+  G->n_active = G->perm ? n - G->cls_count[0] : n;
   G->H = (int32_t)(uint32_t)hcounts[kNumClasses];
   for (int c = 1; c < kNumClasses; ++c) {
     if (c == kClassHub) continue;
@@ -934,11 +939,14 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
   if (lpa_status e = mark(kKidPlan)) return e;
   LPA_HIP(launch_hub_plan(g->off64, ha, g->C, g->F, s));
   if (lpa_status e = mark(kKidFrontier)) return e;
+  // after the first iteration only the vertices of positive degree can be
+  // flagged (without pruning every vertex is, every iteration)
+  const int64_t n_later = o.prune ? g->n_active : n;
   if (rc.feat && rc.infer)
-    LPA_HIP(launch_frontier_learned(n, g->F, g->cls, g->lists, g->chg, g->st, g->lrec, rc.tiles,
+    LPA_HIP(launch_frontier_learned(n, n_later, g->F, g->cls, g->lists, g->chg, g->st, g->lrec, rc.tiles,
                                     rc.tr, g->learn_grid, s));
   else
-    LPA_HIP(launch_frontier(n, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
+    LPA_HIP(launch_frontier(n, n_later, g->F, g->cls, g->lists, g->chg, g->st, g->frontier_grid, s));
   if (g->H > 0 && direct) {
     if (lpa_status e = mark(kKidHubDirect)) return e;
     LPA_HIP(launch_hub_direct(g->off64, ha, g->hub_direct_grid, s));
@@ -1014,7 +1022,7 @@ static lpa_status enqueue_iteration(lpa_graph g, const lpa_options& o, const Run
     LPA_HIP(launch_push_hubs(g->off64, ha, g->hub_fin_grid, s));
   }
   if (lpa_status e = mark(kKidPull)) return e;
-  LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, n, g->cls, g->chg, g->chg_bits, g->F, g->st,
+  LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, g->n_active, g->cls, g->chg, g->chg_bits, g->F, g->st,
                             g->pull_grid, s));
   if (g->H > 0) {
     if (lpa_status e = mark(kKidPullHubs)) return e;
@@ -1626,7 +1634,7 @@ lpa_status lpa_get_flags(lpa_graph g, uint8_t* flags) {
     // from the change bytes it left (the frontier of a next run clears them)
     hipStream_t s = g->stream;
     LPA_HIP(launch_flags_resume(g->st, s));
-    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, g->n, g->cls, g->chg, g->chg_bits, g->F, g->st,
+    LPA_HIP(launch_pull_flags(g->off64, g->off, g->tgt, g->n_active, g->cls, g->chg, g->chg_bits, g->F, g->st,
                               g->pull_grid, s));
     if (g->H > 0)
       LPA_HIP(launch_pull_hubs(g->off64, g->off, g->tgt, g->hub_vid, g->H, g->chg_bits, g->F,

@@ -581,9 +581,9 @@ hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
 // ---- frontier: append flagged vertices to their class list, clear flags ------
 struct ListPtrs { int32_t* p[kNumClasses]; };
 
-__global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
-                                                  ListPtrs lists, uint8_t* chg_clear,
-                                                  DevStats* st) {
+__global__ __launch_bounds__(kBT) void k_frontier(int64_t n_all, int64_t n_later, uint8_t* F,
+                                                  const uint8_t* cls, ListPtrs lists,
+                                                  uint8_t* chg_clear, DevStats* st) {
   // kWords words of four vertices per thread and block step: the block's
   // appends cost one global atomic per class and step
   constexpr int kWords = 8;
@@ -591,6 +591,10 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
   __shared__ uint32_t cnt[kNumClasses];
   __shared__ uint32_t base[kNumClasses];
   if (st->stop) return;
+  // vertices scanned: all in the first iteration, then n_later (the
+  // vertices of degree 0, last in the internal order, are flagged only by
+  // the initialisation)
+  const int64_t n = st->iter == 0 ? n_all : n_later;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -670,12 +674,13 @@ __global__ __launch_bounds__(kBT) void k_frontier(int64_t n, uint8_t* F, const u
   }
 }
 
-hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
+hipError_t launch_frontier(int64_t n, int64_t n_later, uint8_t* F, const uint8_t* cls,
                            int32_t* const* lists, uint8_t* chg_clear, DevStats* st, int grid,
                            hipStream_t s) {
   ListPtrs lp;
   for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
-  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kBT), 0, s, n, F, cls, lp, chg_clear, st);
+  hipLaunchKernelGGL(k_frontier, dim3(grid), dim3(kBT), 0, s, n, n_later, F, cls, lp, chg_clear,
+                     st);
   return hipGetLastError();
 }
 
@@ -706,8 +711,9 @@ constexpr int kLearnWaves = 4;
 constexpr int kLearnChunks = 4;  // 64-vertex chunks per wave and block step
 
 __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
-    int64_t n, uint8_t* F, const uint8_t* cls, ListPtrs lists, uint8_t* chg_clear,
-    DevStats* st, unsigned long long* rec, const MlpTiles* tiles, TraceArgs tr) {
+    int64_t n_all, int64_t n_later, uint8_t* F, const uint8_t* cls, ListPtrs lists,
+    uint8_t* chg_clear, DevStats* st, unsigned long long* rec, const MlpTiles* tiles,
+    TraceArgs tr) {
   __shared__ uint8_t lst_all[kLearnWaves][64];
   __shared__ uint8_t dec_all[kLearnWaves][64];
   __shared__ unsigned long long slot_all[kLearnWaves][16];
@@ -717,6 +723,7 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   // registers they would leave room for two waves per SIMD
   __shared__ MlpTiles wl;
   if (st->stop) return;
+  const int64_t n = st->iter == 0 ? n_all : n_later;  // as in k_frontier
   const int tid = threadIdx.x;
   const int wv = tid >> 6;
   const int lane = tid & 63;
@@ -869,14 +876,14 @@ __global__ __launch_bounds__(kLearnWaves * 64) void k_frontier_learned(
   }
 }
 
-hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
+hipError_t launch_frontier_learned(int64_t n, int64_t n_later, uint8_t* F, const uint8_t* cls,
                                    int32_t* const* lists, uint8_t* chg_clear, DevStats* st,
                                    unsigned long long* rec, const MlpTiles* tiles,
                                    const TraceArgs& tr, int grid, hipStream_t s) {
   ListPtrs lp;
   for (int q = 0; q < kNumClasses; ++q) lp.p[q] = lists[q];
-  hipLaunchKernelGGL(k_frontier_learned, dim3(grid), dim3(kLearnWaves * 64), 0, s, n, F, cls,
-                     lp, chg_clear, st, rec, tiles, tr);
+  hipLaunchKernelGGL(k_frontier_learned, dim3(grid), dim3(kLearnWaves * 64), 0, s, n, n_later,
+                     F, cls, lp, chg_clear, st, rec, tiles, tr);
   return hipGetLastError();
 }
 

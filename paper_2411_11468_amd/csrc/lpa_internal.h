@@ -304,11 +304,12 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
                            hipStream_t s);
 hipError_t launch_hub_plan(bool off64, const HubArgs& a, int32_t* C, uint8_t* F,
                            hipStream_t s);
-hipError_t launch_frontier(int64_t n, uint8_t* F, const uint8_t* cls,
+// n: vertices scanned in iteration 0; n_later: in the iterations after it
+hipError_t launch_frontier(int64_t n, int64_t n_later, uint8_t* F, const uint8_t* cls,
                            int32_t* const* lists_dev, uint8_t* chg_clear, DevStats* st,
                            int grid, hipStream_t s);
 struct MlpTiles;
-hipError_t launch_frontier_learned(int64_t n, uint8_t* F, const uint8_t* cls,
+hipError_t launch_frontier_learned(int64_t n, int64_t n_later, uint8_t* F, const uint8_t* cls,
                                    int32_t* const* lists, uint8_t* chg_clear, DevStats* st,
                                    unsigned long long* rec, const MlpTiles* tiles,
                                    const TraceArgs& tr, int grid, hipStream_t s);
