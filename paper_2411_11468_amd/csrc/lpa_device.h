@@ -175,6 +175,48 @@ __device__ __forceinline__ void lds_accumulate(uint32_t* keys, float* vals, uint
   }
 }
 
+// lds_accumulate that also reports the slot this lane claimed for a new key
+// (-1 when the key was there already), so that the caller can list the
+// occupied slots instead of scanning the whole table afterwards.
+__device__ __forceinline__ int32_t lds_accumulate_claim(uint32_t* keys, float* vals, uint32_t p1,
+                                                        uint32_t k, float v, ProbeCfg pc) {
+  const uint32_t p2 = 2u * p1 + 1u;
+  uint32_t s = k % p1;
+  uint32_t step = 1u % p1;
+  const uint32_t r = (k % p2) % p1;
+  for (int t = 0;; ++t) {
+    uint32_t cur = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    bool mine = false;
+    if (cur == kEmpty) {
+      uint32_t expected = kEmpty;
+      __hip_atomic_compare_exchange_strong(&keys[s], &expected, k, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      mine = expected == kEmpty;
+      cur = mine ? k : expected;
+    }
+    if (cur == k) {
+      __hip_atomic_fetch_add(&vals[s], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return mine ? (int32_t)s : -1;
+    }
+    probe_next(s, step, r, p1, t, pc);
+  }
+}
+
+// Append the slots the lanes of one wave claimed (claimed >= 0) to a list
+// of occupied slots: one LDS atomic per wave on the list's length.
+__device__ __forceinline__ void list_claimed(int32_t claimed, uint16_t* lst, uint32_t* lst_n) {
+  const unsigned long long m = __ballot(claimed >= 0);
+  if (m == 0ull) return;
+  const int lane = threadIdx.x & 63;
+  const int first = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == first)
+    base = __hip_atomic_fetch_add(lst_n, (uint32_t)__popcll(m), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+  base = (uint32_t)__shfl((int)base, first);
+  if (claimed >= 0) lst[base + lane_rank(m)] = (uint16_t)claimed;
+}
+
 // Accumulate (k, v) into a global-memory table; returns the slot and the
 // value the slot holds after this add (values only grow, so the largest value
 // ever returned for a key is its final sum).  SCOPE is the atomics' memory

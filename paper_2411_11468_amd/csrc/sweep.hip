@@ -672,12 +672,18 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
   __shared__ uint32_t keys[SLOTS];
   __shared__ float vals[SLOTS];
   __shared__ unsigned long long red[NW];
+  // the slots occupied by the current row, listed as they are claimed: the
+  // table read-back visits these instead of all p1 slots (a row of d
+  // entries holds at most d labels, and SLOTS >= 2 d - 1)
+  __shared__ uint16_t lst[(SLOTS + 1) / 2];
+  __shared__ uint32_t lst_n;
   if (a.st->stop) return;
   const int pl = a.st->pl;  // fixed for the whole sweep
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  if (tid == 0) lst_n = 0u;
   __syncthreads();
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
@@ -711,8 +717,11 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     #pragma unroll
     for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
+    for (int u = 0; u < U; ++u) {
+      const int32_t cl =
+          lab[u] != kEmpty ? lds_accumulate_claim(keys, vals, p1, lab[u], wt[u], a.probe) : -1;
+      list_claimed(cl, lst, &lst_n);
+    }
     for (int64_t base = (int64_t)BT * U; base < d; base += (int64_t)BT * U) {
       int32_t jj[U];
       float ww[U];
@@ -729,8 +738,11 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
       #pragma unroll
       for (int u = 0; u < U; ++u) merge_lead(lab[u], ww[u], a.w == nullptr);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
+      for (int u = 0; u < U; ++u) {
+        const int32_t cl =
+            lab[u] != kEmpty ? lds_accumulate_claim(keys, vals, p1, lab[u], ww[u], a.probe) : -1;
+        list_claimed(cl, lst, &lst_n);
+      }
     }
     const uint32_t nitem = item + gridDim.x;
     int32_t nv = 0, nj[U];
@@ -739,13 +751,12 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     if (nitem < count) head(nitem, nv, no, nd, nj, nw);
     __syncthreads();
     unsigned long long best = 0;
-    for (uint32_t s = tid; s < p1; s += BT) {
-      const uint32_t kk = keys[s];
-      if (kk != kEmpty) {
-        best = umax64(best, pack_key(vals[s], kk));
-        keys[s] = kEmpty;
-        vals[s] = 0.0f;
-      }
+    const uint32_t nl = lst_n;
+    for (uint32_t i = tid; i < nl; i += BT) {
+      const uint32_t s = lst[i];
+      best = umax64(best, pack_key(vals[s], keys[s]));
+      keys[s] = kEmpty;
+      vals[s] = 0.0f;
     }
     best = wave_max_u64(best);
     if (lane == 0) red[tid >> 6] = best;
@@ -765,8 +776,9 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
       my_edges += (unsigned long long)d;
       my_changed += moved ? 1u : 0u;
       my_flagw += moved ? (unsigned long long)d : 0ull;
+      lst_n = 0u;  // every thread read it before the last barrier
     }
-    __syncthreads();  // red[] is rewritten by the next vertex
+    __syncthreads();  // red[] and the slot list are rewritten by the next vertex
     item = nitem;
     v = nv; o = no; d = nd;
 #pragma unroll
