@@ -203,8 +203,11 @@ __device__ __forceinline__ int32_t lds_accumulate_claim(uint32_t* keys, float* v
 }
 
 // Append the slots the lanes of one wave claimed (claimed >= 0) to a list
-// of occupied slots: one LDS atomic per wave on the list's length.
-__device__ __forceinline__ void list_claimed(int32_t claimed, uint16_t* lst, uint32_t* lst_n) {
+// of occupied slots: one LDS atomic per wave on the list's length.  Entries
+// past cap are not stored (the length still counts them: a caller whose
+// list overflowed reads back the whole table).
+__device__ __forceinline__ void list_claimed(int32_t claimed, uint16_t* lst, uint32_t* lst_n,
+                                             uint32_t cap = 0xFFFFFFFFu) {
   const unsigned long long m = __ballot(claimed >= 0);
   if (m == 0ull) return;
   const int lane = threadIdx.x & 63;
@@ -214,7 +217,8 @@ __device__ __forceinline__ void list_claimed(int32_t claimed, uint16_t* lst, uin
     base = __hip_atomic_fetch_add(lst_n, (uint32_t)__popcll(m), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_WORKGROUP);
   base = (uint32_t)__shfl((int)base, first);
-  if (claimed >= 0) lst[base + lane_rank(m)] = (uint16_t)claimed;
+  const uint32_t pos = base + lane_rank(m);
+  if (claimed >= 0 && pos < cap) lst[pos] = (uint16_t)claimed;
 }
 
 // Accumulate (k, v) into a global-memory table; returns the slot and the

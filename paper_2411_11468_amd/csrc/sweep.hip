@@ -315,6 +315,10 @@ template <typename OffT, int SLOTS, int WAVES, int U, bool FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   __shared__ uint32_t keys_all[WAVES][SLOTS];
   __shared__ float vals_all[WAVES][SLOTS];
+  // per wave: the slots its current row claimed, read back instead of all
+  // p1 slots (a row holds at most (SLOTS + 1) / 2 labels); the count is
+  // wave-uniform and lives in a register
+  __shared__ uint16_t lst_all[WAVES][(SLOTS + 1) / 2];
   if (a.st->stop) return;
   const int pl = a.st->pl;  // fixed for the whole sweep
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
@@ -323,6 +327,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   const int l = a.st->iter;
   uint32_t* keys = keys_all[wv];
   float* vals = vals_all[wv];
+  uint16_t* lst = lst_all[wv];
+  uint32_t nl = 0;
+  auto claim = [&](int32_t cl) {
+    const unsigned long long m = __ballot(cl >= 0);
+    if (cl >= 0) lst[nl + lane_rank(m)] = (uint16_t)cl;
+    nl += (uint32_t)__popcll(m);
+  };
   for (int s = lane; s < SLOTS; s += 64) { keys[s] = kEmpty; vals[s] = 0.0f; }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   const uint32_t count = a.st->active[a.cls];
@@ -358,11 +369,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
     #pragma unroll
     for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
+      int32_t cl = -1;
       if (lab[u] != kEmpty) {
-        lds_accumulate(keys, vals, p1, lab[u], wt[u], a.probe);
+        cl = lds_accumulate_claim(keys, vals, p1, lab[u], wt[u], a.probe);
         if constexpr (FEAT) rp.K += wt[u];
       }
+      claim(cl);
+    }
     for (int64_t base = 64 * U; base < d; base += 64 * U) {
       int32_t jj[U];
       float ww[U];
@@ -379,11 +393,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
       #pragma unroll
       for (int u = 0; u < U; ++u) merge_lead(lab[u], ww[u], a.w == nullptr);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < U; ++u) {
+        int32_t cl = -1;
         if (lab[u] != kEmpty) {
-          lds_accumulate(keys, vals, p1, lab[u], ww[u], a.probe);
+          cl = lds_accumulate_claim(keys, vals, p1, lab[u], ww[u], a.probe);
           if constexpr (FEAT) rp.K += ww[u];
         }
+        claim(cl);
+      }
     }
     // next vertex's head, in flight during the scan below
     const uint32_t nitem = item + stride;
@@ -393,16 +410,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
     if (nitem < count) head(nitem, nv, no, nd, nj, nw);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     unsigned long long best = 0;
-    for (uint32_t s = lane; s < p1; s += 64) {
+    for (uint32_t i = lane; i < nl; i += 64) {
+      const uint32_t s = lst[i];
       const uint32_t kk = keys[s];
-      if (kk != kEmpty) {
-        const unsigned long long pk = pack_key(vals[s], kk);
-        if constexpr (FEAT) rp.slot(pk, kk, vals[s], cur);
-        best = umax64(best, pk);
-        keys[s] = kEmpty;
-        vals[s] = 0.0f;
-      }
+      const unsigned long long pk = pack_key(vals[s], kk);
+      if constexpr (FEAT) rp.slot(pk, kk, vals[s], cur);
+      best = umax64(best, pk);
+      keys[s] = kEmpty;
+      vals[s] = 0.0f;
     }
+    nl = 0;
     best = wave_max_u64(best);
     uint32_t cstar = 0;
     const bool moved = decide(best, cur, pl, &cstar);
@@ -886,10 +903,18 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   __shared__ float vals[SLOTS];
   __shared__ uint32_t hist[kMaxB];
   __shared__ uint32_t wsum[BT / 64];
+  // the slots the current slice claimed: the histogram and partition passes
+  // visit these instead of all p1c slots.  The list holds a little less
+  // than a full slice's labels (the LDS budget): a slice with more distinct
+  // labels than kLst reads back its whole table instead.
+  constexpr uint32_t kLst = (SLOTS + 1) / 2 - 256;
+  __shared__ uint16_t lst[kLst];
+  __shared__ uint32_t lst_n;
   if (a.st->stop) return;
   const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
   const int tid = threadIdx.x;
   for (int s = tid; s < SLOTS; s += BT) { keys[s] = kEmpty; vals[s] = 0.0f; }
+  if (tid == 0) lst_n = 0u;
   __syncthreads();
   const uint32_t nitems = a.st->hub_items;
   // with every hub flagged, the slices grouped by target window: group x
@@ -987,8 +1012,11 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
       #pragma unroll
       for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (lab[u] != kEmpty) lds_accumulate(keys, vals, p1c, lab[u], wt[u], a.probe);
+      for (int u = 0; u < U; ++u) {
+        const int32_t cl =
+            lab[u] != kEmpty ? lds_accumulate_claim(keys, vals, p1c, lab[u], wt[u], a.probe) : -1;
+        list_claimed(cl, lst, &lst_n, kLst);
+      }
     }
     Head nxt{};
     if (nit != kNone) head(nit, nxt);
@@ -997,8 +1025,11 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
     // previous one while thread 0 writes this one)
     if (tid == 0) s_next[par] = nit != kNone ? fetch() : kNone;
     __syncthreads();
-    for (uint32_t s = tid; s < p1c; s += BT) {
-      const uint32_t kk = keys[s];
+    const uint32_t nl = lst_n;
+    const bool listed = nl <= kLst;  // else: the whole table, as p1c slots
+    const uint32_t nv = listed ? nl : p1c;
+    for (uint32_t i = tid; i < nv; i += BT) {
+      const uint32_t kk = keys[listed ? lst[i] : i];
       if (kk != kEmpty) atomicAdd(&hist[bucket_of(kk, lgb)], 1u);
     }
     __syncthreads();
@@ -1014,17 +1045,20 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
       my_pairs += total;
     }
     const int64_t base = (slice0 + c) * (int64_t)a.chunk;
-    for (uint32_t s = tid; s < p1c; s += BT) {
+    for (uint32_t i = tid; i < nv; i += BT) {
+      const uint32_t s = listed ? lst[i] : i;
       const uint32_t kk = keys[s];
-      if (kk != kEmpty) {
-        const uint32_t pos = atomicAdd(&hist[bucket_of(kk, lgb)], 1u);
-        a.part_keys[base + pos] = kk;
-        a.part_vals[base + pos] = vals[s];
-        keys[s] = kEmpty;
-        vals[s] = 0.0f;
-      }
+      if (kk == kEmpty) continue;
+      const uint32_t pos = atomicAdd(&hist[bucket_of(kk, lgb)], 1u);
+      a.part_keys[base + pos] = kk;
+      a.part_vals[base + pos] = vals[s];
+      keys[s] = kEmpty;
+      vals[s] = 0.0f;
     }
-    if (tid == 0) my_edges += (unsigned long long)n;
+    if (tid == 0) {
+      my_edges += (unsigned long long)n;
+      lst_n = 0u;  // read by every thread before the barriers above
+    }
     __syncthreads();
     const uint32_t nn = s_next[par];
     par ^= 1;

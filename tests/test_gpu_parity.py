@@ -127,6 +127,20 @@ def test_det_hub_merge_paths(xcd_local):
     assert_det_parity(graphgen.rmat_graph(16, 16, "int8"), tuning=t2)
 
 
+def test_det_hub_slice_with_more_labels_than_its_slot_list():
+    # a hub of 20,000 leaves whose initial labels are all distinct: its first
+    # 8,192-entry slice holds 8,192 labels, more than the slice kernel's list
+    # of claimed slots keeps, so that slice reads back its whole table; the
+    # leaves are paired up so that they keep moving after the first sweep
+    rng = np.random.default_rng(11)
+    n = 20001
+    edges = [(0, i) for i in range(1, n)] + [(i, i + 1) for i in range(1, n - 1, 2)]
+    g = graphgen.from_edges(n, edges)
+    init = rng.permutation(n).astype(np.int32)
+    assert_det_parity(g, initial=init)
+    assert_det_parity(g, tuning=_tuning(xcd_local=0), initial=init)
+
+
 @pytest.mark.parametrize("cap", [1, 7, 63])
 def test_det_hub_spill_path(cap):
     # bucket tables capped far below the labels of a bucket: most labels
