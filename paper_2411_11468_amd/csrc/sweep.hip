@@ -1438,6 +1438,109 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
+// Plain first sweep of the rows of 5-64 entries, two wave steps at a time:
+// the list entries, row offsets and first targets of both steps are loaded
+// before either step is reduced.  A step is a chain of three
+// dependent loads (list, offsets, targets), which the one-step loop of
+// k_sweep_direct waits for in turn.  Labels are the caller's ids, read from
+// the internal rows that hold them (ctgt) or from the caller's rows.
+template <typename OffT, int G, int BT>
+__global__ __launch_bounds__(BT) void k_sweep_direct2(SweepArgs a) {
+  static_assert(G == 4 || G == 8, "the classes that gain from it");
+  constexpr int kPer = 64 / G;  // vertices per wave step
+  constexpr int UD = 4;         // entries per lane loaded with the step's head
+  constexpr int R = 2;          // steps in flight
+  if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int k = lane & (G - 1);
+  const uint32_t count = a.st->active[a.cls];
+  const uint64_t unit0 = (uint64_t)blockIdx.x * (BT / 64) + (tid >> 6);
+  const uint64_t nunits = (uint64_t)gridDim.x * (BT / 64);
+  const bool cint = a.ctgt != nullptr;
+  const void* roff = cint ? a.off : a.uoff;
+  const int32_t* rt = cint ? a.ctgt : a.utgt;
+  const float* rw = cint ? a.w : a.uw;
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  for (uint64_t base = unit0 * kPer; base < count; base += (uint64_t)R * nunits * kPer) {
+    bool valid[R];
+    int32_t vi[R], v[R];
+    int64_t o[R], d[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t idx = base + (uint64_t)r * nunits * kPer + (uint32_t)lane / G;
+      valid[r] = idx < count;
+      vi[r] = valid[r] ? a.active[idx] : 0;  // internal id
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a.inv ? a.inv[vi[r]] : vi[r];  // caller id = label
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      o[r] = 0;
+      d[r] = 0;
+      if (valid[r]) row_of<OffT>(roff, cint ? vi[r] : v[r], &o[r], &d[r]);
+    }
+    int32_t jr[R][UD];
+    float wj[R][UD];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < UD; ++u) {
+        const int64_t e = (int64_t)u * G + k;
+        const bool has = e < d[r];
+        jr[r][u] = has ? __builtin_nontemporal_load(&rt[o[r] + e]) : v[r];
+        wj[r][u] = has ? edge_weight(rw, o[r] + e) : 0.0f;
+      }
+    unsigned long long best[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      best[r] = 0;
+#pragma unroll
+      for (int u = 0; u < UD; ++u)
+        if (jr[r][u] != v[r]) best[r] = umax64(best[r], pack_key(wj[r][u], (uint32_t)jr[r][u]));
+      // the rest of a row longer than UD * G entries
+      int64_t e = (int64_t)UD * G + k;
+      for (; e + (UD - 1) * G < d[r]; e += UD * G) {
+        int32_t j2[UD];
+        float w2[UD];
+#pragma unroll
+        for (int u = 0; u < UD; ++u) {
+          j2[u] = __builtin_nontemporal_load(&rt[o[r] + e + u * G]);
+          w2[u] = edge_weight(rw, o[r] + e + u * G);
+        }
+#pragma unroll
+        for (int u = 0; u < UD; ++u)
+          if (j2[u] != v[r]) best[r] = umax64(best[r], pack_key(w2[u], (uint32_t)j2[u]));
+      }
+      for (; e < d[r]; e += G) {
+        const int32_t j = __builtin_nontemporal_load(&rt[o[r] + e]);
+        if (j != v[r]) best[r] = umax64(best[r], pack_key(edge_weight(rw, o[r] + e), (uint32_t)j));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      unsigned long long b = quad_max_u64(best[r]);
+      if constexpr (G == 8) b = umax64(b, dpp64<0x141>(b));  // row_half_mirror: the other quad
+      // the vertex's own label is its caller id in this sweep
+      uint32_t cstar = 0;
+      const bool moved = valid[r] && decide(b, v[r], pl, &cstar);
+      if (valid[r] && k == 0) {
+        if (a.async_mode) {
+          if (moved) a.C[vi[r]] = (int32_t)cstar;
+        } else {
+          a.Cn[vi[r]] = moved ? (int32_t)cstar : v[r];
+        }
+        if (moved) a.chg[vi[r]] = 1;
+        my_edges += (unsigned long long)d[r];
+        my_changed += moved ? 1u : 0u;
+        my_flagw += moved ? (unsigned long long)d[r] : 0ull;
+      }
+    }
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
 template <typename OffT, int BT>
 __global__ __launch_bounds__(BT) void k_hub_direct(HubArgs a) {
   if (a.st->stop) return;
@@ -1595,6 +1698,16 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
 
 template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
+  // two steps in flight: 5-16-entry rows 0.43 -> 0.24 ms, 17-64-entry rows
+  // 0.57 -> 0.45 ms on R-MAT 26; the rows of up to 4 entries measured the
+  // same and those of 65-512 entries slower (0.48 -> 0.58 ms)
+  if constexpr (!FEAT) {
+    switch (cls) {
+      case 2: hipLaunchKernelGGL((k_sweep_direct2<OffT, 4, 256>), dim3(grid), dim3(256), 0, s, a); return hipGetLastError();
+      case 3: hipLaunchKernelGGL((k_sweep_direct2<OffT, 8, 256>), dim3(grid), dim3(256), 0, s, a); return hipGetLastError();
+      default: break;
+    }
+  }
   switch (cls) {
     case 1: hipLaunchKernelGGL((k_sweep_direct<OffT, 1, 256, FEAT, true>), dim3(grid), dim3(256), 0, s, a); break;
     case 2:

@@ -50,12 +50,12 @@ _NAME_RULES = [
     # 64 for 513..2048; 256 above), so lpa_profile's direct_wave1023 is
     # "direct_g16", its block2047 + block4095 "direct_g64" and its
     # block8191 + block16383 "direct_g256"
-    (r"k_sweep_direct<[^,]+, 1,", "direct_small4"),
-    (r"k_sweep_direct<[^,]+, 4,", "direct_small16"),
-    (r"k_sweep_direct<[^,]+, 8,", "direct_wave127"),
-    (r"k_sweep_direct<[^,]+, 16,", "direct_g16"),
-    (r"k_sweep_direct<[^,]+, 64,", "direct_g64"),
-    (r"k_sweep_direct<[^,]+, 256,", "direct_g256"),
+    (r"k_sweep_direct2?<[^,]+, 1,", "direct_small4"),
+    (r"k_sweep_direct2?<[^,]+, 4,", "direct_small16"),
+    (r"k_sweep_direct2?<[^,]+, 8,", "direct_wave127"),
+    (r"k_sweep_direct2?<[^,]+, 16,", "direct_g16"),
+    (r"k_sweep_direct2?<[^,]+, 64,", "direct_g64"),
+    (r"k_sweep_direct2?<[^,]+, 256,", "direct_g256"),
     (r"k_sweep_lane4<", "sweep_small4"),
     # the table-value ablation kernels (sweep_tv.hip)
     (r"k_tv_wave<|k_tv_block<", "tv_sweep"),

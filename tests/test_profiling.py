@@ -17,6 +17,7 @@ def test_short_names():
         "void lpa::k_sweep_direct<long, 16, 256, false, false>(lpa::SweepArgs)": "direct_g16",
         "void lpa::k_sweep_direct<long, 4, 256, true, false>(lpa::SweepArgs)": "direct_small16",
         "void lpa::k_sweep_direct<int, 8, 256, false, false>(lpa::SweepArgs)": "direct_wave127",
+        "void lpa::k_sweep_direct2<long, 8, 256>(lpa::SweepArgs)": "direct_wave127",
         "void lpa::k_sweep_direct<long, 256, 256, false, false>(lpa::SweepArgs)": "direct_g256",
         "void lpa::(anonymous namespace)::k_tv_wave<long, double, 1023>(lpa::SweepArgs)":
             "tv_sweep",
