@@ -217,6 +217,85 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
+// Plain k_sweep_small<16> with two wave steps in flight: the list entries,
+// offsets, targets and neighbour labels of both steps are loaded before
+// either is reduced (a step is a chain of four dependent loads).
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_sweep_small16x2(SweepArgs a) {
+  constexpr int G = 16, R = 2;
+  constexpr uint32_t kVpw = 64 / G;
+  if (a.st->stop) return;
+  const int pl = a.st->pl;  // fixed for the whole sweep
+  const bool id0 = a.st->iter == 0 && a.st->ident;  // labels are still the ids
+  const int lane = threadIdx.x & 63;
+  const int k = lane & (G - 1);
+  const uint32_t count = a.st->active[a.cls];
+  const uint32_t wave_id = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  unsigned long long my_edges = 0, my_flagw = 0;
+  uint32_t my_changed = 0;
+  for (uint64_t base = (uint64_t)wave_id * kVpw; base < count;
+       base += (uint64_t)R * nwaves * kVpw) {
+    bool valid[R];
+    int32_t v[R], j[R];
+    int64_t o[R], d[R];
+    float wt[R];
+    uint32_t lab[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t idx = base + (uint64_t)r * nwaves * kVpw + (uint32_t)lane / G;
+      valid[r] = idx < count;
+      v[r] = valid[r] ? a.active[idx] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      o[r] = 0;
+      d[r] = 0;
+      if (valid[r]) row_of<OffT>(a.off, v[r], &o[r], &d[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool has = valid[r] && k < d[r];
+      j[r] = has ? __builtin_nontemporal_load(&a.tgt[o[r] + k]) : -1;
+      wt[r] = has ? edge_weight(a.w, o[r] + k) : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      lab[r] = kEmpty;
+      if (j[r] >= 0 && j[r] != v[r]) lab[r] = id0 ? (uint32_t)j[r] : (uint32_t)a.C[j[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float sum = wt[r], mult = 1.0f;
+      rot16_accum<1, false>(lab[r], wt[r], sum, mult);  rot16_accum<2, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<3, false>(lab[r], wt[r], sum, mult);  rot16_accum<4, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<5, false>(lab[r], wt[r], sum, mult);  rot16_accum<6, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<7, false>(lab[r], wt[r], sum, mult);  rot16_accum<8, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<9, false>(lab[r], wt[r], sum, mult);  rot16_accum<10, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<11, false>(lab[r], wt[r], sum, mult); rot16_accum<12, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<13, false>(lab[r], wt[r], sum, mult); rot16_accum<14, false>(lab[r], wt[r], sum, mult);
+      rot16_accum<15, false>(lab[r], wt[r], sum, mult);
+      const unsigned long long packed = (lab[r] != kEmpty) ? pack_key(sum, lab[r]) : 0ull;
+      const unsigned long long best = row16_max_u64(packed);
+      uint32_t cstar = 0;
+      const int32_t cur = valid[r] ? a.C[v[r]] : 0;
+      const bool moved = valid[r] && decide(best, cur, pl, &cstar);
+      if (valid[r] && k == 0) {
+        if (a.async_mode) {
+          if (moved) a.C[v[r]] = (int32_t)cstar;
+        } else {
+          a.Cn[v[r]] = moved ? (int32_t)cstar : cur;
+        }
+        if (moved) a.chg[v[r]] = 1;
+        my_edges += (unsigned long long)d[r];
+        my_changed += moved ? 1u : 0u;
+        my_flagw += moved ? (unsigned long long)d[r] : 0ull;
+      }
+    }
+  }
+  flush_stats(my_edges, my_changed, my_flagw, a.st, a.cls);
+}
+
 // ---- rows of at most 4 entries: one lane per vertex -------------------------
 // Plain variant for the smallest class: each lane loads its rows' (up to 4)
 // targets, weights and labels at once and sums equal labels among them in
@@ -1668,7 +1747,10 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
       if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_small<OffT, 4, true>), dim3(grid), dim3(256), 0, s, a);
       else hipLaunchKernelGGL((k_sweep_lane4<OffT>), dim3(grid), dim3(256), 0, s, a);
       break;
-    case 2: hipLaunchKernelGGL((k_sweep_small<OffT, 16, FEAT>), dim3(grid), dim3(256), 0, s, a); break;
+    case 2:
+      if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_small<OffT, 16, true>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_small16x2<OffT>), dim3(grid), dim3(256), 0, s, a);
+      break;
     case 3:
       hipLaunchKernelGGL((k_sweep_group<OffT, 127, 16, FEAT>), dim3(grid), dim3(256), 0, s, a);
       break;
