@@ -1763,7 +1763,7 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
       break;
     case 6:
       if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 4095, 256, 4, true>), dim3(grid), dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 4095, 256, 4>), dim3(grid), dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep_block_pipe<OffT, 4095, 256, 8>), dim3(grid), dim3(256), 0, s, a);
       break;
     case 7:
       if constexpr (FEAT) hipLaunchKernelGGL((k_sweep_block<OffT, 8191, kBlockMid, 4, true>), dim3(grid), dim3(kBlockMid), 0, s, a);
