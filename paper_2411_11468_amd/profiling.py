@@ -37,10 +37,9 @@ CSRC = os.path.join(HERE, "csrc")
 _NAME_RULES = [
     (r"k_sweep_small<[^,]+, 4[,>]", "sweep_small4"),
     (r"k_sweep_small<[^,]+, 16[,>]", "sweep_small16"),
-    (r"k_sweep_wave<[^,]+, 127,", "sweep_wave127"),
+    (r"k_sweep_small16x2<", "sweep_small16"),
     (r"k_sweep_group<[^,]+, 127,", "sweep_wave127"),
     (r"k_sweep_wave_pipe<[^,]+, 1023,", "sweep_wave1023"),
-    (r"k_sweep_wave<[^,]+, 1023,", "sweep_wave1023"),
     (r"k_sweep_block(_pipe)?<[^,]+, 2047,", "sweep_block2047"),
     (r"k_sweep_block(_pipe)?<[^,]+, 4095,", "sweep_block4095"),
     (r"k_sweep_block(_pipe)?<[^,]+, 8191,", "sweep_block8191"),

@@ -13,6 +13,8 @@ def test_short_names():
         "void lpa::k_sweep_group<long, 127, 16, false>(lpa::SweepArgs)": "sweep_wave127",
         "void lpa::k_sweep_wave_pipe<long, 1023, 4, 4>(lpa::SweepArgs)": "sweep_wave1023",
         "void lpa::k_sweep_lane4<long>(lpa::SweepArgs)": "sweep_small4",
+        "void lpa::k_sweep_small16x2<long>(lpa::SweepArgs)": "sweep_small16",
+        "void lpa::k_sweep_small<long, 16, true>(lpa::SweepArgs)": "sweep_small16",
         "void lpa::k_sweep_direct<long, 1, 256, false, true>(lpa::SweepArgs)": "direct_small4",
         "void lpa::k_sweep_direct<long, 16, 256, false, false>(lpa::SweepArgs)": "direct_g16",
         "void lpa::k_sweep_direct<long, 4, 256, true, false>(lpa::SweepArgs)": "direct_small16",
