@@ -380,6 +380,34 @@ __device__ __forceinline__ void row_of(const void* off, int32_t v, int64_t* o, i
   *d = b - a;
 }
 
+// A wave-uniform index pinned to a VGPR.  The result of a load from a
+// uniform address is moved into SGPRs, which waits for the load there and
+// then; a load through this index stays a vector load whose result stays in
+// VGPRs until it is read, so that it can be issued a whole row ahead.
+__device__ __forceinline__ uint32_t vgpr_u32(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// The first lane's value of x (wave-uniform values held in VGPRs).
+__device__ __forceinline__ int32_t first_lane_i32(int32_t x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+__device__ __forceinline__ int64_t first_lane_i64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A row's start and end offsets, left unsubtracted so that nothing waits for
+// the loads until the row is processed.
+template <typename OffT>
+__device__ __forceinline__ void row_bounds(const void* off, int32_t v, int64_t* o, int64_t* e) {
+  const OffT* p = reinterpret_cast<const OffT*>(off);
+  *o = (int64_t)p[v];
+  *e = (int64_t)p[v + 1];
+}
+
 // Targets and weights are read once per sweep: streaming (non-temporal)
 // loads keep them from displacing the gathered labels in the caches.
 __device__ __forceinline__ float edge_weight(const float* w, int64_t e) {

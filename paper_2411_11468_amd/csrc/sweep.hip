@@ -419,13 +419,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   const uint32_t stride = gridDim.x * WAVES;
   unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0, my_fneg = 0;
-  int32_t v = 0, j[U];
-  int64_t o = 0, d = 0;
+  int32_t vq = 0, j[U];  // the current row's vertex and offsets, in VGPRs
+  int64_t oq = 0, eq = 0;
   float wt[U];
-  auto head = [&](uint32_t it, int32_t& hv, int64_t& ho, int64_t& hd, int32_t* hj,
-                  float* hw) {
-    hv = a.active[it];
-    row_of<OffT>(a.off, hv, &ho, &hd);
+  // a row's first 64*U targets and weights, its offsets known
+  auto head = [&](int32_t hv, int64_t ho, int64_t hd, int32_t* hj, float* hw) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = u * 64 + lane;
@@ -435,9 +433,28 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
     }
   };
   uint32_t item = blockIdx.x * WAVES + wv;
-  if (item < count) head(item, v, o, d, j, wt);
+  if (item < count) {
+    vq = a.active[vgpr_u32(item)];
+    row_bounds<OffT>(a.off, vq, &oq, &eq);
+    head(vq, oq, eq - oq, j, wt);
+  }
+  // the next row's list entry and offsets (v1, o1, e1): loaded one row
+  // earlier than its targets, so that neither dependent load waits in line
+  // before the table scan
+  int32_t v1 = 0;
+  int64_t o1 = 0, e1 = 0;
+  if (item + stride < count) {
+    v1 = a.active[vgpr_u32(item + stride)];
+    row_bounds<OffT>(a.off, v1, &o1, &e1);
+  }
   while (item < count) {
-    const int32_t cur = a.C[v];
+    const int32_t v = first_lane_i32(vq);
+    const int64_t o = first_lane_i64(oq), d = first_lane_i64(eq) - o;
+    const uint32_t nitem = item + stride;
+    const uint32_t n2item = nitem + stride;
+    const int32_t v2 = n2item < count ? a.active[vgpr_u32(n2item)] : 0;
+    // own label, a vector load: used only by the decision at the row's end
+    const int32_t cur = a.C[vgpr_u32((uint32_t)v)];
     [[maybe_unused]] const unsigned long long rold = (FEAT && lane == 0) ? a.rec[v] : 0ull;
     const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     RecPartial rp;
@@ -481,12 +498,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
         claim(cl);
       }
     }
-    // next vertex's head, in flight during the scan below
-    const uint32_t nitem = item + stride;
-    int32_t nv = 0, nj[U];
-    int64_t no = 0, nd = 0;
+    // next vertex's head and the offsets of the one after, in flight during
+    // the scan below
+    int32_t nj[U];
     float nw[U];
-    if (nitem < count) head(nitem, nv, no, nd, nj, nw);
+    if (nitem < count) head(v1, o1, e1 - o1, nj, nw);
+    int64_t o2 = 0, e2 = 0;
+    if (n2item < count) row_bounds<OffT>(a.off, v2, &o2, &e2);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     unsigned long long best = 0;
     for (uint32_t i = lane; i < nl; i += 64) {
@@ -525,7 +543,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     item = nitem;
-    v = nv; o = no; d = nd;
+    vq = v1; oq = o1; eq = e1;
+    v1 = v2; o1 = o2; e1 = e2;
 #pragma unroll
     for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
   }
@@ -784,13 +803,11 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0;
-  int32_t v = 0, j[U];
-  int64_t o = 0, d = 0;
+  int32_t vq = 0, j[U];  // the current row's vertex and offsets, in VGPRs
+  int64_t oq = 0, eq = 0;
   float wt[U];
-  auto head = [&](uint32_t it, int32_t& hv, int64_t& ho, int64_t& hd, int32_t* hj,
-                  float* hw) {
-    hv = a.active[it];
-    row_of<OffT>(a.off, hv, &ho, &hd);
+  // a row's first BT*U targets and weights, its offsets known
+  auto head = [&](int32_t hv, int64_t ho, int64_t hd, int32_t* hj, float* hw) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t e = (int64_t)u * BT + tid;
@@ -800,11 +817,29 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     }
   };
   uint32_t item = blockIdx.x;
-  if (item < count) head(item, v, o, d, j, wt);
+  if (item < count) {
+    vq = a.active[vgpr_u32(item)];
+    row_bounds<OffT>(a.off, vq, &oq, &eq);
+    head(vq, oq, eq - oq, j, wt);
+  }
+  // the next row's list entry and offsets (v1, o1, e1), loaded one row
+  // earlier than its targets (as in k_sweep_wave_pipe)
+  int32_t v1 = 0;
+  int64_t o1 = 0, e1 = 0;
+  if (item + gridDim.x < count) {
+    v1 = a.active[vgpr_u32(item + gridDim.x)];
+    row_bounds<OffT>(a.off, v1, &o1, &e1);
+  }
   while (item < count) {
+    const int32_t v = first_lane_i32(vq);
+    const int64_t o = first_lane_i64(oq), d = first_lane_i64(eq) - o;
+    const uint32_t nitem = item + gridDim.x;
+    const uint32_t n2item = nitem + gridDim.x;
+    const int32_t v2 = n2item < count ? a.active[vgpr_u32(n2item)] : 0;
     // own label, read before the barriers below: in asynchronous mode thread
-    // 0 overwrites it, and every thread must reach the same move decision
-    const int32_t cur = a.C[v];
+    // 0 overwrites it, and every thread must reach the same move decision (a
+    // vector load: used only by the decision at the row's end)
+    const int32_t cur = a.C[vgpr_u32((uint32_t)v)];
     const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
     uint32_t lab[U];
 #pragma unroll
@@ -840,11 +875,11 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
         list_claimed(cl, lst, &lst_n);
       }
     }
-    const uint32_t nitem = item + gridDim.x;
-    int32_t nv = 0, nj[U];
-    int64_t no = 0, nd = 0;
+    int32_t nj[U];
     float nw[U];
-    if (nitem < count) head(nitem, nv, no, nd, nj, nw);
+    if (nitem < count) head(v1, o1, e1 - o1, nj, nw);
+    int64_t o2 = 0, e2 = 0;
+    if (n2item < count) row_bounds<OffT>(a.off, v2, &o2, &e2);
     __syncthreads();
     unsigned long long best = 0;
     const uint32_t nl = lst_n;
@@ -876,7 +911,8 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     }
     __syncthreads();  // red[] and the slot list are rewritten by the next vertex
     item = nitem;
-    v = nv; o = no; d = nd;
+    vq = v1; oq = o1; eq = e1;
+    v1 = v2; o1 = o2; e1 = e2;
 #pragma unroll
     for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
   }
