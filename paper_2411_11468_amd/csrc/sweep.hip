@@ -419,7 +419,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   const uint32_t stride = gridDim.x * WAVES;
   unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0, my_fneg = 0;
-  int32_t vq = 0, j[U];  // the current row's vertex and offsets, in VGPRs
+  int32_t vq = 0, j[U];  // the current row's vertex and offsets
   int64_t oq = 0, eq = 0;
   float wt[U];
   // a row's first 64*U targets and weights, its offsets known
@@ -434,8 +434,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   };
   uint32_t item = blockIdx.x * WAVES + wv;
   if (item < count) {
-    vq = a.active[vgpr_u32(item)];
+    vq = first_lane_i32(a.active[vgpr_u32(item)]);
     row_bounds<OffT>(a.off, vq, &oq, &eq);
+    oq = first_lane_i64(oq);
+    eq = first_lane_i64(eq);
     head(vq, oq, eq - oq, j, wt);
   }
   // the next row's list entry and offsets (v1, o1, e1): loaded one row
@@ -444,12 +446,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
   int32_t v1 = 0;
   int64_t o1 = 0, e1 = 0;
   if (item + stride < count) {
-    v1 = a.active[vgpr_u32(item + stride)];
+    v1 = first_lane_i32(a.active[vgpr_u32(item + stride)]);
     row_bounds<OffT>(a.off, v1, &o1, &e1);
+    o1 = first_lane_i64(o1);
+    e1 = first_lane_i64(e1);
   }
   while (item < count) {
-    const int32_t v = first_lane_i32(vq);
-    const int64_t o = first_lane_i64(oq), d = first_lane_i64(eq) - o;
+    const int32_t v = vq;
+    const int64_t o = oq, d = eq - o;
     const uint32_t nitem = item + stride;
     const uint32_t n2item = nitem + stride;
     const int32_t v2 = n2item < count ? a.active[vgpr_u32(n2item)] : 0;
@@ -544,7 +548,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_sweep_wave_pipe(SweepArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     item = nitem;
     vq = v1; oq = o1; eq = e1;
-    v1 = v2; o1 = o2; e1 = e2;
+    // complete by now (the rotation of the head's registers waits for them)
+    v1 = first_lane_i32(v2);
+    o1 = first_lane_i64(o2);
+    e1 = first_lane_i64(e2);
 #pragma unroll
     for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
   }
@@ -803,7 +810,7 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
   const uint32_t count = a.st->active[a.cls];
   unsigned long long my_edges = 0, my_flagw = 0;
   uint32_t my_changed = 0;
-  int32_t vq = 0, j[U];  // the current row's vertex and offsets, in VGPRs
+  int32_t vq = 0, j[U];  // the current row's vertex and offsets
   int64_t oq = 0, eq = 0;
   float wt[U];
   // a row's first BT*U targets and weights, its offsets known
@@ -818,8 +825,10 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
   };
   uint32_t item = blockIdx.x;
   if (item < count) {
-    vq = a.active[vgpr_u32(item)];
+    vq = first_lane_i32(a.active[vgpr_u32(item)]);
     row_bounds<OffT>(a.off, vq, &oq, &eq);
+    oq = first_lane_i64(oq);
+    eq = first_lane_i64(eq);
     head(vq, oq, eq - oq, j, wt);
   }
   // the next row's list entry and offsets (v1, o1, e1), loaded one row
@@ -827,12 +836,14 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
   int32_t v1 = 0;
   int64_t o1 = 0, e1 = 0;
   if (item + gridDim.x < count) {
-    v1 = a.active[vgpr_u32(item + gridDim.x)];
+    v1 = first_lane_i32(a.active[vgpr_u32(item + gridDim.x)]);
     row_bounds<OffT>(a.off, v1, &o1, &e1);
+    o1 = first_lane_i64(o1);
+    e1 = first_lane_i64(e1);
   }
   while (item < count) {
-    const int32_t v = first_lane_i32(vq);
-    const int64_t o = first_lane_i64(oq), d = first_lane_i64(eq) - o;
+    const int32_t v = vq;
+    const int64_t o = oq, d = eq - o;
     const uint32_t nitem = item + gridDim.x;
     const uint32_t n2item = nitem + gridDim.x;
     const int32_t v2 = n2item < count ? a.active[vgpr_u32(n2item)] : 0;
@@ -841,6 +852,25 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     // vector load: used only by the decision at the row's end)
     const int32_t cur = a.C[vgpr_u32((uint32_t)v)];
     const uint32_t p1 = table_p1_load((uint32_t)d, a.tload, (uint32_t)SLOTS);
+    // rows longer than the head: each further chunk's targets are loaded
+    // before the labels of the chunk ahead of it are read, so that the two
+    // loads overlap
+    constexpr bool kLong = (SLOTS + 1) / 2 > BT * U;
+    constexpr int64_t kStep = (int64_t)BT * U;
+    int32_t jn[U];
+    float wn[U];
+    auto chunk = [&](int64_t base) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * BT + tid;
+        const bool has = e < d;
+        jn[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
+        wn[u] = has ? edge_weight(a.w, o + e) : 0.0f;
+      }
+    };
+    if constexpr (kLong) {
+      if (kStep < d) chunk(kStep);
+    }
     uint32_t lab[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -853,16 +883,12 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
           lab[u] != kEmpty ? lds_accumulate_claim(keys, vals, p1, lab[u], wt[u], a.probe) : -1;
       list_claimed(cl, lst, &lst_n);
     }
-    for (int64_t base = (int64_t)BT * U; base < d; base += (int64_t)BT * U) {
+    for (int64_t base = kStep; kLong && base < d; base += kStep) {
       int32_t jj[U];
       float ww[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t e = base + u * BT + tid;
-        const bool has = e < d;
-        jj[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e]) : v;
-        ww[u] = has ? edge_weight(a.w, o + e) : 0.0f;
-      }
+      for (int u = 0; u < U; ++u) { jj[u] = jn[u]; ww[u] = wn[u]; }
+      if (base + kStep < d) chunk(base + kStep);
 #pragma unroll
       for (int u = 0; u < U; ++u)
         lab[u] = (jj[u] != v) ? (id0 ? (uint32_t)jj[u] : (uint32_t)a.C[jj[u]]) : kEmpty;
@@ -912,7 +938,10 @@ __global__ __launch_bounds__(BT) void k_sweep_block_pipe(SweepArgs a) {
     __syncthreads();  // red[] and the slot list are rewritten by the next vertex
     item = nitem;
     vq = v1; oq = o1; eq = e1;
-    v1 = v2; o1 = o2; e1 = e2;
+    // complete by now (the rotation of the head's registers waits for them)
+    v1 = first_lane_i32(v2);
+    o1 = first_lane_i64(o2);
+    e1 = first_lane_i64(e2);
 #pragma unroll
     for (int u = 0; u < U; ++u) { j[u] = nj[u]; wt[u] = nw[u]; }
   }
