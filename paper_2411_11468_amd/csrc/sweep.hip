@@ -1091,18 +1091,16 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   // loaded before the barrier that ends the current slice's accumulation, so
   // that they are in flight during its partition phase.
   constexpr int U = 4;
+  constexpr int64_t kStep = (int64_t)BT * U;
   struct Head {
-    int32_t h, c, v;
-    int64_t o, e0, n;
+    int32_t c, v, lgb, bq;
+    int64_t o, e0, n, boff0, slice0;
     int32_t j[U];
     float wt[U];
   };
-  auto head = [&](uint32_t it, Head& H) {
-    H.h = (int32_t)isrc[2 * (uint64_t)it];
-    H.c = (int32_t)isrc[2 * (uint64_t)it + 1];
-    H.v = a.hub_vid[H.h];
-    int64_t d;
-    row_of<OffT>(a.off, H.v, &H.o, &d);
+  // a slice's extent from its hub's row end, and its first BT*U targets
+  auto head_tgt = [&](Head& H, int64_t end) {
+    const int64_t d = end - H.o;
     H.e0 = (int64_t)H.c * a.chunk;
     H.n = (d - H.e0 < a.chunk) ? d - H.e0 : a.chunk;
 #pragma unroll
@@ -1122,37 +1120,64 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
   int par = 0;
   __syncthreads();
   Head cur{};
-  if (it != kNone) head(it, cur);
+  if (it != kNone) {
+    const int32_t h = (int32_t)isrc[2 * (uint64_t)it];
+    cur.c = (int32_t)isrc[2 * (uint64_t)it + 1];
+    cur.v = a.hub_vid[h];
+    cur.lgb = a.hub_lgb[h];
+    cur.bq = a.hub_bq[h];
+    cur.boff0 = a.hub_boff0[h];
+    cur.slice0 = a.hub_slice0[h];
+    int64_t end;
+    row_bounds<OffT>(a.off, cur.v, &cur.o, &end);
+    head_tgt(cur, end);
+  }
   while (it != kNone) {
-    const int32_t h = cur.h, c = cur.c, v = cur.v;
-    const int64_t o = cur.o, e0 = cur.e0, n = cur.n;
-    const int lgb = a.hub_lgb[h];
-    // read here, before the next head's loads are issued, so that waiting
-    // for them later does not wait for that prefetch
-    const int32_t bq = a.hub_bq[h];
-    const int64_t boff0 = a.hub_boff0[h], slice0 = a.hub_slice0[h];
+    const int32_t c = cur.c, v = cur.v, lgb = cur.lgb, bq = cur.bq;
+    const int64_t o = cur.o, e0 = cur.e0, n = cur.n, boff0 = cur.boff0, slice0 = cur.slice0;
+    // the next slice's header in three dependent steps (its item; its hub's
+    // vertex and bucket parameters; the row offsets), vector loads each
+    // issued while a chunk's labels of this slice are in flight
+    const bool more = nit != kNone;
+    uint32_t h1 = 0u, c1 = 0u;
+    if (more) {
+      const uint64_t q = 2 * (uint64_t)vgpr_u32(nit);
+      h1 = isrc[q];
+      c1 = isrc[q + 1];
+    }
+    int32_t v1 = 0, lgb1 = 0, bq1 = 0;
+    int64_t boff1 = 0, sl1 = 0, o1 = 0, end1 = 0;
     const uint32_t nb = 1u << lgb;
     for (uint32_t b = tid; b < nb; b += BT) hist[b] = 0u;
     const uint32_t p1c = table_p1((uint32_t)n);
-    for (int64_t base = 0; base < n; base += (int64_t)BT * U) {
-      int32_t j[U];
-      float wt[U];
-      if (base == 0) {
+    int32_t jn[U];
+    float wn[U];
+    auto chunk = [&](int64_t base) {  // targets of the chunk at base
 #pragma unroll
-        for (int u = 0; u < U; ++u) { j[u] = cur.j[u]; wt[u] = cur.wt[u]; }
-      } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t e = base + u * BT + tid;
-          const bool has = e < n;
-          j[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e0 + e]) : v;
-          wt[u] = has ? edge_weight(a.w, o + e0 + e) : 0.0f;
-        }
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = base + u * BT + tid;
+        const bool has = e < n;
+        jn[u] = has ? __builtin_nontemporal_load(&a.tgt[o + e0 + e]) : v;
+        wn[u] = has ? edge_weight(a.w, o + e0 + e) : 0.0f;
       }
+    };
+    auto accumulate = [&](const int32_t* j, const float* wsrc, int step) {
       uint32_t lab[U];
+      float wt[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < U; ++u) {
         lab[u] = (j[u] != v) ? (id0 ? (uint32_t)j[u] : (uint32_t)a.C[j[u]]) : kEmpty;
+        wt[u] = wsrc[u];
+      }
+      if (more && step == 0) {
+        v1 = a.hub_vid[h1];
+        lgb1 = a.hub_lgb[h1];
+        bq1 = a.hub_bq[h1];
+        boff1 = a.hub_boff0[h1];
+        sl1 = a.hub_slice0[h1];
+      } else if (more && step == 1) {
+        row_bounds<OffT>(a.off, v1, &o1, &end1);
+      }
       #pragma unroll
       for (int u = 0; u < U; ++u) merge_lead(lab[u], wt[u], a.w == nullptr);
 #pragma unroll
@@ -1161,9 +1186,31 @@ __global__ __launch_bounds__(BT) void k_hub_part(HubArgs a) {
             lab[u] != kEmpty ? lds_accumulate_claim(keys, vals, p1c, lab[u], wt[u], a.probe) : -1;
         list_claimed(cl, lst, &lst_n, kLst);
       }
+    };
+    // the head chunk, then the rest, each chunk's targets loaded while the
+    // labels of the chunk ahead of it are read
+    if (kStep < n) chunk(kStep);
+    accumulate(cur.j, cur.wt, 0);
+    for (int64_t base = kStep; base < n; base += kStep) {
+      int32_t jj[U];
+      float ww[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) { jj[u] = jn[u]; ww[u] = wn[u]; }
+      if (base + kStep < n) chunk(base + kStep);
+      accumulate(jj, ww, base == kStep ? 1 : 2);
     }
+    if (more && n <= kStep) row_bounds<OffT>(a.off, v1, &o1, &end1);
     Head nxt{};
-    if (nit != kNone) head(nit, nxt);
+    if (more) {
+      nxt.c = first_lane_i32((int32_t)c1);
+      nxt.v = first_lane_i32(v1);
+      nxt.lgb = first_lane_i32(lgb1);
+      nxt.bq = first_lane_i32(bq1);
+      nxt.boff0 = first_lane_i64(boff1);
+      nxt.slice0 = first_lane_i64(sl1);
+      nxt.o = first_lane_i64(o1);
+      head_tgt(nxt, first_lane_i64(end1));
+    }
     // the slice after the next one, read by every thread after the last
     // barrier of this slice (two words: a slow thread may still read the
     // previous one while thread 0 writes this one)
