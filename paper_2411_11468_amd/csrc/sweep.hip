@@ -1297,93 +1297,152 @@ __global__ __launch_bounds__(BT) void k_hub_reduce(HubArgs a) {
   const uint32_t x = blockIdx.x % nx, lw = blockIdx.x / nx, nlw = gridDim.x / nx;
   if (lw >= nlw) return;  // workgroups past the last full round of XCDs
   const uint32_t per = (nitems + nx - 1) / nx;
-  for (uint32_t j = lw; j < per; j += nlw) {
-    const uint32_t it = x * per + j;
-    if (it >= nitems) break;
-    // pairs of this bucket over all slices (counted by k_hub_part), read
-    // first: the buckets of the other size class are passed over with this
-    // one load
-    const uint32_t E = a.bsize[it];
-    if (E == 0 || (E > kHubSmallE) != LARGE) continue;  // uniform over the workgroup
-    const int32_t h = (int32_t)a.bitems[2 * (uint64_t)it];
-    const uint32_t b = a.bitems[2 * (uint64_t)it + 1];
-    const int32_t v = a.hub_vid[h];
-    int64_t o, d;
-    row_of<OffT>(a.off, v, &o, &d);
-    const uint32_t nch = (uint32_t)((d + a.chunk - 1) / a.chunk);
-    const int lgb = a.hub_lgb[h];
-    const uint32_t nb1 = (1u << lgb) + 1u;
-    const uint32_t* bo = a.boff + a.hub_boff0[h];
-    uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
-    if (p1 > a.table_cap) p1 = a.table_cap;
-    const int64_t slice0 = a.hub_slice0[h];
-    uint32_t* gk = a.gkeys + a.hub_tab[h];
-    float* gv = a.gvals + a.hub_tab[h];
-    const uint32_t p1g = table_p1((uint32_t)d);
-    bool my_spill = false;
-    // the bucket's runs, kRuns slices at a time: their lengths are scanned
-    // into start[], and the workgroup's threads take the pass's entries
-    // evenly, each finding its slice by binary search in start[]
-    for (uint32_t c0 = 0; c0 < nch; c0 += kRuns) {
-      const uint32_t cn = (nch - c0 < (uint32_t)kRuns) ? nch - c0 : (uint32_t)kRuns;
-      for (uint32_t i = tid; i < cn; i += BT) {
-        const uint32_t c = c0 + i;
-        start[i] = bo[c * nb1 + b + 1] - bo[c * nb1 + b];
+  // The workgroup's buckets are x * per + j for j = lw, lw + nlw, ...  They
+  // are taken BT at a time: each thread reads one bucket's pair count
+  // (counted by k_hub_part), the buckets of this size class that hold pairs
+  // are listed in order, and the listed buckets are reduced one after the
+  // other, the next one's header loaded while the current one's pairs are
+  // in flight.
+  __shared__ uint32_t ilist[BT], elist[BT], wcnt[BT / 64];
+  const int wv = tid >> 6;
+  for (uint32_t j0 = lw; j0 < per; j0 += (uint32_t)BT * nlw) {
+    {
+      const uint64_t jt = (uint64_t)j0 + (uint64_t)tid * nlw;
+      const uint64_t itt = (uint64_t)x * per + jt;
+      uint32_t E = 0;
+      if (jt < per && itt < nitems) E = a.bsize[itt];
+      const bool q = E != 0 && (E > kHubSmallE) == LARGE;
+      const unsigned long long m = __ballot(q);
+      if (lane == 0) wcnt[wv] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t pos = 0;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w];
+      if (q) {
+        ilist[pos + lane_rank(m)] = (uint32_t)itt;
+        elist[pos + lane_rank(m)] = E;
       }
       __syncthreads();
-      const uint32_t total = block_exclusive_scan<BT, kRuns / BT>(start, cn, wsum);
-      // whole-wave steps (the last one partial), so that the lanes holding
-      // the label of the wave's first pair can merge before the inserts:
-      // the runs of different slices repeat the same labels
-      for (uint32_t g0 = 0; g0 < total; g0 += BT) {
-        const uint32_t g = g0 + tid;
-        uint32_t kk = kEmpty;
-        float vv = 0.0f;
-        if (g < total) {
-          uint32_t lo = 0, hi = cn - 1;  // largest i with start[i] <= g
-          while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (start[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    uint32_t nlist = 0;
+    for (int w = 0; w < BT / 64; ++w) nlist += wcnt[w];
+    // header of the listed bucket k: its hub and bucket index (step 1), then
+    // the hub's bucket count, run offsets, first slice, spill table and
+    // slice count (step 2); vector loads, made uniform when the bucket is
+    // reached
+    auto step1 = [&](uint32_t k, uint32_t& hh, uint32_t& bb) {
+      const uint64_t q = 2 * (uint64_t)vgpr_u32(ilist[k]);
+      hh = a.bitems[q];
+      bb = a.bitems[q + 1];
+    };
+    struct Hub2 { int32_t lgb, nch; int64_t boff0, slice0, tab; };
+    auto step2 = [&](uint32_t hh, Hub2& r) {
+      r.lgb = a.hub_lgb[hh];
+      r.nch = a.hub_nch[hh];
+      r.boff0 = a.hub_boff0[hh];
+      r.slice0 = a.hub_slice0[hh];
+      r.tab = a.hub_tab[hh];
+    };
+    uint32_t hq = 0u, bq = 0u;
+    Hub2 cq{};
+    if (nlist > 0) {
+      step1(0, hq, bq);
+      step2(hq, cq);
+    }
+    for (uint32_t k = 0; k < nlist; ++k) {
+      const int32_t h = first_lane_i32((int32_t)hq);
+      const uint32_t b = (uint32_t)first_lane_i32((int32_t)bq);
+      const uint32_t E = elist[k];
+      const uint32_t nch = (uint32_t)first_lane_i32(cq.nch);
+      const int lgb = first_lane_i32(cq.lgb);
+      const int64_t boff0 = first_lane_i64(cq.boff0);
+      const int64_t slice0 = first_lane_i64(cq.slice0);
+      const int64_t tab = first_lane_i64(cq.tab);
+      const bool more = k + 1 < nlist;
+      uint32_t h1 = 0u, b1 = 0u;
+      if (more) step1(k + 1, h1, b1);
+      Hub2 c1{};
+      bool c1_done = false;
+      const uint32_t nb1 = (1u << lgb) + 1u;
+      const uint32_t* bo = a.boff + boff0;
+      uint32_t p1 = E <= (uint32_t)(SLOTS + 1) / 2 ? table_p1(E > 0 ? E : 1u) : (uint32_t)SLOTS;
+      if (p1 > a.table_cap) p1 = a.table_cap;
+      uint32_t* gk = a.gkeys + tab;
+      float* gv = a.gvals + tab;
+      bool my_spill = false;
+      // the bucket's runs, kRuns slices at a time: their lengths are scanned
+      // into start[], and the workgroup's threads take the pass's entries
+      // evenly, each finding its slice by binary search in start[]
+      for (uint32_t c0 = 0; c0 < nch; c0 += kRuns) {
+        const uint32_t cn = (nch - c0 < (uint32_t)kRuns) ? nch - c0 : (uint32_t)kRuns;
+        for (uint32_t i = tid; i < cn; i += BT) {
+          const uint32_t c = c0 + i;
+          start[i] = bo[c * nb1 + b + 1] - bo[c * nb1 + b];
+        }
+        if (more && !c1_done) {
+          step2(h1, c1);
+          c1_done = true;
+        }
+        __syncthreads();
+        const uint32_t total = block_exclusive_scan<BT, kRuns / BT>(start, cn, wsum);
+        // whole-wave steps (the last one partial), so that the lanes holding
+        // the label of the wave's first pair can merge before the inserts:
+        // the runs of different slices repeat the same labels
+        for (uint32_t g0 = 0; g0 < total; g0 += BT) {
+          const uint32_t g = g0 + tid;
+          uint32_t kk = kEmpty;
+          float vv = 0.0f;
+          if (g < total) {
+            uint32_t lo = 0, hi = cn - 1;  // largest i with start[i] <= g
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi + 1) >> 1;
+              if (start[mid] <= g) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t c = c0 + lo;
+            const uint32_t e = bo[c * nb1 + b] + (g - start[lo]);
+            const int64_t idx = (slice0 + c) * (int64_t)a.chunk + e;
+            kk = a.part_keys[idx];
+            vv = a.part_vals[idx];
           }
-          const uint32_t c = c0 + lo;
-          const uint32_t e = bo[c * nb1 + b] + (g - start[lo]);
-          const int64_t idx = (slice0 + c) * (int64_t)a.chunk + e;
-          kk = a.part_keys[idx];
-          vv = a.part_vals[idx];
+          merge_lead(kk, vv, false);
+          if (kk == kEmpty) continue;
+          if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.probe)) {
+            // the hub's spill table holds table_p1(degree) slots
+            int64_t o, d;
+            row_of<OffT>(a.off, a.hub_vid[h], &o, &d);
+            float after;
+            (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, table_p1((uint32_t)d), kk,
+                                                              vv, a.probe, &after);
+            my_spill = true;
+          }
         }
-        merge_lead(kk, vv, false);
-        if (kk == kEmpty) continue;
-        if (!lds_accumulate_bounded(keys, vals, p1, kk, vv, a.probe)) {
-          float after;
-          (void)global_accumulate<__HIP_MEMORY_SCOPE_AGENT>(gk, gv, p1g, kk, vv, a.probe,
-                                                            &after);
-          my_spill = true;
+        __syncthreads();  // start[] is rewritten by the next pass
+      }
+      if (more && !c1_done) step2(h1, c1);
+      if (my_spill) spilled = 1;
+      __syncthreads();
+      unsigned long long best = 0;
+      for (uint32_t s = tid; s < p1; s += BT) {
+        const uint32_t kk = keys[s];
+        if (kk != kEmpty) {
+          best = umax64(best, pack_key(vals[s], kk));
+          keys[s] = kEmpty;
+          vals[s] = 0.0f;
         }
       }
-      __syncthreads();  // start[] is rewritten by the next pass
-    }
-    if (my_spill) spilled = 1;
-    __syncthreads();
-    unsigned long long best = 0;
-    for (uint32_t s = tid; s < p1; s += BT) {
-      const uint32_t kk = keys[s];
-      if (kk != kEmpty) {
-        best = umax64(best, pack_key(vals[s], kk));
-        keys[s] = kEmpty;
-        vals[s] = 0.0f;
+      best = wave_max_u64(best);
+      if (lane == 0) red[tid >> 6] = best;
+      __syncthreads();
+      if (tid == 0) {
+        unsigned long long bb = red[0];
+        for (int q = 1; q < BT / 64; ++q) bb = umax64(bb, red[q]);
+        if (bb) atomicMax(&a.hub_best[h], bb);
+        if (spilled) a.hub_ovf[h] = 1;
+        spilled = 0;
       }
+      __syncthreads();
+      hq = h1; bq = b1; cq = c1;
     }
-    best = wave_max_u64(best);
-    if (lane == 0) red[tid >> 6] = best;
-    __syncthreads();
-    if (tid == 0) {
-      unsigned long long bb = red[0];
-      for (int q = 1; q < BT / 64; ++q) bb = umax64(bb, red[q]);
-      if (bb) atomicMax(&a.hub_best[h], bb);
-      if (spilled) a.hub_ovf[h] = 1;
-      spilled = 0;
-    }
-    __syncthreads();
+    __syncthreads();  // ilist, elist and wcnt are rewritten by the next batch
   }
 }
 
