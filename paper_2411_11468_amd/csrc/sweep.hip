@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
 // either is reduced (a step is a chain of four dependent loads).
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_sweep_small16x2(SweepArgs a) {
-  constexpr int G = 16, R = 2;
+  constexpr int G = 16, R = 3;
   constexpr uint32_t kVpw = 64 / G;
   if (a.st->stop) return;
   const int pl = a.st->pl;  // fixed for the whole sweep
@@ -1699,7 +1699,7 @@ __global__ __launch_bounds__(BT) void k_sweep_direct2(SweepArgs a) {
   static_assert(G == 4 || G == 8, "the classes that gain from it");
   constexpr int kPer = 64 / G;  // vertices per wave step
   constexpr int UD = 4;         // entries per lane loaded with the step's head
-  constexpr int R = 2;          // steps in flight
+  constexpr int R = 3;          // steps in flight
   if (a.st->stop) return;
   const int pl = a.st->pl;  // fixed for the whole sweep
   const int tid = threadIdx.x, lane = tid & 63;
