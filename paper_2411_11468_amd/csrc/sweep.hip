@@ -217,9 +217,10 @@ __global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
-// Plain k_sweep_small<16> with two wave steps in flight: the list entries,
-// offsets, targets and neighbour labels of both steps are loaded before
-// either is reduced (a step is a chain of four dependent loads).
+// Plain k_sweep_small<16> with R wave steps in flight (three; two gained
+// less): the list entries, offsets, targets and neighbour labels of all R
+// steps are loaded before any is reduced (a step is a chain of four
+// dependent loads).
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_sweep_small16x2(SweepArgs a) {
   constexpr int G = 16, R = 3;
@@ -1688,9 +1689,9 @@ __global__ __launch_bounds__(BT) void k_sweep_direct(SweepArgs a) {
   if constexpr (FEAT) flush_fneg(my_fneg, a.st);
 }
 
-// Plain first sweep of the rows of 5-64 entries, two wave steps at a time:
-// the list entries, row offsets and first targets of both steps are loaded
-// before either step is reduced.  A step is a chain of three
+// Plain first sweep of the rows of 5-64 entries, R wave steps at a time:
+// the list entries, row offsets and first targets of all R steps are loaded
+// before any step is reduced.  A step is a chain of three
 // dependent loads (list, offsets, targets), which the one-step loop of
 // k_sweep_direct waits for in turn.  Labels are the caller's ids, read from
 // the internal rows that hold them (ctgt) or from the caller's rows.
@@ -1951,9 +1952,10 @@ static hipError_t sweep_t(int cls, const SweepArgs& a, int grid, hipStream_t s) 
 
 template <typename OffT, bool FEAT>
 static hipError_t direct_t(int cls, const SweepArgs& a, int grid, hipStream_t s) {
-  // two steps in flight: 5-16-entry rows 0.43 -> 0.24 ms, 17-64-entry rows
-  // 0.57 -> 0.45 ms on R-MAT 26; the rows of up to 4 entries measured the
-  // same and those of 65-512 entries slower (0.48 -> 0.58 ms)
+  // three steps in flight: 5-16-entry rows 0.43 -> 0.23 ms, 17-64-entry
+  // rows 0.57 -> 0.44 ms on R-MAT 26 (two: 0.24 and 0.45 ms); with two, the
+  // rows of up to 4 entries measured the same and those of 65-512 entries
+  // slower (0.48 -> 0.58 ms)
   if constexpr (!FEAT) {
     switch (cls) {
       case 2: hipLaunchKernelGGL((k_sweep_direct2<OffT, 4, 256>), dim3(grid), dim3(256), 0, s, a); return hipGetLastError();
