@@ -480,7 +480,7 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 // their slices and their label buckets.  One workgroup of 1024 threads. -------
 template <typename OffT>
 __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_t* F) {
-  __shared__ uint32_t scan_s[1024], scan_b[1024];
+  __shared__ uint32_t ws[16], wb[16];
   __shared__ uint32_t run_s, run_b;
   __shared__ uint32_t nproc;
   const int tid = threadIdx.x;
@@ -512,38 +512,83 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
   if (a.witems && tid < kXcds) a.wctr[tid * kQueueCtrStride] = 0u;
   __syncthreads();
   const OffT* off = reinterpret_cast<const OffT*>(a.off);
-  // queue the flagged hubs' slices and buckets (inclusive Hillis-Steele scans
-  // of both counts over each tile of 1024 hubs)
-  for (int32_t tile = 0; tile < a.H; tile += 1024) {
-    const int32_t h = tile + tid;
-    uint32_t nch = 0, nbk = 0;
-    if (h < a.H) {
-      const int32_t v = a.hub_vid[h];
+  // each hub's slice count (0 unless flagged), kB tiles of 1024 hubs at a
+  // time, so that the dependent loads of kB hubs per thread (hub vertex, its
+  // flag, its row offsets) are in flight together; thread tid takes hubs
+  // tid mod 1024 in both passes and reads back only what it wrote
+  constexpr int kB = 4;
+  for (int32_t t0 = 0; t0 < a.H; t0 += 1024 * kB) {
+    int32_t hv[kB];
+    uint8_t hf[kB];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int32_t h = t0 + q * 1024 + tid;
+      hv[q] = h < a.H ? a.hub_vid[h] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kB; ++q) hf[q] = hv[q] >= 0 ? F[hv[q]] : (uint8_t)0;
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int32_t h = t0 + q * 1024 + tid;
+      if (h >= a.H) continue;
+      const int32_t v = hv[q];
       a.hub_best[h] = 0ull;
       a.hub_ovf[h] = 0;
-      if (F[v]) {
+      uint32_t nch = 0;
+      if (hf[q]) {
         F[v] = 0;
         a.hub_old[h] = C[v];
         const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
         nch = (uint32_t)((d + a.chunk - 1) / a.chunk);
-        nbk = 1u << a.hub_lgb[h];
         atomicAdd(&nproc, 1u);
       }
       a.hub_nch[h] = (int32_t)nch;
     }
-    scan_s[tid] = nch;
-    scan_b[tid] = nbk;
-    __syncthreads();
-    for (int ofs = 1; ofs < 1024; ofs <<= 1) {
-      const uint32_t as = tid >= ofs ? scan_s[tid - ofs] : 0u;
-      const uint32_t ab = tid >= ofs ? scan_b[tid - ofs] : 0u;
-      __syncthreads();
-      scan_s[tid] += as;
-      scan_b[tid] += ab;
-      __syncthreads();
+  }
+  // queue the flagged hubs' slices and buckets: a scan of both counts over
+  // each tile of 1024 hubs (within each wave by shuffles, then over the
+  // waves' totals); the next tile's counts are loaded during this one's
+  const int lane = tid & 63, wv = tid >> 6;
+  uint32_t rs = 0, rb = 0;  // slices and buckets queued by earlier tiles
+  int32_t nch_n = tid < a.H ? a.hub_nch[tid] : 0;
+  int32_t lgb_n = tid < a.H ? a.hub_lgb[tid] : 0;
+  for (int32_t tile = 0; tile < a.H; tile += 1024) {
+    const int32_t h = tile + tid;
+    const uint32_t nch = (uint32_t)nch_n;
+    const uint32_t nbk = nch ? 1u << lgb_n : 0u;
+    if (h + 1024 < a.H) {
+      nch_n = a.hub_nch[h + 1024];
+      lgb_n = a.hub_lgb[h + 1024];
+    } else {
+      nch_n = 0;
+      lgb_n = 0;
     }
-    const uint32_t fs = run_s + scan_s[tid] - nch;
-    const uint32_t fb = run_b + scan_b[tid] - nbk;
+    uint32_t xs = nch, xb = nbk;  // inclusive scans within the wave
+#pragma unroll
+    for (int ofs = 1; ofs < 64; ofs <<= 1) {
+      const uint32_t ys = __shfl_up(xs, ofs), yb = __shfl_up(xb, ofs);
+      if (lane >= ofs) {
+        xs += ys;
+        xb += yb;
+      }
+    }
+    if (lane == 63) {
+      ws[wv] = xs;
+      wb[wv] = xb;
+    }
+    __syncthreads();
+    uint32_t bs = 0, bb = 0, ts = 0, tb = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      if (w < wv) {
+        bs += ws[w];
+        bb += wb[w];
+      }
+      ts += ws[w];
+      tb += wb[w];
+    }
+    const uint32_t fs = rs + bs + xs - nch;
+    const uint32_t fb = rb + bb + xb - nbk;
     for (uint32_t c = 0; c < nch; ++c) {
       a.items[2 * (uint64_t)(fs + c)] = (uint32_t)h;
       a.items[2 * (uint64_t)(fs + c) + 1] = c;
@@ -554,13 +599,15 @@ __global__ __launch_bounds__(1024) void k_hub_plan(HubArgs a, int32_t* C, uint8_
       a.bsize[fb + b] = 0u;
     }
     if (nbk) a.hub_bq[h] = (int32_t)fb;
-    __syncthreads();
-    if (tid == 0) {
-      run_s += scan_s[1023];
-      run_b += scan_b[1023];
-    }
-    __syncthreads();
+    rs += ts;
+    rb += tb;
+    __syncthreads();  // ws and wb are rewritten by the next tile
   }
+  if (tid == 0) {
+    run_s = rs;
+    run_b = rb;
+  }
+  __syncthreads();
   if (tid == 0) {
     st->hub_items = run_s;
     st->hub_bitems = run_b;
